@@ -359,7 +359,7 @@ int orc_exact(void *h, int which, const uint8_t *p, int m, uint64_t *k_out, uint
  * segments are disjoint, so the count is a lower bound on the differences
  * of any transcript of w[0..i].
  */
-static void darray(const fm_t *rv, const uint8_t *w, int m, uint8_t *D, uint64_t *touch, int bpl)
+static void darray(const fm_t *rv, const uint8_t *w, int m, uint8_t *D, uint64_t *touch, int bpl, int maxd)
 {
     uint64_t k = 0, l = (uint64_t)rv->n;
     int z = 0;
@@ -376,6 +376,12 @@ static void darray(const fm_t *rv, const uint8_t *w, int m, uint8_t *D, uint64_t
             z++;
             k = 0;
             l = (uint64_t)rv->n;
+            if (z > maxd) {
+                /* the strand is already out of budget at the root; the rest
+                 * of the scan cannot change any decision */
+                for (int j = i; j < m; j++) D[j] = (uint8_t)(z > 255 ? 255 : z);
+                return;
+            }
         }
         D[i] = (uint8_t)(z > 255 ? 255 : z);
     }
@@ -386,7 +392,7 @@ static void darray(const fm_t *rv, const uint8_t *w, int m, uint8_t *D, uint64_t
 void orc_darray(void *h, int which, const uint8_t *w, int m, uint8_t *D)
 {
     const orc_index *ix = (const orc_index *)h;
-    darray(which ? &ix->fwd : &ix->rev, w, m, D, NULL, 1);
+    darray(which ? &ix->fwd : &ix->rev, w, m, D, NULL, 1, 255);
 }
 
 /* ------------------------------------------------------------------ */
@@ -588,7 +594,7 @@ static void align_one(const orc_index *ix, const uint8_t *W, int m, int maxd, co
         c.fm = srch;
         c.w = ws;
         c.strand = strand;
-        darray(other, ws, m, D, &cnt->touch_d, p->bases_per_line);
+        darray(other, ws, m, D, &cnt->touch_d, p->bases_per_line, maxd);
         c.D = D;
         /* the root: nothing consumed, interval of the empty string */
         if (!p->use_d || D[m - 1] <= maxd) visit(&c, m - 1, 0, (uint64_t)ix->n, 0, 0, 0, GAP_NONE, 0, 0, 0);
