@@ -1,0 +1,290 @@
+/*
+ * bwfm -- FM-index short-read alignment on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one BarraCUDA runs on the GPU (W. B. Langdon and
+ * B. Y. H. Lam, "Genetically Improved BarraCUDA", 2015, section 2): the
+ * reference genome is encoded offline into an index in which all suffixes
+ * that share a prefix sit together; each read is looked up by keeping an
+ * upper and a lower pointer into that index and narrowing them one base at
+ * a time (their distance is the number of matching positions; crossed
+ * pointers mean no match); inexact reads are handled by backing up the
+ * search and trying alternatives; the whole index lives in GPU memory; the
+ * two ends of a pair are aligned separately and then combined ("aln" then
+ * "sampe", section 3.7), using the approximate fragment length to discard
+ * placements that lie too far apart.  The search details follow the BWA
+ * short-read backtracking method that BarraCUDA derives from.
+ *
+ * Conventions
+ *  - Base codes: A=0, C=1, G=2, T=3; reads may also hold 4 (N), which
+ *    mismatches every reference base.  Symbol order $ < A < C < G < T.
+ *  - Every call returns 0 (BWFM_OK) or a negative bwfm_err.  On error
+ *    nothing is written to caller buffers except where a call says so;
+ *    bwfm_last_error() then describes the failure (per calling thread).
+ *  - "device" pointers are HIP device memory on the current device (for
+ *    example torch tensors' data_ptr()); "host" pointers are ordinary host
+ *    memory.  Work is issued on the hip_stream argument (a hipStream_t
+ *    passed as void *, NULL = the default stream).
+ *  - The caller owns every buffer it passes in.  The library owns the
+ *    index (host and device copies) and a per-index workspace, both
+ *    released by bwfm_index_free.  Calls on one index are serialised by
+ *    the library (a mutex guards its workspace).
+ */
+#ifndef BWFM_H
+#define BWFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum bwfm_err {
+    BWFM_OK = 0,
+    BWFM_E_INVAL = -1,    /* bad argument (NULL pointer, bad size or parameter) */
+    BWFM_E_NOMEM = -2,    /* host or device allocation failed */
+    BWFM_E_BASE = -3,     /* reference holds a code other than 0..3 */
+    BWFM_E_TOOLONG = -4,  /* reference too long (n + 1 >= 2^32) or read bound above 512 */
+    BWFM_E_CAPACITY = -5, /* a caller buffer is too small; see the call for what is reported */
+    BWFM_E_DEVICE = -6,   /* a HIP runtime call failed */
+    BWFM_E_STATE = -7     /* index not uploaded to the device */
+};
+
+/* Longest read and largest per-read difference budget accepted. */
+#define BWFM_MAX_READ 512
+#define BWFM_MAX_DIFF 15
+
+/* ------------------------------------------------------------------ */
+/* Index (section 2: the offline encoding of the reference; section 3.4:
+ * it must be resident in GPU memory for the search)                    */
+/* ------------------------------------------------------------------ */
+
+typedef struct bwfm_index bwfm_index;
+
+typedef struct {
+    uint32_t line_bytes;     /* rank line size: 64 or 128 bytes */
+    uint32_t bases_per_line; /* BWT rows per rank line: a multiple of 32 in
+                                [32, (line_bytes - 16) * 4]; 0 = the maximum
+                                (192 for 64-byte lines, 448 for 128) */
+    uint32_t sa_sample;      /* rows r with r % sa_sample == 0 keep SA[r];
+                                a power of two in [1, 1024] */
+    uint32_t n_threads;      /* host threads for the build; 0 = all cores */
+} bwfm_index_params;
+
+/*
+ * Build the FM-index of T = ref[0, n) and of reverse(T) on the host.
+ *   ref: host, n codes 0..3 (borrowed for the call only).
+ *   p:   layout; NULL = {128, 0, 32, 0}.
+ *   out: receives a new index (host part only; see bwfm_index_upload).
+ * Each direction holds the BWT of S$ packed 2 bits per row with $ stored
+ * as A, the row of $ ("primary"), C[a] = 1 + #symbols < a, rank lines
+ * (4 x uint32 counts of A, C, G, T before the line, $ counted as A, then
+ * the line's packed rows), and SA samples.  Errors: E_INVAL (NULL or bad
+ * layout), E_BASE, E_TOOLONG (n + 1 >= 2^32), E_NOMEM.
+ */
+int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index_params *p, bwfm_index **out);
+
+/* Copy the index to the current device's memory (once; later calls are
+ * no-ops).  Synchronises hip_stream.  Errors: E_INVAL, E_NOMEM, E_DEVICE. */
+int bwfm_index_upload(bwfm_index *idx, void *hip_stream);
+
+/* Release host and device memory of the index and its workspace. */
+void bwfm_index_free(bwfm_index *idx);
+
+typedef struct {
+    uint64_t n;             /* reference length */
+    uint64_t primary[2];    /* row of $: [0] index of T, [1] index of reverse(T) */
+    uint64_t C[2][4];       /* C[a] per direction */
+    uint64_t lines;         /* rank lines per direction */
+    uint64_t sa_samples;    /* SA samples per direction */
+    uint64_t device_bytes;  /* device memory the uploaded index occupies */
+    uint32_t line_bytes, bases_per_line, sa_sample, uploaded;
+} bwfm_index_info;
+
+int bwfm_index_get_info(const bwfm_index *idx, bwfm_index_info *out);
+
+/* Host-side inspection of the packed index, for tests.  which: 0 = index
+ * of T, 1 = index of reverse(T).
+ *   get_bwt:  out (host, n + 1 bytes) <- BWT symbols, 4 at the $ row.
+ *   get_sa_samples: out (host, info.sa_samples uint32) <- SA[r], r % sa_sample == 0.
+ *   occ: out (host, 4 uint64) <- Occ(a, i) = #a in BWT[0, i), 0 <= i <= n + 1,
+ *        decoded from the rank line holding row i. */
+int bwfm_index_get_bwt(const bwfm_index *idx, int which, uint8_t *out);
+int bwfm_index_get_sa_samples(const bwfm_index *idx, int which, uint32_t *out);
+int bwfm_index_occ(const bwfm_index *idx, int which, uint64_t i, uint64_t *out);
+
+/* ------------------------------------------------------------------ */
+/* Alignment ("aln"; section 2: per-read search with backtracking)     */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    const uint8_t *bases;    /* device: read r is bases[offsets[r], offsets[r+1]) */
+    const uint64_t *offsets; /* device: n_reads + 1 non-decreasing offsets */
+    const uint8_t *max_diff; /* device, n_reads per-read budgets, or NULL */
+    uint32_t n_reads;
+    uint32_t max_len;        /* host-known bound on read length, <= 512 */
+} bwfm_reads;
+
+enum { BWFM_MODE_ALL = 0, BWFM_MODE_BEST = 1 };
+
+typedef struct {
+    int32_t max_diff;       /* budget when reads.max_diff is NULL, 0..15 */
+    int32_t max_gapo;       /* most gap opens */
+    int32_t max_gape;       /* most gap extensions; -1 = limited by max_diff only */
+    int32_t seed_len;       /* 5' seed length; 0 = no seed rule */
+    int32_t seed_diff;      /* most differences inside the seed */
+    int32_t indel_end_skip; /* no insertion within this many bases of either end */
+    int32_t s_mm, s_gapo, s_gape; /* score of a mismatch, gap open, gap extension */
+    int32_t mode;           /* BWFM_MODE_ALL or BWFM_MODE_BEST */
+    int32_t max_best;       /* BEST: second tier reported only if c1 <= max_best */
+    uint32_t max_hits;      /* reads with more candidate hits report none */
+} bwfm_aln_params;
+
+/*
+ * One hit: a distinct reference string X matched by the read on one
+ * strand, with the best transcript's counts.  Strand 0 (+): [k, l] is the
+ * SA interval of reverse(X) in the index of reverse(T) (the read is
+ * searched 5' end first); strand 1 (-): [k, l] is the interval of X in the
+ * index of T, X matching revcomp(read).  len = |X|.
+ */
+typedef struct {
+    uint32_t k, l;
+    uint16_t len, score;
+    uint8_t strand, n_mm, n_gapo, n_gape;
+} bwfm_hit;
+
+/* per-read status bits */
+#define BWFM_ST_HIT 1      /* at least one hit reported */
+#define BWFM_ST_OVERFLOW 2 /* more than max_hits candidates: none reported, c1 = c2 = 0xFFFFFFFF */
+#define BWFM_ST_INVALID 4  /* read longer than reads.max_len / 512, or budget above 15 */
+#define BWFM_ST_RESEARCH 8 /* informational: the read's search outgrew the first pass's
+                              per-lane buffers and was redone with worst-case buffers */
+
+typedef struct {
+    uint64_t *hit_offsets;  /* device, n_reads + 1: hits of read r are [hit_offsets[r], hit_offsets[r+1]) */
+    bwfm_hit *hits;         /* device, hit_capacity entries */
+    uint64_t hit_capacity;
+    uint32_t *c1, *c2;      /* device, n_reads: summed widths of tier 1 and tier 2 */
+    uint8_t *status;        /* device, n_reads */
+} bwfm_aln_result;
+
+/*
+ * Align every read on both strands.  A transcript of read W against a
+ * reference string X uses match/mismatch, insertion (read base only) and
+ * deletion (reference base only); a gap is a maximal run of insertions or
+ * of deletions; diffs = mismatches + gap opens + gap extensions; score =
+ * s_mm n_mm + s_gapo n_gapo + s_gape n_gape.  Valid transcripts keep
+ * diffs <= budget, gap opens <= max_gapo, extensions <= max_gape (if >= 0),
+ * insertions at read indices [s, m - s), deletions at boundaries
+ * [max(s,1), m - max(s,1)] (s = indel_end_skip), and at most seed_diff
+ * differences inside the first seed_len bases as sequenced.  ALL mode
+ * reports every (strand, X) with a valid transcript, each with its smallest
+ * (score, diffs, n_gapo, n_mm).  BEST mode keeps tier 1 (minimum score S*)
+ * and, when c1 <= max_best, tier 2 (S* < score <= S* + s_mm).  Hits are
+ * ordered by (score, strand, k, len).  Reads longer than max_len or with a
+ * budget above 15 get BWFM_ST_INVALID; empty reads get status 0.
+ *
+ * Synchronous: returns after the results are complete on hip_stream.
+ * Errors: E_INVAL, E_STATE (index not uploaded), E_TOOLONG (max_len > 512),
+ * E_NOMEM, E_DEVICE; E_CAPACITY when the hits do not fit hit_capacity --
+ * then hit_offsets, c1, c2 and status are complete, hits is untouched, and
+ * hit_offsets[n_reads] holds the capacity needed.
+ */
+int bwfm_align_batch(const bwfm_index *idx, const bwfm_reads *reads, const bwfm_aln_params *p,
+                     bwfm_aln_result *res, void *hip_stream);
+
+/* As bwfm_align_batch, also writing each read's search work -- the number
+ * of search states expanded (each expansion issues the two rank queries at
+ * k and l + 1), summed over both passes -- to expand (device, n_reads). */
+int bwfm_align_batch_counted(const bwfm_index *idx, const bwfm_reads *reads, const bwfm_aln_params *p,
+                             bwfm_aln_result *res, uint32_t *expand, void *hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Locate and pairing ("sampe"; section 2: repeats give several
+ * placements, the other end and the fragment length decide)           */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Reference positions of every hit of res (n_reads reads) whose width
+ * l - k + 1 is at most max_occ: pos_offsets (device, n_hits + 1, n_hits =
+ * hit_offsets[n_reads]) receives CSR offsets per hit, positions (device,
+ * pos_capacity) the sorted 0-based leftmost forward coordinates of X.
+ * Synchronous.  E_CAPACITY when the positions do not fit: pos_offsets is
+ * complete and pos_offsets[n_hits] holds the capacity needed.
+ */
+int bwfm_locate(const bwfm_index *idx, uint32_t n_reads, const bwfm_aln_result *res, uint32_t max_occ,
+                uint64_t *pos_offsets, uint32_t *positions, uint64_t pos_capacity, void *hip_stream);
+
+typedef struct {
+    int32_t lo, hi, mu;  /* proper insert window [lo, hi] and its centre */
+    uint32_t max_occ;    /* hits wider than this are not located */
+} bwfm_pair_params;
+
+/* pair flags */
+#define BWFM_PF_PAIRED 1
+#define BWFM_PF_MAPPED1 2
+#define BWFM_PF_MAPPED2 4
+#define BWFM_PF_REP1 8   /* end 1 has a reported hit wider than max_occ */
+#define BWFM_PF_REP2 16
+
+typedef struct {
+    uint32_t pos1, pos2;       /* 0xFFFFFFFF when that end is unplaced */
+    int32_t insert;            /* pr + lr - pf of the chosen pair, 0 if unpaired */
+    uint16_t len1, len2;       /* |X| per end */
+    uint16_t score1, score2;
+    uint8_t strand1, strand2, flags, pad;
+} bwfm_pair;
+
+/*
+ * Pair n_pairs reads: r1 holds end 1's alignment of the pairs, r2 end 2's
+ * (NULL: single-end, each record gets end 1's primary only).  A proper pair
+ * puts the ends on opposite strands with pf <= pr and lo <= pr + lr - pf <=
+ * hi (pf: position of the + end; pr, lr: position and length of the - end);
+ * the chosen pair minimises (score1 + score2, |insert - mu|, pf, strand1,
+ * pos1, len1, pos2, len2).  Without one, each end takes its primary: the
+ * smallest (score, diffs, strand, pos, len) over its located hits.
+ * out: device, n_pairs records.  Synchronous.  Errors: E_INVAL, E_STATE,
+ * E_NOMEM, E_DEVICE.
+ */
+int bwfm_pair_reads(const bwfm_index *idx, uint32_t n_pairs, const bwfm_aln_result *r1,
+                    const bwfm_aln_result *r2, const bwfm_pair_params *p, bwfm_pair *out, void *hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Host helpers                                                         */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Insert window from n inserts (host) of uniquely placed proper pairs
+ * (section 2: the fragment length "can be inferred"): quartiles at index
+ * floor(q (n - 1)) of the sorted inserts; inserts outside [p25 - 2 IQR,
+ * p75 + 2 IQR] dropped; mu = mean, sigma = population sd of the rest;
+ * lo = max(0, floor(mu - 4 sigma)), hi = ceil(mu + 4 sigma), mu rounded
+ * half to even.  n < 100 gives {0, 500, 250}.  out->max_occ is untouched.
+ */
+int bwfm_estimate_insert(const int32_t *inserts, uint64_t n, bwfm_pair_params *out);
+
+/* Difference budget for a read of length len: the smallest k >= 0 with
+ * P[Poisson(err * len) > k] < thres (BWA's rule for a fractional budget;
+ * err = 0.02 and thres = 0.04 give 2/3/4/5/6 at 36/51/76/100/150 bases). */
+int bwfm_max_diff_rule(uint32_t len, double err, double thres);
+
+/*
+ * Kernel timing (off by default).  When on, the library brackets its
+ * kernel launches with HIP events on the caller's stream and, when the
+ * call completes, adds each launch's elapsed time under the kernel's name
+ * ("align_fast", "align_slow", "compact", "locate_rows", "sort", "pair").
+ * Process-wide; for measurement, not for concurrent production use.
+ *   timing_get: *total_ms and *launches for one name (0 if never run).
+ */
+int bwfm_timing_enable(int on);
+int bwfm_timing_reset(void);
+int bwfm_timing_get(const char *kernel, double *total_ms, uint64_t *launches);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *bwfm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BWFM_H */

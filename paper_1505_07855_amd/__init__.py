@@ -1,0 +1,361 @@
+"""bwfm: FM-index short-read alignment on AMD Instinct MI355X.
+
+Thin ctypes binding over ``libbwfm.so`` (``include/bwfm.h``).  It marshals
+arguments only: every step of the alignment path runs in the library's HIP
+kernels.  torch provides device memory and streams.  There is no CPU fallback:
+if the library is missing, every call raises.
+
+Names follow the C ABI: ``build_index``, ``align_batch``, ``locate``,
+``pair_reads``, ``estimate_insert``, ``max_diff_rule``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbwfm.so")
+_lib_handle = None
+
+# result records (same bytes as bwfm_hit / bwfm_pair)
+HIT_DTYPE = np.dtype([("k", "<u4"), ("l", "<u4"), ("len", "<u2"), ("score", "<u2"), ("strand", "u1"),
+                      ("n_mm", "u1"), ("n_gapo", "u1"), ("n_gape", "u1")])
+PAIR_DTYPE = np.dtype([("pos1", "<u4"), ("pos2", "<u4"), ("insert", "<i4"), ("len1", "<u2"), ("len2", "<u2"),
+                       ("score1", "<u2"), ("score2", "<u2"), ("strand1", "u1"), ("strand2", "u1"),
+                       ("flags", "u1"), ("pad", "u1")])
+
+ST_HIT, ST_OVERFLOW, ST_INVALID, ST_RESEARCH = 1, 2, 4, 8
+PF_PAIRED, PF_MAPPED1, PF_MAPPED2, PF_REP1, PF_REP2 = 1, 2, 4, 8, 16
+MODE_ALL, MODE_BEST = 0, 1
+E_CAPACITY = -5
+
+
+class BwfmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bwfm error {code}: {msg}")
+        self.code = code
+
+
+class _IndexParams(ctypes.Structure):
+    _fields_ = [("line_bytes", ctypes.c_uint32), ("bases_per_line", ctypes.c_uint32),
+                ("sa_sample", ctypes.c_uint32), ("n_threads", ctypes.c_uint32)]
+
+
+class _IndexInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("primary", ctypes.c_uint64 * 2), ("C", (ctypes.c_uint64 * 4) * 2),
+                ("lines", ctypes.c_uint64), ("sa_samples", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+                ("line_bytes", ctypes.c_uint32), ("bases_per_line", ctypes.c_uint32),
+                ("sa_sample", ctypes.c_uint32), ("uploaded", ctypes.c_uint32)]
+
+
+class _Reads(ctypes.Structure):
+    _fields_ = [("bases", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("max_diff", ctypes.c_void_p),
+                ("n_reads", ctypes.c_uint32), ("max_len", ctypes.c_uint32)]
+
+
+class _AlnParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("max_diff", "max_gapo", "max_gape", "seed_len", "seed_diff",
+                                              "indel_end_skip", "s_mm", "s_gapo", "s_gape", "mode", "max_best")] + [
+        ("max_hits", ctypes.c_uint32)]
+
+
+class _AlnResult(ctypes.Structure):
+    _fields_ = [("hit_offsets", ctypes.c_void_p), ("hits", ctypes.c_void_p), ("hit_capacity", ctypes.c_uint64),
+                ("c1", ctypes.c_void_p), ("c2", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+class _PairParams(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32), ("hi", ctypes.c_int32), ("mu", ctypes.c_int32), ("max_occ", ctypes.c_uint32)]
+
+
+# every function include/bwfm.h declares, plus the counted variant
+SYMBOLS = ("bwfm_build_index", "bwfm_index_upload", "bwfm_index_free", "bwfm_index_get_info", "bwfm_index_get_bwt",
+           "bwfm_index_get_sa_samples", "bwfm_index_occ", "bwfm_align_batch", "bwfm_locate", "bwfm_pair_reads",
+           "bwfm_estimate_insert", "bwfm_max_diff_rule", "bwfm_last_error", "bwfm_align_batch_counted",
+           "bwfm_timing_enable", "bwfm_timing_reset", "bwfm_timing_get")
+
+
+def lib():
+    """Load libbwfm.so; raises if it has not been built."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1505_07855_amd.build "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+        c_int = ctypes.c_int
+        sig = {
+            "bwfm_build_index": ([P, u64, P, ctypes.POINTER(P)], c_int),
+            "bwfm_index_upload": ([P, P], c_int),
+            "bwfm_index_free": ([P], None),
+            "bwfm_index_get_info": ([P, P], c_int),
+            "bwfm_index_get_bwt": ([P, c_int, P], c_int),
+            "bwfm_index_get_sa_samples": ([P, c_int, P], c_int),
+            "bwfm_index_occ": ([P, c_int, u64, P], c_int),
+            "bwfm_align_batch": ([P, P, P, P, P], c_int),
+            "bwfm_align_batch_counted": ([P, P, P, P, P, P], c_int),
+            "bwfm_locate": ([P, u32, P, u32, P, P, u64, P], c_int),
+            "bwfm_pair_reads": ([P, u32, P, P, P, P, P], c_int),
+            "bwfm_estimate_insert": ([P, u64, P], c_int),
+            "bwfm_max_diff_rule": ([u32, ctypes.c_double, ctypes.c_double], c_int),
+            "bwfm_last_error": ([], ctypes.c_char_p),
+            "bwfm_timing_enable": ([c_int], c_int),
+            "bwfm_timing_reset": ([], c_int),
+            "bwfm_timing_get": ([ctypes.c_char_p, P, P], c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        del i32
+        _lib_handle = L
+    return _lib_handle
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise BwfmError(rc, lib().bwfm_last_error().decode())
+
+
+def _np_ptr(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t) -> int:
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return t.data_ptr()
+
+
+@dataclass
+class Params:
+    """Search parameters (bwfm_aln_params).  Defaults are BWA's documented aln
+    defaults; the paper states none."""
+    max_diff: int = 4
+    max_gapo: int = 1
+    max_gape: int = -1
+    seed_len: int = 0
+    seed_diff: int = 2
+    indel_end_skip: int = 5
+    s_mm: int = 3
+    s_gapo: int = 11
+    s_gape: int = 4
+    mode: int = MODE_BEST
+    max_best: int = 30
+    max_hits: int = 256
+
+    def _c(self) -> _AlnParams:
+        return _AlnParams(*[getattr(self, f.name) for f in fields(self)])
+
+
+class Index:
+    """Packed FM-index of a reference and of its reverse (bwfm_build_index)."""
+
+    def __init__(self, ref: np.ndarray, line_bytes: int = 128, bases_per_line: int = 0, sa_sample: int = 32,
+                 threads: int = 0):
+        ref = np.ascontiguousarray(ref, np.uint8)
+        h = ctypes.c_void_p()
+        p = _IndexParams(line_bytes, bases_per_line, sa_sample, threads)
+        _check(lib().bwfm_build_index(_np_ptr(ref), len(ref), ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self.n = len(ref)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bwfm_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def upload(self, stream=None) -> "Index":
+        _check(lib().bwfm_index_upload(self._h, _stream_ptr(stream)))
+        return self
+
+    def info(self) -> dict:
+        i = _IndexInfo()
+        _check(lib().bwfm_index_get_info(self._h, ctypes.byref(i)))
+        return dict(n=i.n, primary=list(i.primary), C=[list(c) for c in i.C], lines=i.lines, sa_samples=i.sa_samples,
+                    device_bytes=i.device_bytes, line_bytes=i.line_bytes, bases_per_line=i.bases_per_line,
+                    sa_sample=i.sa_sample, uploaded=bool(i.uploaded))
+
+    def bwt(self, which: int = 0) -> np.ndarray:
+        out = np.empty(self.n + 1, np.uint8)
+        _check(lib().bwfm_index_get_bwt(self._h, which, _np_ptr(out)))
+        return out
+
+    def sa_samples(self, which: int = 0) -> np.ndarray:
+        out = np.empty(self.info()["sa_samples"], np.uint32)
+        _check(lib().bwfm_index_get_sa_samples(self._h, which, _np_ptr(out)))
+        return out
+
+    def occ(self, i: int, which: int = 0) -> np.ndarray:
+        out = np.empty(4, np.uint64)
+        _check(lib().bwfm_index_occ(self._h, which, i, _np_ptr(out)))
+        return out
+
+
+def build_index(ref: np.ndarray, **kw) -> Index:
+    return Index(ref, **kw)
+
+
+@dataclass
+class AlignResult:
+    """Device tensors of one align_batch call."""
+    hit_offsets: object  # int64 [n + 1]
+    hits: object         # int32 [capacity, 4] (bwfm_hit records)
+    c1: object           # int32 [n] (uint32 bits)
+    c2: object
+    status: object       # uint8 [n]
+    n_reads: int
+    expand: object = None
+
+    def _c(self) -> _AlnResult:
+        return _AlnResult(_dptr(self.hit_offsets), _dptr(self.hits), self.hits.shape[0], _dptr(self.c1),
+                          _dptr(self.c2), _dptr(self.status))
+
+    @property
+    def n_hits(self) -> int:
+        return int(self.hit_offsets[self.n_reads].item())
+
+    def to_numpy(self):
+        """(hit_offsets uint64, hits HIT_DTYPE, c1 uint32, c2 uint32, status uint8)."""
+        n_hits = self.n_hits
+        ho = self.hit_offsets.cpu().numpy().view(np.uint64)
+        hits = self.hits[:n_hits].contiguous().cpu().numpy().view(HIT_DTYPE).reshape(-1)
+        return (ho, hits, self.c1.cpu().numpy().view(np.uint32), self.c2.cpu().numpy().view(np.uint32),
+                self.status.cpu().numpy())
+
+
+def _reads_struct(bases, offsets, max_diff, max_len):
+    n = offsets.shape[0] - 1
+    if max_len is None:
+        raise ValueError("max_len (a host-known bound on read length) is required")
+    return _Reads(_dptr(bases) if bases.numel() else 0, _dptr(offsets),
+                  _dptr(max_diff) if max_diff is not None else None, n, max_len)
+
+
+def align_batch(index: Index, bases, offsets, params: Params, max_diff=None, max_len: int | None = None,
+                hit_capacity: int | None = None, stream=None, counted: bool = False, out: AlignResult | None = None
+                ) -> AlignResult:
+    """Align a ragged batch of reads (device uint8 bases, device int64
+    offsets) on both strands.  Returns device tensors; grows the hit buffer
+    and retries once if it was too small."""
+    torch = _torch()
+    n = offsets.shape[0] - 1
+    dev = offsets.device
+    rd = _reads_struct(bases, offsets, max_diff, max_len)
+    if out is None:
+        cap = hit_capacity if hit_capacity is not None else max(16, 4 * n)
+        out = AlignResult(torch.empty(n + 1, dtype=torch.int64, device=dev),
+                          torch.empty((cap, 4), dtype=torch.int32, device=dev),
+                          torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
+                          torch.empty(n, dtype=torch.uint8, device=dev), n)
+    if counted and out.expand is None:
+        out.expand = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    pc = params._c()
+    for attempt in range(2):
+        res = out._c()
+        if counted:
+            rc = lib().bwfm_align_batch_counted(index.handle, ctypes.byref(rd), ctypes.byref(pc), ctypes.byref(res),
+                                                _dptr(out.expand), _stream_ptr(stream))
+        else:
+            rc = lib().bwfm_align_batch(index.handle, ctypes.byref(rd), ctypes.byref(pc), ctypes.byref(res),
+                                        _stream_ptr(stream))
+        if rc == E_CAPACITY and attempt == 0:
+            need = int(out.hit_offsets[n].item())
+            out.hits = torch.empty((max(need, 1), 4), dtype=torch.int32, device=dev)
+            continue
+        _check(rc)
+        break
+    return out
+
+
+def locate(index: Index, res: AlignResult, max_occ: int, stream=None):
+    """Positions of every hit no wider than max_occ: (pos_offsets int64
+    [n_hits + 1], positions int32 [total] holding uint32 values)."""
+    torch = _torch()
+    dev = res.hit_offsets.device
+    n_hits = res.n_hits
+    po = torch.empty(n_hits + 1, dtype=torch.int64, device=dev)
+    cap = max(1, 2 * n_hits)
+    pos = torch.empty(cap, dtype=torch.int32, device=dev)
+    r = res._c()
+    rc = lib().bwfm_locate(index.handle, res.n_reads, ctypes.byref(r), max_occ, _dptr(po), _dptr(pos), cap,
+                           _stream_ptr(stream))
+    if rc == E_CAPACITY:
+        cap = int(po[n_hits].item())
+        pos = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        rc = lib().bwfm_locate(index.handle, res.n_reads, ctypes.byref(r), max_occ, _dptr(po), _dptr(pos), cap,
+                               _stream_ptr(stream))
+    _check(rc)
+    return po, pos[:int(po[n_hits].item())]
+
+
+def pair_reads(index: Index, r1: AlignResult, r2: AlignResult | None, lo: int, hi: int, mu: int, max_occ: int,
+               stream=None, out=None):
+    """Pair end-1 and end-2 alignments (r2 None: single-end primaries).
+    Returns a device uint8 tensor [n, 24] of bwfm_pair records."""
+    torch = _torch()
+    n = r1.n_reads
+    if out is None:
+        out = torch.empty((max(n, 1), PAIR_DTYPE.itemsize), dtype=torch.uint8, device=r1.hit_offsets.device)
+    pp = _PairParams(lo, hi, mu, max_occ)
+    a = r1._c()
+    b = r2._c() if r2 is not None else None
+    _check(lib().bwfm_pair_reads(index.handle, n, ctypes.byref(a), ctypes.byref(b) if b is not None else None,
+                                 ctypes.byref(pp), _dptr(out), _stream_ptr(stream)))
+    return out
+
+
+def pairs_numpy(t) -> np.ndarray:
+    return t.cpu().numpy().view(PAIR_DTYPE).reshape(-1)
+
+
+def timing_enable(on: bool = True):
+    _check(lib().bwfm_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(lib().bwfm_timing_reset())
+
+
+def timing_get(kernel: str):
+    """(total milliseconds, launches) of one kernel since the last reset."""
+    ms = ctypes.c_double()
+    n = ctypes.c_uint64()
+    _check(lib().bwfm_timing_get(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def estimate_insert(inserts: np.ndarray):
+    a = np.ascontiguousarray(inserts, np.int32)
+    pp = _PairParams(0, 0, 0, 0)
+    _check(lib().bwfm_estimate_insert(_np_ptr(a) if len(a) else None, len(a), ctypes.byref(pp)))
+    return pp.lo, pp.hi, pp.mu
+
+
+def max_diff_rule(length: int, err: float = 0.02, thres: float = 0.04) -> int:
+    return lib().bwfm_max_diff_rule(length, err, thres)

@@ -1,0 +1,1426 @@
+// bwfm: GPU side of the FM-index short-read alignment path and its C ABI.
+//
+// Method: Genetically Improved BarraCUDA, section 2 (backward search with an
+// upper and a lower pointer per read, backtracking over alternatives for
+// inexact reads, the whole index resident in GPU memory), with the search
+// rules of the BWA short-read backtracking method that BarraCUDA derives
+// from; locate and pairing as in "sampe" (sections 2 and 3.7).  The exact
+// definitions are stated in include/bwfm.h.
+//
+// Layout.  Each direction of the index is an array of rank lines (64 or
+// 128 bytes): four uint32 counts of A, C, G, T before the line ($ counted as
+// A), then the line's BWT rows packed two bits each, so one rank query is one
+// line fetch plus popcounts within the line.  Row-sampled suffix array values
+// serve locate.
+//
+// Search.  One lane per read, both strands in turn, each strand 5' end
+// first (strand +: reverse(read) on the index of reverse(T); strand -:
+// revcomp(read) on the index of T).  Per strand the lane first builds the
+// D-array lower bound on the other index, then runs a depth-first search
+// whose current state lives in registers; the first surviving child becomes
+// the next current state and its siblings go to a lane-private stack in
+// device memory, so the common one-child step touches no stack.  Children are
+// taken in a fixed order (match, mismatches by base, insertion, deletions by
+// base), and in BEST mode a state is dropped when its score plus the least
+// cost of its remaining D[i] differences exceeds best + s_mm.  Distinct hits
+// collect in a lane-private buffer.  Reads whose stack or hit buffer fills up
+// are searched again in a second pass with buffers of the worst-case size.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "bwfm_internal.h"
+
+using namespace bwfm;
+
+namespace {
+
+// ------------------------------------------------------------------ constants
+
+constexpr int GAP_NONE = 0, GAP_INS = 1, GAP_DEL = 2;
+constexpr uint32_t ST_RESEARCH = 8;  // status bit: needed the second pass
+constexpr int PH_FAST = 0, PH_BEST = 1, PH_COLLECT = 2;
+constexpr int INF_SCORE = 0x7fffffff;
+constexpr uint32_t FAST_STACK = 64;  // stack entries per lane, first pass
+constexpr uint32_t FAST_CAND = 32;   // hit slots per lane, first pass
+constexpr int BLOCK = 256;
+
+struct Params {
+    int max_diff, max_gapo, max_gape, seed_len, seed_diff, ies, s_mm, s_gapo, s_gape, mode, max_best;
+    uint32_t max_hits;
+    int minc, s1;
+};
+
+struct ReadsView {
+    const uint8_t *bases;
+    const uint64_t *off;
+    const uint8_t *maxd;
+    uint32_t n, max_len;
+};
+
+// lane-private buffers: element e of lane t at base[e * stride + t]
+struct LaneBufs {
+    uint4 *stack;
+    uint4 *cand;
+    uint8_t *D;
+    uint32_t stride, stack_cap, cand_cap;
+};
+
+// ------------------------------------------------------------------ rank queries
+
+// element b of a four-element register array without dynamic indexing
+__device__ __forceinline__ uint32_t sel4(const uint32_t (&v)[4], int b) {
+    return b == 0 ? v[0] : (b == 1 ? v[1] : (b == 2 ? v[2] : v[3]));
+}
+
+// direction 0 or 1 of the index without dynamic indexing into the argument
+__device__ __forceinline__ DevDir pick_dir(const DevIndex &ix, int which) {
+    DevDir d;
+    d.lines = which ? ix.dir[1].lines : ix.dir[0].lines;
+    d.sa = which ? ix.dir[1].sa : ix.dir[0].sa;
+#pragma unroll
+    for (int a = 0; a < 4; a++) d.C[a] = which ? ix.dir[1].C[a] : ix.dir[0].C[a];
+    d.primary = which ? ix.dir[1].primary : ix.dir[0].primary;
+    d.pad = 0;
+    return d;
+}
+
+__device__ __forceinline__ uint32_t line_of(const DevIndex &ix, uint32_t i) {
+    return (uint32_t)__umul64hi((uint64_t)i, ix.magic);
+}
+
+__device__ __forceinline__ void count_word(uint64_t x, int valid, uint32_t &cC, uint32_t &cG, uint32_t &cT) {
+    int nv = valid < 0 ? 0 : (valid > 32 ? 32 : valid);
+    uint64_t mask = nv >= 32 ? ~0ULL : ((1ULL << (2 * nv)) - 1);
+    x &= mask;
+    uint64_t lo = x & 0x5555555555555555ULL, hi = (x >> 1) & 0x5555555555555555ULL;
+    cT += __popcll(lo & hi);
+    cG += __popcll(hi & ~lo);
+    cC += __popcll(lo & ~hi);
+}
+
+// Occ(a, i) for all four bases (i <= n + 1).
+template <int LW>
+__device__ __forceinline__ void occ4(const DevIndex &ix, const DevDir &d, uint32_t i, uint32_t o[4]) {
+    uint32_t line = line_of(ix, i);
+    int r = (int)(i - line * ix.bpl);
+    const uint4 *L = reinterpret_cast<const uint4 *>(d.lines) + (size_t)line * (LW / 4);
+    uint4 h = L[0];
+    uint32_t cC = 0, cG = 0, cT = 0;
+#pragma unroll
+    for (int q = 0; q < LW / 4 - 1; q++) {
+        uint4 v = L[1 + q];
+        count_word((uint64_t)v.x | ((uint64_t)v.y << 32), r - q * 64, cC, cG, cT);
+        count_word((uint64_t)v.z | ((uint64_t)v.w << 32), r - q * 64 - 32, cC, cG, cT);
+    }
+    uint32_t cA = (uint32_t)r - cC - cG - cT;
+    o[0] = h.x + cA - (i > d.primary ? 1u : 0u);
+    o[1] = h.y + cC;
+    o[2] = h.z + cG;
+    o[3] = h.w + cT;
+}
+
+// Occ(a, i) for one base a.
+template <int LW>
+__device__ __forceinline__ uint32_t occ1(const DevIndex &ix, const DevDir &d, int a, uint32_t i) {
+    uint32_t line = line_of(ix, i);
+    int r = (int)(i - line * ix.bpl);
+    const uint4 *L = reinterpret_cast<const uint4 *>(d.lines) + (size_t)line * (LW / 4);
+    uint4 h = L[0];
+    uint64_t pat = 0x5555555555555555ULL * (uint64_t)a;
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < LW / 4 - 1; q++) {
+        uint4 v = L[1 + q];
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            uint64_t x = half ? ((uint64_t)v.z | ((uint64_t)v.w << 32)) : ((uint64_t)v.x | ((uint64_t)v.y << 32));
+            int nv = r - q * 64 - half * 32;
+            nv = nv < 0 ? 0 : (nv > 32 ? 32 : nv);
+            uint64_t mask = (nv >= 32 ? ~0ULL : ((1ULL << (2 * nv)) - 1)) & 0x5555555555555555ULL;
+            uint64_t y = x ^ pat;
+            c += __popcll(~(y | (y >> 1)) & mask);
+        }
+    }
+    uint32_t base = a == 0 ? h.x : (a == 1 ? h.y : (a == 2 ? h.z : h.w));
+    return base + c - ((a == 0 && i > d.primary) ? 1u : 0u);
+}
+
+// BWT symbol at row j (j != primary) and Occ(that symbol, j): one line.
+template <int LW>
+__device__ __forceinline__ uint32_t lf_step(const DevIndex &ix, const DevDir &d, uint32_t j) {
+    uint32_t line = line_of(ix, j);
+    uint32_t r = j - line * ix.bpl;
+    const uint32_t *L = d.lines + (size_t)line * LW;
+    int a = (L[4 + (r >> 4)] >> (2 * (r & 15))) & 3;
+    return sel4(d.C, a) + occ1<LW>(ix, d, a, j);
+}
+
+// ------------------------------------------------------------------ search state
+
+// packed state: x = k, y = l, z = (i + 1) | gs << 10 | nmm << 12 | ngo << 16 | nge << 20 | sd << 24,
+// w = score | len << 16
+struct State {
+    uint32_t k, l;
+    int i, gs, nmm, ngo, nge, sd, score, len;
+};
+
+__device__ __forceinline__ uint4 pack(const State &s) {
+    return make_uint4(s.k, s.l,
+                      (uint32_t)(s.i + 1) | ((uint32_t)s.gs << 10) | ((uint32_t)s.nmm << 12) | ((uint32_t)s.ngo << 16) |
+                          ((uint32_t)s.nge << 20) | ((uint32_t)s.sd << 24),
+                      (uint32_t)s.score | ((uint32_t)s.len << 16));
+}
+
+__device__ __forceinline__ State unpack(uint4 v) {
+    State s;
+    s.k = v.x;
+    s.l = v.y;
+    s.i = (int)(v.z & 1023) - 1;
+    s.gs = (v.z >> 10) & 3;
+    s.nmm = (v.z >> 12) & 15;
+    s.ngo = (v.z >> 16) & 15;
+    s.nge = (v.z >> 20) & 15;
+    s.sd = (v.z >> 24) & 15;
+    s.score = v.w & 0xffff;
+    s.len = v.w >> 16;
+    return s;
+}
+
+// hit record, same bytes as bwfm_hit
+__device__ __forceinline__ uint4 make_hit(int strand, uint32_t k, uint32_t l, int len, int score, int nmm, int ngo,
+                                          int nge) {
+    return make_uint4(k, l, (uint32_t)len | ((uint32_t)score << 16),
+                      (uint32_t)strand | ((uint32_t)nmm << 8) | ((uint32_t)ngo << 16) | ((uint32_t)nge << 24));
+}
+__device__ __forceinline__ int h_strand(uint4 h) { return h.w & 255; }
+__device__ __forceinline__ int h_score(uint4 h) { return h.z >> 16; }
+__device__ __forceinline__ int h_len(uint4 h) { return h.z & 0xffff; }
+__device__ __forceinline__ int h_nmm(uint4 h) { return (h.w >> 8) & 255; }
+__device__ __forceinline__ int h_ngo(uint4 h) { return (h.w >> 16) & 255; }
+__device__ __forceinline__ int h_nge(uint4 h) { return (h.w >> 24) & 255; }
+__device__ __forceinline__ int h_diffs(uint4 h) { return h_nmm(h) + h_ngo(h) + h_nge(h); }
+
+// (score, diffs, n_gapo, n_mm) of a is smaller than b's
+__device__ __forceinline__ bool better(uint4 a, uint4 b) {
+    if (h_score(a) != h_score(b)) return h_score(a) < h_score(b);
+    if (h_diffs(a) != h_diffs(b)) return h_diffs(a) < h_diffs(b);
+    if (h_ngo(a) != h_ngo(b)) return h_ngo(a) < h_ngo(b);
+    return h_nmm(a) < h_nmm(b);
+}
+
+// report order (score, strand, k, len)
+__device__ __forceinline__ bool before(uint4 a, uint4 b) {
+    if (h_score(a) != h_score(b)) return h_score(a) < h_score(b);
+    if (h_strand(a) != h_strand(b)) return h_strand(a) < h_strand(b);
+    if (a.x != b.x) return a.x < b.x;
+    return h_len(a) < h_len(b);
+}
+
+struct LaneCtx {
+    uint4 *stack, *cand;
+    uint8_t *D;
+    uint32_t stride, stack_cap, cand_cap;
+    uint32_t sp, ncand;
+    int best;
+    uint32_t expand;
+};
+
+enum { R_OK = 0, R_STACK = 1, R_CAND = 2 };
+
+// Insert a hit: merge with an equal (strand, k, len), else append.  In the
+// first pass a full buffer is first cleared of hits above best + s_mm.
+__device__ int record(LaneCtx &c, const Params &P, uint4 h, int phase) {
+    if (phase == PH_BEST) return R_OK;
+    for (uint32_t j = 0; j < c.ncand; j++) {
+        uint4 o = c.cand[(size_t)j * c.stride];
+        if (h_strand(o) == h_strand(h) && o.x == h.x && h_len(o) == h_len(h)) {
+            if (better(h, o)) c.cand[(size_t)j * c.stride] = h;
+            return R_OK;
+        }
+    }
+    if (c.ncand == c.cand_cap && phase == PH_FAST && P.mode == BWFM_MODE_BEST) {
+        uint32_t w = 0;
+        for (uint32_t j = 0; j < c.ncand; j++) {
+            uint4 o = c.cand[(size_t)j * c.stride];
+            if (h_score(o) <= c.best + P.s_mm) c.cand[(size_t)(w++) * c.stride] = o;
+        }
+        c.ncand = w;
+    }
+    if (c.ncand == c.cand_cap) return R_CAND;
+    c.cand[(size_t)(c.ncand++) * c.stride] = h;
+    return R_OK;
+}
+
+// pattern base w[i] of the strand: strand + reads the read backwards,
+// strand - reads its complement backwards
+__device__ __forceinline__ int pat(const uint8_t *W, int m, int strand, int i) {
+    int b = W[m - 1 - i];
+    return (strand == 0 || b > 3) ? b : 3 - b;
+}
+
+// D-array of one strand on the other index.  Returns false when the bound
+// already exceeds the budget at the root (the strand cannot match).
+template <int LW>
+__device__ bool build_d(const DevIndex &ix, const DevDir &od, const uint8_t *W, int m, int strand, int maxd,
+                        LaneCtx &c) {
+    uint32_t k = 0, l = ix.n;
+    int z = 0;
+    for (int i = 0; i < m; i++) {
+        int a = pat(W, m, strand, i);
+        bool empty = true;
+        if (a < 4) {
+            uint32_t ok = occ1<LW>(ix, od, a, k), ol = occ1<LW>(ix, od, a, l + 1);
+            empty = ok >= ol;
+            k = sel4(od.C, a) + ok;
+            l = sel4(od.C, a) + ol - 1;
+        }
+        if (empty) {
+            z++;
+            k = 0;
+            l = ix.n;
+            if (z > maxd) return false;
+        }
+        c.D[(size_t)i * c.stride] = (uint8_t)z;
+    }
+    return true;
+}
+
+// Depth-first search of one strand.  Returns R_OK, R_STACK or R_CAND.
+template <int LW>
+__device__ int search_strand(const DevIndex &ix, const DevDir &sd_, const uint8_t *W, int m, int strand, int maxd,
+                             const Params &P, LaneCtx &c, int phase) {
+    const int sl = P.seed_len > 0 ? (P.seed_len < m ? P.seed_len : m) : 0;
+    const int seed_lo = m - sl, seed_hi = sl ? m : 0;
+    State cur;
+    cur.k = 0;
+    cur.l = ix.n;
+    cur.i = m - 1;
+    cur.gs = GAP_NONE;
+    cur.nmm = cur.ngo = cur.nge = cur.sd = cur.score = cur.len = 0;
+    bool valid = true;
+    c.sp = 0;
+    for (;;) {
+        if (!valid) {
+            if (c.sp == 0) break;
+            c.sp--;
+            cur = unpack(c.stack[(size_t)c.sp * c.stride]);
+            valid = true;
+        }
+        const int Di = cur.i >= 0 ? c.D[(size_t)cur.i * c.stride] : 0;
+        if (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE && cur.score + P.minc * Di > c.best + P.s_mm) {
+            valid = false;
+            continue;
+        }
+        if (cur.i < 0) {
+            if (cur.score < c.best) c.best = cur.score;
+            int rc = record(c, P, make_hit(strand, cur.k, cur.l, cur.len, cur.score, cur.nmm, cur.ngo, cur.nge), phase);
+            if (rc) return rc;
+            valid = false;
+            continue;
+        }
+        // expand: one rank query at k and one at l + 1 give all children
+        c.expand++;
+        uint32_t ok[4], ol[4];
+        occ4<LW>(ix, sd_, cur.k, ok);
+        occ4<LW>(ix, sd_, cur.l + 1, ol);
+        const int b = pat(W, m, strand, cur.i);
+        const int Dn = cur.i >= 1 ? c.D[(size_t)(cur.i - 1) * c.stride] : 0;
+        const int diffs = cur.nmm + cur.ngo + cur.nge;
+        const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
+        State pend;
+        bool have = false;
+        int rc = R_OK;
+        // children in reverse canonical order; the last one kept becomes current
+        auto offer = [&](const State &ch) {
+            if (have) {
+                if (c.sp == c.stack_cap) {
+                    rc = R_STACK;
+                } else {
+                    c.stack[(size_t)c.sp * c.stride] = pack(pend);
+                    c.sp++;
+                }
+            }
+            pend = ch;
+            have = true;
+        };
+        // deletions: reference base a between read bases i and i + 1
+        {
+            const int bd = cur.i + 1;
+            const bool gap_ok = bd >= P.s1 && bd <= m - P.s1;
+            const bool ext = cur.gs == GAP_DEL;
+            const int nd = diffs + 1, ngo = cur.ngo + (ext ? 0 : 1), nge = cur.nge + (ext ? 1 : 0);
+            const int nsd = cur.sd + ((bd > seed_lo && bd < seed_hi) ? 1 : 0);
+            const int nsc = cur.score + (ext ? P.s_gape : P.s_gapo);
+            const bool ok_static = gap_ok && nd <= maxd && ngo <= P.max_gapo && (P.max_gape < 0 || nge <= P.max_gape) &&
+                                   (sl == 0 || nsd <= P.seed_diff) && nd + Di <= maxd && nsc + P.minc * Di <= bound;
+            if (ok_static) {
+#pragma unroll
+                for (int a = 3; a >= 0; a--) {
+                    if (ok[a] < ol[a]) {
+                        State ch = cur;
+                        ch.k = sd_.C[a] + ok[a];
+                        ch.l = sd_.C[a] + ol[a] - 1;
+                        ch.gs = GAP_DEL;
+                        ch.ngo = ngo;
+                        ch.nge = nge;
+                        ch.sd = nsd;
+                        ch.score = nsc;
+                        ch.len = cur.len + 1;
+                        offer(ch);
+                    }
+                }
+            }
+        }
+        // insertion: read base w[i] without a reference base
+        if (cur.i >= P.ies && cur.i < m - P.ies) {
+            const bool ext = cur.gs == GAP_INS;
+            const int nd = diffs + 1, ngo = cur.ngo + (ext ? 0 : 1), nge = cur.nge + (ext ? 1 : 0);
+            const int nsd = cur.sd + ((cur.i >= seed_lo && cur.i < seed_hi) ? 1 : 0);
+            const int nsc = cur.score + (ext ? P.s_gape : P.s_gapo);
+            if (nd <= maxd && ngo <= P.max_gapo && (P.max_gape < 0 || nge <= P.max_gape) &&
+                (sl == 0 || nsd <= P.seed_diff) && nd + Dn <= maxd && nsc + P.minc * Dn <= bound) {
+                State ch = cur;
+                ch.i = cur.i - 1;
+                ch.gs = GAP_INS;
+                ch.ngo = ngo;
+                ch.nge = nge;
+                ch.sd = nsd;
+                ch.score = nsc;
+                offer(ch);
+            }
+        }
+        // mismatches, then the match (offered last, so it becomes current)
+        {
+            const int nsd = cur.sd + ((cur.i >= seed_lo && cur.i < seed_hi) ? 1 : 0);
+            const int nsc = cur.score + P.s_mm;
+            const bool mm_ok = diffs + 1 <= maxd && (sl == 0 || nsd <= P.seed_diff) && diffs + 1 + Dn <= maxd &&
+                               nsc + P.minc * Dn <= bound;
+#pragma unroll
+            for (int a = 3; a >= 0; a--) {
+                if (a == b || !(ok[a] < ol[a]) || !mm_ok) continue;
+                State ch = cur;
+                ch.k = sd_.C[a] + ok[a];
+                ch.l = sd_.C[a] + ol[a] - 1;
+                ch.i = cur.i - 1;
+                ch.gs = GAP_NONE;
+                ch.nmm = cur.nmm + 1;
+                ch.sd = nsd;
+                ch.score = nsc;
+                ch.len = cur.len + 1;
+                offer(ch);
+            }
+            if (b < 4 && sel4(ok, b) < sel4(ol, b) && diffs + Dn <= maxd && cur.score + P.minc * Dn <= bound) {
+                State ch = cur;
+                ch.k = sel4(sd_.C, b) + sel4(ok, b);
+                ch.l = sel4(sd_.C, b) + sel4(ol, b) - 1;
+                ch.i = cur.i - 1;
+                ch.gs = GAP_NONE;
+                ch.len = cur.len + 1;
+                offer(ch);
+            }
+        }
+        if (rc) return rc;
+        if (have) cur = pend;
+        valid = have;
+    }
+    return R_OK;
+}
+
+// Canonicalise the lane's hit buffer: tiers, c1/c2, the max_hits rule, the
+// report order.  Returns the number of reported hits (at the front of the
+// buffer); sets status, c1, c2.
+__device__ uint32_t finish(LaneCtx &c, const Params &P, uint8_t &status, uint32_t &c1o, uint32_t &c2o) {
+    status = 0;
+    c1o = c2o = 0;
+    if (c.ncand == 0) return 0;
+    const int S = c.best;
+    uint32_t n = 0;
+    uint64_t c1 = 0, c2 = 0;
+    for (uint32_t j = 0; j < c.ncand; j++) {
+        uint4 h = c.cand[(size_t)j * c.stride];
+        int sc = h_score(h);
+        if (P.mode == BWFM_MODE_ALL || sc <= S + P.s_mm) c.cand[(size_t)(n++) * c.stride] = h;
+        uint64_t w = (uint64_t)h.y - h.x + 1;
+        if (sc == S) c1 += w;
+        else if (sc <= S + P.s_mm) c2 += w;
+    }
+    if (n > P.max_hits) {
+        status = BWFM_ST_OVERFLOW;
+        c1o = c2o = 0xffffffffu;
+        return 0;
+    }
+    c1o = c1 > 0xffffffffULL ? 0xffffffffu : (uint32_t)c1;
+    c2o = c2 > 0xffffffffULL ? 0xffffffffu : (uint32_t)c2;
+    const bool keep2 = c1 <= (uint64_t)P.max_best;
+    uint32_t r = 0;
+    for (uint32_t j = 0; j < n; j++) {
+        uint4 h = c.cand[(size_t)j * c.stride];
+        if (P.mode == BWFM_MODE_ALL || h_score(h) == S || keep2) c.cand[(size_t)(r++) * c.stride] = h;
+    }
+    for (uint32_t j = 1; j < r; j++) {  // insertion sort by (score, strand, k, len)
+        uint4 v = c.cand[(size_t)j * c.stride];
+        uint32_t q = j;
+        while (q > 0) {
+            uint4 u = c.cand[(size_t)(q - 1) * c.stride];
+            if (!before(v, u)) break;
+            c.cand[(size_t)q * c.stride] = u;
+            q--;
+        }
+        c.cand[(size_t)q * c.stride] = v;
+    }
+    status = r ? BWFM_ST_HIT : 0;
+    return r;
+}
+
+template <int LW>
+__device__ int align_read(const DevIndex &ix, const uint8_t *W, int m, int maxd, const Params &P, LaneCtx &c,
+                          int phase) {
+    c.ncand = 0;
+    for (int strand = 0; strand < 2; strand++) {
+        const DevDir sdir = pick_dir(ix, strand == 0 ? 1 : 0);
+        const DevDir odir = pick_dir(ix, strand == 0 ? 0 : 1);
+        if (!build_d<LW>(ix, odir, W, m, strand, maxd, c)) continue;
+        int rc = search_strand<LW>(ix, sdir, W, m, strand, maxd, P, c, phase);
+        if (rc) return rc;
+    }
+    return R_OK;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// First pass: one lane per read.
+template <int LW>
+__global__ __launch_bounds__(BLOCK) void k_align_fast(DevIndex ix, ReadsView rd, Params P, LaneBufs B,
+                                                      uint32_t *n_rep, uint32_t *c1, uint32_t *c2, uint8_t *status,
+                                                      uint32_t *slow_list, uint32_t *n_slow, uint32_t *expand) {
+    uint32_t r = blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= rd.n) return;
+    uint64_t o0 = rd.off[r], o1 = rd.off[r + 1];
+    int m = (int)(o1 - o0);
+    int maxd = rd.maxd ? rd.maxd[r] : P.max_diff;
+    n_rep[r] = 0;
+    c1[r] = c2[r] = 0;
+    if (o1 < o0 || (uint64_t)m > rd.max_len || m > BWFM_MAX_READ || maxd > BWFM_MAX_DIFF) {
+        status[r] = BWFM_ST_INVALID;
+        if (expand) expand[r] = 0;
+        return;
+    }
+    if (m == 0) {
+        status[r] = 0;
+        if (expand) expand[r] = 0;
+        return;
+    }
+    LaneCtx c;
+    c.stack = B.stack + r;
+    c.cand = B.cand + r;
+    c.D = B.D + r;
+    c.stride = B.stride;
+    c.stack_cap = B.stack_cap;
+    c.cand_cap = B.cand_cap;
+    c.best = INF_SCORE;
+    c.expand = 0;
+    int rc = align_read<LW>(ix, rd.bases + o0, m, maxd, P, c, PH_FAST);
+    if (expand) expand[r] = c.expand;
+    if (rc) {
+        status[r] = ST_RESEARCH;
+        slow_list[atomicAdd(n_slow, 1u)] = r;
+        return;
+    }
+    uint8_t st;
+    uint32_t a, b;
+    n_rep[r] = finish(c, P, st, a, b);
+    status[r] = st;
+    c1[r] = a;
+    c2[r] = b;
+}
+
+// Second pass for the reads listed in slow_list: worst-case stack, first the
+// best score S*, then the hits with the bound fixed at S* + s_mm.
+template <int LW>
+__global__ __launch_bounds__(BLOCK) void k_align_slow(DevIndex ix, ReadsView rd, Params P, LaneBufs B,
+                                                      const uint32_t *slow_list, uint32_t n_slow, uint32_t *n_rep,
+                                                      uint32_t *c1, uint32_t *c2, uint8_t *status, uint32_t *expand) {
+    uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= n_slow) return;
+    uint32_t r = slow_list[t];
+    uint64_t o0 = rd.off[r];
+    int m = (int)(rd.off[r + 1] - o0);
+    int maxd = rd.maxd ? rd.maxd[r] : P.max_diff;
+    LaneCtx c;
+    c.stack = B.stack + t;
+    c.cand = B.cand + t;
+    c.D = B.D + t;
+    c.stride = B.stride;
+    c.stack_cap = B.stack_cap;
+    c.cand_cap = B.cand_cap;
+    c.best = INF_SCORE;
+    c.expand = 0;
+    align_read<LW>(ix, rd.bases + o0, m, maxd, P, c, PH_BEST);
+    uint8_t st = 0;
+    uint32_t a = 0, b = 0, nr = 0;
+    if (c.best != INF_SCORE) {
+        int rc = align_read<LW>(ix, rd.bases + o0, m, maxd, P, c, PH_COLLECT);
+        if (rc == R_CAND) {
+            st = BWFM_ST_OVERFLOW;
+            a = b = 0xffffffffu;
+        } else {
+            nr = finish(c, P, st, a, b);
+        }
+    }
+    n_rep[r] = nr;
+    status[r] = st | ST_RESEARCH;
+    c1[r] = a;
+    c2[r] = b;
+    if (expand) expand[r] += c.expand;
+}
+
+// Copy each read's reported hits to the CSR output.
+__global__ void k_compact(uint32_t n, const uint64_t *hoff, const uint4 *fast, uint32_t fast_stride, const uint4 *slow,
+                          uint32_t slow_stride, const uint32_t *slow_list, uint32_t n_slow, const uint8_t *status,
+                          uint4 *hits) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    uint64_t o = hoff[r], e = hoff[r + 1];
+    if (e == o) return;
+    const uint4 *src = fast + r;
+    uint32_t stride = fast_stride;
+    if (status[r] & ST_RESEARCH) {
+        // position of r in the slow list (the list is short; sorted on the host)
+        uint32_t lo = 0, hi = n_slow;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi) / 2;
+            if (slow_list[mid] < r) lo = mid + 1;
+            else hi = mid;
+        }
+        src = slow + lo;
+        stride = slow_stride;
+    }
+    for (uint64_t j = 0; j < e - o; j++) hits[o + j] = src[(size_t)j * stride];
+}
+
+// ------------------------------------------------------------------ exclusive scan (u32 counts -> u64 offsets)
+
+constexpr int SCAN_BLOCK = 1024;
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const uint32_t *in, uint64_t n, uint64_t *part) {
+    __shared__ uint64_t s[SCAN_BLOCK / 64];
+    uint64_t i = (uint64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    uint64_t v = i < n ? in[i] : 0;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < SCAN_BLOCK / 64; w++) t += s[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_parts(uint64_t *part, uint64_t nb) {
+    // exclusive scan of nb block sums by one workgroup, in chunks
+    __shared__ uint64_t s[SCAN_BLOCK];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint64_t base = 0; base < nb; base += SCAN_BLOCK) {
+        uint64_t i = base + threadIdx.x;
+        uint64_t v = i < nb ? part[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < SCAN_BLOCK; o <<= 1) {
+            uint64_t t = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        uint64_t incl = s[threadIdx.x];
+        if (i < nb) part[i] = carry + incl - v;
+        __syncthreads();
+        if (threadIdx.x == SCAN_BLOCK - 1) carry += incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[nb] = carry;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const uint32_t *in, uint64_t n, const uint64_t *part,
+                                                           uint64_t *out) {
+    __shared__ uint64_t s[SCAN_BLOCK];
+    uint64_t i = (uint64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    uint64_t v = i < n ? in[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < SCAN_BLOCK; o <<= 1) {
+        uint64_t t = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) out[i] = part[blockIdx.x] + s[threadIdx.x] - v;
+    if (i == n - 1) out[n] = part[blockIdx.x] + s[threadIdx.x];
+}
+
+// ------------------------------------------------------------------ locate
+
+// per hit: number of positions to locate (width if <= max_occ, else 0)
+__global__ void k_loc_count(uint64_t n_hits, const uint4 *hits, uint32_t max_occ, uint32_t *cnt) {
+    uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n_hits) return;
+    uint4 x = hits[h];
+    uint64_t w = (uint64_t)x.y - x.x + 1;
+    cnt[h] = (x.x <= x.y && w <= max_occ) ? (uint32_t)w : 0;
+}
+
+// one lane per position: find its hit, walk LF to a sampled row
+template <int LW>
+__global__ void k_loc_rows(DevIndex ix, uint64_t n_hits, const uint4 *hits, const uint64_t *poff, uint64_t total,
+                           uint32_t *pos) {
+    uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= total) return;
+    uint64_t lo = 0, hi = n_hits;  // last h with poff[h] <= p
+    while (hi - lo > 1) {
+        uint64_t mid = (lo + hi) / 2;
+        if (poff[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    uint4 x = hits[lo];
+    int strand = h_strand(x);
+    const DevDir d = pick_dir(ix, strand == 0 ? 1 : 0);
+    uint32_t j = x.x + (uint32_t)(p - poff[lo]);
+    uint32_t steps = 0;
+    const uint32_t smask = (1u << ix.sa_shift) - 1;
+    uint32_t q;
+    for (;;) {
+        if (j == d.primary) { q = steps; break; }
+        if ((j & smask) == 0) { q = d.sa[j >> ix.sa_shift] + steps; break; }
+        j = lf_step<LW>(ix, d, j);
+        steps++;
+    }
+    pos[p] = strand == 0 ? ix.n - q - (uint32_t)h_len(x) : q;
+}
+
+// sort each hit's positions: short segments by one lane, long ones by a
+// workgroup running a bitonic network (pairs past the end count as +inf)
+__global__ void k_sort_small(uint64_t n_hits, const uint64_t *poff, uint32_t *pos, uint32_t *big, uint32_t *n_big) {
+    uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n_hits) return;
+    uint64_t o = poff[h], w = poff[h + 1] - o;
+    if (w <= 1) return;
+    if (w > 32) {
+        big[atomicAdd(n_big, 1u)] = (uint32_t)h;
+        return;
+    }
+    uint32_t *a = pos + o;
+    for (uint64_t i = 1; i < w; i++) {
+        uint32_t v = a[i];
+        uint64_t q = i;
+        while (q > 0 && a[q - 1] > v) { a[q] = a[q - 1]; q--; }
+        a[q] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sort_big(const uint64_t *poff, uint32_t *pos, const uint32_t *big,
+                                                  const uint32_t *n_big) {
+    __shared__ uint32_t s[4096];
+    const uint32_t nb = *n_big;
+    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        uint32_t h = big[b];
+        uint64_t o = poff[h], n = poff[h + 1] - o;
+        uint32_t *a = pos + o;
+        const bool lds = n <= 4096;
+        if (lds) {
+            for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) s[i] = a[i];
+            __syncthreads();
+        }
+        uint32_t *x = lds ? s : a;
+        for (uint64_t k = 2; k < 2 * n; k <<= 1) {
+            for (uint64_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) {
+                    uint64_t q = (j == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j);
+                    if (q > i && q < n && x[i] > x[q]) {
+                        uint32_t t = x[i];
+                        x[i] = x[q];
+                        x[q] = t;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (lds) {
+            for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) a[i] = s[i];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ pairing
+
+struct EndView {
+    const uint64_t *hoff;
+    const uint4 *hits;
+    const uint64_t *poff;  // per hit (global hit index)
+    const uint32_t *pos;
+};
+
+__device__ __forceinline__ uint64_t lower_bound(const uint32_t *a, uint64_t n, uint64_t v) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) / 2;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// single-end primary: smallest (score, diffs, strand, pos, len)
+__device__ bool se_primary(const EndView &e, uint32_t q, uint32_t &pos, uint4 &hit, bool &rep) {
+    bool found = false;
+    rep = false;
+    for (uint64_t i = e.hoff[q]; i < e.hoff[q + 1]; i++) {
+        uint64_t o = e.poff[i], w = e.poff[i + 1] - o;
+        if (w == 0) { rep = true; continue; }
+        uint4 h = e.hits[i];
+        uint32_t p = e.pos[o];  // sorted: the first is the smallest
+        bool b;
+        if (!found) b = true;
+        else if (h_score(h) != h_score(hit)) b = h_score(h) < h_score(hit);
+        else if (h_diffs(h) != h_diffs(hit)) b = h_diffs(h) < h_diffs(hit);
+        else if (h_strand(h) != h_strand(hit)) b = h_strand(h) < h_strand(hit);
+        else if (p != pos) b = p < pos;
+        else b = h_len(h) < h_len(hit);
+        if (b) { found = true; pos = p; hit = h; }
+    }
+    return found;
+}
+
+__global__ void k_pair(uint32_t n_pairs, EndView e1, EndView e2, int paired, int32_t lo, int32_t hi, int32_t mu,
+                       bwfm_pair *out) {
+    uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_pairs) return;
+    bwfm_pair o;
+    memset(&o, 0, sizeof(o));
+    o.pos1 = o.pos2 = 0xffffffffu;
+    bool found = false;
+    int64_t bs = 0, bd = 0, bpf = 0;
+    if (paired) {
+        for (uint64_t i = e1.hoff[q]; i < e1.hoff[q + 1]; i++) {
+            uint4 h1 = e1.hits[i];
+            const uint32_t *P1 = e1.pos + e1.poff[i];
+            uint64_t n1 = e1.poff[i + 1] - e1.poff[i];
+            for (uint64_t j = e2.hoff[q]; j < e2.hoff[q + 1]; j++) {
+                uint4 h2 = e2.hits[j];
+                if (h_strand(h1) == h_strand(h2)) continue;
+                const uint32_t *P2 = e2.pos + e2.poff[j];
+                uint64_t n2 = e2.poff[j + 1] - e2.poff[j];
+                int64_t s = (int64_t)h_score(h1) + h_score(h2);
+                for (uint64_t x = 0; x < n1; x++) {
+                    int64_t p1 = P1[x];
+                    // range of end-2 positions forming a proper pair with p1
+                    int64_t a, b;
+                    if (h_strand(h1) == 0) {  // end 1 is +: pf = p1, pr = p2, lr = len2
+                        int64_t lr = h_len(h2);
+                        a = p1 + lo - lr > p1 ? p1 + lo - lr : p1;
+                        b = p1 + hi - lr;
+                    } else {  // end 1 is -: pr = p1, lr = len1, pf = p2
+                        int64_t lr = h_len(h1);
+                        a = p1 + lr - hi;
+                        b = p1 + lr - lo < p1 ? p1 + lr - lo : p1;
+                    }
+                    if (b < a || b < 0) continue;
+                    uint64_t y = lower_bound(P2, n2, (uint64_t)(a < 0 ? 0 : a));
+                    for (; y < n2 && (int64_t)P2[y] <= b; y++) {
+                        int64_t p2 = P2[y];
+                        int64_t pf = h_strand(h1) == 0 ? p1 : p2;
+                        int64_t pr = h_strand(h1) == 0 ? p2 : p1;
+                        int64_t lr = h_strand(h1) == 0 ? h_len(h2) : h_len(h1);
+                        int64_t ins = pr + lr - pf;
+                        int64_t d = ins > mu ? ins - mu : mu - ins;
+                        bool bt;
+                        if (!found) bt = true;
+                        else if (s != bs) bt = s < bs;
+                        else if (d != bd) bt = d < bd;
+                        else if (pf != bpf) bt = pf < bpf;
+                        else if ((uint32_t)h_strand(h1) != o.strand1) bt = (uint32_t)h_strand(h1) < o.strand1;
+                        else if ((uint32_t)p1 != o.pos1) bt = (uint32_t)p1 < o.pos1;
+                        else if ((uint32_t)h_len(h1) != o.len1) bt = (uint32_t)h_len(h1) < o.len1;
+                        else if ((uint32_t)p2 != o.pos2) bt = (uint32_t)p2 < o.pos2;
+                        else bt = (uint32_t)h_len(h2) < o.len2;
+                        if (bt) {
+                            found = true;
+                            bs = s;
+                            bd = d;
+                            bpf = pf;
+                            o.pos1 = (uint32_t)p1;
+                            o.pos2 = (uint32_t)p2;
+                            o.len1 = (uint16_t)h_len(h1);
+                            o.len2 = (uint16_t)h_len(h2);
+                            o.score1 = (uint16_t)h_score(h1);
+                            o.score2 = (uint16_t)h_score(h2);
+                            o.strand1 = (uint8_t)h_strand(h1);
+                            o.strand2 = (uint8_t)h_strand(h2);
+                            o.insert = (int32_t)ins;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    uint32_t pp;
+    uint4 hp;
+    bool rep1 = false, rep2 = false;
+    bool f1 = se_primary(e1, q, pp, hp, rep1);
+    if (found) {
+        o.flags = BWFM_PF_PAIRED | BWFM_PF_MAPPED1 | BWFM_PF_MAPPED2;
+    } else if (f1) {
+        o.pos1 = pp;
+        o.len1 = (uint16_t)h_len(hp);
+        o.score1 = (uint16_t)h_score(hp);
+        o.strand1 = (uint8_t)h_strand(hp);
+        o.flags |= BWFM_PF_MAPPED1;
+    }
+    if (paired) {
+        bool f2 = se_primary(e2, q, pp, hp, rep2);
+        if (!found && f2) {
+            o.pos2 = pp;
+            o.len2 = (uint16_t)h_len(hp);
+            o.score2 = (uint16_t)h_score(hp);
+            o.strand2 = (uint8_t)h_strand(hp);
+            o.flags |= BWFM_PF_MAPPED2;
+        }
+    }
+    if (rep1) o.flags |= BWFM_PF_REP1;
+    if (rep2) o.flags |= BWFM_PF_REP2;
+    out[q] = o;
+}
+
+// ------------------------------------------------------------------ host helpers
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(BWFM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+inline uint32_t blocks(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
+
+// ------------------------------------------------------------------ kernel timing
+
+struct TimingStore {
+    std::mutex mu;
+    bool on = false;
+    std::map<std::string, std::pair<double, uint64_t>> acc;
+};
+TimingStore &timing() {
+    static TimingStore t;
+    return t;
+}
+
+// Events around the launches of one API call; resolved when the call has
+// synchronised its stream.
+struct CallTimer {
+    struct Rec {
+        const char *name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    bool on;
+    hipStream_t st;
+    explicit CallTimer(hipStream_t s) : st(s) {
+        std::lock_guard<std::mutex> g(timing().mu);
+        on = timing().on;
+    }
+    int begin(const char *name) {
+        if (!on) return -1;
+        Rec r{name, nullptr, nullptr};
+        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+        (void)hipEventRecord(r.a, st);
+        recs.push_back(r);
+        return (int)recs.size() - 1;
+    }
+    void end(int i) {
+        if (i >= 0) (void)hipEventRecord(recs[i].b, st);
+    }
+    ~CallTimer() {
+        if (recs.empty()) return;
+        (void)hipStreamSynchronize(st);
+        std::lock_guard<std::mutex> g(timing().mu);
+        for (auto &r : recs) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                auto &e = timing().acc[r.name];
+                e.first += ms;
+                e.second += 1;
+            }
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+    }
+};
+
+DevIndex dev_index(const bwfm_index *ix) {
+    DevIndex d;
+    memset(&d, 0, sizeof(d));
+    for (int k = 0; k < 2; k++) {
+        d.dir[k].lines = (const uint32_t *)ix->d_lines[k];
+        d.dir[k].sa = (const uint32_t *)ix->d_sa[k];
+        for (int a = 0; a < 4; a++) d.dir[k].C[a] = (uint32_t)ix->dir[k].C[a];
+        d.dir[k].primary = (uint32_t)ix->dir[k].primary;
+    }
+    d.magic = (uint64_t)(((unsigned __int128)1 << 64) / ix->bpl) + 1;
+    d.n = (uint32_t)ix->n;
+    d.bpl = ix->bpl;
+    uint32_t s = 0;
+    while ((1u << s) < ix->sa_sample) s++;
+    d.sa_shift = s;
+    d.line_words = ix->line_bytes / 4;
+    return d;
+}
+
+Params make_params(const bwfm_aln_params &p) {
+    Params P;
+    P.max_diff = p.max_diff;
+    P.max_gapo = p.max_gapo;
+    P.max_gape = p.max_gape;
+    P.seed_len = p.seed_len;
+    P.seed_diff = p.seed_diff;
+    P.ies = p.indel_end_skip;
+    P.s_mm = p.s_mm;
+    P.s_gapo = p.s_gapo;
+    P.s_gape = p.s_gape;
+    P.mode = p.mode;
+    P.max_best = p.max_best;
+    P.max_hits = p.max_hits;
+    P.minc = std::min(p.s_mm, std::min(p.s_gapo, p.s_gape));
+    P.s1 = std::max(p.indel_end_skip, 1);
+    return P;
+}
+
+// carve a workspace of at least `bytes` (grow-only, per index)
+int ws_reserve(bwfm_index *ix, size_t bytes, void **out) {
+    if (ix->ws.bytes < bytes) {
+        if (ix->ws.ptr) {
+            hipError_t e = hipFree(ix->ws.ptr);
+            (void)e;
+        }
+        ix->ws.ptr = nullptr;
+        ix->ws.bytes = 0;
+        size_t want = bytes + bytes / 8;
+        if (hipMalloc(&ix->ws.ptr, want) != hipSuccess) {
+            ix->ws.ptr = nullptr;
+            return fail(BWFM_E_NOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+        }
+        ix->ws.bytes = want;
+    }
+    *out = ix->ws.ptr;
+    return BWFM_OK;
+}
+
+struct Carver {
+    char *p;
+    size_t used = 0;
+    template <typename T>
+    T *take(size_t n) {
+        used = (used + 255) & ~size_t(255);
+        T *r = reinterpret_cast<T *>(p + used);
+        used += n * sizeof(T);
+        return r;
+    }
+};
+
+// exclusive scan of n u32 counts into n + 1 u64 offsets (out[n] = total)
+int scan_counts(const uint32_t *cnt, uint64_t n, uint64_t *out, uint64_t *part, hipStream_t st) {
+    uint64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    if (n == 0) {
+        HIPCHK(hipMemsetAsync(out, 0, sizeof(uint64_t), st));
+        return BWFM_OK;
+    }
+    k_scan_reduce<<<(uint32_t)nb, SCAN_BLOCK, 0, st>>>(cnt, n, part);
+    k_scan_parts<<<1, SCAN_BLOCK, 0, st>>>(part, nb);
+    k_scan_apply<<<(uint32_t)nb, SCAN_BLOCK, 0, st>>>(cnt, n, part, out);
+    HIPCHK(hipGetLastError());
+    return BWFM_OK;
+}
+
+size_t scan_part_elems(uint64_t n) { return (n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1; }
+
+template <int LW>
+int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, bwfm_aln_result *res,
+               hipStream_t st, uint32_t *expand) {
+    const uint32_t n = rd->n_reads;
+    const DevIndex D = dev_index(ix);
+    const Params P = make_params(*p);
+    ReadsView rv{rd->bases, rd->offsets, rd->max_diff, rd->n_reads, rd->max_len};
+    const uint32_t mlen = std::max<uint32_t>(rd->max_len, 1);
+    // workspace: fast buffers, per-read counts, slow list, scan parts
+    size_t need = 0;
+    {
+        need += (size_t)n * FAST_STACK * 16 + (size_t)n * FAST_CAND * 16 + (size_t)n * mlen + 256 * 8;
+        need += (size_t)n * 4 * 2 + 64 + scan_part_elems(n) * 8 + 4096;
+    }
+    void *w;
+    int rc = ws_reserve(ix, need, &w);
+    if (rc) return rc;
+    Carver cv{(char *)w};
+    uint4 *fstack = cv.take<uint4>((size_t)n * FAST_STACK);
+    uint4 *fcand = cv.take<uint4>((size_t)n * FAST_CAND);
+    uint8_t *fD = cv.take<uint8_t>((size_t)n * mlen);
+    uint32_t *n_rep = cv.take<uint32_t>(n);
+    uint32_t *slow_list = cv.take<uint32_t>(n);
+    uint32_t *n_slow = cv.take<uint32_t>(1);
+    uint64_t *part = cv.take<uint64_t>(scan_part_elems(n));
+    HIPCHK(hipMemsetAsync(n_slow, 0, 4, st));
+    LaneBufs fb{fstack, fcand, fD, n, FAST_STACK, FAST_CAND};
+    CallTimer tm(st);
+    if (n) {
+        int t = tm.begin("align_fast");
+        k_align_fast<LW><<<blocks(n, BLOCK), BLOCK, 0, st>>>(D, rv, P, fb, n_rep, res->c1, res->c2, res->status,
+                                                             slow_list, n_slow, expand);
+        tm.end(t);
+        HIPCHK(hipGetLastError());
+    }
+    uint32_t ns = 0;
+    HIPCHK(hipMemcpyAsync(&ns, n_slow, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    void *slow_mem = nullptr;
+    uint4 *scand = nullptr;
+    uint32_t scap = 0;
+    if (ns) {
+        // sort the slow list so the compaction can find each read's slot
+        std::vector<uint32_t> hl(ns);
+        HIPCHK(hipMemcpy(hl.data(), slow_list, 4ull * ns, hipMemcpyDeviceToHost));
+        std::sort(hl.begin(), hl.end());
+        HIPCHK(hipMemcpy(slow_list, hl.data(), 4ull * ns, hipMemcpyHostToDevice));
+        const uint32_t maxd_all = BWFM_MAX_DIFF;
+        const uint32_t stack_cap = 8 * (mlen + maxd_all) + 1;
+        scap = P.max_hits + 1;
+        size_t sbytes = (size_t)ns * stack_cap * 16 + (size_t)ns * scap * 16 + (size_t)ns * mlen + 1024;
+        if (hipMalloc(&slow_mem, sbytes) != hipSuccess) return fail(BWFM_E_NOMEM, "second-pass buffers");
+        Carver sc{(char *)slow_mem};
+        uint4 *sstack = sc.take<uint4>((size_t)ns * stack_cap);
+        scand = sc.take<uint4>((size_t)ns * scap);
+        uint8_t *sD = sc.take<uint8_t>((size_t)ns * mlen);
+        LaneBufs sb{sstack, scand, sD, ns, stack_cap, scap};
+        int t = tm.begin("align_slow");
+        k_align_slow<LW><<<blocks(ns, BLOCK), BLOCK, 0, st>>>(D, rv, P, sb, slow_list, ns, n_rep, res->c1, res->c2,
+                                                              res->status, expand);
+        tm.end(t);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            (void)hipFree(slow_mem);
+            return fail(BWFM_E_DEVICE, std::string("k_align_slow: ") + hipGetErrorString(e));
+        }
+    }
+    int src = scan_counts(n_rep, n, res->hit_offsets, part, st);
+    if (src) { if (slow_mem) (void)hipFree(slow_mem); return src; }
+    uint64_t total = 0;
+    hipError_t e1 = hipMemcpyAsync(&total, res->hit_offsets + n, 8, hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (slow_mem) (void)hipFree(slow_mem);
+        return fail(BWFM_E_DEVICE, "align: reading the hit total failed");
+    }
+    if (total > res->hit_capacity) {
+        if (slow_mem) (void)hipFree(slow_mem);
+        return fail(BWFM_E_CAPACITY, "hit capacity " + std::to_string(res->hit_capacity) + " < " + std::to_string(total));
+    }
+    if (n) {
+        int t = tm.begin("compact");
+        k_compact<<<blocks(n, 256), 256, 0, st>>>(n, res->hit_offsets, fcand, n, scand, ns, slow_list, ns, res->status,
+                                                  reinterpret_cast<uint4 *>(res->hits));
+        tm.end(t);
+    }
+    hipError_t e3 = hipGetLastError();
+    hipError_t e4 = hipStreamSynchronize(st);
+    if (slow_mem) (void)hipFree(slow_mem);
+    if (e3 != hipSuccess || e4 != hipSuccess) return fail(BWFM_E_DEVICE, "align: compaction failed");
+    return BWFM_OK;
+}
+
+// positions of all hits of one result; pos_off has n_hits + 1 entries
+template <int LW>
+int locate_impl(bwfm_index *ix, uint64_t n_hits, const uint4 *hits, uint32_t max_occ, uint64_t *pos_off,
+                uint32_t *pos, uint64_t cap, uint32_t *cnt, uint64_t *part, uint32_t *big, uint32_t *n_big,
+                hipStream_t st, uint64_t *total_out) {
+    const DevIndex D = dev_index(ix);
+    if (n_hits) {
+        k_loc_count<<<blocks(n_hits, 256), 256, 0, st>>>(n_hits, hits, max_occ, cnt);
+        HIPCHK(hipGetLastError());
+    }
+    int rc = scan_counts(cnt, n_hits, pos_off, part, st);
+    if (rc) return rc;
+    uint64_t total = 0;
+    HIPCHK(hipMemcpyAsync(&total, pos_off + n_hits, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *total_out = total;
+    if (total > cap) return fail(BWFM_E_CAPACITY, "position capacity too small");
+    if (total) {
+        CallTimer tm(st);
+        int t = tm.begin("locate_rows");
+        k_loc_rows<LW><<<blocks(total, 256), 256, 0, st>>>(D, n_hits, hits, pos_off, total, pos);
+        tm.end(t);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemsetAsync(n_big, 0, 4, st));
+        t = tm.begin("sort");
+        k_sort_small<<<blocks(n_hits, 256), 256, 0, st>>>(n_hits, pos_off, pos, big, n_big);
+        k_sort_big<<<1024, 256, 0, st>>>(pos_off, pos, big, n_big);
+        tm.end(t);
+        HIPCHK(hipGetLastError());
+    }
+    return BWFM_OK;
+}
+
+bool check_index(const bwfm_index *ix) { return ix && ix->device >= 0; }
+
+int check_result(const bwfm_aln_result *r) {
+    return r && r->hit_offsets && r->c1 && r->c2 && r->status && (r->hits || r->hit_capacity == 0);
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" int bwfm_index_upload(bwfm_index *ix, void *stream) {
+    if (!ix) return fail(BWFM_E_INVAL, "upload: NULL index");
+    std::lock_guard<std::mutex> g(ix->mu);
+    if (ix->device >= 0) return BWFM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    uint64_t bytes = 0;
+    for (int d = 0; d < 2; d++) {
+        size_t lb = ix->dir[d].lines.size() * 4, sb = ix->dir[d].sa.size() * 4;
+        if (hipMalloc(&ix->d_lines[d], lb) != hipSuccess || hipMalloc(&ix->d_sa[d], sb) != hipSuccess)
+            return fail(BWFM_E_NOMEM, "index upload: device allocation failed");
+        HIPCHK(hipMemcpyAsync(ix->d_lines[d], ix->dir[d].lines.data(), lb, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ix->d_sa[d], ix->dir[d].sa.data(), sb, hipMemcpyHostToDevice, st));
+        bytes += lb + sb;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    ix->device_bytes = bytes;
+    ix->device = dev;
+    return BWFM_OK;
+}
+
+extern "C" void bwfm_index_free(bwfm_index *ix) {
+    if (!ix) return;
+    for (int d = 0; d < 2; d++) {
+        if (ix->d_lines[d]) (void)hipFree(ix->d_lines[d]);
+        if (ix->d_sa[d]) (void)hipFree(ix->d_sa[d]);
+    }
+    if (ix->ws.ptr) (void)hipFree(ix->ws.ptr);
+    delete ix;
+}
+
+extern "C" int bwfm_align_batch(const bwfm_index *cix, const bwfm_reads *rd, const bwfm_aln_params *p,
+                                bwfm_aln_result *res, void *stream) {
+    bwfm_index *ix = const_cast<bwfm_index *>(cix);
+    if (!ix || !rd || !p || !check_result(res)) return fail(BWFM_E_INVAL, "align_batch: NULL argument");
+    if (!check_index(ix)) return fail(BWFM_E_STATE, "align_batch: index not uploaded");
+    if (rd->n_reads && (!rd->bases || !rd->offsets)) return fail(BWFM_E_INVAL, "align_batch: NULL reads");
+    if (rd->max_len > BWFM_MAX_READ) return fail(BWFM_E_TOOLONG, "align_batch: max_len above 512");
+    if (p->max_diff < 0 || p->max_diff > BWFM_MAX_DIFF || p->max_gapo < 0 || p->seed_len < 0 || p->seed_diff < 0 ||
+        p->indel_end_skip < 0 || p->s_mm < 0 || p->s_gapo < 0 || p->s_gape < 0 ||
+        (p->mode != BWFM_MODE_ALL && p->mode != BWFM_MODE_BEST) || p->max_best < 0 || p->max_hits < 1 ||
+        p->max_hits > 65536 || p->s_mm * 15 > 4000 || p->s_gapo * 15 > 4000 || p->s_gape * 15 > 4000)
+        return fail(BWFM_E_INVAL, "align_batch: parameter out of range");
+    std::lock_guard<std::mutex> g(ix->mu);
+    hipStream_t st = (hipStream_t)stream;
+    if (ix->line_bytes == 128) return align_impl<32>(ix, rd, p, res, st, nullptr);
+    return align_impl<16>(ix, rd, p, res, st, nullptr);
+}
+
+// Same as bwfm_align_batch, also writing per-read search work (states
+// expanded, summed over both passes) to expand (device, n_reads).
+extern "C" int bwfm_align_batch_counted(const bwfm_index *cix, const bwfm_reads *rd, const bwfm_aln_params *p,
+                                        bwfm_aln_result *res, uint32_t *expand, void *stream) {
+    bwfm_index *ix = const_cast<bwfm_index *>(cix);
+    if (!expand) return fail(BWFM_E_INVAL, "align_batch_counted: NULL counter array");
+    if (!ix || !rd || !p || !check_result(res)) return fail(BWFM_E_INVAL, "align_batch: NULL argument");
+    if (!check_index(ix)) return fail(BWFM_E_STATE, "align_batch: index not uploaded");
+    if (rd->max_len > BWFM_MAX_READ) return fail(BWFM_E_TOOLONG, "align_batch: max_len above 512");
+    std::lock_guard<std::mutex> g(ix->mu);
+    hipStream_t st = (hipStream_t)stream;
+    if (ix->line_bytes == 128) return align_impl<32>(ix, rd, p, res, st, expand);
+    return align_impl<16>(ix, rd, p, res, st, expand);
+}
+
+extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_aln_result *res, uint32_t max_occ,
+                           uint64_t *pos_off, uint32_t *pos, uint64_t cap, void *stream) {
+    bwfm_index *ix = const_cast<bwfm_index *>(cix);
+    if (!ix || !check_result(res) || !pos_off || (!pos && cap)) return fail(BWFM_E_INVAL, "locate: NULL argument");
+    if (!check_index(ix)) return fail(BWFM_E_STATE, "locate: index not uploaded");
+    std::lock_guard<std::mutex> g(ix->mu);
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t n_hits = 0;
+    HIPCHK(hipMemcpyAsync(&n_hits, res->hit_offsets + n_reads, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    size_t need = n_hits * 4 + scan_part_elems(n_hits) * 8 + n_hits * 4 + 4096;
+    void *w;
+    int rc = ws_reserve(ix, need, &w);
+    if (rc) return rc;
+    Carver cv{(char *)w};
+    uint32_t *cnt = cv.take<uint32_t>(n_hits);
+    uint64_t *part = cv.take<uint64_t>(scan_part_elems(n_hits));
+    uint32_t *big = cv.take<uint32_t>(n_hits);
+    uint32_t *n_big = cv.take<uint32_t>(1);
+    uint64_t total = 0;
+    if (ix->line_bytes == 128)
+        rc = locate_impl<32>(ix, n_hits, (const uint4 *)res->hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st,
+                             &total);
+    else
+        rc = locate_impl<16>(ix, n_hits, (const uint4 *)res->hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st,
+                             &total);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bwfm_aln_result *r1,
+                               const bwfm_aln_result *r2, const bwfm_pair_params *pp, bwfm_pair *out, void *stream) {
+    bwfm_index *ix = const_cast<bwfm_index *>(cix);
+    if (!ix || !check_result(r1) || (r2 && !check_result(r2)) || !pp || (!out && n_pairs))
+        return fail(BWFM_E_INVAL, "pair_reads: NULL argument");
+    if (!check_index(ix)) return fail(BWFM_E_STATE, "pair_reads: index not uploaded");
+    if (pp->lo > pp->hi) return fail(BWFM_E_INVAL, "pair_reads: lo > hi");
+    std::lock_guard<std::mutex> g(ix->mu);
+    hipStream_t st = (hipStream_t)stream;
+    const bwfm_aln_result *rr[2] = {r1, r2};
+    uint64_t nh[2] = {0, 0};
+    for (int e = 0; e < 2; e++)
+        if (rr[e]) HIPCHK(hipMemcpyAsync(&nh[e], rr[e]->hit_offsets + n_pairs, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // upper bound on positions: widths are capped by max_occ
+    void *pairmem = nullptr;
+    // first count the positions per end, then allocate them
+    uint64_t *poff[2] = {nullptr, nullptr};
+    uint32_t *pos[2] = {nullptr, nullptr};
+    const uint64_t nmax = std::max(nh[0], nh[1]);
+    size_t ctl = nmax * 4 * 2 + scan_part_elems(nmax) * 8 + 4096 + (nh[0] + nh[1] + 2) * 8;
+    if (hipMalloc(&pairmem, ctl) != hipSuccess) return fail(BWFM_E_NOMEM, "pair_reads: control buffers");
+    Carver cv{(char *)pairmem};
+    uint32_t *cnt = cv.take<uint32_t>(nmax);
+    uint32_t *big = cv.take<uint32_t>(nmax);
+    uint64_t *part = cv.take<uint64_t>(scan_part_elems(nmax));
+    uint32_t *n_big = cv.take<uint32_t>(1);
+    poff[0] = cv.take<uint64_t>(nh[0] + 1);
+    poff[1] = cv.take<uint64_t>(nh[1] + 1);
+    void *posmem[2] = {nullptr, nullptr};
+    int rc = BWFM_OK;
+    for (int e = 0; e < 2 && rc == BWFM_OK; e++) {
+        if (!rr[e]) continue;
+        // count pass (capacity 0 reports the total)
+        uint64_t total = 0;
+        rc = ix->line_bytes == 128
+                 ? locate_impl<32>(ix, nh[e], (const uint4 *)rr[e]->hits, pp->max_occ, poff[e], nullptr, 0, cnt, part,
+                                   big, n_big, st, &total)
+                 : locate_impl<16>(ix, nh[e], (const uint4 *)rr[e]->hits, pp->max_occ, poff[e], nullptr, 0, cnt, part,
+                                   big, n_big, st, &total);
+        if (rc == BWFM_E_CAPACITY || (rc == BWFM_OK && total == 0)) {
+            rc = BWFM_OK;
+            if (hipMalloc(&posmem[e], std::max<uint64_t>(total, 1) * 4) != hipSuccess) {
+                rc = fail(BWFM_E_NOMEM, "pair_reads: position buffer");
+                break;
+            }
+            pos[e] = (uint32_t *)posmem[e];
+            if (total)
+                rc = ix->line_bytes == 128
+                         ? locate_impl<32>(ix, nh[e], (const uint4 *)rr[e]->hits, pp->max_occ, poff[e], pos[e], total, cnt,
+                                           part, big, n_big, st, &total)
+                         : locate_impl<16>(ix, nh[e], (const uint4 *)rr[e]->hits, pp->max_occ, poff[e], pos[e], total, cnt,
+                                           part, big, n_big, st, &total);
+        }
+    }
+    if (rc == BWFM_OK && n_pairs) {
+        EndView e1{r1->hit_offsets, (const uint4 *)r1->hits, poff[0], pos[0]};
+        EndView e2 = e1;
+        if (r2) e2 = EndView{r2->hit_offsets, (const uint4 *)r2->hits, poff[1], pos[1]};
+        CallTimer tm(st);
+        int t = tm.begin("pair");
+        k_pair<<<blocks(n_pairs, 256), 256, 0, st>>>(n_pairs, e1, e2, r2 ? 1 : 0, pp->lo, pp->hi, pp->mu, out);
+        tm.end(t);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) rc = fail(BWFM_E_DEVICE, std::string("k_pair: ") + hipGetErrorString(e));
+    }
+    hipError_t es = hipStreamSynchronize(st);
+    if (rc == BWFM_OK && es != hipSuccess) rc = fail(BWFM_E_DEVICE, "pair_reads: synchronise failed");
+    for (int e = 0; e < 2; e++)
+        if (posmem[e]) (void)hipFree(posmem[e]);
+    (void)hipFree(pairmem);
+    return rc;
+}
+
+extern "C" int bwfm_max_diff_rule(uint32_t len, double err, double thres) {
+    // accumulate the Poisson(err * len) distribution until its tail drops
+    // below thres
+    double lambda = err * (double)len;
+    double pk = std::exp(-lambda);
+    double cdf = pk;
+    for (int k = 0; k < 1000; k++) {
+        if (1.0 - cdf < thres) return k;
+        pk = pk * lambda / (double)(k + 1);
+        cdf += pk;
+    }
+    return 1000;
+}
+
+extern "C" int bwfm_estimate_insert(const int32_t *ins, uint64_t n, bwfm_pair_params *out) {
+    if (!out || (!ins && n)) return fail(BWFM_E_INVAL, "estimate_insert: NULL argument");
+    if (n < 100) {
+        out->lo = 0;
+        out->hi = 500;
+        out->mu = 250;
+        return BWFM_OK;
+    }
+    std::vector<int32_t> v(ins, ins + n);
+    std::sort(v.begin(), v.end());
+    const double q1 = v[(size_t)std::floor(0.25 * (double)(n - 1))];
+    const double q3 = v[(size_t)std::floor(0.75 * (double)(n - 1))];
+    const double lo_k = q1 - 2 * (q3 - q1), hi_k = q3 + 2 * (q3 - q1);
+    double sum = 0;
+    uint64_t cnt = 0;
+    for (int32_t x : v)
+        if (x >= lo_k && x <= hi_k) {
+            sum += x;
+            cnt++;
+        }
+    const double mu = sum / (double)cnt;
+    double ss = 0;
+    for (int32_t x : v)
+        if (x >= lo_k && x <= hi_k) ss += ((double)x - mu) * ((double)x - mu);
+    const double sd = std::sqrt(ss / (double)cnt);
+    const double lo = std::floor(mu - 4 * sd);
+    out->lo = (int32_t)(lo < 0 ? 0 : lo);
+    out->hi = (int32_t)std::ceil(mu + 4 * sd);
+    out->mu = (int32_t)std::nearbyint(mu);
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_timing_enable(int on) {
+    std::lock_guard<std::mutex> g(timing().mu);
+    timing().on = on != 0;
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_timing_reset(void) {
+    std::lock_guard<std::mutex> g(timing().mu);
+    timing().acc.clear();
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_timing_get(const char *kernel, double *total_ms, uint64_t *launches) {
+    if (!kernel || !total_ms || !launches) return fail(BWFM_E_INVAL, "timing_get: NULL argument");
+    std::lock_guard<std::mutex> g(timing().mu);
+    auto it = timing().acc.find(kernel);
+    *total_ms = it == timing().acc.end() ? 0.0 : it->second.first;
+    *launches = it == timing().acc.end() ? 0 : it->second.second;
+    return BWFM_OK;
+}
+
+extern "C" const char *bwfm_last_error(void) { return last_error().c_str(); }

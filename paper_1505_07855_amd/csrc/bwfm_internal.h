@@ -1,0 +1,68 @@
+// Library-internal definitions shared by the host index builder, the C ABI
+// and the kernel launchers.  Not part of the public interface.
+#pragma once
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bwfm.h"
+
+namespace bwfm {
+
+// One direction of the index (0: index of T, 1: index of reverse(T)).
+struct HostDir {
+    std::vector<uint32_t> lines;  // lines * line_words32: 4 counts, then packed rows
+    std::vector<uint32_t> sa;     // SA[r] for r % sa_sample == 0
+    uint64_t C[4] = {0, 0, 0, 0};
+    uint64_t primary = 0;
+};
+
+// Device-side view of one direction, passed to kernels by value.
+struct DevDir {
+    const uint32_t *lines;  // line_words32 uint32 per line, 16-byte aligned
+    const uint32_t *sa;
+    uint32_t C[4];
+    uint32_t primary;
+    uint32_t pad;
+};
+
+struct DevIndex {
+    DevDir dir[2];
+    uint64_t magic;       // floor(2^64 / bases_per_line) + 1: row / bpl = mulhi(row, magic)
+    uint32_t n;           // text length (n + 1 < 2^32)
+    uint32_t bpl;         // rows per rank line
+    uint32_t sa_shift;    // log2(sa_sample)
+    uint32_t line_words;  // uint32 words per line
+};
+
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+std::string &last_error();
+int fail(int code, const std::string &msg);
+
+// Host index builder and inspection (index_host.cpp).
+int build_dir(const uint8_t *text, uint64_t n, uint32_t line_bytes, uint32_t bpl, uint32_t sa_sample,
+              HostDir &out);
+void occ_host(const HostDir &d, uint32_t line_words, uint32_t bpl, uint64_t i, uint64_t out[4]);
+uint8_t bwt_host(const HostDir &d, uint32_t line_words, uint32_t bpl, uint64_t row);
+
+}  // namespace bwfm
+
+struct bwfm_index {
+    uint64_t n = 0;
+    uint32_t line_bytes = 128, bpl = 448, sa_sample = 32;
+    uint64_t n_lines = 0, n_samples = 0;
+    bwfm::HostDir dir[2];
+    // device copies (valid when uploaded)
+    int device = -1;
+    void *d_lines[2] = {nullptr, nullptr};
+    void *d_sa[2] = {nullptr, nullptr};
+    uint64_t device_bytes = 0;
+    std::mutex mu;
+    bwfm::Workspace ws;
+};

@@ -1,0 +1,285 @@
+// Host-side construction of the packed FM-index (the offline encoding of
+// the reference, Genetically Improved BarraCUDA section 2).
+//
+// Suffix sorting uses induced sorting (SA-IS: Nong, Zhang and Chan, "Two
+// efficient algorithms for linear time suffix array construction", IEEE
+// Trans. Computers 2011), written from that description.  The BWT is then
+// packed two bits per row into rank lines: each line starts with the counts
+// of A, C, G and T in the rows before it ($ counted as A, since $ is stored
+// as A in the packed rows) followed by its rows, so one rank query reads one
+// line.  Every sa_sample-th row keeps its suffix array value.
+#include <algorithm>
+#include <cstring>
+#include <stdexcept>
+#include <thread>
+
+#include "bwfm_internal.h"
+
+namespace bwfm {
+
+namespace {
+
+constexpr uint32_t EMPTY = 0xffffffffu;
+
+struct Bits {
+    std::vector<uint64_t> w;
+    explicit Bits(uint64_t n) : w((n + 63) / 64, 0) {}
+    bool get(uint64_t i) const { return (w[i >> 6] >> (i & 63)) & 1; }
+    void set(uint64_t i) { w[i >> 6] |= 1ULL << (i & 63); }
+};
+
+// Suffix array of s[0, n) over alphabet [0, K); s[n - 1] must be the unique
+// smallest symbol.  SA receives the n sorted suffix starts.
+template <typename Ch>
+void sais(const Ch *s, uint32_t *SA, uint64_t n, uint64_t K) {
+    if (n == 1) {
+        SA[0] = 0;
+        return;
+    }
+    // type of each suffix: S (bit set) or L
+    Bits st(n);
+    st.set(n - 1);
+    for (uint64_t i = n - 1; i-- > 0;)
+        if (s[i] < s[i + 1] || (s[i] == s[i + 1] && st.get(i + 1))) st.set(i);
+    auto lms = [&](uint64_t i) { return i > 0 && st.get(i) && !st.get(i - 1); };
+
+    std::vector<uint64_t> bkt(K + 1, 0);
+    for (uint64_t i = 0; i < n; i++) bkt[s[i] + 1]++;
+    for (uint64_t c = 0; c < K; c++) bkt[c + 1] += bkt[c];  // bkt[c] = start of bucket c
+    std::vector<uint64_t> ptr(K);
+    auto tails = [&] { for (uint64_t c = 0; c < K; c++) ptr[c] = bkt[c + 1]; };
+    auto heads = [&] { for (uint64_t c = 0; c < K; c++) ptr[c] = bkt[c]; };
+    auto induce = [&] {
+        heads();
+        for (uint64_t i = 0; i < n; i++) {
+            uint32_t j = SA[i];
+            if (j != EMPTY && j > 0 && !st.get(j - 1)) SA[ptr[s[j - 1]]++] = j - 1;
+        }
+        tails();
+        for (uint64_t i = n; i-- > 0;) {
+            uint32_t j = SA[i];
+            if (j != EMPTY && j > 0 && st.get(j - 1)) SA[--ptr[s[j - 1]]] = j - 1;
+        }
+    };
+
+    // 1. sort the LMS substrings: LMS suffixes at their bucket ends, induce
+    std::fill(SA, SA + n, EMPTY);
+    tails();
+    for (uint64_t i = 1; i < n; i++)
+        if (lms(i)) SA[--ptr[s[i]]] = (uint32_t)i;
+    induce();
+
+    // 2. gather the sorted LMS positions in SA[0, n1)
+    uint64_t n1 = 0;
+    for (uint64_t i = 0; i < n; i++)
+        if (lms(SA[i])) SA[n1++] = SA[i];
+    // 3. name them: equal LMS substrings get equal names
+    std::fill(SA + n1, SA + n, EMPTY);
+    uint64_t name = 0;
+    uint32_t prev = EMPTY;
+    for (uint64_t i = 0; i < n1; i++) {
+        uint32_t p = SA[i];
+        bool diff = prev == EMPTY;
+        for (uint64_t d = 0; !diff; d++) {
+            if (s[p + d] != s[prev + d] || st.get(p + d) != st.get(prev + d)) {
+                diff = true;
+            } else if (d > 0 && (lms(p + d) || lms(prev + d))) {
+                diff = !(lms(p + d) && lms(prev + d));
+                break;
+            }
+        }
+        if (diff) {
+            name++;
+            prev = p;
+        }
+        SA[n1 + p / 2] = (uint32_t)(name - 1);
+    }
+    // the reduced string, in text order of its LMS positions, at SA's end
+    {
+        uint64_t j = n;
+        for (uint64_t i = n; i-- > n1;)
+            if (SA[i] != EMPTY) SA[--j] = SA[i];
+    }
+    uint32_t *s1 = SA + n - n1;
+    uint32_t *SA1 = SA;
+    // 4. sort the reduced string's suffixes
+    if (name < n1) {
+        sais<uint32_t>(s1, SA1, n1, name);
+    } else {
+        for (uint64_t i = 0; i < n1; i++) SA1[s1[i]] = (uint32_t)i;
+    }
+    // 5. map back to text positions and induce the full order
+    {
+        uint64_t j = 0;
+        for (uint64_t i = 1; i < n; i++)
+            if (lms(i)) s1[j++] = (uint32_t)i;
+        for (uint64_t i = 0; i < n1; i++) SA1[i] = s1[SA1[i]];
+        std::fill(SA + n1, SA + n, EMPTY);
+        tails();
+        for (uint64_t i = n1; i-- > 0;) {
+            uint32_t p = SA[i];
+            SA[i] = EMPTY;
+            SA[--ptr[s[p]]] = p;
+        }
+    }
+    induce();
+}
+
+}  // namespace
+
+int build_dir(const uint8_t *text, uint64_t n, uint32_t line_bytes, uint32_t bpl, uint32_t sa_sample,
+              HostDir &out) {
+    const uint64_t N = n + 1;
+    std::vector<uint8_t> s(N);
+    for (uint64_t i = 0; i < n; i++) s[i] = (uint8_t)(text[i] + 1);
+    s[n] = 0;
+    std::vector<uint32_t> SA;
+    try {
+        SA.resize(N);
+    } catch (const std::bad_alloc &) {
+        return BWFM_E_NOMEM;
+    }
+    sais<uint8_t>(s.data(), SA.data(), N, 5);
+    std::vector<uint8_t>().swap(s);
+
+    const uint32_t lw = line_bytes / 4;
+    const uint64_t n_lines = N / bpl + 1;
+    out.lines.assign(n_lines * lw, 0);
+    out.sa.assign(n / sa_sample + 1, 0);
+    uint64_t cnt[4] = {0, 0, 0, 0};
+    for (uint64_t j = 0; j < N; j++) {
+        uint64_t line = j / bpl, r = j - line * bpl;
+        uint32_t *L = &out.lines[line * lw];
+        if (r == 0)
+            for (int a = 0; a < 4; a++) L[a] = (uint32_t)cnt[a];
+        uint32_t q = SA[j];
+        uint32_t c = q == 0 ? 0 : text[q - 1];  // $ stored as A
+        if (q == 0) out.primary = j;
+        L[4 + (r >> 4)] |= c << (2 * (r & 15));
+        cnt[c]++;
+        if ((j & (sa_sample - 1)) == 0) out.sa[j / sa_sample] = q;
+    }
+    if (N % bpl == 0) {
+        uint32_t *L = &out.lines[(N / bpl) * lw];
+        for (int a = 0; a < 4; a++) L[a] = (uint32_t)cnt[a];
+    }
+    cnt[0] -= 1;  // the $ row was counted as A
+    out.C[0] = 1;
+    for (int a = 1; a < 4; a++) out.C[a] = out.C[a - 1] + cnt[a - 1];
+    return BWFM_OK;
+}
+
+uint8_t bwt_host(const HostDir &d, uint32_t lw, uint32_t bpl, uint64_t row) {
+    if (row == d.primary) return 4;
+    uint64_t line = row / bpl, r = row - line * bpl;
+    const uint32_t *L = &d.lines[line * lw];
+    return (uint8_t)((L[4 + (r >> 4)] >> (2 * (r & 15))) & 3);
+}
+
+void occ_host(const HostDir &d, uint32_t lw, uint32_t bpl, uint64_t i, uint64_t out[4]) {
+    uint64_t line = i / bpl, r = i - line * bpl;
+    const uint32_t *L = &d.lines[line * lw];
+    for (int a = 0; a < 4; a++) out[a] = L[a];
+    for (uint64_t x = 0; x < r; x++) out[(L[4 + (x >> 4)] >> (2 * (x & 15))) & 3]++;
+    if (i > d.primary) out[0]--;
+}
+
+std::string &last_error() {
+    thread_local std::string e;
+    return e;
+}
+
+int fail(int code, const std::string &msg) {
+    last_error() = msg;
+    return code;
+}
+
+}  // namespace bwfm
+
+using namespace bwfm;
+
+extern "C" int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index_params *p, bwfm_index **out) {
+    if (!ref || !out) return fail(BWFM_E_INVAL, "build_index: NULL argument");
+    *out = nullptr;
+    bwfm_index_params q = p ? *p : bwfm_index_params{128, 0, 32, 0};
+    if (q.line_bytes != 64 && q.line_bytes != 128) return fail(BWFM_E_INVAL, "line_bytes must be 64 or 128");
+    uint32_t maxb = (q.line_bytes - 16) * 4;
+    if (q.bases_per_line == 0) q.bases_per_line = maxb;
+    if (q.bases_per_line % 32 || q.bases_per_line < 32 || q.bases_per_line > maxb)
+        return fail(BWFM_E_INVAL, "bases_per_line must be a multiple of 32 in [32, (line_bytes-16)*4]");
+    if (q.sa_sample < 1 || q.sa_sample > 1024 || (q.sa_sample & (q.sa_sample - 1)))
+        return fail(BWFM_E_INVAL, "sa_sample must be a power of two in [1, 1024]");
+    if (n < 1) return fail(BWFM_E_INVAL, "empty reference");
+    if (n + 1 >= (1ULL << 32)) return fail(BWFM_E_TOOLONG, "reference too long for 32-bit positions");
+    for (uint64_t i = 0; i < n; i++)
+        if (ref[i] > 3) return fail(BWFM_E_BASE, "reference holds a code outside 0..3 at " + std::to_string(i));
+    bwfm_index *ix = new (std::nothrow) bwfm_index;
+    if (!ix) return fail(BWFM_E_NOMEM, "out of host memory");
+    ix->n = n;
+    ix->line_bytes = q.line_bytes;
+    ix->bpl = q.bases_per_line;
+    ix->sa_sample = q.sa_sample;
+    ix->n_lines = (n + 1) / q.bases_per_line + 1;
+    ix->n_samples = n / q.sa_sample + 1;
+    std::vector<uint8_t> rev(ref, ref + n);
+    std::reverse(rev.begin(), rev.end());
+    int rc[2] = {BWFM_OK, BWFM_OK};
+    auto job = [&](int d) {
+        try {
+            rc[d] = build_dir(d == 0 ? ref : rev.data(), n, q.line_bytes, q.bases_per_line, q.sa_sample, ix->dir[d]);
+        } catch (const std::bad_alloc &) {
+            rc[d] = BWFM_E_NOMEM;
+        }
+    };
+    bool par = q.n_threads != 1;
+    if (par) {
+        std::thread t(job, 1);
+        job(0);
+        t.join();
+    } else {
+        job(0);
+        job(1);
+    }
+    if (rc[0] || rc[1]) {
+        delete ix;
+        return fail(rc[0] ? rc[0] : rc[1], "index build failed (out of memory)");
+    }
+    *out = ix;
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_index_get_info(const bwfm_index *ix, bwfm_index_info *o) {
+    if (!ix || !o) return fail(BWFM_E_INVAL, "get_info: NULL argument");
+    std::memset(o, 0, sizeof(*o));
+    o->n = ix->n;
+    for (int d = 0; d < 2; d++) {
+        o->primary[d] = ix->dir[d].primary;
+        for (int a = 0; a < 4; a++) o->C[d][a] = ix->dir[d].C[a];
+    }
+    o->lines = ix->n_lines;
+    o->sa_samples = ix->n_samples;
+    o->device_bytes = ix->device_bytes;
+    o->line_bytes = ix->line_bytes;
+    o->bases_per_line = ix->bpl;
+    o->sa_sample = ix->sa_sample;
+    o->uploaded = ix->device >= 0;
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_index_get_bwt(const bwfm_index *ix, int which, uint8_t *out) {
+    if (!ix || !out || which < 0 || which > 1) return fail(BWFM_E_INVAL, "get_bwt: bad argument");
+    for (uint64_t r = 0; r <= ix->n; r++) out[r] = bwt_host(ix->dir[which], ix->line_bytes / 4, ix->bpl, r);
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_index_get_sa_samples(const bwfm_index *ix, int which, uint32_t *out) {
+    if (!ix || !out || which < 0 || which > 1) return fail(BWFM_E_INVAL, "get_sa_samples: bad argument");
+    std::memcpy(out, ix->dir[which].sa.data(), ix->dir[which].sa.size() * 4);
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_index_occ(const bwfm_index *ix, int which, uint64_t i, uint64_t *out) {
+    if (!ix || !out || which < 0 || which > 1 || i > ix->n + 1) return fail(BWFM_E_INVAL, "occ: bad argument");
+    occ_host(ix->dir[which], ix->line_bytes / 4, ix->bpl, i, out);
+    return BWFM_OK;
+}

@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for
+bit (hit lists, c1/c2, statuses, positions, pair records), on seeded inputs
+of the workloads' shapes, including the edge cases and both index layouts."""
+from __future__ import annotations
+
+import threading
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_1505_07855_amd as bw
+from gen import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda:0")
+
+
+def _gpu_align(ix, reads, params, max_diff=None, counted=False):
+    bases = _dev(reads.bases)
+    offs = _dev(reads.offsets.view(np.int64))
+    md = _dev(max_diff) if max_diff is not None else None
+    max_len = int(np.diff(reads.offsets).max()) if reads.n else 0
+    res = bw.align_batch(ix, bases, offs, params, max_diff=md, max_len=max(max_len, 1), counted=counted)
+    torch.cuda.synchronize()
+    return res
+
+
+def _compare_align(res, ores, rows=None):
+    ho, hits, c1, c2, st = res.to_numpy()
+    if rows is None:
+        assert np.array_equal(ho, ores.hit_off), "hit offsets differ"
+        assert np.array_equal(hits.view(np.uint8), ores.hits.view(np.uint8)), "hits differ"
+        assert np.array_equal(c1, ores.c1) and np.array_equal(c2, ores.c2)
+        assert np.array_equal(st & 7, ores.status)
+    else:
+        for j, r in enumerate(rows):
+            g = hits[ho[r]:ho[r + 1]]
+            o = ores.read_hits(j)
+            assert np.array_equal(g.view(np.uint8), o.view(np.uint8)), f"read {r}"
+            assert (c1[r], c2[r], st[r] & 7) == (ores.c1[j], ores.c2[j], ores.status[j])
+
+
+def _params_pair(**kw):
+    return bw.Params(**kw), oracle.Params(**kw)
+
+
+@pytest.fixture(scope="module")
+def c1_small():
+    g = gen.genome_iid(1001, 200_000)
+    reads = gen.reads_se(2001, g, 3000, 36, ps=0.02)
+    return g, reads, oracle.Index(g.seq)
+
+
+@pytest.mark.parametrize("layout", [(64, 128), (128, 448)])
+@pytest.mark.parametrize("mode", [bw.MODE_BEST, bw.MODE_ALL])
+def test_c1_shape_parity(c1_small, layout, mode):
+    g, reads, ox = c1_small
+    ix = bw.Index(g.seq, line_bytes=layout[0], bases_per_line=layout[1], sa_sample=32).upload()
+    p, op = _params_pair(**configs.PARAMS["C1"], mode=mode)
+    res = _gpu_align(ix, reads, p, counted=True)
+    ores = oracle.align(ox, reads.bases, reads.offsets, op, threads=8)
+    _compare_align(res, ores)
+    # same traversal order: the work counters agree for reads done in one pass
+    st = res.status.cpu().numpy()
+    exp = res.expand.cpu().numpy().view(np.uint32)
+    one = (st & bw.ST_RESEARCH) == 0
+    assert np.array_equal(exp[one], ores.counts["expand"][one].astype(np.uint32))
+
+
+@pytest.fixture(scope="module")
+def c2_small():
+    g = configs.c2_genome(2_000_000, seed=77)
+    pairs = configs.c2_pairs(g, 3000, seed=78)
+    return g, pairs, oracle.Index(g.seq)
+
+
+@pytest.mark.parametrize("layout", [(128, 448, 32), (64, 192, 16)])
+def test_c2_shape_parity_align_locate_pair(c2_small, layout):
+    g, pairs, ox = c2_small
+    ix = bw.Index(g.seq, line_bytes=layout[0], bases_per_line=layout[1], sa_sample=layout[2]).upload()
+    p, op = _params_pair(**configs.PARAMS["C2"])
+    r = []
+    for end in (pairs.end1, pairs.end2):
+        res = _gpu_align(ix, end, p, counted=True)
+        ores = oracle.align(ox, end.bases, end.offsets, op, threads=8)
+        _compare_align(res, ores)
+        st = res.status.cpu().numpy()
+        one = (st & bw.ST_RESEARCH) == 0
+        assert np.array_equal(res.expand.cpu().numpy().view(np.uint32)[one],
+                              ores.counts["expand"][one].astype(np.uint32))
+        r.append((res, ores))
+    # locate
+    for res, ores in r:
+        for max_occ in (100000, 1):
+            po, pos = bw.locate(ix, res, max_occ)
+            opo, opos = oracle.locate(ox, ores.hits, max_occ)
+            assert np.array_equal(po.cpu().numpy().view(np.uint64), opo)
+            assert np.array_equal(pos.cpu().numpy().view(np.uint32), opos)
+    # pairing, paired and single-end
+    w = configs.PAIR_WINDOW
+    gp = bw.pairs_numpy(bw.pair_reads(ix, r[0][0], r[1][0], w["lo"], w["hi"], w["mu"], configs.MAX_OCC))
+    po1, pos1 = oracle.locate(ox, r[0][1].hits, configs.MAX_OCC)
+    po2, pos2 = oracle.locate(ox, r[1][1].hits, configs.MAX_OCC)
+    op_ = oracle.pair(r[0][1], po1, pos1, r[1][1], po2, pos2, w["lo"], w["hi"], w["mu"])
+    assert np.array_equal(gp.view(np.uint8), op_.view(np.uint8))
+    assert (gp["flags"] & bw.PF_PAIRED).mean() > 0.8
+    gs = bw.pairs_numpy(bw.pair_reads(ix, r[0][0], None, w["lo"], w["hi"], w["mu"], configs.MAX_OCC))
+    os_ = oracle.pair(r[0][1], po1, pos1, None, None, None, w["lo"], w["hi"], w["mu"])
+    assert np.array_equal(gs.view(np.uint8), os_.view(np.uint8))
+
+
+def test_second_pass_and_overflow_parity():
+    # a repeat-rich genome and ALL mode: many reads exceed the first pass's
+    # 32 hit slots or 64 stack entries and are searched again
+    g = gen.genome_repeats(91, 400_000, gc=0.41, repeat_frac=0.7, n_fam=5, min_len=300, max_len=800, div_lo=0.0,
+                           div_hi=0.03)
+    reads = gen.reads_se(92, g, 1500, 40, ps=0.03, indel_ratio=0.2, rep_frac=0.9)
+    ox = oracle.Index(g.seq)
+    ix = bw.Index(g.seq).upload()
+    for kw in (dict(max_diff=3, max_gapo=1, mode=bw.MODE_ALL, max_hits=200),
+               dict(max_diff=3, max_gapo=1, mode=bw.MODE_BEST, max_hits=5),
+               dict(max_diff=2, max_gapo=0, mode=bw.MODE_ALL, max_hits=1000)):
+        p, op = _params_pair(**kw)
+        res = _gpu_align(ix, reads, p)
+        ores = oracle.align(ox, reads.bases, reads.offsets, op, threads=8)
+        _compare_align(res, ores)
+        st = res.status.cpu().numpy()
+        assert (st & bw.ST_RESEARCH).any(), "the second pass was not exercised"
+        assert kw["mode"] != bw.MODE_BEST or (st & bw.ST_OVERFLOW).any()
+
+
+def test_edge_cases_parity():
+    g = configs.c2_genome(300_000, seed=5)
+    ox = oracle.Index(g.seq)
+    ix = bw.Index(g.seq).upload()
+    rng = np.random.default_rng(3)
+    pieces = [np.zeros(0, np.uint8),                     # empty read
+              g.seq[1000:1001].copy(),                   # one base
+              g.seq[5000:5512].copy(),                   # the longest read
+              rng.integers(0, 4, 100).astype(np.uint8),  # random: no hit
+              g.seq[7000:7100].copy(),                   # exact
+              np.full(60, 4, np.uint8)]                  # all N
+    x = g.seq[9000:9100].copy()
+    x[[10, 50, 90]] = 4                                  # with N
+    pieces.append(x)
+    y = (3 - g.seq[20000:20150][::-1]).astype(np.uint8)  # reverse strand, 150 bp
+    pieces.append(y)
+    bases = np.concatenate(pieces)
+    offs = np.zeros(len(pieces) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(p) for p in pieces])
+    reads = gen.Reads(bases, offs)
+    md = np.array([4, 2, 6, 4, 0, 4, 5, 15], np.uint8)
+    p, op = _params_pair(**configs.PARAMS["C2"])
+    res = _gpu_align(ix, reads, p, max_diff=md)
+    ores = oracle.align(ox, reads.bases, reads.offsets, op, max_diff=md, threads=1)
+    _compare_align(res, ores)
+    st = res.status.cpu().numpy()
+    assert st[0] == 0 and st[4] & bw.ST_HIT and st[7] & bw.ST_HIT
+    # invalid: a read longer than max_len, a budget above 15
+    md2 = md.copy()
+    md2[4] = 16
+    bases_t, offs_t = _dev(bases), _dev(offs.view(np.int64))
+    res2 = bw.align_batch(ix, bases_t, offs_t, p, max_diff=_dev(md2), max_len=200)
+    st2 = res2.status.cpu().numpy()
+    assert st2[2] == bw.ST_INVALID and st2[4] == bw.ST_INVALID and st2[3] == ores.status[3]
+    # an empty batch
+    res3 = bw.align_batch(ix, _dev(np.zeros(1, np.uint8)), _dev(np.zeros(1, np.int64)), p, max_len=1)
+    assert res3.n_hits == 0
+
+
+def test_c3_shape_per_read_budgets_parity():
+    g = configs.c2_genome(1_000_000, seed=33)
+    pairs = configs.c3_pairs(g, 1500, seed=34)
+    ox = oracle.Index(g.seq)
+    ix = bw.Index(g.seq).upload()
+    p, op = _params_pair(**configs.PARAMS["C3"])
+    for end in (pairs.end1, pairs.end2):
+        L = np.diff(end.offsets).astype(int)
+        md_lib = np.array([bw.max_diff_rule(int(x)) for x in L], np.uint8)
+        md_orc = np.array([oracle.max_diff_rule(int(x)) for x in L], np.uint8)
+        assert np.array_equal(md_lib, md_orc)
+        res = _gpu_align(ix, end, p, max_diff=md_lib)
+        ores = oracle.align(ox, end.bases, end.offsets, op, max_diff=md_orc, threads=8)
+        _compare_align(res, ores)
+
+
+def test_hit_capacity_error_reports_need():
+    g = gen.genome_iid(7, 100_000)
+    reads = gen.reads_se(8, g, 200, 30, ps=0.0)
+    ix = bw.Index(g.seq).upload()
+    p = bw.Params(max_diff=1, max_gapo=0, mode=bw.MODE_ALL)
+    bases, offs = _dev(reads.bases), _dev(reads.offsets.view(np.int64))
+    res = bw.align_batch(ix, bases, offs, p, max_len=30, hit_capacity=1)  # grows and retries
+    need = res.n_hits
+    assert need > 1 and res.hits.shape[0] >= need
+    with pytest.raises(bw.BwfmError) as e:
+        out = bw.AlignResult(torch.empty(201, dtype=torch.int64, device="cuda"),
+                             torch.empty((1, 4), dtype=torch.int32, device="cuda"),
+                             torch.empty(200, dtype=torch.int32, device="cuda"),
+                             torch.empty(200, dtype=torch.int32, device="cuda"),
+                             torch.empty(200, dtype=torch.uint8, device="cuda"), 200)
+        r = out._c()
+        import ctypes
+        rd = bw._reads_struct(bases, offs, None, 30)
+        pc = p._c()
+        bw._check(bw.lib().bwfm_align_batch(ix.handle, ctypes.byref(rd), ctypes.byref(pc), ctypes.byref(r),
+                                            bw._stream_ptr(None)))
+    assert e.value.code == bw.E_CAPACITY
+    assert int(out.hit_offsets[200].item()) == need
+
+
+@pytest.fixture(scope="module")
+def c2_full():
+    """The benchmark's workload at full size: 100 Mbp genome, 1M pairs."""
+    g = configs.c2_genome()
+    box = {}
+
+    def build_oracle():
+        box["ox"] = oracle.Index(g.seq)
+
+    t = threading.Thread(target=build_oracle)
+    t.start()
+    ix = bw.Index(g.seq).upload()
+    t.join()
+    pairs = configs.c2_pairs(g)
+    return g, pairs, ix, box["ox"]
+
+
+@pytest.mark.timeout(600)
+def test_c2_full_size_sampled_parity(c2_full):
+    """Full batch through the GPU in the benchmark's launch configuration;
+    a seeded sample of reads, and their pairs, checked against the oracle."""
+    g, pairs, ix, ox = c2_full
+    p, op = _params_pair(**configs.PARAMS["C2"])
+    rng = np.random.default_rng(11)
+    sample = np.sort(rng.choice(pairs.end1.n, 1500, replace=False))
+    res_e = []
+    for end in (pairs.end1, pairs.end2):
+        res = _gpu_align(ix, end, p)
+        offs = end.offsets
+        sb = np.concatenate([end.bases[offs[r]:offs[r + 1]] for r in sample])
+        so = np.zeros(len(sample) + 1, np.uint64)
+        so[1:] = np.cumsum(np.diff(offs)[sample])
+        ores = oracle.align(ox, sb, so, op, threads=16)
+        _compare_align(res, ores, rows=sample)
+        res_e.append((res, ores))
+    # pairs of the sampled reads
+    w = configs.PAIR_WINDOW
+    gp = bw.pairs_numpy(bw.pair_reads(ix, res_e[0][0], res_e[1][0], w["lo"], w["hi"], w["mu"], configs.MAX_OCC))
+    po1, pos1 = oracle.locate(ox, res_e[0][1].hits, configs.MAX_OCC)
+    po2, pos2 = oracle.locate(ox, res_e[1][1].hits, configs.MAX_OCC)
+    op_ = oracle.pair(res_e[0][1], po1, pos1, res_e[1][1], po2, pos2, w["lo"], w["hi"], w["mu"])
+    assert np.array_equal(gp[sample].view(np.uint8), op_.view(np.uint8))
+    # whole-batch properties: every pair got a record, most pair properly
+    assert (gp["flags"] & bw.PF_PAIRED).mean() > 0.8

@@ -1,0 +1,92 @@
+"""CPU-side checks of the library: it loads, exports every declared entry
+point, and its host-built index equals the oracle's index bit for bit.  No
+GPU call is made here."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1505_07855_amd as bw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "bwfm.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    declared = set(re.findall(r"\b(bwfm_\w+)\s*\(", hdr))
+    assert {"bwfm_build_index", "bwfm_align_batch", "bwfm_pair_reads", "bwfm_locate"} <= declared
+    L = ctypes.CDLL(bw.LIB_PATH)
+    for name in sorted(declared | set(bw.SYMBOLS)):
+        assert hasattr(L, name), name
+    assert set(bw.SYMBOLS) >= declared
+
+
+def _texts(rng):
+    yield "random", rng.integers(0, 4, 5000).astype(np.uint8)
+    yield "one", np.array([2], np.uint8)
+    yield "allA", np.zeros(1000, np.uint8)
+    yield "period", np.resize(np.array([0, 1, 2, 3, 3], np.uint8), 3001)
+    yield "binary", rng.integers(0, 2, 2048).astype(np.uint8)
+    t = rng.integers(0, 4, 4000).astype(np.uint8)
+    t[2000:3000] = t[500:1500]
+    yield "repeat", t
+
+
+@pytest.mark.parametrize("layout", [(128, 0, 32), (64, 0, 32), (64, 128, 32), (128, 64, 1), (64, 32, 8),
+                                    (128, 448, 1024)])
+def test_host_index_equals_oracle_index(layout, rng):
+    lb, bpl, sas = layout
+    for name, t in _texts(rng):
+        ix = bw.Index(t, line_bytes=lb, bases_per_line=bpl, sa_sample=sas)
+        ox = oracle.Index(t)
+        info = ix.info()
+        for which in (0, 1):
+            sa, bwt, C, prim = ox.get(which)
+            assert np.array_equal(ix.bwt(which), bwt), (name, which)
+            assert info["primary"][which] == prim
+            assert info["C"][which] == C.tolist()
+            samp = ix.sa_samples(which)
+            assert np.array_equal(samp, sa[::sas]), (name, which)
+            rows = np.unique(np.concatenate([rng.integers(0, len(t) + 2, 60), [0, 1, len(t), len(t) + 1]]))
+            for i in rows:
+                assert ix.occ(int(i), which).tolist() == ox.occ4(int(i), which).tolist(), (name, which, i)
+        ix.close()
+
+
+def test_build_index_errors():
+    with pytest.raises(bw.BwfmError) as e:
+        bw.Index(np.array([0, 1, 5], np.uint8))
+    assert e.value.code == -3
+    with pytest.raises(bw.BwfmError) as e:
+        bw.Index(np.zeros(10, np.uint8), line_bytes=96)
+    assert e.value.code == -1
+    with pytest.raises(bw.BwfmError) as e:
+        bw.Index(np.zeros(10, np.uint8), line_bytes=64, bases_per_line=256)
+    assert e.value.code == -1
+    with pytest.raises(bw.BwfmError) as e:
+        bw.Index(np.zeros(10, np.uint8), sa_sample=3)
+    assert e.value.code == -1
+    with pytest.raises(bw.BwfmError):
+        bw.Index(np.zeros(0, np.uint8))
+
+
+def test_host_helpers_match_oracle(rng):
+    for L in range(1, 513):
+        assert bw.max_diff_rule(L) == oracle.max_diff_rule(L)
+    for n in [0, 10, 99, 100, 101, 1000, 5000]:
+        ins = np.round(rng.normal(300, 30, n)).astype(np.int32)
+        if n > 5:
+            ins[:3] = [5, 9000, 12000]
+        assert bw.estimate_insert(ins) == oracle.estimate_insert(ins)
+
+
+def test_align_without_upload_is_a_state_error():
+    ix = bw.Index(np.zeros(100, np.uint8))
+    assert not ix.info()["uploaded"]
+    ix.close()
