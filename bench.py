@@ -3,11 +3,13 @@
 Workload: 100 Mbp synthetic genome (41% GC, 40% repeat copies from 500
 families) and 1M read pairs 2 x 100 bp (fragment ~ N(300, 30), 1%
 substitutions, 0.1% indel events), seeded.  One step = the whole path over
-the batch: align end 1 (1M reads), align end 2 (1M reads), then locate and
-pair, with reads and index resident in HBM before the timed region.
+the batch -- align both ends, locate, pair -- with reads and index resident
+in HBM before the timed region.  Two forms are timed and must agree bit for
+bit: plain (one lane per read, one launch per end) and batched (one
+persistent work-stealing launch for both ends); `value` is the batched one.
 
 Prints one JSON line.  The roofline entry is for the dominant kernel (the
-first-pass search), timed with HIP events on the launch stream inside the
+persistent search), timed with HIP events on the launch stream inside the
 library; its algorithmic bytes per launch are the oracle's index-line
 touches per read (same traversal order) x line size x reads per launch.  The
 CPU baseline is the oracle itself on a bounded sample of the same pairs.
@@ -41,10 +43,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--pairs", type=int, default=1_000_000)
     ap.add_argument("--genome", type=int, default=100_000_000)
-    ap.add_argument("--cpu-pairs", type=int, default=3000, help="pairs in the oracle's timed sample")
+    ap.add_argument("--cpu-pairs", type=int, default=100000, help="pairs in the oracle's timed sample")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--line-bytes", type=int, default=128)
+    ap.add_argument("--steps-plain", type=int, default=0, help="steps for the plain form (default: --steps)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path would shard "
@@ -77,56 +80,86 @@ def main():
     ix = bw.Index(g.seq, line_bytes=args.line_bytes, sa_sample=32).upload()
     log(f"library index built and uploaded in {time.time() - t0:.1f}s ({ix.info()['device_bytes'] / 1e6:.1f} MB)")
 
-    params = bw.Params(**configs.PARAMS["C2"])
     w = configs.PAIR_WINDOW
-    ends = []
-    for end in (pairs.end1, pairs.end2):
-        b = torch.from_numpy(end.bases).cuda()
-        o = torch.from_numpy(end.offsets.view(np.int64)).cuda()
-        ends.append((b, o))
+    n = args.pairs
+    # device inputs: each end on its own (plain form), both ends as one batch (batched form)
+    e1, e2 = pairs.end1, pairs.end2
+    ends = [(torch.from_numpy(e.bases).cuda(), torch.from_numpy(e.offsets.view(np.int64)).cuda()) for e in (e1, e2)]
+    both_b = torch.cat([ends[0][0], ends[1][0]])
+    both_o = torch.from_numpy(np.concatenate([e1.offsets[:-1], e1.offsets[-1] + e2.offsets]).view(np.int64)).cuda()
     stream = torch.cuda.current_stream()
-    res = [None, None]
-    pair_out = None
+    p_plain = bw.Params(**configs.PARAMS["C2"], form=bw.FORM_PLAIN)
+    p_batched = bw.Params(**configs.PARAMS["C2"], form=bw.FORM_BATCHED)
+    state = {"plain": [None, None, None], "batched": [None, None]}
 
-    def step():
-        nonlocal pair_out
-        for e in range(2):
-            res[e] = bw.align_batch(ix, ends[e][0], ends[e][1], params, max_len=100, out=res[e],
-                                    hit_capacity=4 * args.pairs, stream=stream)
-        pair_out = bw.pair_reads(ix, res[0], res[1], w["lo"], w["hi"], w["mu"], configs.MAX_OCC, stream=stream,
-                                 out=pair_out)
+    def step_plain():
+        s = state["plain"]
+        for k in range(2):
+            s[k] = bw.align_batch(ix, ends[k][0], ends[k][1], p_plain, max_len=100, out=s[k],
+                                  hit_capacity=4 * n, stream=stream)
+        s[2] = bw.pair_reads(ix, s[0], s[1], w["lo"], w["hi"], w["mu"], configs.MAX_OCC, stream=stream, out=s[2])
+        return s[0], s[1], s[2]
 
-    for i in range(args.warmup):
-        step()
-        log(f"warmup step {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    bw.timing_enable(True)
-    bw.timing_reset()
-    times = []
-    torch.cuda.synchronize()
-    t_all = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        step()
+    def step_batched():
+        s = state["batched"]
+        s[0] = bw.align_batch(ix, both_b, both_o, p_batched, max_len=100, out=s[0], hit_capacity=8 * n, stream=stream)
+        r1, r2 = s[0].window(0, n), s[0].window(n, 2 * n)
+        s[1] = bw.pair_reads(ix, r1, r2, w["lo"], w["hi"], w["mu"], configs.MAX_OCC, stream=stream, out=s[1])
+        return r1, r2, s[1]
+
+    def run(name, fn, steps):
+        for i in range(args.warmup):
+            fn()
+            log(f"{name}: warmup step {i + 1}/{args.warmup} done")
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - ts)
-        log(f"step {i + 1}/{args.steps}: {times[-1] * 1e3:.1f} ms")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_all
-    bw.timing_enable(False)
-    kernel_ms = {}
-    for name in ("align_fast", "align_slow", "compact", "locate_rows", "sort", "pair"):
-        ms, n = bw.timing_get(name)
-        if n:
-            kernel_ms[name] = {"avg_ms": ms / n, "launches": n}
+        bw.timing_enable(True)
+        bw.timing_reset()
+        times = []
+        t_all = time.perf_counter()
+        out = None
+        for i in range(steps):
+            ts = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - ts)
+            log(f"{name}: step {i + 1}/{steps}: {times[-1] * 1e3:.1f} ms")
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_all
+        bw.timing_enable(False)
+        kms = {}
+        for k in ("align_plain", "align_persistent", "align_slow", "compact", "locate_rows", "sort", "pair"):
+            ms, cnt = bw.timing_get(k)
+            if cnt:
+                kms[k] = {"avg_ms": ms / cnt, "launches": cnt}
+        r1, r2, po = out
+        st = [r.status.cpu().numpy() for r in (r1, r2)]
+        aligned = int(sum(((x & bw.ST_HIT) != 0).sum() for x in st))
+        research = int(sum(((x & bw.ST_RESEARCH) != 0).sum() for x in st))
+        flags = bw.pairs_numpy(po)["flags"][:n]
+        ms_step = total / steps * 1e3
+        return {"steps": steps, "ms_per_step": ms_step, "aligned_reads_per_s": aligned / (ms_step / 1e3), "aligned": aligned,
+                "p50_ms": float(np.percentile(np.array(times) * 1e3, 50)),
+                "p99_ms": float(np.percentile(np.array(times) * 1e3, 99)),
+                "research_reads": research, "paired_fraction": float((flags & bw.PF_PAIRED).astype(bool).mean()),
+                "kernel_ms": kms, "out": out}
 
-    st = [r.status.cpu().numpy() for r in res]
-    aligned = int(sum(((s & bw.ST_HIT) != 0).sum() for s in st))
-    n_reads = 2 * args.pairs
-    flags = bw.pairs_numpy(pair_out)["flags"]
-    ms_step = total / args.steps * 1e3
-    value = aligned / (ms_step / 1e3)
-    research = int(sum(((s & bw.ST_RESEARCH) != 0).sum() for s in st))
+    plain = run("plain", step_plain, args.steps_plain or args.steps)
+    batched = run("batched", step_batched, args.steps)
+    # both forms must agree exactly
+    a1, a2, ap = plain.pop("out")
+    b1, b2, bp = batched.pop("out")
+    for x, y in ((a1, b1), (a2, b2)):
+        hx, hy = x.to_numpy(), y.to_numpy()
+        same = all(np.array_equal(u.view(np.uint8), v.view(np.uint8)) for u, v in zip(hx[:4], hy[:4]))
+        if not (same and np.array_equal(hx[4] & 7, hy[4] & 7)):
+            raise SystemExit("plain and batched forms disagree")
+    if not np.array_equal(bw.pairs_numpy(ap).view(np.uint8), bw.pairs_numpy(bp).view(np.uint8)):
+        raise SystemExit("plain and batched pair records disagree")
+    n_reads = 2 * n
+    aligned = batched["aligned"]
+    ms_step = batched["ms_per_step"]
+    value = batched["aligned_reads_per_s"]
+    kernel_ms = batched["kernel_ms"]
 
     roofline = None
     cpu = None
@@ -151,14 +184,14 @@ def main():
         # method touches per read (D-array scans + search), same order as the kernel
         touches = np.concatenate([r.counts["touch_s"] + r.counts["touch_d"] for r in ores]).astype(np.float64)
         bytes_per_read = float(touches.mean()) * ix.info()["line_bytes"]
-        kf = kernel_ms.get("align_fast")
+        kf = kernel_ms.get("align_persistent")
         if kf:
-            per_launch = bytes_per_read * args.pairs
+            per_launch = bytes_per_read * n_reads
             achieved = per_launch / (kf["avg_ms"] / 1e3) / 1e9
             roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "k_align_fast", "bytes_per_read": bytes_per_read,
-                        "reads_per_launch": args.pairs, "avg_launch_ms": kf["avg_ms"]}
+                        "kernel": "k_align_persistent", "bytes_per_read": bytes_per_read,
+                        "reads_per_launch": n_reads, "avg_launch_ms": kf["avg_ms"]}
 
     out = {
         "metric": METRIC, "value": value, "unit": "aligned reads/s", "n_gpus": 1, "steps": args.steps,
@@ -166,13 +199,12 @@ def main():
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"C2 mid: {args.genome / 1e6:.0f} Mbp synthetic genome (GC 41%, 40% repeats), "
                                f"{args.pairs} pairs 2x100 bp, <=4 diffs, 1 gap open, seed 32/<=2",
-                   "pairs": args.pairs, "reads": n_reads, "form": "plain", "line_bytes": args.line_bytes,
-                   "parallelism": "1 GPU"},
-        "p50_ms": float(np.percentile(np.array(times) * 1e3, 50)),
-        "p99_ms": float(np.percentile(np.array(times) * 1e3, 99)),
-        "reads_per_s": n_reads / (ms_step / 1e3), "pairs_per_s": args.pairs / (ms_step / 1e3),
-        "aligned_fraction": aligned / n_reads, "paired_fraction": float((flags & bw.PF_PAIRED).astype(bool).mean()),
-        "research_reads": research, "kernel_ms": kernel_ms,
+                   "pairs": args.pairs, "reads": n_reads, "form": "batched (one persistent launch for both ends)",
+                   "line_bytes": args.line_bytes, "parallelism": "1 GPU"},
+        "p50_ms": batched["p50_ms"], "p99_ms": batched["p99_ms"],
+        "reads_per_s": n_reads / (ms_step / 1e3), "pairs_per_s": n / (ms_step / 1e3),
+        "aligned_fraction": aligned / n_reads, "paired_fraction": batched["paired_fraction"],
+        "plain": {k: v for k, v in plain.items()}, "batched": {k: v for k, v in batched.items()},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -127,6 +127,12 @@ typedef struct {
 
 enum { BWFM_MODE_ALL = 0, BWFM_MODE_BEST = 1 };
 
+/* Execution form; results are identical.  BATCHED: one persistent launch
+ * whose lanes pull reads from a shared counter, each lane taking the next
+ * read as soon as its current one is done.  PLAIN: one lane per read, one
+ * launch per batch. */
+enum { BWFM_FORM_BATCHED = 0, BWFM_FORM_PLAIN = 1 };
+
 typedef struct {
     int32_t max_diff;       /* budget when reads.max_diff is NULL, 0..15 */
     int32_t max_gapo;       /* most gap opens */
@@ -137,7 +143,8 @@ typedef struct {
     int32_t s_mm, s_gapo, s_gape; /* score of a mismatch, gap open, gap extension */
     int32_t mode;           /* BWFM_MODE_ALL or BWFM_MODE_BEST */
     int32_t max_best;       /* BEST: second tier reported only if c1 <= max_best */
-    uint32_t max_hits;      /* reads with more candidate hits report none */
+    uint32_t max_hits;      /* reads with more candidate hits report none, 1..65536 */
+    int32_t form;           /* BWFM_FORM_BATCHED or BWFM_FORM_PLAIN */
 } bwfm_aln_params;
 
 /*
@@ -207,8 +214,10 @@ int bwfm_align_batch_counted(const bwfm_index *idx, const bwfm_reads *reads, con
 /*
  * Reference positions of every hit of res (n_reads reads) whose width
  * l - k + 1 is at most max_occ: pos_offsets (device, n_hits + 1, n_hits =
- * hit_offsets[n_reads]) receives CSR offsets per hit, positions (device,
- * pos_capacity) the sorted 0-based leftmost forward coordinates of X.
+ * hit_offsets[n_reads] - hit_offsets[0]) receives CSR offsets per hit
+ * (hit hit_offsets[0] + j has entry j), positions (device, pos_capacity)
+ * the sorted 0-based leftmost forward coordinates of X.  res may be a
+ * window of a larger result (hit_offsets need not start at 0).
  * Synchronous.  E_CAPACITY when the positions do not fit: pos_offsets is
  * complete and pos_offsets[n_hits] holds the capacity needed.
  */
@@ -237,7 +246,8 @@ typedef struct {
 
 /*
  * Pair n_pairs reads: r1 holds end 1's alignment of the pairs, r2 end 2's
- * (NULL: single-end, each record gets end 1's primary only).  A proper pair
+ * (NULL: single-end, each record gets end 1's primary only).  Either may be
+ * a window of a larger result (for example both ends aligned in one call).  A proper pair
  * puts the ends on opposite strands with pf <= pr and lo <= pr + lr - pf <=
  * hi (pf: position of the + end; pr, lr: position and length of the - end);
  * the chosen pair minimises (score1 + score2, |insert - mu|, pf, strand1,

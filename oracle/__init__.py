@@ -33,7 +33,7 @@ PAIR_DTYPE = np.dtype([("pos1", "<u4"), ("pos2", "<u4"), ("insert", "<i4"), ("le
                        ("flags", "u1"), ("pad", "u1")])
 REC_DTYPE = np.dtype([("pos", "<u4"), ("len", "<u2"), ("score", "<u2"), ("strand", "u1"), ("n_mm", "u1"),
                       ("n_gapo", "u1"), ("n_gape", "u1")])
-COUNT_DTYPE = np.dtype([("expand", "<u8"), ("touch_s", "<u8"), ("touch_d", "<u8"), ("pad", "<u8")])
+COUNT_DTYPE = np.dtype([("expand", "<u8"), ("touch_s", "<u8"), ("touch_d", "<u8"), ("max_stack", "<u8")])
 
 ST_HIT, ST_OVERFLOW, ST_INVALID = 1, 2, 4
 PF_PAIRED, PF_MAPPED1, PF_MAPPED2, PF_REP1, PF_REP2 = 1, 2, 4, 8, 16

@@ -419,7 +419,9 @@ typedef struct {
     uint64_t expand;  /* states expanded (each issues rank queries at k and l + 1) */
     uint64_t touch_s; /* index lines touched by the search */
     uint64_t touch_d; /* index lines touched by the D-array scans */
-    uint64_t pad;
+    uint64_t max_stack; /* deepest pending-sibling stack of a depth-first search
+                           that keeps the first surviving child current and
+                           stacks the others (the GPU kernel's scheme) */
 } orc_count;
 
 typedef struct {
@@ -459,25 +461,40 @@ static void record(dfs_t *c, uint64_t k, uint64_t l, int len, int nmm, int ngo, 
 static inline int in_seed(const dfs_t *c, int i) { return i >= c->seed_lo && i < c->seed_hi; }
 static inline int in_seed_gap(const dfs_t *c, int b) { return b > c->seed_lo && b < c->seed_hi; }
 
-static void visit(dfs_t *c, int i, uint64_t k, uint64_t l, int nmm, int ngo, int nge, int gs, int sd, int len,
-                  int score);
+/* One child of an expanded state. */
+typedef struct {
+    int i;
+    uint64_t k, l;
+    int nmm, ngo, nge, gs, sd, len, score;
+} kid_t;
 
-/* Apply the static validity constraints to a child, then visit it. */
-static void child(dfs_t *c, int i, uint64_t k, uint64_t l, int nmm, int ngo, int nge, int gs, int sd, int len,
-                  int score)
+static void visit(dfs_t *c, int i, uint64_t k, uint64_t l, int nmm, int ngo, int nge, int gs, int sd, int len,
+                  int score, int sp);
+
+/* The static validity constraints of a child. */
+static int child_ok(const dfs_t *c, const kid_t *x)
 {
     const orc_params *p = c->p;
-    int diffs = nmm + ngo + nge;
-    if (diffs > c->maxd) return;
-    if (ngo > p->max_gapo) return;
-    if (p->max_gape >= 0 && nge > p->max_gape) return;
-    if (p->seed_len > 0 && sd > p->seed_diff) return;
-    if (p->use_d && i >= 0 && diffs + c->D[i] > c->maxd) return;
-    visit(c, i, k, l, nmm, ngo, nge, gs, sd, len, score);
+    int diffs = x->nmm + x->ngo + x->nge;
+    if (diffs > c->maxd) return 0;
+    if (x->ngo > p->max_gapo) return 0;
+    if (p->max_gape >= 0 && x->nge > p->max_gape) return 0;
+    if (p->seed_len > 0 && x->sd > p->seed_diff) return 0;
+    if (p->use_d && x->i >= 0 && diffs + c->D[x->i] > c->maxd) return 0;
+    return 1;
+}
+
+/* Would the BEST bound drop this child right now? */
+static int child_bound_ok(const dfs_t *c, const kid_t *x)
+{
+    const orc_params *p = c->p;
+    if (p->mode != MODE_BEST || c->best == INF_SCORE) return 1;
+    int lb = x->score + (p->use_d && x->i >= 0 ? c->minc * c->D[x->i] : 0);
+    return lb <= c->best + p->s_mm;
 }
 
 static void visit(dfs_t *c, int i, uint64_t k, uint64_t l, int nmm, int ngo, int nge, int gs, int sd, int len,
-                  int score)
+                  int score, int sp)
 {
     const orc_params *p = c->p;
     const fm_t *f = c->fm;
@@ -486,6 +503,7 @@ static void visit(dfs_t *c, int i, uint64_t k, uint64_t l, int nmm, int ngo, int
         int lb = score + (p->use_d && i >= 0 ? c->minc * c->D[i] : 0);
         if (lb > c->best + p->s_mm) return;
     }
+    if (sp > (int)c->cnt->max_stack) c->cnt->max_stack = (uint64_t)sp;
     if (i < 0) {
         record(c, k, l, len, nmm, ngo, nge, score);
         return;
@@ -498,19 +516,27 @@ static void visit(dfs_t *c, int i, uint64_t k, uint64_t l, int nmm, int ngo, int
         la[a] = f->C[a] + occ(f, a, l + 1) - 1;
     }
     int b = c->w[i];
+    /* children in the fixed order: match, mismatches by base, insertion,
+     * deletions by base */
+    kid_t kids[9];
+    int nk = 0;
+#define KID(I, K, L, NMM, NGO, NGE, GS, SD, LEN, SC)                                                     \
+    do {                                                                                              \
+        kid_t x_ = {(I), (K), (L), (NMM), (NGO), (NGE), (GS), (SD), (LEN), (SC)};                     \
+        if (child_ok(c, &x_)) kids[nk++] = x_;                                                        \
+    } while (0)
     /* match */
-    if (b < 4 && ka[b] <= la[b]) child(c, i - 1, ka[b], la[b], nmm, ngo, nge, GAP_NONE, sd, len + 1, score);
+    if (b < 4 && ka[b] <= la[b]) KID(i - 1, ka[b], la[b], nmm, ngo, nge, GAP_NONE, sd, len + 1, score);
     /* mismatches */
     for (int a = 0; a < 4; a++)
         if (a != b && ka[a] <= la[a])
-            child(c, i - 1, ka[a], la[a], nmm + 1, ngo, nge, GAP_NONE, sd + in_seed(c, i), len + 1,
-                  score + p->s_mm);
+            KID(i - 1, ka[a], la[a], nmm + 1, ngo, nge, GAP_NONE, sd + in_seed(c, i), len + 1, score + p->s_mm);
     /* insertion: read base w[i] has no reference base */
     if (i >= p->indel_end_skip && i < c->m - p->indel_end_skip) {
         if (gs == GAP_INS)
-            child(c, i - 1, k, l, nmm, ngo, nge + 1, GAP_INS, sd + in_seed(c, i), len, score + p->s_gape);
+            KID(i - 1, k, l, nmm, ngo, nge + 1, GAP_INS, sd + in_seed(c, i), len, score + p->s_gape);
         else
-            child(c, i - 1, k, l, nmm, ngo + 1, nge, GAP_INS, sd + in_seed(c, i), len, score + p->s_gapo);
+            KID(i - 1, k, l, nmm, ngo + 1, nge, GAP_INS, sd + in_seed(c, i), len, score + p->s_gapo);
     }
     /* deletion: reference base a between read bases i and i + 1 */
     int bd = i + 1;
@@ -518,12 +544,21 @@ static void visit(dfs_t *c, int i, uint64_t k, uint64_t l, int nmm, int ngo, int
         for (int a = 0; a < 4; a++) {
             if (ka[a] > la[a]) continue;
             if (gs == GAP_DEL)
-                child(c, i, ka[a], la[a], nmm, ngo, nge + 1, GAP_DEL, sd + in_seed_gap(c, bd), len + 1,
-                      score + p->s_gape);
+                KID(i, ka[a], la[a], nmm, ngo, nge + 1, GAP_DEL, sd + in_seed_gap(c, bd), len + 1, score + p->s_gape);
             else
-                child(c, i, ka[a], la[a], nmm, ngo + 1, nge, GAP_DEL, sd + in_seed_gap(c, bd), len + 1,
-                      score + p->s_gapo);
+                KID(i, ka[a], la[a], nmm, ngo + 1, nge, GAP_DEL, sd + in_seed_gap(c, bd), len + 1, score + p->s_gapo);
         }
+    }
+#undef KID
+    /* stack depth bookkeeping: the kernel keeps the first child that the
+     * bound lets through current and stacks the others above sp */
+    int v = 0;
+    int pos_[9];
+    for (int j = 0; j < nk; j++) pos_[j] = child_bound_ok(c, &kids[j]) ? v++ : -1;
+    for (int j = 0; j < nk; j++) {
+        int csp = pos_[j] < 0 ? sp : sp + v - 1 - pos_[j];
+        visit(c, kids[j].i, kids[j].k, kids[j].l, kids[j].nmm, kids[j].ngo, kids[j].nge, kids[j].gs, kids[j].sd,
+              kids[j].len, kids[j].score, csp);
     }
 }
 
@@ -597,7 +632,7 @@ static void align_one(const orc_index *ix, const uint8_t *W, int m, int maxd, co
         darray(other, ws, m, D, &cnt->touch_d, p->bases_per_line, maxd);
         c.D = D;
         /* the root: nothing consumed, interval of the empty string */
-        if (!p->use_d || D[m - 1] <= maxd) visit(&c, m - 1, 0, (uint64_t)ix->n, 0, 0, 0, GAP_NONE, 0, 0, 0);
+        if (!p->use_d || D[m - 1] <= maxd) visit(&c, m - 1, 0, (uint64_t)ix->n, 0, 0, 0, GAP_NONE, 0, 0, 0, 0);
     }
     if (c.oom) { free(c.cand); ro->status = ST_INVALID; return; }
     /* deduplicate by (strand, k, len), keeping the smallest (score, diffs, n_gapo, n_mm) */

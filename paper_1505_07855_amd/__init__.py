@@ -30,6 +30,7 @@ PAIR_DTYPE = np.dtype([("pos1", "<u4"), ("pos2", "<u4"), ("insert", "<i4"), ("le
 ST_HIT, ST_OVERFLOW, ST_INVALID, ST_RESEARCH = 1, 2, 4, 8
 PF_PAIRED, PF_MAPPED1, PF_MAPPED2, PF_REP1, PF_REP2 = 1, 2, 4, 8, 16
 MODE_ALL, MODE_BEST = 0, 1
+FORM_BATCHED, FORM_PLAIN = 0, 1
 E_CAPACITY = -5
 
 
@@ -59,7 +60,7 @@ class _Reads(ctypes.Structure):
 class _AlnParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("max_diff", "max_gapo", "max_gape", "seed_len", "seed_diff",
                                               "indel_end_skip", "s_mm", "s_gapo", "s_gape", "mode", "max_best")] + [
-        ("max_hits", ctypes.c_uint32)]
+        ("max_hits", ctypes.c_uint32), ("form", ctypes.c_int32)]
 
 
 class _AlnResult(ctypes.Structure):
@@ -139,7 +140,7 @@ def _stream_ptr(stream):
 
 def _dptr(t) -> int:
     assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
-    return t.data_ptr()
+    return t.data_ptr() if t.numel() else 0
 
 
 @dataclass
@@ -158,6 +159,7 @@ class Params:
     mode: int = MODE_BEST
     max_best: int = 30
     max_hits: int = 256
+    form: int = FORM_BATCHED
 
     def _c(self) -> _AlnParams:
         return _AlnParams(*[getattr(self, f.name) for f in fields(self)])
@@ -238,13 +240,20 @@ class AlignResult:
 
     @property
     def n_hits(self) -> int:
-        return int(self.hit_offsets[self.n_reads].item())
+        return int(self.hit_offsets[self.n_reads].item()) - int(self.hit_offsets[0].item())
+
+    def window(self, start: int, stop: int) -> "AlignResult":
+        """Reads [start, stop) of this result, sharing its buffers."""
+        return AlignResult(self.hit_offsets[start:stop + 1], self.hits, self.c1[start:stop], self.c2[start:stop],
+                           self.status[start:stop], stop - start,
+                           self.expand[start:stop] if self.expand is not None else None)
 
     def to_numpy(self):
-        """(hit_offsets uint64, hits HIT_DTYPE, c1 uint32, c2 uint32, status uint8)."""
-        n_hits = self.n_hits
+        """(hit_offsets uint64 rebased to 0, hits HIT_DTYPE, c1 uint32, c2 uint32, status uint8)."""
         ho = self.hit_offsets.cpu().numpy().view(np.uint64)
-        hits = self.hits[:n_hits].contiguous().cpu().numpy().view(HIT_DTYPE).reshape(-1)
+        h0, h1 = int(ho[0]), int(ho[-1])
+        ho = ho - np.uint64(h0)
+        hits = self.hits[h0:h1].contiguous().cpu().numpy().view(HIT_DTYPE).reshape(-1)
         return (ho, hits, self.c1.cpu().numpy().view(np.uint32), self.c2.cpu().numpy().view(np.uint32),
                 self.status.cpu().numpy())
 

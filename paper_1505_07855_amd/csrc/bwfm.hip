@@ -47,8 +47,8 @@ constexpr int GAP_NONE = 0, GAP_INS = 1, GAP_DEL = 2;
 constexpr uint32_t ST_RESEARCH = 8;  // status bit: needed the second pass
 constexpr int PH_FAST = 0, PH_BEST = 1, PH_COLLECT = 2;
 constexpr int INF_SCORE = 0x7fffffff;
-constexpr uint32_t FAST_STACK = 64;  // stack entries per lane, first pass
-constexpr uint32_t FAST_CAND = 32;   // hit slots per lane, first pass
+constexpr uint32_t PLAIN_STACK = 320;  // stack entries per lane, plain form first pass
+constexpr uint32_t FAST_CAND = 64;     // hit slots per lane, first pass
 constexpr int BLOCK = 256;
 
 struct Params {
@@ -265,6 +265,161 @@ __device__ __forceinline__ int pat(const uint8_t *W, int m, int strand, int i) {
     return (strand == 0 || b > 3) ? b : 3 - b;
 }
 
+// seed window of the strand pattern: the read's 5' end, consumed first
+struct Seed {
+    int sl, lo, hi;
+};
+__device__ __forceinline__ Seed seed_of(const Params &P, int m) {
+    Seed s;
+    s.sl = P.seed_len > 0 ? (P.seed_len < m ? P.seed_len : m) : 0;
+    s.lo = m - s.sl;
+    s.hi = s.sl ? m : 0;
+    return s;
+}
+
+__device__ __forceinline__ State root_state(const DevIndex &ix, int m) {
+    State s;
+    s.k = 0;
+    s.l = ix.n;
+    s.i = m - 1;
+    s.gs = GAP_NONE;
+    s.nmm = s.ngo = s.nge = s.sd = s.score = s.len = 0;
+    return s;
+}
+
+// Advance the search until the current state needs expanding: pop, drop
+// states the BEST bound excludes, record completed hits.  Returns 1 when cur
+// must be expanded (Di = D[cur.i]), 0 when the strand's search is over, or
+// -R_CAND when the hit buffer overflowed.
+__device__ int resolve(State &cur, bool &valid, int strand, const Params &P, LaneCtx &c, int phase, int &Di) {
+    for (;;) {
+        if (!valid) {
+            if (c.sp == 0) return 0;
+            c.sp--;
+            cur = unpack(c.stack[(size_t)c.sp * c.stride]);
+            valid = true;
+        }
+        Di = cur.i >= 0 ? c.D[(size_t)cur.i * c.stride] : 0;
+        if (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE && cur.score + P.minc * Di > c.best + P.s_mm) {
+            valid = false;
+            continue;
+        }
+        if (cur.i < 0) {
+            if (cur.score < c.best) c.best = cur.score;
+            int rc = record(c, P, make_hit(strand, cur.k, cur.l, cur.len, cur.score, cur.nmm, cur.ngo, cur.nge), phase);
+            if (rc) return -rc;
+            valid = false;
+            continue;
+        }
+        return 1;
+    }
+}
+
+// Children of an expanded state, from the rank counts at k (ok) and l + 1
+// (ol) on the search index: taken in reverse of the fixed order (match,
+// mismatches by base, insertion, deletions by base); the first surviving one
+// becomes cur, the others are pushed.  Returns R_OK or R_STACK.
+__device__ int expand_children(State &cur, bool &valid, const uint32_t (&ok)[4], const uint32_t (&ol)[4],
+                               const DevDir &sd_, int b, int m, int maxd, int Di, int Dn, const Seed &S,
+                               const Params &P, LaneCtx &c) {
+    const int diffs = cur.nmm + cur.ngo + cur.nge;
+    const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
+    State pend;
+    bool have = false;
+    int rc = R_OK;
+    auto offer = [&](const State &ch) {
+        if (have) {
+            if (c.sp == c.stack_cap) {
+                rc = R_STACK;
+            } else {
+                c.stack[(size_t)c.sp * c.stride] = pack(pend);
+                c.sp++;
+            }
+        }
+        pend = ch;
+        have = true;
+    };
+    // deletions: reference base a between read bases i and i + 1
+    {
+        const int bd = cur.i + 1;
+        const bool gap_ok = bd >= P.s1 && bd <= m - P.s1;
+        const bool ext = cur.gs == GAP_DEL;
+        const int nd = diffs + 1, ngo = cur.ngo + (ext ? 0 : 1), nge = cur.nge + (ext ? 1 : 0);
+        const int nsd = cur.sd + ((bd > S.lo && bd < S.hi) ? 1 : 0);
+        const int nsc = cur.score + (ext ? P.s_gape : P.s_gapo);
+        const bool ok_static = gap_ok && nd <= maxd && ngo <= P.max_gapo && (P.max_gape < 0 || nge <= P.max_gape) &&
+                               (S.sl == 0 || nsd <= P.seed_diff) && nd + Di <= maxd && nsc + P.minc * Di <= bound;
+        if (ok_static) {
+#pragma unroll
+            for (int a = 3; a >= 0; a--) {
+                if (ok[a] < ol[a]) {
+                    State ch = cur;
+                    ch.k = sd_.C[a] + ok[a];
+                    ch.l = sd_.C[a] + ol[a] - 1;
+                    ch.gs = GAP_DEL;
+                    ch.ngo = ngo;
+                    ch.nge = nge;
+                    ch.sd = nsd;
+                    ch.score = nsc;
+                    ch.len = cur.len + 1;
+                    offer(ch);
+                }
+            }
+        }
+    }
+    // insertion: read base w[i] without a reference base
+    if (cur.i >= P.ies && cur.i < m - P.ies) {
+        const bool ext = cur.gs == GAP_INS;
+        const int nd = diffs + 1, ngo = cur.ngo + (ext ? 0 : 1), nge = cur.nge + (ext ? 1 : 0);
+        const int nsd = cur.sd + ((cur.i >= S.lo && cur.i < S.hi) ? 1 : 0);
+        const int nsc = cur.score + (ext ? P.s_gape : P.s_gapo);
+        if (nd <= maxd && ngo <= P.max_gapo && (P.max_gape < 0 || nge <= P.max_gape) &&
+            (S.sl == 0 || nsd <= P.seed_diff) && nd + Dn <= maxd && nsc + P.minc * Dn <= bound) {
+            State ch = cur;
+            ch.i = cur.i - 1;
+            ch.gs = GAP_INS;
+            ch.ngo = ngo;
+            ch.nge = nge;
+            ch.sd = nsd;
+            ch.score = nsc;
+            offer(ch);
+        }
+    }
+    // mismatches, then the match (offered last, so it becomes current)
+    {
+        const int nsd = cur.sd + ((cur.i >= S.lo && cur.i < S.hi) ? 1 : 0);
+        const int nsc = cur.score + P.s_mm;
+        const bool mm_ok = diffs + 1 <= maxd && (S.sl == 0 || nsd <= P.seed_diff) && diffs + 1 + Dn <= maxd &&
+                           nsc + P.minc * Dn <= bound;
+#pragma unroll
+        for (int a = 3; a >= 0; a--) {
+            if (a == b || !(ok[a] < ol[a]) || !mm_ok) continue;
+            State ch = cur;
+            ch.k = sd_.C[a] + ok[a];
+            ch.l = sd_.C[a] + ol[a] - 1;
+            ch.i = cur.i - 1;
+            ch.gs = GAP_NONE;
+            ch.nmm = cur.nmm + 1;
+            ch.sd = nsd;
+            ch.score = nsc;
+            ch.len = cur.len + 1;
+            offer(ch);
+        }
+        if (b < 4 && sel4(ok, b) < sel4(ol, b) && diffs + Dn <= maxd && cur.score + P.minc * Dn <= bound) {
+            State ch = cur;
+            ch.k = sel4(sd_.C, b) + sel4(ok, b);
+            ch.l = sel4(sd_.C, b) + sel4(ol, b) - 1;
+            ch.i = cur.i - 1;
+            ch.gs = GAP_NONE;
+            ch.len = cur.len + 1;
+            offer(ch);
+        }
+    }
+    if (have) cur = pend;
+    valid = have;
+    return rc;
+}
+
 // D-array of one strand on the other index.  Returns false when the bound
 // already exceeds the budget at the root (the strand cannot match).
 template <int LW>
@@ -292,145 +447,28 @@ __device__ bool build_d(const DevIndex &ix, const DevDir &od, const uint8_t *W, 
     return true;
 }
 
-// Depth-first search of one strand.  Returns R_OK, R_STACK or R_CAND.
+// Depth-first search of one strand, one lane, start to end.
 template <int LW>
 __device__ int search_strand(const DevIndex &ix, const DevDir &sd_, const uint8_t *W, int m, int strand, int maxd,
                              const Params &P, LaneCtx &c, int phase) {
-    const int sl = P.seed_len > 0 ? (P.seed_len < m ? P.seed_len : m) : 0;
-    const int seed_lo = m - sl, seed_hi = sl ? m : 0;
-    State cur;
-    cur.k = 0;
-    cur.l = ix.n;
-    cur.i = m - 1;
-    cur.gs = GAP_NONE;
-    cur.nmm = cur.ngo = cur.nge = cur.sd = cur.score = cur.len = 0;
+    const Seed S = seed_of(P, m);
+    State cur = root_state(ix, m);
     bool valid = true;
     c.sp = 0;
     for (;;) {
-        if (!valid) {
-            if (c.sp == 0) break;
-            c.sp--;
-            cur = unpack(c.stack[(size_t)c.sp * c.stride]);
-            valid = true;
-        }
-        const int Di = cur.i >= 0 ? c.D[(size_t)cur.i * c.stride] : 0;
-        if (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE && cur.score + P.minc * Di > c.best + P.s_mm) {
-            valid = false;
-            continue;
-        }
-        if (cur.i < 0) {
-            if (cur.score < c.best) c.best = cur.score;
-            int rc = record(c, P, make_hit(strand, cur.k, cur.l, cur.len, cur.score, cur.nmm, cur.ngo, cur.nge), phase);
-            if (rc) return rc;
-            valid = false;
-            continue;
-        }
-        // expand: one rank query at k and one at l + 1 give all children
+        int Di;
+        int rr = resolve(cur, valid, strand, P, c, phase, Di);
+        if (rr == 0) return R_OK;
+        if (rr < 0) return -rr;
         c.expand++;
         uint32_t ok[4], ol[4];
         occ4<LW>(ix, sd_, cur.k, ok);
         occ4<LW>(ix, sd_, cur.l + 1, ol);
         const int b = pat(W, m, strand, cur.i);
         const int Dn = cur.i >= 1 ? c.D[(size_t)(cur.i - 1) * c.stride] : 0;
-        const int diffs = cur.nmm + cur.ngo + cur.nge;
-        const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
-        State pend;
-        bool have = false;
-        int rc = R_OK;
-        // children in reverse canonical order; the last one kept becomes current
-        auto offer = [&](const State &ch) {
-            if (have) {
-                if (c.sp == c.stack_cap) {
-                    rc = R_STACK;
-                } else {
-                    c.stack[(size_t)c.sp * c.stride] = pack(pend);
-                    c.sp++;
-                }
-            }
-            pend = ch;
-            have = true;
-        };
-        // deletions: reference base a between read bases i and i + 1
-        {
-            const int bd = cur.i + 1;
-            const bool gap_ok = bd >= P.s1 && bd <= m - P.s1;
-            const bool ext = cur.gs == GAP_DEL;
-            const int nd = diffs + 1, ngo = cur.ngo + (ext ? 0 : 1), nge = cur.nge + (ext ? 1 : 0);
-            const int nsd = cur.sd + ((bd > seed_lo && bd < seed_hi) ? 1 : 0);
-            const int nsc = cur.score + (ext ? P.s_gape : P.s_gapo);
-            const bool ok_static = gap_ok && nd <= maxd && ngo <= P.max_gapo && (P.max_gape < 0 || nge <= P.max_gape) &&
-                                   (sl == 0 || nsd <= P.seed_diff) && nd + Di <= maxd && nsc + P.minc * Di <= bound;
-            if (ok_static) {
-#pragma unroll
-                for (int a = 3; a >= 0; a--) {
-                    if (ok[a] < ol[a]) {
-                        State ch = cur;
-                        ch.k = sd_.C[a] + ok[a];
-                        ch.l = sd_.C[a] + ol[a] - 1;
-                        ch.gs = GAP_DEL;
-                        ch.ngo = ngo;
-                        ch.nge = nge;
-                        ch.sd = nsd;
-                        ch.score = nsc;
-                        ch.len = cur.len + 1;
-                        offer(ch);
-                    }
-                }
-            }
-        }
-        // insertion: read base w[i] without a reference base
-        if (cur.i >= P.ies && cur.i < m - P.ies) {
-            const bool ext = cur.gs == GAP_INS;
-            const int nd = diffs + 1, ngo = cur.ngo + (ext ? 0 : 1), nge = cur.nge + (ext ? 1 : 0);
-            const int nsd = cur.sd + ((cur.i >= seed_lo && cur.i < seed_hi) ? 1 : 0);
-            const int nsc = cur.score + (ext ? P.s_gape : P.s_gapo);
-            if (nd <= maxd && ngo <= P.max_gapo && (P.max_gape < 0 || nge <= P.max_gape) &&
-                (sl == 0 || nsd <= P.seed_diff) && nd + Dn <= maxd && nsc + P.minc * Dn <= bound) {
-                State ch = cur;
-                ch.i = cur.i - 1;
-                ch.gs = GAP_INS;
-                ch.ngo = ngo;
-                ch.nge = nge;
-                ch.sd = nsd;
-                ch.score = nsc;
-                offer(ch);
-            }
-        }
-        // mismatches, then the match (offered last, so it becomes current)
-        {
-            const int nsd = cur.sd + ((cur.i >= seed_lo && cur.i < seed_hi) ? 1 : 0);
-            const int nsc = cur.score + P.s_mm;
-            const bool mm_ok = diffs + 1 <= maxd && (sl == 0 || nsd <= P.seed_diff) && diffs + 1 + Dn <= maxd &&
-                               nsc + P.minc * Dn <= bound;
-#pragma unroll
-            for (int a = 3; a >= 0; a--) {
-                if (a == b || !(ok[a] < ol[a]) || !mm_ok) continue;
-                State ch = cur;
-                ch.k = sd_.C[a] + ok[a];
-                ch.l = sd_.C[a] + ol[a] - 1;
-                ch.i = cur.i - 1;
-                ch.gs = GAP_NONE;
-                ch.nmm = cur.nmm + 1;
-                ch.sd = nsd;
-                ch.score = nsc;
-                ch.len = cur.len + 1;
-                offer(ch);
-            }
-            if (b < 4 && sel4(ok, b) < sel4(ol, b) && diffs + Dn <= maxd && cur.score + P.minc * Dn <= bound) {
-                State ch = cur;
-                ch.k = sel4(sd_.C, b) + sel4(ok, b);
-                ch.l = sel4(sd_.C, b) + sel4(ol, b) - 1;
-                ch.i = cur.i - 1;
-                ch.gs = GAP_NONE;
-                ch.len = cur.len + 1;
-                offer(ch);
-            }
-        }
+        int rc = expand_children(cur, valid, ok, ol, sd_, b, m, maxd, Di, Dn, S, P, c);
         if (rc) return rc;
-        if (have) cur = pend;
-        valid = have;
     }
-    return R_OK;
 }
 
 // Canonicalise the lane's hit buffer: tiers, c1/c2, the max_hits rule, the
@@ -493,30 +531,77 @@ __device__ int align_read(const DevIndex &ix, const uint8_t *W, int m, int maxd,
     return R_OK;
 }
 
-// ------------------------------------------------------------------ kernels
+// Per-read outputs shared by the kernels.
+struct ReadOut {
+    uint32_t *n_rep, *c1, *c2;
+    uint8_t *status;
+    uint32_t *slow_list, *n_slow;
+    uint4 *stage;                    // reported hits, a block per read
+    unsigned long long *stage_used;  // staging slots taken
+    uint64_t stage_cap;
+    uint64_t *stage_off;             // per read: first staging slot
+    uint32_t *expand;                // per read work counter, or NULL
+};
 
-// First pass: one lane per read.
-template <int LW>
-__global__ __launch_bounds__(BLOCK) void k_align_fast(DevIndex ix, ReadsView rd, Params P, LaneBufs B,
-                                                      uint32_t *n_rep, uint32_t *c1, uint32_t *c2, uint8_t *status,
-                                                      uint32_t *slow_list, uint32_t *n_slow, uint32_t *expand) {
-    uint32_t r = blockIdx.x * BLOCK + threadIdx.x;
-    if (r >= rd.n) return;
-    uint64_t o0 = rd.off[r], o1 = rd.off[r + 1];
-    int m = (int)(o1 - o0);
-    int maxd = rd.maxd ? rd.maxd[r] : P.max_diff;
-    n_rep[r] = 0;
-    c1[r] = c2[r] = 0;
-    if (o1 < o0 || (uint64_t)m > rd.max_len || m > BWFM_MAX_READ || maxd > BWFM_MAX_DIFF) {
-        status[r] = BWFM_ST_INVALID;
-        if (expand) expand[r] = 0;
-        return;
+__device__ __forceinline__ void send_to_second_pass(const ReadOut &O, uint32_t r) {
+    O.status[r] = ST_RESEARCH;
+    O.n_rep[r] = 0;
+    O.slow_list[atomicAdd(O.n_slow, 1u)] = r;
+}
+
+// Canonicalise a finished read and move its reported hits to the staging
+// arena; a read whose hits do not fit goes to the second pass.
+__device__ void publish(LaneCtx &c, const Params &P, const ReadOut &O, uint32_t r) {
+    uint8_t st;
+    uint32_t a, b;
+    uint32_t nr = finish(c, P, st, a, b);
+    if (O.expand) O.expand[r] = c.expand;
+    if (nr) {
+        unsigned long long off = atomicAdd(O.stage_used, (unsigned long long)nr);
+        if (off + nr > O.stage_cap) {
+            send_to_second_pass(O, r);
+            return;
+        }
+        for (uint32_t j = 0; j < nr; j++) O.stage[off + j] = c.cand[(size_t)j * c.stride];
+        O.stage_off[r] = off;
+    }
+    O.n_rep[r] = nr;
+    O.status[r] = st;
+    O.c1[r] = a;
+    O.c2[r] = b;
+}
+
+// validity of read r: 0 = search it, 1 = done (empty or invalid, outputs written)
+__device__ __forceinline__ int check_read(const ReadsView &rd, const Params &P, const ReadOut &O, uint32_t r, int &m,
+                                          int &maxd, uint64_t &o0) {
+    o0 = rd.off[r];
+    uint64_t o1 = rd.off[r + 1];
+    m = (int)(o1 - o0);
+    maxd = rd.maxd ? rd.maxd[r] : P.max_diff;
+    O.n_rep[r] = 0;
+    O.c1[r] = O.c2[r] = 0;
+    if (O.expand) O.expand[r] = 0;
+    if (o1 < o0 || o1 - o0 > rd.max_len || m > BWFM_MAX_READ || maxd > BWFM_MAX_DIFF) {
+        O.status[r] = BWFM_ST_INVALID;
+        return 1;
     }
     if (m == 0) {
-        status[r] = 0;
-        if (expand) expand[r] = 0;
-        return;
+        O.status[r] = 0;
+        return 1;
     }
+    return 0;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// Plain form: one lane per read, one launch per batch.
+template <int LW>
+__global__ __launch_bounds__(BLOCK) void k_align_plain(DevIndex ix, ReadsView rd, Params P, LaneBufs B, ReadOut O) {
+    uint32_t r = blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= rd.n) return;
+    int m, maxd;
+    uint64_t o0;
+    if (check_read(rd, P, O, r, m, maxd, o0)) return;
     LaneCtx c;
     c.stack = B.stack + r;
     c.cand = B.cand + r;
@@ -527,22 +612,194 @@ __global__ __launch_bounds__(BLOCK) void k_align_fast(DevIndex ix, ReadsView rd,
     c.best = INF_SCORE;
     c.expand = 0;
     int rc = align_read<LW>(ix, rd.bases + o0, m, maxd, P, c, PH_FAST);
-    if (expand) expand[r] = c.expand;
     if (rc) {
-        status[r] = ST_RESEARCH;
-        slow_list[atomicAdd(n_slow, 1u)] = r;
+        if (O.expand) O.expand[r] = c.expand;
+        send_to_second_pass(O, r);
         return;
     }
-    uint8_t st;
-    uint32_t a, b;
-    n_rep[r] = finish(c, P, st, a, b);
-    status[r] = st;
-    c1[r] = a;
-    c2[r] = b;
+    publish(c, P, O, r);
+}
+
+enum { PZ_IDLE = 0, PZ_DSCAN = 1, PZ_SEARCH = 2 };
+enum { ACT_NONE = 0, ACT_DSTEP = 1, ACT_EXPAND = 2 };
+
+// Batched form: a persistent grid whose lanes pull reads from a shared
+// counter.  Each loop iteration performs one rank-query pair per busy lane --
+// a D-array step or a search expansion -- so lanes at different stages of
+// different reads still share the expensive part, and a lane whose read is
+// done takes the next one at once (wave-wide ballot, one atomic per wave).
+template <int LW>
+__global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsView rd, Params P, LaneBufs B, ReadOut O,
+                                                            uint32_t *next_read) {
+    const uint32_t gl = blockIdx.x * BLOCK + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    LaneCtx c;
+    c.stack = B.stack + gl;
+    c.cand = B.cand + gl;
+    c.D = B.D + gl;
+    c.stride = B.stride;
+    c.stack_cap = B.stack_cap;
+    c.cand_cap = B.cand_cap;
+    c.sp = 0;
+    c.ncand = 0;
+    c.best = INF_SCORE;
+    c.expand = 0;
+
+    int phase = PZ_IDLE;
+    bool exhausted = false;
+    uint32_t r = 0;
+    int m = 0, maxd = 0, strand = 0;
+    const uint8_t *W = nullptr;
+    // D scan state
+    int di = 0, dz = 0;
+    uint32_t dk = 0, dl = 0;
+    // search state
+    State cur;
+    bool valid = false;
+    Seed S{0, 0, 0};
+
+    for (;;) {
+        // refill idle lanes, one atomic per wave
+        const bool want = phase == PZ_IDLE && !exhausted;
+        const unsigned long long wm = __ballot(want);
+        if (wm) {
+            const int leader = __ffsll(wm) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(next_read, (uint32_t)__popcll(wm));
+            base = __shfl(base, leader);
+            if (want) {
+                const uint32_t rr = base + (uint32_t)__popcll(wm & ((1ULL << lane) - 1));
+                if (rr >= rd.n) {
+                    exhausted = true;
+                } else {
+                    r = rr;
+                    uint64_t o0;
+                    if (!check_read(rd, P, O, r, m, maxd, o0)) {
+                        W = rd.bases + o0;
+                        c.ncand = 0;
+                        c.best = INF_SCORE;
+                        c.expand = 0;
+                        strand = 0;
+                        phase = PZ_DSCAN;
+                        di = 0;
+                        dz = 0;
+                        dk = 0;
+                        dl = ix.n;
+                        S = seed_of(P, m);
+                    }
+                }
+            }
+        }
+        if (__ballot(phase != PZ_IDLE) == 0) {
+            if (__ballot(!exhausted) == 0) break;
+            continue;
+        }
+
+        // decide this lane's action and rank queries; a lane that changes
+        // phase here acts in its new phase from the next iteration on
+        int act = ACT_NONE;
+        bool query = false;
+        int qdir = 0;  // index queried: 0 = T, 1 = reverse(T)
+        uint32_t q1 = 0, q2 = 0;
+        int Di = 0, da = 4;
+        if (phase == PZ_DSCAN) {
+            act = ACT_DSTEP;
+            da = pat(W, m, strand, di);
+            if (da < 4) {
+                query = true;
+                qdir = strand == 0 ? 0 : 1;
+                q1 = dk;
+                q2 = dl + 1;
+            }
+        } else if (phase == PZ_SEARCH) {
+            int rr = resolve(cur, valid, strand, P, c, PH_FAST, Di);
+            if (rr < 0) {
+                send_to_second_pass(O, r);
+                if (O.expand) O.expand[r] = c.expand;
+                phase = PZ_IDLE;
+            } else if (rr == 0) {
+                if (strand == 0) {
+                    strand = 1;
+                    phase = PZ_DSCAN;
+                    di = 0;
+                    dz = 0;
+                    dk = 0;
+                    dl = ix.n;
+                } else {
+                    publish(c, P, O, r);
+                    phase = PZ_IDLE;
+                }
+            } else {
+                act = ACT_EXPAND;
+                query = true;
+                qdir = strand == 0 ? 1 : 0;
+                q1 = cur.k;
+                q2 = cur.l + 1;
+            }
+        }
+
+        // the shared part: rank counts at q1 and q2 on one index
+        uint32_t ok[4] = {0, 0, 0, 0}, ol[4] = {0, 0, 0, 0};
+        const DevDir qd = pick_dir(ix, qdir);
+        if (query) {
+            occ4<LW>(ix, qd, q1, ok);
+            occ4<LW>(ix, qd, q2, ol);
+        }
+
+        // consume
+        if (act == ACT_DSTEP) {
+            bool empty = true;
+            if (da < 4) {
+                const uint32_t a1 = sel4(ok, da), a2 = sel4(ol, da);
+                empty = a1 >= a2;
+                dk = sel4(qd.C, da) + a1;
+                dl = sel4(qd.C, da) + a2 - 1;
+            }
+            bool skip = false;
+            if (empty) {
+                dz++;
+                dk = 0;
+                dl = ix.n;
+                skip = dz > maxd;
+            }
+            if (!skip) {
+                c.D[(size_t)di * c.stride] = (uint8_t)dz;
+                di++;
+            }
+            if (skip || di == m) {
+                if (!skip) {
+                    phase = PZ_SEARCH;
+                    cur = root_state(ix, m);
+                    valid = true;
+                    c.sp = 0;
+                } else if (strand == 0) {
+                    strand = 1;
+                    di = 0;
+                    dz = 0;
+                    dk = 0;
+                    dl = ix.n;
+                } else {
+                    publish(c, P, O, r);
+                    phase = PZ_IDLE;
+                }
+            }
+        } else if (act == ACT_EXPAND) {
+            c.expand++;
+            const int b = pat(W, m, strand, cur.i);
+            const int Dn = cur.i >= 1 ? c.D[(size_t)(cur.i - 1) * c.stride] : 0;
+            int rc = expand_children(cur, valid, ok, ol, qd, b, m, maxd, Di, Dn, S, P, c);
+            if (rc) {
+                send_to_second_pass(O, r);
+                if (O.expand) O.expand[r] = c.expand;
+                phase = PZ_IDLE;
+            }
+        }
+    }
 }
 
 // Second pass for the reads listed in slow_list: worst-case stack, first the
-// best score S*, then the hits with the bound fixed at S* + s_mm.
+// best score S*, then the hits with the bound fixed at S* + s_mm.  Results
+// stay in this pass's lane buffers.
 template <int LW>
 __global__ __launch_bounds__(BLOCK) void k_align_slow(DevIndex ix, ReadsView rd, Params P, LaneBufs B,
                                                       const uint32_t *slow_list, uint32_t n_slow, uint32_t *n_rep,
@@ -581,28 +838,28 @@ __global__ __launch_bounds__(BLOCK) void k_align_slow(DevIndex ix, ReadsView rd,
     if (expand) expand[r] += c.expand;
 }
 
-// Copy each read's reported hits to the CSR output.
-__global__ void k_compact(uint32_t n, const uint64_t *hoff, const uint4 *fast, uint32_t fast_stride, const uint4 *slow,
-                          uint32_t slow_stride, const uint32_t *slow_list, uint32_t n_slow, const uint8_t *status,
-                          uint4 *hits) {
+// Copy each read's reported hits to the CSR output: from the staging arena,
+// or from the second pass's lane buffers for the reads it handled.
+__global__ void k_compact(uint32_t n, const uint64_t *hoff, const uint4 *stage, const uint64_t *stage_off,
+                          const uint4 *slow, uint32_t slow_stride, const uint32_t *slow_list, uint32_t n_slow,
+                          const uint8_t *status, uint4 *hits) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     uint64_t o = hoff[r], e = hoff[r + 1];
     if (e == o) return;
-    const uint4 *src = fast + r;
-    uint32_t stride = fast_stride;
     if (status[r] & ST_RESEARCH) {
-        // position of r in the slow list (the list is short; sorted on the host)
+        // position of r in the slow list (sorted on the host)
         uint32_t lo = 0, hi = n_slow;
         while (lo < hi) {
             uint32_t mid = (lo + hi) / 2;
             if (slow_list[mid] < r) lo = mid + 1;
             else hi = mid;
         }
-        src = slow + lo;
-        stride = slow_stride;
+        for (uint64_t j = 0; j < e - o; j++) hits[o + j] = slow[(size_t)j * slow_stride + lo];
+    } else {
+        const uint4 *src = stage + stage_off[r];
+        for (uint64_t j = 0; j < e - o; j++) hits[o + j] = src[j];
     }
-    for (uint64_t j = 0; j < e - o; j++) hits[o + j] = src[(size_t)j * stride];
 }
 
 // ------------------------------------------------------------------ exclusive scan (u32 counts -> u64 offsets)
@@ -764,8 +1021,9 @@ __global__ __launch_bounds__(256) void k_sort_big(const uint64_t *poff, uint32_t
 struct EndView {
     const uint64_t *hoff;
     const uint4 *hits;
-    const uint64_t *poff;  // per hit (global hit index)
+    const uint64_t *poff;  // per hit, indexed by (hit index - hbase)
     const uint32_t *pos;
+    uint64_t hbase;        // hoff[0]
 };
 
 __device__ __forceinline__ uint64_t lower_bound(const uint32_t *a, uint64_t n, uint64_t v) {
@@ -783,7 +1041,7 @@ __device__ bool se_primary(const EndView &e, uint32_t q, uint32_t &pos, uint4 &h
     bool found = false;
     rep = false;
     for (uint64_t i = e.hoff[q]; i < e.hoff[q + 1]; i++) {
-        uint64_t o = e.poff[i], w = e.poff[i + 1] - o;
+        uint64_t o = e.poff[i - e.hbase], w = e.poff[i - e.hbase + 1] - o;
         if (w == 0) { rep = true; continue; }
         uint4 h = e.hits[i];
         uint32_t p = e.pos[o];  // sorted: the first is the smallest
@@ -811,13 +1069,13 @@ __global__ void k_pair(uint32_t n_pairs, EndView e1, EndView e2, int paired, int
     if (paired) {
         for (uint64_t i = e1.hoff[q]; i < e1.hoff[q + 1]; i++) {
             uint4 h1 = e1.hits[i];
-            const uint32_t *P1 = e1.pos + e1.poff[i];
-            uint64_t n1 = e1.poff[i + 1] - e1.poff[i];
+            const uint32_t *P1 = e1.pos + e1.poff[i - e1.hbase];
+            uint64_t n1 = e1.poff[i - e1.hbase + 1] - e1.poff[i - e1.hbase];
             for (uint64_t j = e2.hoff[q]; j < e2.hoff[q + 1]; j++) {
                 uint4 h2 = e2.hits[j];
                 if (h_strand(h1) == h_strand(h2)) continue;
-                const uint32_t *P2 = e2.pos + e2.poff[j];
-                uint64_t n2 = e2.poff[j + 1] - e2.poff[j];
+                const uint32_t *P2 = e2.pos + e2.poff[j - e2.hbase];
+                uint64_t n2 = e2.poff[j - e2.hbase + 1] - e2.poff[j - e2.hbase];
                 int64_t s = (int64_t)h_score(h1) + h_score(h2);
                 for (uint64_t x = 0; x < n1; x++) {
                     int64_t p1 = P1[x];
@@ -998,6 +1256,7 @@ Params make_params(const bwfm_aln_params &p) {
     P.max_best = p.max_best;
     P.max_hits = p.max_hits;
     P.minc = std::min(p.s_mm, std::min(p.s_gapo, p.s_gape));
+    (void)p.form;
     P.s1 = std::max(p.indel_end_skip, 1);
     return P;
 }
@@ -1050,6 +1309,22 @@ int scan_counts(const uint32_t *cnt, uint64_t n, uint64_t *out, uint64_t *part, 
 
 size_t scan_part_elems(uint64_t n) { return (n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1; }
 
+// Lanes of a persistent grid that fit on the device at once.
+template <int LW>
+uint32_t persistent_lanes() {
+    static uint32_t cached = 0;
+    if (cached) return cached;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_align_persistent<LW>, BLOCK, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    cached = (uint32_t)cus * (uint32_t)per_cu * BLOCK;
+    return cached;
+}
+
 template <int LW>
 int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, bwfm_aln_result *res,
                hipStream_t st, uint32_t *expand) {
@@ -1058,31 +1333,43 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     const Params P = make_params(*p);
     ReadsView rv{rd->bases, rd->offsets, rd->max_diff, rd->n_reads, rd->max_len};
     const uint32_t mlen = std::max<uint32_t>(rd->max_len, 1);
-    // workspace: fast buffers, per-read counts, slow list, scan parts
-    size_t need = 0;
-    {
-        need += (size_t)n * FAST_STACK * 16 + (size_t)n * FAST_CAND * 16 + (size_t)n * mlen + 256 * 8;
-        need += (size_t)n * 4 * 2 + 64 + scan_part_elems(n) * 8 + 4096;
-    }
+    const uint32_t worst_stack = 8 * (mlen + BWFM_MAX_DIFF) + 1;  // never overflows
+    const bool plain = p->form == BWFM_FORM_PLAIN;
+    const uint32_t lanes = plain ? std::max<uint32_t>(n, 1) : std::min<uint32_t>(persistent_lanes<LW>(),
+                                                                                 ((std::max<uint32_t>(n, 1) + 255) / 256) * 256);
+    const uint32_t stack_cap = plain ? std::min<uint32_t>(worst_stack, PLAIN_STACK) : worst_stack;
+    const uint64_t stage_cap = std::max<uint64_t>(4ull * n, 4096);
+    size_t need = (size_t)lanes * stack_cap * 16 + (size_t)lanes * FAST_CAND * 16 + (size_t)lanes * mlen;
+    need += (size_t)n * 4 * 2 + (size_t)n * 8 + stage_cap * 16 + scan_part_elems(n) * 8 + 16 * 256;
     void *w;
     int rc = ws_reserve(ix, need, &w);
     if (rc) return rc;
     Carver cv{(char *)w};
-    uint4 *fstack = cv.take<uint4>((size_t)n * FAST_STACK);
-    uint4 *fcand = cv.take<uint4>((size_t)n * FAST_CAND);
-    uint8_t *fD = cv.take<uint8_t>((size_t)n * mlen);
+    uint4 *lstack = cv.take<uint4>((size_t)lanes * stack_cap);
+    uint4 *lcand = cv.take<uint4>((size_t)lanes * FAST_CAND);
+    uint8_t *lD = cv.take<uint8_t>((size_t)lanes * mlen);
     uint32_t *n_rep = cv.take<uint32_t>(n);
     uint32_t *slow_list = cv.take<uint32_t>(n);
-    uint32_t *n_slow = cv.take<uint32_t>(1);
+    uint64_t *stage_off = cv.take<uint64_t>(n);
+    uint4 *stage = cv.take<uint4>(stage_cap);
     uint64_t *part = cv.take<uint64_t>(scan_part_elems(n));
-    HIPCHK(hipMemsetAsync(n_slow, 0, 4, st));
-    LaneBufs fb{fstack, fcand, fD, n, FAST_STACK, FAST_CAND};
+    uint32_t *ctl = cv.take<uint32_t>(16);  // n_slow, next_read, stage_used (64-bit)
+    uint32_t *n_slow = ctl, *next_read = ctl + 1;
+    unsigned long long *stage_used = reinterpret_cast<unsigned long long *>(ctl + 2);
+    HIPCHK(hipMemsetAsync(ctl, 0, 64, st));
+    LaneBufs lb{lstack, lcand, lD, lanes, stack_cap, FAST_CAND};
+    ReadOut O{n_rep, res->c1, res->c2, res->status, slow_list, n_slow, stage, stage_used, stage_cap, stage_off, expand};
     CallTimer tm(st);
     if (n) {
-        int t = tm.begin("align_fast");
-        k_align_fast<LW><<<blocks(n, BLOCK), BLOCK, 0, st>>>(D, rv, P, fb, n_rep, res->c1, res->c2, res->status,
-                                                             slow_list, n_slow, expand);
-        tm.end(t);
+        if (plain) {
+            int t = tm.begin("align_plain");
+            k_align_plain<LW><<<blocks(n, BLOCK), BLOCK, 0, st>>>(D, rv, P, lb, O);
+            tm.end(t);
+        } else {
+            int t = tm.begin("align_persistent");
+            k_align_persistent<LW><<<lanes / BLOCK, BLOCK, 0, st>>>(D, rv, P, lb, O, next_read);
+            tm.end(t);
+        }
         HIPCHK(hipGetLastError());
     }
     uint32_t ns = 0;
@@ -1097,16 +1384,14 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
         HIPCHK(hipMemcpy(hl.data(), slow_list, 4ull * ns, hipMemcpyDeviceToHost));
         std::sort(hl.begin(), hl.end());
         HIPCHK(hipMemcpy(slow_list, hl.data(), 4ull * ns, hipMemcpyHostToDevice));
-        const uint32_t maxd_all = BWFM_MAX_DIFF;
-        const uint32_t stack_cap = 8 * (mlen + maxd_all) + 1;
         scap = P.max_hits + 1;
-        size_t sbytes = (size_t)ns * stack_cap * 16 + (size_t)ns * scap * 16 + (size_t)ns * mlen + 1024;
+        size_t sbytes = (size_t)ns * worst_stack * 16 + (size_t)ns * scap * 16 + (size_t)ns * mlen + 1024;
         if (hipMalloc(&slow_mem, sbytes) != hipSuccess) return fail(BWFM_E_NOMEM, "second-pass buffers");
         Carver sc{(char *)slow_mem};
-        uint4 *sstack = sc.take<uint4>((size_t)ns * stack_cap);
+        uint4 *sstack = sc.take<uint4>((size_t)ns * worst_stack);
         scand = sc.take<uint4>((size_t)ns * scap);
         uint8_t *sD = sc.take<uint8_t>((size_t)ns * mlen);
-        LaneBufs sb{sstack, scand, sD, ns, stack_cap, scap};
+        LaneBufs sb{sstack, scand, sD, ns, worst_stack, scap};
         int t = tm.begin("align_slow");
         k_align_slow<LW><<<blocks(ns, BLOCK), BLOCK, 0, st>>>(D, rv, P, sb, slow_list, ns, n_rep, res->c1, res->c2,
                                                               res->status, expand);
@@ -1132,8 +1417,8 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     }
     if (n) {
         int t = tm.begin("compact");
-        k_compact<<<blocks(n, 256), 256, 0, st>>>(n, res->hit_offsets, fcand, n, scand, ns, slow_list, ns, res->status,
-                                                  reinterpret_cast<uint4 *>(res->hits));
+        k_compact<<<blocks(n, 256), 256, 0, st>>>(n, res->hit_offsets, stage, stage_off, scand, ns, slow_list, ns,
+                                                  res->status, reinterpret_cast<uint4 *>(res->hits));
         tm.end(t);
     }
     hipError_t e3 = hipGetLastError();
@@ -1178,8 +1463,9 @@ int locate_impl(bwfm_index *ix, uint64_t n_hits, const uint4 *hits, uint32_t max
 
 bool check_index(const bwfm_index *ix) { return ix && ix->device >= 0; }
 
-int check_result(const bwfm_aln_result *r) {
-    return r && r->hit_offsets && r->c1 && r->c2 && r->status && (r->hits || r->hit_capacity == 0);
+// result buffers: per-read arrays may be NULL only for an empty batch
+int check_result(const bwfm_aln_result *r, uint32_t n) {
+    return r && r->hit_offsets && (n == 0 || (r->c1 && r->c2 && r->status)) && (r->hits || r->hit_capacity == 0);
 }
 
 }  // namespace
@@ -1221,13 +1507,14 @@ extern "C" void bwfm_index_free(bwfm_index *ix) {
 extern "C" int bwfm_align_batch(const bwfm_index *cix, const bwfm_reads *rd, const bwfm_aln_params *p,
                                 bwfm_aln_result *res, void *stream) {
     bwfm_index *ix = const_cast<bwfm_index *>(cix);
-    if (!ix || !rd || !p || !check_result(res)) return fail(BWFM_E_INVAL, "align_batch: NULL argument");
+    if (!ix || !rd || !p || !check_result(res, rd->n_reads)) return fail(BWFM_E_INVAL, "align_batch: NULL argument");
     if (!check_index(ix)) return fail(BWFM_E_STATE, "align_batch: index not uploaded");
     if (rd->n_reads && (!rd->bases || !rd->offsets)) return fail(BWFM_E_INVAL, "align_batch: NULL reads");
     if (rd->max_len > BWFM_MAX_READ) return fail(BWFM_E_TOOLONG, "align_batch: max_len above 512");
     if (p->max_diff < 0 || p->max_diff > BWFM_MAX_DIFF || p->max_gapo < 0 || p->seed_len < 0 || p->seed_diff < 0 ||
         p->indel_end_skip < 0 || p->s_mm < 0 || p->s_gapo < 0 || p->s_gape < 0 ||
         (p->mode != BWFM_MODE_ALL && p->mode != BWFM_MODE_BEST) || p->max_best < 0 || p->max_hits < 1 ||
+        (p->form != BWFM_FORM_BATCHED && p->form != BWFM_FORM_PLAIN) ||
         p->max_hits > 65536 || p->s_mm * 15 > 4000 || p->s_gapo * 15 > 4000 || p->s_gape * 15 > 4000)
         return fail(BWFM_E_INVAL, "align_batch: parameter out of range");
     std::lock_guard<std::mutex> g(ix->mu);
@@ -1242,7 +1529,7 @@ extern "C" int bwfm_align_batch_counted(const bwfm_index *cix, const bwfm_reads 
                                         bwfm_aln_result *res, uint32_t *expand, void *stream) {
     bwfm_index *ix = const_cast<bwfm_index *>(cix);
     if (!expand) return fail(BWFM_E_INVAL, "align_batch_counted: NULL counter array");
-    if (!ix || !rd || !p || !check_result(res)) return fail(BWFM_E_INVAL, "align_batch: NULL argument");
+    if (!ix || !rd || !p || !check_result(res, rd->n_reads)) return fail(BWFM_E_INVAL, "align_batch: NULL argument");
     if (!check_index(ix)) return fail(BWFM_E_STATE, "align_batch: index not uploaded");
     if (rd->max_len > BWFM_MAX_READ) return fail(BWFM_E_TOOLONG, "align_batch: max_len above 512");
     std::lock_guard<std::mutex> g(ix->mu);
@@ -1254,13 +1541,16 @@ extern "C" int bwfm_align_batch_counted(const bwfm_index *cix, const bwfm_reads 
 extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_aln_result *res, uint32_t max_occ,
                            uint64_t *pos_off, uint32_t *pos, uint64_t cap, void *stream) {
     bwfm_index *ix = const_cast<bwfm_index *>(cix);
-    if (!ix || !check_result(res) || !pos_off || (!pos && cap)) return fail(BWFM_E_INVAL, "locate: NULL argument");
+    if (!ix || !check_result(res, n_reads) || !pos_off || (!pos && cap)) return fail(BWFM_E_INVAL, "locate: NULL argument");
     if (!check_index(ix)) return fail(BWFM_E_STATE, "locate: index not uploaded");
     std::lock_guard<std::mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
-    uint64_t n_hits = 0;
-    HIPCHK(hipMemcpyAsync(&n_hits, res->hit_offsets + n_reads, 8, hipMemcpyDeviceToHost, st));
+    uint64_t h0 = 0, h1 = 0;
+    HIPCHK(hipMemcpyAsync(&h0, res->hit_offsets, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&h1, res->hit_offsets + n_reads, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (h1 < h0) return fail(BWFM_E_INVAL, "locate: hit offsets decrease");
+    const uint64_t n_hits = h1 - h0;
     size_t need = n_hits * 4 + scan_part_elems(n_hits) * 8 + n_hits * 4 + 4096;
     void *w;
     int rc = ws_reserve(ix, need, &w);
@@ -1271,12 +1561,11 @@ extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_a
     uint32_t *big = cv.take<uint32_t>(n_hits);
     uint32_t *n_big = cv.take<uint32_t>(1);
     uint64_t total = 0;
+    const uint4 *hits = (const uint4 *)res->hits + h0;
     if (ix->line_bytes == 128)
-        rc = locate_impl<32>(ix, n_hits, (const uint4 *)res->hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st,
-                             &total);
+        rc = locate_impl<32>(ix, n_hits, hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st, &total);
     else
-        rc = locate_impl<16>(ix, n_hits, (const uint4 *)res->hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st,
-                             &total);
+        rc = locate_impl<16>(ix, n_hits, hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st, &total);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(st));
     return BWFM_OK;
@@ -1285,20 +1574,26 @@ extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_a
 extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bwfm_aln_result *r1,
                                const bwfm_aln_result *r2, const bwfm_pair_params *pp, bwfm_pair *out, void *stream) {
     bwfm_index *ix = const_cast<bwfm_index *>(cix);
-    if (!ix || !check_result(r1) || (r2 && !check_result(r2)) || !pp || (!out && n_pairs))
+    if (!ix || !check_result(r1, n_pairs) || (r2 && !check_result(r2, n_pairs)) || !pp || (!out && n_pairs))
         return fail(BWFM_E_INVAL, "pair_reads: NULL argument");
     if (!check_index(ix)) return fail(BWFM_E_STATE, "pair_reads: index not uploaded");
     if (pp->lo > pp->hi) return fail(BWFM_E_INVAL, "pair_reads: lo > hi");
     std::lock_guard<std::mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
     const bwfm_aln_result *rr[2] = {r1, r2};
-    uint64_t nh[2] = {0, 0};
+    uint64_t hb[2] = {0, 0}, he[2] = {0, 0}, nh[2] = {0, 0};
     for (int e = 0; e < 2; e++)
-        if (rr[e]) HIPCHK(hipMemcpyAsync(&nh[e], rr[e]->hit_offsets + n_pairs, 8, hipMemcpyDeviceToHost, st));
+        if (rr[e]) {
+            HIPCHK(hipMemcpyAsync(&hb[e], rr[e]->hit_offsets, 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(&he[e], rr[e]->hit_offsets + n_pairs, 8, hipMemcpyDeviceToHost, st));
+        }
     HIPCHK(hipStreamSynchronize(st));
-    // upper bound on positions: widths are capped by max_occ
+    for (int e = 0; e < 2; e++) {
+        if (he[e] < hb[e]) return fail(BWFM_E_INVAL, "pair_reads: hit offsets decrease");
+        nh[e] = he[e] - hb[e];
+    }
+    // control buffers, then the positions of each end's hits
     void *pairmem = nullptr;
-    // first count the positions per end, then allocate them
     uint64_t *poff[2] = {nullptr, nullptr};
     uint32_t *pos[2] = {nullptr, nullptr};
     const uint64_t nmax = std::max(nh[0], nh[1]);
@@ -1315,13 +1610,12 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
     int rc = BWFM_OK;
     for (int e = 0; e < 2 && rc == BWFM_OK; e++) {
         if (!rr[e]) continue;
+        const uint4 *hits = (const uint4 *)rr[e]->hits + hb[e];
         // count pass (capacity 0 reports the total)
         uint64_t total = 0;
         rc = ix->line_bytes == 128
-                 ? locate_impl<32>(ix, nh[e], (const uint4 *)rr[e]->hits, pp->max_occ, poff[e], nullptr, 0, cnt, part,
-                                   big, n_big, st, &total)
-                 : locate_impl<16>(ix, nh[e], (const uint4 *)rr[e]->hits, pp->max_occ, poff[e], nullptr, 0, cnt, part,
-                                   big, n_big, st, &total);
+                 ? locate_impl<32>(ix, nh[e], hits, pp->max_occ, poff[e], nullptr, 0, cnt, part, big, n_big, st, &total)
+                 : locate_impl<16>(ix, nh[e], hits, pp->max_occ, poff[e], nullptr, 0, cnt, part, big, n_big, st, &total);
         if (rc == BWFM_E_CAPACITY || (rc == BWFM_OK && total == 0)) {
             rc = BWFM_OK;
             if (hipMalloc(&posmem[e], std::max<uint64_t>(total, 1) * 4) != hipSuccess) {
@@ -1331,16 +1625,16 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
             pos[e] = (uint32_t *)posmem[e];
             if (total)
                 rc = ix->line_bytes == 128
-                         ? locate_impl<32>(ix, nh[e], (const uint4 *)rr[e]->hits, pp->max_occ, poff[e], pos[e], total, cnt,
-                                           part, big, n_big, st, &total)
-                         : locate_impl<16>(ix, nh[e], (const uint4 *)rr[e]->hits, pp->max_occ, poff[e], pos[e], total, cnt,
-                                           part, big, n_big, st, &total);
+                         ? locate_impl<32>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total, cnt, part, big, n_big,
+                                           st, &total)
+                         : locate_impl<16>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total, cnt, part, big, n_big,
+                                           st, &total);
         }
     }
     if (rc == BWFM_OK && n_pairs) {
-        EndView e1{r1->hit_offsets, (const uint4 *)r1->hits, poff[0], pos[0]};
+        EndView e1{r1->hit_offsets, (const uint4 *)r1->hits, poff[0], pos[0], hb[0]};
         EndView e2 = e1;
-        if (r2) e2 = EndView{r2->hit_offsets, (const uint4 *)r2->hits, poff[1], pos[1]};
+        if (r2) e2 = EndView{r2->hit_offsets, (const uint4 *)r2->hits, poff[1], pos[1], hb[1]};
         CallTimer tm(st);
         int t = tm.begin("pair");
         k_pair<<<blocks(n_pairs, 256), 256, 0, st>>>(n_pairs, e1, e2, r2 ? 1 : 0, pp->lo, pp->hi, pp->mu, out);

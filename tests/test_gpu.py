@@ -50,8 +50,11 @@ def _compare_align(res, ores, rows=None):
             assert (c1[r], c2[r], st[r] & 7) == (ores.c1[j], ores.c2[j], ores.status[j])
 
 
-def _params_pair(**kw):
-    return bw.Params(**kw), oracle.Params(**kw)
+def _params_pair(form=None, **kw):
+    p = bw.Params(**kw)
+    if form is not None:
+        p.form = form
+    return p, oracle.Params(**kw)
 
 
 @pytest.fixture(scope="module")
@@ -61,12 +64,17 @@ def c1_small():
     return g, reads, oracle.Index(g.seq)
 
 
+FORMS = [bw.FORM_BATCHED, bw.FORM_PLAIN]
+
+
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("layout", [(64, 128), (128, 448)])
 @pytest.mark.parametrize("mode", [bw.MODE_BEST, bw.MODE_ALL])
-def test_c1_shape_parity(c1_small, layout, mode):
+def test_c1_shape_parity(c1_small, layout, mode, form):
     g, reads, ox = c1_small
     ix = bw.Index(g.seq, line_bytes=layout[0], bases_per_line=layout[1], sa_sample=32).upload()
     p, op = _params_pair(**configs.PARAMS["C1"], mode=mode)
+    p.form = form
     res = _gpu_align(ix, reads, p, counted=True)
     ores = oracle.align(ox, reads.bases, reads.offsets, op, threads=8)
     _compare_align(res, ores)
@@ -84,11 +92,12 @@ def c2_small():
     return g, pairs, oracle.Index(g.seq)
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("layout", [(128, 448, 32), (64, 192, 16)])
-def test_c2_shape_parity_align_locate_pair(c2_small, layout):
+def test_c2_shape_parity_align_locate_pair(c2_small, layout, form):
     g, pairs, ox = c2_small
     ix = bw.Index(g.seq, line_bytes=layout[0], bases_per_line=layout[1], sa_sample=layout[2]).upload()
-    p, op = _params_pair(**configs.PARAMS["C2"])
+    p, op = _params_pair(form=form, **configs.PARAMS["C2"])
     r = []
     for end in (pairs.end1, pairs.end2):
         res = _gpu_align(ix, end, p, counted=True)
@@ -119,27 +128,58 @@ def test_c2_shape_parity_align_locate_pair(c2_small, layout):
     assert np.array_equal(gs.view(np.uint8), os_.view(np.uint8))
 
 
-def test_second_pass_and_overflow_parity():
+def test_both_ends_in_one_batch(c2_small):
+    """The batched form aligns both ends in one launch; windows of the one
+    result feed pairing."""
+    g, pairs, ox = c2_small
+    ix = bw.Index(g.seq).upload()
+    p, op = _params_pair(**configs.PARAMS["C2"])
+    n = pairs.end1.n
+    both = gen.Reads(np.concatenate([pairs.end1.bases, pairs.end2.bases]),
+                     np.concatenate([pairs.end1.offsets[:-1], pairs.end1.offsets[-1] + pairs.end2.offsets]))
+    res = _gpu_align(ix, both, p)
+    o1 = oracle.align(ox, pairs.end1.bases, pairs.end1.offsets, op, threads=8)
+    o2 = oracle.align(ox, pairs.end2.bases, pairs.end2.offsets, op, threads=8)
+    w1, w2 = res.window(0, n), res.window(n, 2 * n)
+    _compare_align(w1, o1)
+    _compare_align(w2, o2)
+    po, pos = bw.locate(ix, w2, configs.MAX_OCC)
+    opo, opos = oracle.locate(ox, o2.hits, configs.MAX_OCC)
+    assert np.array_equal(po.cpu().numpy().view(np.uint64), opo)
+    assert np.array_equal(pos.cpu().numpy().view(np.uint32), opos)
+    w = configs.PAIR_WINDOW
+    gp = bw.pairs_numpy(bw.pair_reads(ix, w1, w2, w["lo"], w["hi"], w["mu"], configs.MAX_OCC))
+    po1, pos1 = oracle.locate(ox, o1.hits, configs.MAX_OCC)
+    opr = oracle.pair(o1, po1, pos1, o2, opo, opos, w["lo"], w["hi"], w["mu"])
+    assert np.array_equal(gp.view(np.uint8), opr.view(np.uint8))
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_second_pass_and_overflow_parity(form):
     # a repeat-rich genome and ALL mode: many reads exceed the first pass's
-    # 32 hit slots or 64 stack entries and are searched again
+    # hit slots (or, in the plain form, its stack) and are searched again
     g = gen.genome_repeats(91, 400_000, gc=0.41, repeat_frac=0.7, n_fam=5, min_len=300, max_len=800, div_lo=0.0,
                            div_hi=0.03)
     reads = gen.reads_se(92, g, 1500, 40, ps=0.03, indel_ratio=0.2, rep_frac=0.9)
     ox = oracle.Index(g.seq)
     ix = bw.Index(g.seq).upload()
+    researched = overflowed = 0
     for kw in (dict(max_diff=3, max_gapo=1, mode=bw.MODE_ALL, max_hits=200),
                dict(max_diff=3, max_gapo=1, mode=bw.MODE_BEST, max_hits=5),
                dict(max_diff=2, max_gapo=0, mode=bw.MODE_ALL, max_hits=1000)):
-        p, op = _params_pair(**kw)
+        p, op = _params_pair(form=form, **kw)
         res = _gpu_align(ix, reads, p)
         ores = oracle.align(ox, reads.bases, reads.offsets, op, threads=8)
         _compare_align(res, ores)
         st = res.status.cpu().numpy()
-        assert (st & bw.ST_RESEARCH).any(), "the second pass was not exercised"
-        assert kw["mode"] != bw.MODE_BEST or (st & bw.ST_OVERFLOW).any()
+        researched += int((st & bw.ST_RESEARCH).astype(bool).sum())
+        overflowed += int((st & bw.ST_OVERFLOW).astype(bool).sum())
+    assert researched > 0, "the second pass was not exercised"
+    assert overflowed > 0, "the max_hits rule was not exercised"
 
 
-def test_edge_cases_parity():
+@pytest.mark.parametrize("form", FORMS)
+def test_edge_cases_parity(form):
     g = configs.c2_genome(300_000, seed=5)
     ox = oracle.Index(g.seq)
     ix = bw.Index(g.seq).upload()
@@ -160,7 +200,7 @@ def test_edge_cases_parity():
     offs[1:] = np.cumsum([len(p) for p in pieces])
     reads = gen.Reads(bases, offs)
     md = np.array([4, 2, 6, 4, 0, 4, 5, 15], np.uint8)
-    p, op = _params_pair(**configs.PARAMS["C2"])
+    p, op = _params_pair(form=form, **configs.PARAMS["C2"])
     res = _gpu_align(ix, reads, p, max_diff=md)
     ores = oracle.align(ox, reads.bases, reads.offsets, op, max_diff=md, threads=1)
     _compare_align(res, ores)
@@ -178,12 +218,13 @@ def test_edge_cases_parity():
     assert res3.n_hits == 0
 
 
-def test_c3_shape_per_read_budgets_parity():
+@pytest.mark.parametrize("form", FORMS)
+def test_c3_shape_per_read_budgets_parity(form):
     g = configs.c2_genome(1_000_000, seed=33)
     pairs = configs.c3_pairs(g, 1500, seed=34)
     ox = oracle.Index(g.seq)
     ix = bw.Index(g.seq).upload()
-    p, op = _params_pair(**configs.PARAMS["C3"])
+    p, op = _params_pair(form=form, **configs.PARAMS["C3"])
     for end in (pairs.end1, pairs.end2):
         L = np.diff(end.offsets).astype(int)
         md_lib = np.array([bw.max_diff_rule(int(x)) for x in L], np.uint8)
@@ -244,9 +285,13 @@ def test_c2_full_size_sampled_parity(c2_full):
     p, op = _params_pair(**configs.PARAMS["C2"])
     rng = np.random.default_rng(11)
     sample = np.sort(rng.choice(pairs.end1.n, 1500, replace=False))
+    n = pairs.end1.n
+    both = gen.Reads(np.concatenate([pairs.end1.bases, pairs.end2.bases]),
+                     np.concatenate([pairs.end1.offsets[:-1], pairs.end1.offsets[-1] + pairs.end2.offsets]))
+    full = _gpu_align(ix, both, p)
     res_e = []
-    for end in (pairs.end1, pairs.end2):
-        res = _gpu_align(ix, end, p)
+    for e, end in enumerate((pairs.end1, pairs.end2)):
+        res = full.window(e * n, (e + 1) * n)
         offs = end.offsets
         sb = np.concatenate([end.bases[offs[r]:offs[r + 1]] for r in sample])
         so = np.zeros(len(sample) + 1, np.uint64)
