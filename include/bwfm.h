@@ -118,11 +118,15 @@ int bwfm_index_occ(const bwfm_index *idx, int which, uint64_t i, uint64_t *out);
 /* ------------------------------------------------------------------ */
 
 typedef struct {
-    const uint8_t *bases;    /* device: read r is bases[offsets[r], offsets[r+1]) */
-    const uint64_t *offsets; /* device: n_reads + 1 non-decreasing offsets */
-    const uint8_t *max_diff; /* device, n_reads per-read budgets, or NULL */
+    const uint8_t *bases;     /* device: read r starts at bases[offsets[r]] */
+    const uint64_t *offsets;  /* device: n_reads + 1 non-decreasing offsets (read r
+                                 ends at offsets[r+1]), or n_reads start offsets
+                                 when lengths is given */
+    const uint8_t *max_diff;  /* device, n_reads per-read budgets, or NULL */
     uint32_t n_reads;
-    uint32_t max_len;        /* host-known bound on read length, <= 512 */
+    uint32_t max_len;         /* host-known bound on read length, <= 512 */
+    const uint32_t *lengths;  /* device, n_reads read lengths, or NULL; with
+                                 lengths, reads may sit anywhere in bases */
 } bwfm_reads;
 
 enum { BWFM_MODE_ALL = 0, BWFM_MODE_BEST = 1 };
@@ -260,6 +264,67 @@ int bwfm_pair_reads(const bwfm_index *idx, uint32_t n_pairs, const bwfm_aln_resu
                     const bwfm_aln_result *r2, const bwfm_pair_params *p, bwfm_pair *out, void *hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* Serving (continuous batching over the path above)                    */
+/* ------------------------------------------------------------------ */
+
+/*
+ * A request server for the paired-end path.  Requests (host buffers) are
+ * copied at submit and queued; a worker thread with its own stream admits
+ * them in arrival order while their reads fit in a device arena of
+ * arena_bytes, then runs scheduling steps of at most step_pairs pairs taken
+ * from every admitted request, oldest first -- so requests that arrive while
+ * others are on the GPU join the next step and share its launch.  Each step
+ * aligns both ends in one call (form and search parameters from ap), pairs
+ * them (pp) and copies the pair records back.  A request's results are the
+ * same whatever it was mixed with.  The index must stay alive and uploaded
+ * while the server exists.
+ */
+typedef struct bwfm_server bwfm_server;
+
+typedef struct {
+    uint64_t arena_bytes;  /* device bytes for admitted requests' bases */
+    uint32_t step_pairs;   /* most pairs per scheduling step */
+    uint32_t max_len;      /* longest read accepted, <= 512 */
+    int32_t paired;        /* 1: requests carry both ends, 0: single-end */
+    int32_t budget_rule;   /* 1: each read's difference budget is
+                              bwfm_max_diff_rule(length, 0.02, 0.04);
+                              0: ap->max_diff for every read */
+} bwfm_server_params;
+
+typedef struct {
+    double queued_ms;   /* submit -> admitted */
+    double service_ms;  /* admitted -> results ready */
+    double latency_ms;  /* submit -> results ready */
+} bwfm_request_times;
+
+typedef struct {
+    uint64_t steps, pairs, requests_done;
+    double busy_ms;     /* wall time the worker spent in steps */
+} bwfm_server_stats;
+
+/* Errors: E_INVAL, E_STATE (index not uploaded), E_NOMEM, E_DEVICE. */
+int bwfm_server_create(const bwfm_index *idx, const bwfm_aln_params *ap, const bwfm_pair_params *pp,
+                       const bwfm_server_params *sp, bwfm_server **out);
+
+/* Queue a request of n_pairs pairs: end e's pair j is bases_e[offsets_e[j],
+ * offsets_e[j+1]) (host; offsets need not start at 0).  bases2/offsets2 are
+ * ignored for a single-end server.  *ticket identifies it for
+ * bwfm_server_wait.  Errors: E_INVAL, E_CAPACITY (larger than the arena),
+ * E_STATE (server stopping). */
+int bwfm_server_submit(bwfm_server *srv, const uint8_t *bases1, const uint64_t *offsets1, const uint8_t *bases2,
+                       const uint64_t *offsets2, uint32_t n_pairs, uint64_t *ticket);
+
+/* Block until the request is done; copy its n_pairs pair records to out
+ * (host, may be NULL) and its times to *times (may be NULL).  Each ticket
+ * can be waited for once. */
+int bwfm_server_wait(bwfm_server *srv, uint64_t ticket, bwfm_pair *out, bwfm_request_times *times);
+
+int bwfm_server_get_stats(bwfm_server *srv, bwfm_server_stats *out);
+
+/* Finish every queued request, stop the worker, free device memory. */
+void bwfm_server_destroy(bwfm_server *srv);
+
+/* ------------------------------------------------------------------ */
 /* Host helpers                                                         */
 /* ------------------------------------------------------------------ */
 
@@ -289,6 +354,19 @@ int bwfm_max_diff_rule(uint32_t len, double err, double thres);
 int bwfm_timing_enable(int on);
 int bwfm_timing_reset(void);
 int bwfm_timing_get(const char *kernel, double *total_ms, uint64_t *launches);
+
+/*
+ * Random-line probe: the achievable rate of dependent random line fetches,
+ * the access pattern of the search (each rank query is one line at an index
+ * the previous query decided).  lanes (a multiple of 256) each perform iters
+ * dependent fetches of whole line_bytes (64 or 128) lines at pseudo-random
+ * line indices within buf (device, bytes long; contents arbitrary).  sink:
+ * device, lanes uint32 (defeats dead-code removal).  *ms_out receives the
+ * kernel time from HIP events on hip_stream.  Synchronous.  Lines/s =
+ * lanes * iters / (ms / 1000).
+ */
+int bwfm_probe_gather(const void *buf, uint64_t bytes, uint32_t line_bytes, uint32_t lanes, uint32_t iters,
+                      uint32_t *sink, double *ms_out, void *hip_stream);
 
 /* Description of the last error on the calling thread ("" if none). */
 const char *bwfm_last_error(void);

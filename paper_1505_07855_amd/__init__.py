@@ -54,7 +54,7 @@ class _IndexInfo(ctypes.Structure):
 
 class _Reads(ctypes.Structure):
     _fields_ = [("bases", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("max_diff", ctypes.c_void_p),
-                ("n_reads", ctypes.c_uint32), ("max_len", ctypes.c_uint32)]
+                ("n_reads", ctypes.c_uint32), ("max_len", ctypes.c_uint32), ("lengths", ctypes.c_void_p)]
 
 
 class _AlnParams(ctypes.Structure):
@@ -68,6 +68,20 @@ class _AlnResult(ctypes.Structure):
                 ("c1", ctypes.c_void_p), ("c2", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
+class _ServerParams(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("step_pairs", ctypes.c_uint32), ("max_len", ctypes.c_uint32),
+                ("paired", ctypes.c_int32), ("budget_rule", ctypes.c_int32)]
+
+
+class _Times(ctypes.Structure):
+    _fields_ = [("queued_ms", ctypes.c_double), ("service_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint64), ("pairs", ctypes.c_uint64), ("requests_done", ctypes.c_uint64),
+                ("busy_ms", ctypes.c_double)]
+
+
 class _PairParams(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_int32), ("hi", ctypes.c_int32), ("mu", ctypes.c_int32), ("max_occ", ctypes.c_uint32)]
 
@@ -76,13 +90,22 @@ class _PairParams(ctypes.Structure):
 SYMBOLS = ("bwfm_build_index", "bwfm_index_upload", "bwfm_index_free", "bwfm_index_get_info", "bwfm_index_get_bwt",
            "bwfm_index_get_sa_samples", "bwfm_index_occ", "bwfm_align_batch", "bwfm_locate", "bwfm_pair_reads",
            "bwfm_estimate_insert", "bwfm_max_diff_rule", "bwfm_last_error", "bwfm_align_batch_counted",
-           "bwfm_timing_enable", "bwfm_timing_reset", "bwfm_timing_get")
+           "bwfm_timing_enable", "bwfm_timing_reset", "bwfm_timing_get", "bwfm_probe_gather",
+           "bwfm_server_create", "bwfm_server_submit", "bwfm_server_wait", "bwfm_server_get_stats",
+           "bwfm_server_destroy")
 
 
 def lib():
     """Load libbwfm.so; raises if it has not been built."""
     global _lib_handle
     if _lib_handle is None:
+        # torch ships its own HIP runtime under the same soname; import it
+        # first so that the library binds to that one runtime rather than
+        # loading a second copy from /opt/rocm
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1505_07855_amd.build "
                                "(there is no CPU fallback)")
@@ -107,6 +130,12 @@ def lib():
             "bwfm_timing_enable": ([c_int], c_int),
             "bwfm_timing_reset": ([], c_int),
             "bwfm_timing_get": ([ctypes.c_char_p, P, P], c_int),
+            "bwfm_probe_gather": ([P, u64, u32, u32, u32, P, P, P], c_int),
+            "bwfm_server_create": ([P, P, P, P, ctypes.POINTER(P)], c_int),
+            "bwfm_server_submit": ([P, P, P, P, P, u32, P], c_int),
+            "bwfm_server_wait": ([P, u64, P, P], c_int),
+            "bwfm_server_get_stats": ([P, P], c_int),
+            "bwfm_server_destroy": ([P], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -258,24 +287,26 @@ class AlignResult:
                 self.status.cpu().numpy())
 
 
-def _reads_struct(bases, offsets, max_diff, max_len):
-    n = offsets.shape[0] - 1
+def _reads_struct(bases, offsets, max_diff, max_len, lengths=None):
+    n = offsets.shape[0] - 1 if lengths is None else lengths.shape[0]
     if max_len is None:
         raise ValueError("max_len (a host-known bound on read length) is required")
     return _Reads(_dptr(bases) if bases.numel() else 0, _dptr(offsets),
-                  _dptr(max_diff) if max_diff is not None else None, n, max_len)
+                  _dptr(max_diff) if max_diff is not None else None, n, max_len,
+                  _dptr(lengths) if lengths is not None else None)
 
 
 def align_batch(index: Index, bases, offsets, params: Params, max_diff=None, max_len: int | None = None,
-                hit_capacity: int | None = None, stream=None, counted: bool = False, out: AlignResult | None = None
-                ) -> AlignResult:
+                hit_capacity: int | None = None, stream=None, counted: bool = False, out: AlignResult | None = None,
+                lengths=None) -> AlignResult:
     """Align a ragged batch of reads (device uint8 bases, device int64
-    offsets) on both strands.  Returns device tensors; grows the hit buffer
-    and retries once if it was too small."""
+    offsets; or start offsets plus device int32 lengths) on both strands.
+    Returns device tensors; grows the hit buffer and retries once if it was
+    too small."""
     torch = _torch()
-    n = offsets.shape[0] - 1
+    n = offsets.shape[0] - 1 if lengths is None else lengths.shape[0]
     dev = offsets.device
-    rd = _reads_struct(bases, offsets, max_diff, max_len)
+    rd = _reads_struct(bases, offsets, max_diff, max_len, lengths)
     if out is None:
         cap = hit_capacity if hit_capacity is not None else max(16, 4 * n)
         out = AlignResult(torch.empty(n + 1, dtype=torch.int64, device=dev),
@@ -359,6 +390,19 @@ def timing_get(kernel: str):
     return ms.value, n.value
 
 
+def probe_gather(buf, line_bytes: int = 128, lanes: int = 0, iters: int = 256, stream=None) -> float:
+    """Dependent random line fetches over the device tensor buf; returns
+    lines per second.  lanes defaults to 256 per CU x 16."""
+    torch = _torch()
+    if lanes == 0:
+        lanes = torch.cuda.get_device_properties(buf.device).multi_processor_count * 256 * 16
+    sink = torch.empty(lanes, dtype=torch.int32, device=buf.device)
+    ms = ctypes.c_double()
+    _check(lib().bwfm_probe_gather(_dptr(buf), buf.numel() * buf.element_size(), line_bytes, lanes, iters,
+                                   _dptr(sink), ctypes.byref(ms), _stream_ptr(stream)))
+    return lanes * iters / (ms.value / 1e3)
+
+
 def estimate_insert(inserts: np.ndarray):
     a = np.ascontiguousarray(inserts, np.int32)
     pp = _PairParams(0, 0, 0, 0)
@@ -368,3 +412,56 @@ def estimate_insert(inserts: np.ndarray):
 
 def max_diff_rule(length: int, err: float = 0.02, thres: float = 0.04) -> int:
     return lib().bwfm_max_diff_rule(length, err, thres)
+
+
+class Server:
+    """Continuous-batching request server (bwfm_server_*): submit host read
+    pairs, wait for their pair records.  Thread safe."""
+
+    def __init__(self, index: Index, params: Params, lo: int, hi: int, mu: int, max_occ: int,
+                 arena_bytes: int = 1 << 30, step_pairs: int = 65536, max_len: int = 150, paired: bool = True,
+                 budget_rule: bool = False):
+        self._index = index  # keep the index alive
+        h = ctypes.c_void_p()
+        ap = params._c()
+        pp = _PairParams(lo, hi, mu, max_occ)
+        sp = _ServerParams(arena_bytes, step_pairs, max_len, 1 if paired else 0, 1 if budget_rule else 0)
+        _check(lib().bwfm_server_create(index.handle, ctypes.byref(ap), ctypes.byref(pp), ctypes.byref(sp),
+                                        ctypes.byref(h)))
+        self._h = h
+        self.paired = paired
+
+    def submit(self, bases1: np.ndarray, offsets1: np.ndarray, bases2: np.ndarray | None = None,
+               offsets2: np.ndarray | None = None) -> int:
+        b1 = np.ascontiguousarray(bases1, np.uint8)
+        o1 = np.ascontiguousarray(offsets1, np.uint64)
+        b2 = np.ascontiguousarray(bases2, np.uint8) if bases2 is not None else None
+        o2 = np.ascontiguousarray(offsets2, np.uint64) if offsets2 is not None else None
+        t = ctypes.c_uint64()
+        _check(lib().bwfm_server_submit(self._h, _np_ptr(b1) if len(b1) else None, _np_ptr(o1),
+                                        _np_ptr(b2) if b2 is not None and len(b2) else None,
+                                        _np_ptr(o2) if o2 is not None else None, len(o1) - 1, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, n_pairs: int):
+        """(pair records PAIR_DTYPE[n_pairs], {queued_ms, service_ms, latency_ms})."""
+        out = np.zeros(n_pairs, PAIR_DTYPE)
+        tm = _Times()
+        _check(lib().bwfm_server_wait(self._h, ticket, _np_ptr(out), ctypes.byref(tm)))
+        return out, {"queued_ms": tm.queued_ms, "service_ms": tm.service_ms, "latency_ms": tm.latency_ms}
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(lib().bwfm_server_get_stats(self._h, ctypes.byref(s)))
+        return {"steps": s.steps, "pairs": s.pairs, "requests_done": s.requests_done, "busy_ms": s.busy_ms}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bwfm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -31,9 +31,10 @@ def build() -> str:
     o = os.path.join(OUT, "index_host.o")
     _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "index_host.cpp"), "-o", o])
     objs.append(o)
-    o = os.path.join(OUT, "bwfm.o")
-    _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "bwfm.hip"), "-o", o])
-    objs.append(o)
+    for src in ("bwfm.hip", "server.cpp"):
+        o = os.path.join(OUT, os.path.splitext(src)[0] + ".o")
+        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
+        objs.append(o)
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, LIB)

@@ -60,16 +60,35 @@ struct Params {
 struct ReadsView {
     const uint8_t *bases;
     const uint64_t *off;
+    const uint32_t *len;  // per-read lengths, or NULL: read r ends where read r + 1 starts
     const uint8_t *maxd;
     uint32_t n, max_len;
 };
 
-// lane-private buffers: element e of lane t at base[e * stride + t]
+// start and length of read r
+__device__ __forceinline__ void read_span(const ReadsView &rd, uint32_t r, uint64_t &o0, uint64_t &len, bool &bad) {
+    o0 = rd.off[r];
+    if (rd.len) {
+        len = rd.len[r];
+        bad = false;
+    } else {
+        const uint64_t o1 = rd.off[r + 1];
+        bad = o1 < o0;
+        len = bad ? 0 : o1 - o0;
+    }
+}
+
+// Lane-private buffers in device memory.  Element e of lane t sits at
+// base[t * lane_step + e * stride]: interleaved (lane_step 1, stride = lanes)
+// when a wave's lanes move in step, contiguous (lane_step = cap, stride 1)
+// when they do not.  Each lane's strand pattern and D-array live in LDS,
+// lds_stride bytes per lane.
 struct LaneBufs {
     uint4 *stack;
     uint4 *cand;
-    uint8_t *D;
-    uint32_t stride, stack_cap, cand_cap;
+    uint32_t stack_lane_step, stack_stride, stack_cap;
+    uint32_t cand_lane_step, cand_stride, cand_cap;
+    uint32_t lds_stride;
 };
 
 // ------------------------------------------------------------------ rank queries
@@ -225,12 +244,31 @@ __device__ __forceinline__ bool before(uint4 a, uint4 b) {
 
 struct LaneCtx {
     uint4 *stack, *cand;
-    uint8_t *D;
-    uint32_t stride, stack_cap, cand_cap;
+    uint8_t *pd;  // LDS, per pattern position i: base code | D[i] << 3
+    uint32_t sstride, cstride, stack_cap, cand_cap;
     uint32_t sp, ncand;
     int best;
     uint32_t expand;
 };
+
+extern __shared__ uint8_t lds_bytes[];
+
+__device__ __forceinline__ void init_ctx(LaneCtx &c, const LaneBufs &B, uint32_t lane) {
+    c.stack = B.stack + (size_t)lane * B.stack_lane_step;
+    c.cand = B.cand + (size_t)lane * B.cand_lane_step;
+    c.pd = lds_bytes + (size_t)threadIdx.x * B.lds_stride;
+    c.sstride = B.stack_stride;
+    c.cstride = B.cand_stride;
+    c.stack_cap = B.stack_cap;
+    c.cand_cap = B.cand_cap;
+    c.sp = 0;
+    c.ncand = 0;
+    c.best = INF_SCORE;
+    c.expand = 0;
+}
+
+__device__ __forceinline__ int pd_base(const LaneCtx &c, int i) { return c.pd[i] & 7; }
+__device__ __forceinline__ int pd_d(const LaneCtx &c, int i) { return i >= 0 ? (c.pd[i] >> 3) : 0; }
 
 enum { R_OK = 0, R_STACK = 1, R_CAND = 2 };
 
@@ -239,22 +277,22 @@ enum { R_OK = 0, R_STACK = 1, R_CAND = 2 };
 __device__ int record(LaneCtx &c, const Params &P, uint4 h, int phase) {
     if (phase == PH_BEST) return R_OK;
     for (uint32_t j = 0; j < c.ncand; j++) {
-        uint4 o = c.cand[(size_t)j * c.stride];
+        uint4 o = c.cand[(size_t)j * c.cstride];
         if (h_strand(o) == h_strand(h) && o.x == h.x && h_len(o) == h_len(h)) {
-            if (better(h, o)) c.cand[(size_t)j * c.stride] = h;
+            if (better(h, o)) c.cand[(size_t)j * c.cstride] = h;
             return R_OK;
         }
     }
     if (c.ncand == c.cand_cap && phase == PH_FAST && P.mode == BWFM_MODE_BEST) {
         uint32_t w = 0;
         for (uint32_t j = 0; j < c.ncand; j++) {
-            uint4 o = c.cand[(size_t)j * c.stride];
-            if (h_score(o) <= c.best + P.s_mm) c.cand[(size_t)(w++) * c.stride] = o;
+            uint4 o = c.cand[(size_t)j * c.cstride];
+            if (h_score(o) <= c.best + P.s_mm) c.cand[(size_t)(w++) * c.cstride] = o;
         }
         c.ncand = w;
     }
     if (c.ncand == c.cand_cap) return R_CAND;
-    c.cand[(size_t)(c.ncand++) * c.stride] = h;
+    c.cand[(size_t)(c.ncand++) * c.cstride] = h;
     return R_OK;
 }
 
@@ -296,10 +334,10 @@ __device__ int resolve(State &cur, bool &valid, int strand, const Params &P, Lan
         if (!valid) {
             if (c.sp == 0) return 0;
             c.sp--;
-            cur = unpack(c.stack[(size_t)c.sp * c.stride]);
+            cur = unpack(c.stack[(size_t)c.sp * c.sstride]);
             valid = true;
         }
-        Di = cur.i >= 0 ? c.D[(size_t)cur.i * c.stride] : 0;
+        Di = pd_d(c, cur.i);
         if (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE && cur.score + P.minc * Di > c.best + P.s_mm) {
             valid = false;
             continue;
@@ -332,7 +370,7 @@ __device__ int expand_children(State &cur, bool &valid, const uint32_t (&ok)[4],
             if (c.sp == c.stack_cap) {
                 rc = R_STACK;
             } else {
-                c.stack[(size_t)c.sp * c.stride] = pack(pend);
+                c.stack[(size_t)c.sp * c.sstride] = pack(pend);
                 c.sp++;
             }
         }
@@ -442,7 +480,7 @@ __device__ bool build_d(const DevIndex &ix, const DevDir &od, const uint8_t *W, 
             l = ix.n;
             if (z > maxd) return false;
         }
-        c.D[(size_t)i * c.stride] = (uint8_t)z;
+        c.pd[i] = (uint8_t)(a | (z << 3));
     }
     return true;
 }
@@ -464,8 +502,8 @@ __device__ int search_strand(const DevIndex &ix, const DevDir &sd_, const uint8_
         uint32_t ok[4], ol[4];
         occ4<LW>(ix, sd_, cur.k, ok);
         occ4<LW>(ix, sd_, cur.l + 1, ol);
-        const int b = pat(W, m, strand, cur.i);
-        const int Dn = cur.i >= 1 ? c.D[(size_t)(cur.i - 1) * c.stride] : 0;
+        const int b = pd_base(c, cur.i);
+        const int Dn = pd_d(c, cur.i - 1);
         int rc = expand_children(cur, valid, ok, ol, sd_, b, m, maxd, Di, Dn, S, P, c);
         if (rc) return rc;
     }
@@ -482,9 +520,9 @@ __device__ uint32_t finish(LaneCtx &c, const Params &P, uint8_t &status, uint32_
     uint32_t n = 0;
     uint64_t c1 = 0, c2 = 0;
     for (uint32_t j = 0; j < c.ncand; j++) {
-        uint4 h = c.cand[(size_t)j * c.stride];
+        uint4 h = c.cand[(size_t)j * c.cstride];
         int sc = h_score(h);
-        if (P.mode == BWFM_MODE_ALL || sc <= S + P.s_mm) c.cand[(size_t)(n++) * c.stride] = h;
+        if (P.mode == BWFM_MODE_ALL || sc <= S + P.s_mm) c.cand[(size_t)(n++) * c.cstride] = h;
         uint64_t w = (uint64_t)h.y - h.x + 1;
         if (sc == S) c1 += w;
         else if (sc <= S + P.s_mm) c2 += w;
@@ -499,19 +537,19 @@ __device__ uint32_t finish(LaneCtx &c, const Params &P, uint8_t &status, uint32_
     const bool keep2 = c1 <= (uint64_t)P.max_best;
     uint32_t r = 0;
     for (uint32_t j = 0; j < n; j++) {
-        uint4 h = c.cand[(size_t)j * c.stride];
-        if (P.mode == BWFM_MODE_ALL || h_score(h) == S || keep2) c.cand[(size_t)(r++) * c.stride] = h;
+        uint4 h = c.cand[(size_t)j * c.cstride];
+        if (P.mode == BWFM_MODE_ALL || h_score(h) == S || keep2) c.cand[(size_t)(r++) * c.cstride] = h;
     }
     for (uint32_t j = 1; j < r; j++) {  // insertion sort by (score, strand, k, len)
-        uint4 v = c.cand[(size_t)j * c.stride];
+        uint4 v = c.cand[(size_t)j * c.cstride];
         uint32_t q = j;
         while (q > 0) {
-            uint4 u = c.cand[(size_t)(q - 1) * c.stride];
+            uint4 u = c.cand[(size_t)(q - 1) * c.cstride];
             if (!before(v, u)) break;
-            c.cand[(size_t)q * c.stride] = u;
+            c.cand[(size_t)q * c.cstride] = u;
             q--;
         }
-        c.cand[(size_t)q * c.stride] = v;
+        c.cand[(size_t)q * c.cstride] = v;
     }
     status = r ? BWFM_ST_HIT : 0;
     return r;
@@ -562,7 +600,7 @@ __device__ void publish(LaneCtx &c, const Params &P, const ReadOut &O, uint32_t 
             send_to_second_pass(O, r);
             return;
         }
-        for (uint32_t j = 0; j < nr; j++) O.stage[off + j] = c.cand[(size_t)j * c.stride];
+        for (uint32_t j = 0; j < nr; j++) O.stage[off + j] = c.cand[(size_t)j * c.cstride];
         O.stage_off[r] = off;
     }
     O.n_rep[r] = nr;
@@ -574,14 +612,15 @@ __device__ void publish(LaneCtx &c, const Params &P, const ReadOut &O, uint32_t 
 // validity of read r: 0 = search it, 1 = done (empty or invalid, outputs written)
 __device__ __forceinline__ int check_read(const ReadsView &rd, const Params &P, const ReadOut &O, uint32_t r, int &m,
                                           int &maxd, uint64_t &o0) {
-    o0 = rd.off[r];
-    uint64_t o1 = rd.off[r + 1];
-    m = (int)(o1 - o0);
+    uint64_t len;
+    bool bad;
+    read_span(rd, r, o0, len, bad);
+    m = (int)len;
     maxd = rd.maxd ? rd.maxd[r] : P.max_diff;
     O.n_rep[r] = 0;
     O.c1[r] = O.c2[r] = 0;
     if (O.expand) O.expand[r] = 0;
-    if (o1 < o0 || o1 - o0 > rd.max_len || m > BWFM_MAX_READ || maxd > BWFM_MAX_DIFF) {
+    if (bad || len > rd.max_len || len > BWFM_MAX_READ || maxd > BWFM_MAX_DIFF) {
         O.status[r] = BWFM_ST_INVALID;
         return 1;
     }
@@ -597,20 +636,13 @@ __device__ __forceinline__ int check_read(const ReadsView &rd, const Params &P, 
 // Plain form: one lane per read, one launch per batch.
 template <int LW>
 __global__ __launch_bounds__(BLOCK) void k_align_plain(DevIndex ix, ReadsView rd, Params P, LaneBufs B, ReadOut O) {
-    uint32_t r = blockIdx.x * BLOCK + threadIdx.x;
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rd.n) return;
     int m, maxd;
     uint64_t o0;
     if (check_read(rd, P, O, r, m, maxd, o0)) return;
     LaneCtx c;
-    c.stack = B.stack + r;
-    c.cand = B.cand + r;
-    c.D = B.D + r;
-    c.stride = B.stride;
-    c.stack_cap = B.stack_cap;
-    c.cand_cap = B.cand_cap;
-    c.best = INF_SCORE;
-    c.expand = 0;
+    init_ctx(c, B, r);
     int rc = align_read<LW>(ix, rd.bases + o0, m, maxd, P, c, PH_FAST);
     if (rc) {
         if (O.expand) O.expand[r] = c.expand;
@@ -631,19 +663,10 @@ enum { ACT_NONE = 0, ACT_DSTEP = 1, ACT_EXPAND = 2 };
 template <int LW>
 __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsView rd, Params P, LaneBufs B, ReadOut O,
                                                             uint32_t *next_read) {
-    const uint32_t gl = blockIdx.x * BLOCK + threadIdx.x;
+    const uint32_t gl = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     LaneCtx c;
-    c.stack = B.stack + gl;
-    c.cand = B.cand + gl;
-    c.D = B.D + gl;
-    c.stride = B.stride;
-    c.stack_cap = B.stack_cap;
-    c.cand_cap = B.cand_cap;
-    c.sp = 0;
-    c.ncand = 0;
-    c.best = INF_SCORE;
-    c.expand = 0;
+    init_ctx(c, B, gl);
 
     int phase = PZ_IDLE;
     bool exhausted = false;
@@ -763,7 +786,7 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
                 skip = dz > maxd;
             }
             if (!skip) {
-                c.D[(size_t)di * c.stride] = (uint8_t)dz;
+                c.pd[di] = (uint8_t)(da | (dz << 3));
                 di++;
             }
             if (skip || di == m) {
@@ -785,8 +808,8 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
             }
         } else if (act == ACT_EXPAND) {
             c.expand++;
-            const int b = pat(W, m, strand, cur.i);
-            const int Dn = cur.i >= 1 ? c.D[(size_t)(cur.i - 1) * c.stride] : 0;
+            const int b = pd_base(c, cur.i);
+            const int Dn = pd_d(c, cur.i - 1);
             int rc = expand_children(cur, valid, ok, ol, qd, b, m, maxd, Di, Dn, S, P, c);
             if (rc) {
                 send_to_second_pass(O, r);
@@ -804,21 +827,16 @@ template <int LW>
 __global__ __launch_bounds__(BLOCK) void k_align_slow(DevIndex ix, ReadsView rd, Params P, LaneBufs B,
                                                       const uint32_t *slow_list, uint32_t n_slow, uint32_t *n_rep,
                                                       uint32_t *c1, uint32_t *c2, uint8_t *status, uint32_t *expand) {
-    uint32_t t = blockIdx.x * BLOCK + threadIdx.x;
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_slow) return;
     uint32_t r = slow_list[t];
-    uint64_t o0 = rd.off[r];
-    int m = (int)(rd.off[r + 1] - o0);
+    uint64_t o0, len;
+    bool bad;
+    read_span(rd, r, o0, len, bad);
+    const int m = (int)len;
     int maxd = rd.maxd ? rd.maxd[r] : P.max_diff;
     LaneCtx c;
-    c.stack = B.stack + t;
-    c.cand = B.cand + t;
-    c.D = B.D + t;
-    c.stride = B.stride;
-    c.stack_cap = B.stack_cap;
-    c.cand_cap = B.cand_cap;
-    c.best = INF_SCORE;
-    c.expand = 0;
+    init_ctx(c, B, t);
     align_read<LW>(ix, rd.bases + o0, m, maxd, P, c, PH_BEST);
     uint8_t st = 0;
     uint32_t a = 0, b = 0, nr = 0;
@@ -1157,6 +1175,35 @@ __global__ void k_pair(uint32_t n_pairs, EndView e1, EndView e2, int paired, int
     out[q] = o;
 }
 
+
+// ------------------------------------------------------------------ random-line probe
+
+// Each lane performs `iters` dependent fetches of whole lines at
+// pseudo-random line indices; the next index depends on the data just read,
+// as in the search's pointer chase.  Every index is reduced into
+// [0, n_lines), so any buffer contents are safe.
+template <int LW>
+__global__ __launch_bounds__(256) void k_probe_gather(const uint4 *buf, uint64_t n_lines, uint32_t iters,
+                                                      uint32_t *sink) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t x = 0x9E3779B97F4A7C15ULL * (t + 1);
+    uint32_t acc = 0;
+    for (uint32_t it = 0; it < iters; it++) {
+        x ^= x >> 31;
+        x *= 0xBF58476D1CE4E5B9ULL;
+        x ^= x >> 29;
+        const uint64_t line = __umul64hi(x, n_lines);
+        const uint4 *L = buf + line * (LW / 4);
+#pragma unroll
+        for (int q = 0; q < LW / 4; q++) {
+            uint4 v = L[q];
+            acc += v.x ^ v.y ^ v.z ^ v.w;
+        }
+        x += acc;
+    }
+    sink[t] = acc;
+}
+
 // ------------------------------------------------------------------ host helpers
 
 #define HIPCHK(expr)                                                                        \
@@ -1309,20 +1356,32 @@ int scan_counts(const uint32_t *cnt, uint64_t n, uint64_t *out, uint64_t *part, 
 
 size_t scan_part_elems(uint64_t n) { return (n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1; }
 
-// Lanes of a persistent grid that fit on the device at once.
+// Lanes of a persistent grid that fit on the device at once, for a block
+// size and its dynamic LDS.
 template <int LW>
-uint32_t persistent_lanes() {
-    static uint32_t cached = 0;
-    if (cached) return cached;
+uint32_t persistent_lanes(uint32_t bs, size_t lds) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_align_persistent<LW>, BLOCK, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_align_persistent<LW>, (int)bs, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    cached = (uint32_t)cus * (uint32_t)per_cu * BLOCK;
-    return cached;
+    return (uint32_t)cus * (uint32_t)per_cu * bs;
+}
+
+// LDS bytes per lane for reads up to mlen bases (an odd number of dwords,
+// which spreads the lanes' rows over the banks) and the largest block that
+// keeps a block's LDS within 64 KB.
+inline uint32_t lds_stride_for(uint32_t mlen) {
+    uint32_t dw = (mlen + 3) / 4;
+    if ((dw & 1) == 0) dw++;
+    return dw * 4;
+}
+inline uint32_t block_for(uint32_t stride) {
+    uint32_t bs = BLOCK;
+    while (bs > 64 && (size_t)bs * stride > 65536) bs /= 2;
+    return bs;
 }
 
 template <int LW>
@@ -1331,15 +1390,18 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     const uint32_t n = rd->n_reads;
     const DevIndex D = dev_index(ix);
     const Params P = make_params(*p);
-    ReadsView rv{rd->bases, rd->offsets, rd->max_diff, rd->n_reads, rd->max_len};
+    ReadsView rv{rd->bases, rd->offsets, rd->lengths, rd->max_diff, rd->n_reads, rd->max_len};
     const uint32_t mlen = std::max<uint32_t>(rd->max_len, 1);
     const uint32_t worst_stack = 8 * (mlen + BWFM_MAX_DIFF) + 1;  // never overflows
+    const uint32_t lstride = lds_stride_for(mlen);
+    const uint32_t bs = block_for(lstride);
+    const size_t lds = (size_t)bs * lstride;
     const bool plain = p->form == BWFM_FORM_PLAIN;
-    const uint32_t lanes = plain ? std::max<uint32_t>(n, 1) : std::min<uint32_t>(persistent_lanes<LW>(),
-                                                                                 ((std::max<uint32_t>(n, 1) + 255) / 256) * 256);
+    const uint32_t nr_up = ((std::max<uint32_t>(n, 1) + bs - 1) / bs) * bs;
+    const uint32_t lanes = plain ? nr_up : std::min<uint32_t>(persistent_lanes<LW>(bs, lds), nr_up);
     const uint32_t stack_cap = plain ? std::min<uint32_t>(worst_stack, PLAIN_STACK) : worst_stack;
     const uint64_t stage_cap = std::max<uint64_t>(4ull * n, 4096);
-    size_t need = (size_t)lanes * stack_cap * 16 + (size_t)lanes * FAST_CAND * 16 + (size_t)lanes * mlen;
+    size_t need = (size_t)lanes * stack_cap * 16 + (size_t)lanes * FAST_CAND * 16;
     need += (size_t)n * 4 * 2 + (size_t)n * 8 + stage_cap * 16 + scan_part_elems(n) * 8 + 16 * 256;
     void *w;
     int rc = ws_reserve(ix, need, &w);
@@ -1347,7 +1409,6 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     Carver cv{(char *)w};
     uint4 *lstack = cv.take<uint4>((size_t)lanes * stack_cap);
     uint4 *lcand = cv.take<uint4>((size_t)lanes * FAST_CAND);
-    uint8_t *lD = cv.take<uint8_t>((size_t)lanes * mlen);
     uint32_t *n_rep = cv.take<uint32_t>(n);
     uint32_t *slow_list = cv.take<uint32_t>(n);
     uint64_t *stage_off = cv.take<uint64_t>(n);
@@ -1357,17 +1418,20 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     uint32_t *n_slow = ctl, *next_read = ctl + 1;
     unsigned long long *stage_used = reinterpret_cast<unsigned long long *>(ctl + 2);
     HIPCHK(hipMemsetAsync(ctl, 0, 64, st));
-    LaneBufs lb{lstack, lcand, lD, lanes, stack_cap, FAST_CAND};
+    // plain lanes start together and stay roughly in step: interleave their
+    // buffers; persistent lanes drift apart: give each a contiguous run
+    LaneBufs lb = plain ? LaneBufs{lstack, lcand, 1, lanes, stack_cap, 1, lanes, FAST_CAND, lstride}
+                        : LaneBufs{lstack, lcand, stack_cap, 1, stack_cap, FAST_CAND, 1, FAST_CAND, lstride};
     ReadOut O{n_rep, res->c1, res->c2, res->status, slow_list, n_slow, stage, stage_used, stage_cap, stage_off, expand};
     CallTimer tm(st);
     if (n) {
         if (plain) {
             int t = tm.begin("align_plain");
-            k_align_plain<LW><<<blocks(n, BLOCK), BLOCK, 0, st>>>(D, rv, P, lb, O);
+            k_align_plain<LW><<<nr_up / bs, bs, lds, st>>>(D, rv, P, lb, O);
             tm.end(t);
         } else {
             int t = tm.begin("align_persistent");
-            k_align_persistent<LW><<<lanes / BLOCK, BLOCK, 0, st>>>(D, rv, P, lb, O, next_read);
+            k_align_persistent<LW><<<lanes / bs, bs, lds, st>>>(D, rv, P, lb, O, next_read);
             tm.end(t);
         }
         HIPCHK(hipGetLastError());
@@ -1385,16 +1449,16 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
         std::sort(hl.begin(), hl.end());
         HIPCHK(hipMemcpy(slow_list, hl.data(), 4ull * ns, hipMemcpyHostToDevice));
         scap = P.max_hits + 1;
-        size_t sbytes = (size_t)ns * worst_stack * 16 + (size_t)ns * scap * 16 + (size_t)ns * mlen + 1024;
+        size_t sbytes = (size_t)ns * worst_stack * 16 + (size_t)ns * scap * 16 + 1024;
         if (hipMalloc(&slow_mem, sbytes) != hipSuccess) return fail(BWFM_E_NOMEM, "second-pass buffers");
         Carver sc{(char *)slow_mem};
         uint4 *sstack = sc.take<uint4>((size_t)ns * worst_stack);
         scand = sc.take<uint4>((size_t)ns * scap);
-        uint8_t *sD = sc.take<uint8_t>((size_t)ns * mlen);
-        LaneBufs sb{sstack, scand, sD, ns, worst_stack, scap};
+        // hit slots interleaved (stride ns): the compaction reads them that way
+        LaneBufs sb{sstack, scand, worst_stack, 1, worst_stack, 1, ns, scap, lstride};
         int t = tm.begin("align_slow");
-        k_align_slow<LW><<<blocks(ns, BLOCK), BLOCK, 0, st>>>(D, rv, P, sb, slow_list, ns, n_rep, res->c1, res->c2,
-                                                              res->status, expand);
+        k_align_slow<LW><<<blocks(ns, bs), bs, lds, st>>>(D, rv, P, sb, slow_list, ns, n_rep, res->c1, res->c2,
+                                                          res->status, expand);
         tm.end(t);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
@@ -1714,6 +1778,33 @@ extern "C" int bwfm_timing_get(const char *kernel, double *total_ms, uint64_t *l
     auto it = timing().acc.find(kernel);
     *total_ms = it == timing().acc.end() ? 0.0 : it->second.first;
     *launches = it == timing().acc.end() ? 0 : it->second.second;
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_probe_gather(const void *buf, uint64_t bytes, uint32_t line_bytes, uint32_t lanes, uint32_t iters,
+                                 uint32_t *sink, double *ms_out, void *stream) {
+    if (!buf || !sink || !ms_out || (line_bytes != 64 && line_bytes != 128) || lanes == 0 || lanes % 256 ||
+        bytes < line_bytes)
+        return fail(BWFM_E_INVAL, "probe_gather: bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t n_lines = bytes / line_bytes;
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, st));
+    if (line_bytes == 128)
+        k_probe_gather<32><<<lanes / 256, 256, 0, st>>>((const uint4 *)buf, n_lines, iters, sink);
+    else
+        k_probe_gather<16><<<lanes / 256, 256, 0, st>>>((const uint4 *)buf, n_lines, iters, sink);
+    hipError_t e = hipGetLastError();
+    HIPCHK(hipEventRecord(b, st));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return fail(BWFM_E_DEVICE, std::string("k_probe_gather: ") + hipGetErrorString(e));
+    *ms_out = ms;
     return BWFM_OK;
 }
 

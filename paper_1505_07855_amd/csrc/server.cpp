@@ -1,0 +1,399 @@
+// Continuous-batching request server over the alignment path.
+//
+// Requests (read pairs in host memory) are queued by bwfm_server_submit.  A
+// worker thread owns a HIP stream and a device arena of fixed size; it
+// admits queued requests in arrival order while their reads fit in the
+// arena, copies them there, and then runs scheduling steps.  Each step takes
+// up to step_pairs pairs from the admitted requests, oldest first, so the
+// tail of one request and the head of the next share a launch; it aligns both
+// ends of every selected pair in one batched launch (reads addressed by start
+// offset and length inside the arena), pairs them, and copies the pair
+// records back.  A request completes when its last pair has been processed;
+// its arena range is then freed, which admits the next waiting request.
+// Results do not depend on how requests are mixed: every read is aligned and
+// every pair decided on its own.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+
+#include "bwfm_internal.h"
+
+using namespace bwfm;
+
+namespace {
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    uint64_t id = 0;
+    uint32_t n_pairs = 0;
+    std::vector<uint8_t> bases[2];
+    std::vector<uint64_t> offs[2];  // n_pairs + 1 each
+    uint64_t bytes = 0;             // arena bytes (both ends, 256-byte aligned)
+    uint64_t arena_off = 0;
+    uint64_t end_off[2] = {0, 0};   // arena offset of each end's bases
+    uint32_t next_pair = 0;         // first pair not yet scheduled
+    uint32_t done_pairs = 0;
+    std::vector<bwfm_pair> out;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int state = 0;  // 0 queued, 1 admitted, 2 done, 3 failed
+    int err = 0;
+};
+
+// first-fit allocator over [0, size)
+struct Arena {
+    std::map<uint64_t, uint64_t> free_;  // offset -> size
+    explicit Arena(uint64_t size) { free_[0] = size; }
+    bool alloc(uint64_t n, uint64_t &off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                off = it->first;
+                uint64_t rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n) {
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+inline uint64_t round256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+}  // namespace
+
+struct bwfm_server {
+    const bwfm_index *ix = nullptr;
+    bwfm_aln_params ap{};
+    bwfm_pair_params pp{};
+    bwfm_server_params sp{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // device memory
+    uint8_t *arena_mem = nullptr;
+    uint64_t *d_off = nullptr;   // 2 * step_pairs start offsets
+    uint32_t *d_len = nullptr;   // 2 * step_pairs lengths
+    uint8_t *d_md = nullptr;     // 2 * step_pairs budgets (length rule)
+    uint64_t *d_hoff = nullptr;  // 2 * step_pairs + 1
+    uint4 *d_hits = nullptr;
+    uint64_t hit_cap = 0;
+    uint32_t *d_c1 = nullptr, *d_c2 = nullptr;
+    uint8_t *d_status = nullptr;
+    bwfm_pair *d_pairs = nullptr;
+    // host staging
+    std::vector<uint64_t> h_off;
+    std::vector<uint32_t> h_len;
+    std::vector<uint8_t> h_md;
+    uint8_t rule[BWFM_MAX_READ + 1];
+    std::vector<bwfm_pair> h_pairs;
+    // state
+    Arena arena{0};
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Request>> queued;
+    std::vector<std::shared_ptr<Request>> active;  // admission order
+    std::unordered_map<uint64_t, std::shared_ptr<Request>> all;
+    uint64_t next_id = 1;
+    bool stop = false;
+    int worker_error = 0;
+    std::string worker_msg;
+    bwfm_server_stats stats{};
+    std::thread worker;
+};
+
+namespace {
+
+void release_device(bwfm_server *s) {
+    void *ptrs[] = {s->arena_mem, s->d_off, s->d_len, s->d_md,   s->d_hoff,
+                    s->d_hits,      s->d_c1,  s->d_c2,  s->d_status, s->d_pairs};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+}
+
+// One scheduling step over the chunks (request, first pair, pair count).
+int run_step(bwfm_server *s, std::vector<std::tuple<std::shared_ptr<Request>, uint32_t, uint32_t>> &chunks) {
+    uint32_t P = 0;
+    for (auto &c : chunks) P += std::get<2>(c);
+    const bool paired = s->sp.paired != 0;
+    const uint32_t ends = paired ? 2 : 1;
+    // reads: all end-1 reads of the step, then all end-2 reads
+    uint32_t k = 0;
+    for (uint32_t e = 0; e < ends; e++)
+        for (auto &c : chunks) {
+            Request &q = *std::get<0>(c);
+            for (uint32_t j = std::get<1>(c); j < std::get<1>(c) + std::get<2>(c); j++) {
+                s->h_off[k] = q.end_off[e] + q.offs[e][j];
+                s->h_len[k] = (uint32_t)(q.offs[e][j + 1] - q.offs[e][j]);
+                s->h_md[k] = s->rule[std::min<uint32_t>(s->h_len[k], BWFM_MAX_READ)];
+                k++;
+            }
+        }
+    const uint32_t n = k;
+    const bool rule = s->sp.budget_rule != 0;
+    if (hipMemcpyAsync(s->d_off, s->h_off.data(), 8ull * n, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(s->d_len, s->h_len.data(), 4ull * n, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        (rule && hipMemcpyAsync(s->d_md, s->h_md.data(), n, hipMemcpyHostToDevice, s->stream) != hipSuccess))
+        return fail(BWFM_E_DEVICE, "server: step upload failed");
+    bwfm_reads rd{s->arena_mem, s->d_off, rule ? s->d_md : nullptr, n, s->sp.max_len, s->d_len};
+    bwfm_aln_result res{s->d_hoff, reinterpret_cast<bwfm_hit *>(s->d_hits), s->hit_cap, s->d_c1, s->d_c2, s->d_status};
+    int rc = bwfm_align_batch(s->ix, &rd, &s->ap, &res, s->stream);
+    if (rc == BWFM_E_CAPACITY) {
+        uint64_t need = 0;
+        if (hipMemcpy(&need, s->d_hoff + n, 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(BWFM_E_DEVICE, "server: reading hit need failed");
+        (void)hipFree(s->d_hits);
+        s->d_hits = nullptr;
+        s->hit_cap = need + need / 4 + 1024;
+        if (hipMalloc(&s->d_hits, s->hit_cap * 16) != hipSuccess) return fail(BWFM_E_NOMEM, "server: hit buffer");
+        res.hits = reinterpret_cast<bwfm_hit *>(s->d_hits);
+        res.hit_capacity = s->hit_cap;
+        rc = bwfm_align_batch(s->ix, &rd, &s->ap, &res, s->stream);
+    }
+    if (rc) return rc;
+    bwfm_aln_result r1 = res, r2 = res;
+    r2.hit_offsets = s->d_hoff + P;
+    r2.c1 = s->d_c1 + P;
+    r2.c2 = s->d_c2 + P;
+    r2.status = s->d_status + P;
+    rc = bwfm_pair_reads(s->ix, P, &r1, paired ? &r2 : nullptr, &s->pp, s->d_pairs, s->stream);
+    if (rc) return rc;
+    if (hipMemcpyAsync(s->h_pairs.data(), s->d_pairs, sizeof(bwfm_pair) * P, hipMemcpyDeviceToHost, s->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return fail(BWFM_E_DEVICE, "server: result download failed");
+    uint32_t o = 0;
+    for (auto &c : chunks) {
+        Request &q = *std::get<0>(c);
+        std::memcpy(q.out.data() + std::get<1>(c), s->h_pairs.data() + o, sizeof(bwfm_pair) * std::get<2>(c));
+        o += std::get<2>(c);
+    }
+    return BWFM_OK;
+}
+
+void worker_main(bwfm_server *s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        // admit in arrival order while the arena has room
+        std::vector<std::shared_ptr<Request>> admitted;
+        while (!s->queued.empty()) {
+            auto q = s->queued.front();
+            uint64_t off;
+            if (!s->arena.alloc(q->bytes, off)) break;
+            s->queued.pop_front();
+            q->arena_off = off;
+            q->end_off[0] = off;
+            q->end_off[1] = off + round256(q->bases[0].size());
+            q->state = 1;
+            q->t_admit = now_ms();
+            s->active.push_back(q);
+            admitted.push_back(q);
+        }
+        // choose this step's chunks, oldest request first
+        std::vector<std::tuple<std::shared_ptr<Request>, uint32_t, uint32_t>> chunks;
+        uint32_t room = s->sp.step_pairs;
+        for (auto &q : s->active) {
+            if (!room) break;
+            uint32_t left = q->n_pairs - q->next_pair;
+            if (!left) continue;
+            uint32_t take = std::min(left, room);
+            chunks.emplace_back(q, q->next_pair, take);
+            q->next_pair += take;
+            room -= take;
+        }
+        if (chunks.empty()) {
+            if (s->stop && s->queued.empty()) break;
+            s->cv_work.wait(lk);
+            continue;
+        }
+        lk.unlock();
+        int rc = BWFM_OK;
+        for (auto &q : admitted) {
+            for (int e = 0; e < 2 && rc == BWFM_OK; e++) {
+                if (q->bases[e].empty()) continue;
+                if (hipMemcpyAsync(s->arena_mem + q->end_off[e], q->bases[e].data(), q->bases[e].size(),
+                                   hipMemcpyHostToDevice, s->stream) != hipSuccess)
+                    rc = fail(BWFM_E_DEVICE, "server: request upload failed");
+            }
+        }
+        double t0 = now_ms();
+        if (rc == BWFM_OK) rc = run_step(s, chunks);
+        double t1 = now_ms();
+        std::string msg = rc ? last_error() : std::string();
+        lk.lock();
+        s->stats.steps++;
+        s->stats.busy_ms += t1 - t0;
+        for (auto &c : chunks) {
+            auto &q = std::get<0>(c);
+            if (rc) {
+                q->state = 3;
+                q->err = rc;
+            }
+            q->done_pairs += std::get<2>(c);
+            s->stats.pairs += std::get<2>(c);
+        }
+        if (rc) {
+            s->worker_error = rc;
+            s->worker_msg = msg;
+        }
+        // retire finished requests and free their arena ranges
+        std::vector<std::shared_ptr<Request>> keep;
+        for (auto &q : s->active) {
+            if (q->done_pairs == q->n_pairs || q->state == 3) {
+                if (q->state != 3) q->state = 2;
+                q->t_done = now_ms();
+                s->arena.release(q->arena_off, q->bytes);
+                for (int e = 0; e < 2; e++) {
+                    std::vector<uint8_t>().swap(q->bases[e]);
+                }
+                s->stats.requests_done++;
+            } else {
+                keep.push_back(q);
+            }
+        }
+        s->active.swap(keep);
+        s->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" int bwfm_server_create(const bwfm_index *ix, const bwfm_aln_params *ap, const bwfm_pair_params *pp,
+                                  const bwfm_server_params *sp, bwfm_server **out) {
+    if (!ix || !ap || !pp || !sp || !out) return fail(BWFM_E_INVAL, "server_create: NULL argument");
+    *out = nullptr;
+    if (ix->device < 0) return fail(BWFM_E_STATE, "server_create: index not uploaded");
+    if (sp->step_pairs < 1 || sp->arena_bytes < 4096 || sp->max_len < 1 || sp->max_len > BWFM_MAX_READ)
+        return fail(BWFM_E_INVAL, "server_create: bad server parameters");
+    if (ap->form != BWFM_FORM_BATCHED && ap->form != BWFM_FORM_PLAIN)
+        return fail(BWFM_E_INVAL, "server_create: bad form");
+    auto s = std::make_unique<bwfm_server>();
+    s->ix = ix;
+    s->ap = *ap;
+    s->pp = *pp;
+    s->sp = *sp;
+    s->device = ix->device;
+    s->arena = Arena(sp->arena_bytes);
+    const uint64_t R = 2ull * sp->step_pairs;
+    s->hit_cap = 4 * R + 1024;
+    if (hipSetDevice(s->device) != hipSuccess || hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(BWFM_E_DEVICE, "server_create: stream creation failed");
+    if (hipMalloc(&s->arena_mem, sp->arena_bytes) != hipSuccess || hipMalloc(&s->d_off, 8 * R) != hipSuccess ||
+        hipMalloc(&s->d_len, 4 * R) != hipSuccess || hipMalloc(&s->d_md, R) != hipSuccess ||
+        hipMalloc(&s->d_hoff, 8 * (R + 1)) != hipSuccess ||
+        hipMalloc(&s->d_hits, 16 * s->hit_cap) != hipSuccess || hipMalloc(&s->d_c1, 4 * R) != hipSuccess ||
+        hipMalloc(&s->d_c2, 4 * R) != hipSuccess || hipMalloc(&s->d_status, R) != hipSuccess ||
+        hipMalloc(&s->d_pairs, sizeof(bwfm_pair) * sp->step_pairs) != hipSuccess) {
+        release_device(s.get());
+        return fail(BWFM_E_NOMEM, "server_create: device allocation failed");
+    }
+    s->h_off.resize(R);
+    s->h_len.resize(R);
+    s->h_md.resize(R);
+    for (uint32_t L = 0; L <= BWFM_MAX_READ; L++)
+        s->rule[L] = (uint8_t)std::min(bwfm_max_diff_rule(L, 0.02, 0.04), BWFM_MAX_DIFF);
+    s->h_pairs.resize(sp->step_pairs);
+    bwfm_server *raw = s.release();
+    raw->worker = std::thread(worker_main, raw);
+    *out = raw;
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_server_submit(bwfm_server *s, const uint8_t *b1, const uint64_t *o1, const uint8_t *b2,
+                                  const uint64_t *o2, uint32_t n_pairs, uint64_t *ticket) {
+    if (!s || !o1 || !ticket || (s->sp.paired && !o2)) return fail(BWFM_E_INVAL, "server_submit: NULL argument");
+    if (n_pairs == 0) return fail(BWFM_E_INVAL, "server_submit: empty request");
+    auto q = std::make_shared<Request>();
+    q->n_pairs = n_pairs;
+    const int ends = s->sp.paired ? 2 : 1;
+    const uint8_t *bb[2] = {b1, b2};
+    const uint64_t *oo[2] = {o1, o2};
+    for (int e = 0; e < ends; e++) {
+        const uint64_t base = oo[e][0], total = oo[e][n_pairs] - base;
+        if (oo[e][n_pairs] < base || (total && !bb[e])) return fail(BWFM_E_INVAL, "server_submit: bad offsets");
+        for (uint32_t j = 0; j < n_pairs; j++)
+            if (oo[e][j + 1] < oo[e][j]) return fail(BWFM_E_INVAL, "server_submit: offsets decrease");
+        q->bases[e].assign(bb[e] + base, bb[e] + base + total);
+        q->offs[e].resize(n_pairs + 1);
+        for (uint32_t j = 0; j <= n_pairs; j++) q->offs[e][j] = oo[e][j] - base;
+        q->bytes += round256(total);
+    }
+    q->bytes = std::max<uint64_t>(q->bytes, 256);
+    if (q->bytes > s->sp.arena_bytes)
+        return fail(BWFM_E_CAPACITY, "server_submit: request larger than the arena");
+    q->out.resize(n_pairs);
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->stop) return fail(BWFM_E_STATE, "server_submit: server is stopping");
+    q->id = s->next_id++;
+    q->t_submit = now_ms();
+    s->all[q->id] = q;
+    s->queued.push_back(q);
+    *ticket = q->id;
+    s->cv_work.notify_one();
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_server_wait(bwfm_server *s, uint64_t ticket, bwfm_pair *out, bwfm_request_times *times) {
+    if (!s) return fail(BWFM_E_INVAL, "server_wait: NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(BWFM_E_INVAL, "server_wait: unknown ticket");
+    auto q = it->second;
+    s->cv_done.wait(lk, [&] { return q->state >= 2; });
+    s->all.erase(it);
+    if (q->state == 3) return fail(q->err, "server: request failed: " + s->worker_msg);
+    if (out) std::memcpy(out, q->out.data(), sizeof(bwfm_pair) * q->n_pairs);
+    if (times) {
+        times->queued_ms = q->t_admit - q->t_submit;
+        times->latency_ms = q->t_done - q->t_submit;
+        times->service_ms = q->t_done - q->t_admit;
+    }
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_server_get_stats(bwfm_server *s, bwfm_server_stats *out) {
+    if (!s || !out) return fail(BWFM_E_INVAL, "server_get_stats: NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    *out = s->stats;
+    return BWFM_OK;
+}
+
+extern "C" void bwfm_server_destroy(bwfm_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    release_device(s);
+    delete s;
+}

@@ -1,0 +1,122 @@
+"""Served form: continuous batching must not change any result.  Each
+request's pair records equal those of the same pairs aligned alone through
+the direct path (and, on a sample, the oracle's), whatever the mix, the step
+size and the arena pressure."""
+from __future__ import annotations
+
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1505_07855_amd as bw
+from gen import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _direct(ix, p, req, w):
+    """The request alone: both ends aligned in one batched call, paired."""
+    b1, o1, b2, o2, n = req
+    both = np.concatenate([b1, b2])
+    offs = np.concatenate([o1[:-1], o1[-1] + o2]).astype(np.uint64)
+    L = np.diff(offs).astype(int)
+    md = np.array([bw.max_diff_rule(int(x)) for x in L], np.uint8)
+    res = bw.align_batch(ix, torch.from_numpy(both).cuda(), torch.from_numpy(offs.view(np.int64)).cuda(), p,
+                         max_diff=torch.from_numpy(md).cuda(), max_len=150)
+    r1, r2 = res.window(0, n), res.window(n, 2 * n)
+    out = bw.pairs_numpy(bw.pair_reads(ix, r1, r2, w["lo"], w["hi"], w["mu"], configs.MAX_OCC))
+    return out[:n], md
+
+
+@pytest.fixture(scope="module")
+def setup():
+    g = configs.c2_genome(2_000_000, seed=55)
+    ix = bw.Index(g.seq).upload()
+    sizes = [300, 5000, 1200, 17, 9000, 2500, 1, 640]
+    reqs = []
+    for i, s in enumerate(sizes):
+        pr = configs.c4_request(g, s, 900 + i)
+        reqs.append((pr.end1.bases, pr.end1.offsets, pr.end2.bases, pr.end2.offsets, s))
+    return g, ix, reqs
+
+
+def _arena_need(r):
+    # both ends' bases, each rounded up to 256 bytes (the server's accounting)
+    return sum(-(-int(o[-1] - o[0]) // 256) * 256 for o in (r[1], r[3]))
+
+
+@pytest.mark.parametrize("step_pairs,arena", [(1024, 4 << 20), (700, "tight"), (65536, 64 << 20)])
+def test_served_equals_alone(setup, step_pairs, arena):
+    g, ix, reqs = setup
+    w = configs.PAIR_WINDOW
+    p = bw.Params(**configs.PARAMS["C3"])
+    if arena == "tight":  # room for the largest request only: admission must wait
+        arena = max(_arena_need(r) for r in reqs) + 512
+    srv = bw.Server(ix, p, w["lo"], w["hi"], w["mu"], configs.MAX_OCC, arena_bytes=arena,
+                    step_pairs=step_pairs, max_len=150, budget_rule=True)
+    # submit from two threads at once so requests interleave in steps
+    tickets = [None] * len(reqs)
+
+    def sub(idx):
+        for i in idx:
+            r = reqs[i]
+            tickets[i] = srv.submit(r[0], r[1], r[2], r[3])
+
+    ts = [threading.Thread(target=sub, args=(range(k, len(reqs), 2),)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert all(t is not None for t in tickets)
+    outs = [srv.wait(tickets[i], reqs[i][4]) for i in range(len(reqs))]
+    st = srv.stats()
+    srv.close()
+    assert st["requests_done"] == len(reqs) and st["pairs"] == sum(r[4] for r in reqs)
+    if step_pairs < 2000:
+        assert st["steps"] > len(reqs)  # requests were split across steps
+    for i, r in enumerate(reqs):
+        alone, _ = _direct(ix, p, r, w)
+        assert np.array_equal(outs[i][0].view(np.uint8), alone.view(np.uint8)), f"request {i}"
+        assert outs[i][1]["latency_ms"] >= outs[i][1]["service_ms"] >= 0
+
+
+def test_served_matches_oracle_on_a_request(setup):
+    g, ix, reqs = setup
+    w = configs.PAIR_WINDOW
+    p = bw.Params(**configs.PARAMS["C3"])
+    srv = bw.Server(ix, p, w["lo"], w["hi"], w["mu"], configs.MAX_OCC, step_pairs=2048, max_len=150,
+                    budget_rule=True)
+    r = reqs[2]
+    t = srv.submit(r[0], r[1], r[2], r[3])
+    got, _ = srv.wait(t, r[4])
+    srv.close()
+    ox = oracle.Index(g.seq)
+    op = oracle.Params(**configs.PARAMS["C3"])
+    ores = []
+    for b, o in ((r[0], r[1]), (r[2], r[3])):
+        md = np.array([oracle.max_diff_rule(int(x)) for x in np.diff(o)], np.uint8)
+        ores.append(oracle.align(ox, b, o, op, max_diff=md, threads=8))
+    po1, pos1 = oracle.locate(ox, ores[0].hits, configs.MAX_OCC)
+    po2, pos2 = oracle.locate(ox, ores[1].hits, configs.MAX_OCC)
+    exp = oracle.pair(ores[0], po1, pos1, ores[1], po2, pos2, w["lo"], w["hi"], w["mu"])
+    assert np.array_equal(got.view(np.uint8), exp.view(np.uint8))
+
+
+def test_request_larger_than_arena_is_rejected(setup):
+    g, ix, reqs = setup
+    w = configs.PAIR_WINDOW
+    srv = bw.Server(ix, bw.Params(**configs.PARAMS["C3"]), w["lo"], w["hi"], w["mu"], configs.MAX_OCC,
+                    arena_bytes=64 << 10, step_pairs=512, max_len=150)
+    r = reqs[4]  # 9000 pairs, ~2 MB of bases
+    with pytest.raises(bw.BwfmError) as e:
+        srv.submit(r[0], r[1], r[2], r[3])
+    assert e.value.code == -5
+    small = reqs[3]
+    t = srv.submit(small[0], small[1], small[2], small[3])
+    out, _ = srv.wait(t, small[4])
+    srv.close()
+    assert len(out) == small[4]
