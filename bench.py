@@ -46,7 +46,7 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=100000, help="pairs in the oracle's timed sample")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--line-bytes", type=int, default=128)
+    ap.add_argument("--line-bytes", type=int, default=64)
     ap.add_argument("--steps-plain", type=int, default=0, help="steps for the plain form (default: --steps)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -27,9 +27,9 @@ PARAMS = {
 # index layout per workload: rows per rank line, SA sample interval
 LAYOUT = {
     "C1": dict(line_bytes=64, bases_per_line=128, sa_sample=32),
-    "C2": dict(line_bytes=128, bases_per_line=448, sa_sample=32),
-    "C3": dict(line_bytes=128, bases_per_line=448, sa_sample=32),
-    "C5": dict(line_bytes=128, bases_per_line=448, sa_sample=32),
+    "C2": dict(line_bytes=64, bases_per_line=192, sa_sample=32),
+    "C3": dict(line_bytes=64, bases_per_line=192, sa_sample=32),
+    "C5": dict(line_bytes=64, bases_per_line=192, sa_sample=32),
 }
 # fixed insert window for the N(300, 30) fragment model: mu +- 4 sd
 PAIR_WINDOW = dict(lo=180, hi=420, mu=300)

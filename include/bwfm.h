@@ -144,7 +144,7 @@ typedef struct {
     int32_t seed_len;       /* 5' seed length; 0 = no seed rule */
     int32_t seed_diff;      /* most differences inside the seed */
     int32_t indel_end_skip; /* no insertion within this many bases of either end */
-    int32_t s_mm, s_gapo, s_gape; /* score of a mismatch, gap open, gap extension */
+    int32_t s_mm, s_gapo, s_gape; /* score of a mismatch, gap open, gap extension, 0..63 */
     int32_t mode;           /* BWFM_MODE_ALL or BWFM_MODE_BEST */
     int32_t max_best;       /* BEST: second tier reported only if c1 <= max_best */
     uint32_t max_hits;      /* reads with more candidate hits report none, 1..65536 */

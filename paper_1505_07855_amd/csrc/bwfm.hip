@@ -50,6 +50,7 @@ constexpr int INF_SCORE = 0x7fffffff;
 constexpr uint32_t PLAIN_STACK = 320;  // stack entries per lane, plain form first pass
 constexpr uint32_t FAST_CAND = 64;     // hit slots per lane, first pass
 constexpr int BLOCK = 256;
+constexpr int POPS_PER_STEP = 4;  // stack pops per lane per persistent iteration
 
 struct Params {
     int max_diff, max_gapo, max_gape, seed_len, seed_diff, ies, s_mm, s_gapo, s_gape, mode, max_best;
@@ -184,18 +185,21 @@ __device__ __forceinline__ uint32_t lf_step(const DevIndex &ix, const DevDir &d,
 // ------------------------------------------------------------------ search state
 
 // packed state: x = k, y = l, z = (i + 1) | gs << 10 | nmm << 12 | ngo << 16 | nge << 20 | sd << 24,
-// w = score | len << 16
+// w = score | len << 10 | lb << 20, where lb = score + minc * D[i] is the
+// state's lower bound on its final score, fixed once D is built
 struct State {
     uint32_t k, l;
     int i, gs, nmm, ngo, nge, sd, score, len;
 };
 
-__device__ __forceinline__ uint4 pack(const State &s) {
+__device__ __forceinline__ uint4 pack(const State &s, int lb) {
     return make_uint4(s.k, s.l,
                       (uint32_t)(s.i + 1) | ((uint32_t)s.gs << 10) | ((uint32_t)s.nmm << 12) | ((uint32_t)s.ngo << 16) |
                           ((uint32_t)s.nge << 20) | ((uint32_t)s.sd << 24),
-                      (uint32_t)s.score | ((uint32_t)s.len << 16));
+                      (uint32_t)s.score | ((uint32_t)s.len << 10) | ((uint32_t)lb << 20));
 }
+
+__device__ __forceinline__ int entry_lb(uint4 v) { return (int)(v.w >> 20); }
 
 __device__ __forceinline__ State unpack(uint4 v) {
     State s;
@@ -207,8 +211,8 @@ __device__ __forceinline__ State unpack(uint4 v) {
     s.ngo = (v.z >> 16) & 15;
     s.nge = (v.z >> 20) & 15;
     s.sd = (v.z >> 24) & 15;
-    s.score = v.w & 0xffff;
-    s.len = v.w >> 16;
+    s.score = v.w & 1023;
+    s.len = (v.w >> 10) & 1023;
     return s;
 }
 
@@ -326,19 +330,27 @@ __device__ __forceinline__ State root_state(const DevIndex &ix, int m) {
 }
 
 // Advance the search until the current state needs expanding: pop, drop
-// states the BEST bound excludes, record completed hits.  Returns 1 when cur
-// must be expanded (Di = D[cur.i]), 0 when the strand's search is over, or
+// states the BEST bound excludes (a popped entry by its stored lower bound,
+// without unpacking), record completed hits.  At most max_pops entries are
+// popped.  Returns 1 when cur must be expanded (Di = D[cur.i]), 0 when the
+// strand's search is over, 2 when the pop limit was reached first, or
 // -R_CAND when the hit buffer overflowed.
-__device__ int resolve(State &cur, bool &valid, int strand, const Params &P, LaneCtx &c, int phase, int &Di) {
-    for (;;) {
+__device__ int resolve(State &cur, bool &valid, int strand, const Params &P, LaneCtx &c, int phase, int &Di,
+                       int max_pops) {
+    for (int pops = 0;;) {
+        const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
         if (!valid) {
             if (c.sp == 0) return 0;
+            if (pops == max_pops) return 2;
+            pops++;
             c.sp--;
-            cur = unpack(c.stack[(size_t)c.sp * c.sstride]);
+            const uint4 e = c.stack[(size_t)c.sp * c.sstride];
+            if (entry_lb(e) > bound) continue;
+            cur = unpack(e);
             valid = true;
         }
         Di = pd_d(c, cur.i);
-        if (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE && cur.score + P.minc * Di > c.best + P.s_mm) {
+        if (cur.score + P.minc * Di > bound) {
             valid = false;
             continue;
         }
@@ -363,18 +375,20 @@ __device__ int expand_children(State &cur, bool &valid, const uint32_t (&ok)[4],
     const int diffs = cur.nmm + cur.ngo + cur.nge;
     const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
     State pend;
+    int pend_lb = 0;
     bool have = false;
     int rc = R_OK;
-    auto offer = [&](const State &ch) {
+    auto offer = [&](const State &ch, int lb) {
         if (have) {
             if (c.sp == c.stack_cap) {
                 rc = R_STACK;
             } else {
-                c.stack[(size_t)c.sp * c.sstride] = pack(pend);
+                c.stack[(size_t)c.sp * c.sstride] = pack(pend, pend_lb);
                 c.sp++;
             }
         }
         pend = ch;
+        pend_lb = lb;
         have = true;
     };
     // deletions: reference base a between read bases i and i + 1
@@ -400,7 +414,7 @@ __device__ int expand_children(State &cur, bool &valid, const uint32_t (&ok)[4],
                     ch.sd = nsd;
                     ch.score = nsc;
                     ch.len = cur.len + 1;
-                    offer(ch);
+                    offer(ch, nsc + P.minc * Di);
                 }
             }
         }
@@ -420,7 +434,7 @@ __device__ int expand_children(State &cur, bool &valid, const uint32_t (&ok)[4],
             ch.nge = nge;
             ch.sd = nsd;
             ch.score = nsc;
-            offer(ch);
+            offer(ch, nsc + P.minc * Dn);
         }
     }
     // mismatches, then the match (offered last, so it becomes current)
@@ -441,7 +455,7 @@ __device__ int expand_children(State &cur, bool &valid, const uint32_t (&ok)[4],
             ch.sd = nsd;
             ch.score = nsc;
             ch.len = cur.len + 1;
-            offer(ch);
+            offer(ch, nsc + P.minc * Dn);
         }
         if (b < 4 && sel4(ok, b) < sel4(ol, b) && diffs + Dn <= maxd && cur.score + P.minc * Dn <= bound) {
             State ch = cur;
@@ -450,7 +464,7 @@ __device__ int expand_children(State &cur, bool &valid, const uint32_t (&ok)[4],
             ch.i = cur.i - 1;
             ch.gs = GAP_NONE;
             ch.len = cur.len + 1;
-            offer(ch);
+            offer(ch, cur.score + P.minc * Dn);
         }
     }
     if (have) cur = pend;
@@ -495,7 +509,7 @@ __device__ int search_strand(const DevIndex &ix, const DevDir &sd_, const uint8_
     c.sp = 0;
     for (;;) {
         int Di;
-        int rr = resolve(cur, valid, strand, P, c, phase, Di);
+        int rr = resolve(cur, valid, strand, P, c, phase, Di, 0x7fffffff);
         if (rr == 0) return R_OK;
         if (rr < 0) return -rr;
         c.expand++;
@@ -735,8 +749,10 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
                 q2 = dl + 1;
             }
         } else if (phase == PZ_SEARCH) {
-            int rr = resolve(cur, valid, strand, P, c, PH_FAST, Di);
-            if (rr < 0) {
+            int rr = resolve(cur, valid, strand, P, c, PH_FAST, Di, POPS_PER_STEP);
+            if (rr == 2) {
+                // pop limit reached: keep popping next iteration
+            } else if (rr < 0) {
                 send_to_second_pass(O, r);
                 if (O.expand) O.expand[r] = c.expand;
                 phase = PZ_IDLE;
@@ -1579,7 +1595,7 @@ extern "C" int bwfm_align_batch(const bwfm_index *cix, const bwfm_reads *rd, con
         p->indel_end_skip < 0 || p->s_mm < 0 || p->s_gapo < 0 || p->s_gape < 0 ||
         (p->mode != BWFM_MODE_ALL && p->mode != BWFM_MODE_BEST) || p->max_best < 0 || p->max_hits < 1 ||
         (p->form != BWFM_FORM_BATCHED && p->form != BWFM_FORM_PLAIN) ||
-        p->max_hits > 65536 || p->s_mm * 15 > 4000 || p->s_gapo * 15 > 4000 || p->s_gape * 15 > 4000)
+        p->max_hits > 65536 || p->s_mm > 63 || p->s_gapo > 63 || p->s_gape > 63)
         return fail(BWFM_E_INVAL, "align_batch: parameter out of range");
     std::lock_guard<std::mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
