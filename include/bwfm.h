@@ -76,10 +76,11 @@ typedef struct {
  *   ref: host, n codes 0..3 (borrowed for the call only).
  *   p:   layout; NULL = {128, 0, 32, 0}.
  *   out: receives a new index (host part only; see bwfm_index_upload).
- * Each direction holds the BWT of S$ packed 2 bits per row with $ stored
- * as A, the row of $ ("primary"), C[a] = 1 + #symbols < a, rank lines
- * (4 x uint32 counts of A, C, G, T before the line, $ counted as A, then
- * the line's packed rows), and SA samples.  Errors: E_INVAL (NULL or bad
+ * Each direction holds the BWT of S$ with $ stored as A, the row of $
+ * ("primary"), C[a] = 1 + #symbols < a, rank lines (4 x uint32 counts of
+ * A, C, G, T before the line, $ counted as A, then the line's rows as bit
+ * planes: for each 32 rows a uint32 of the 2-bit codes' high bits followed
+ * by a uint32 of their low bits), and SA samples.  Errors: E_INVAL (NULL or bad
  * layout), E_BASE, E_TOOLONG (n + 1 >= 2^32), E_NOMEM.
  */
 int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index_params *p, bwfm_index **out);
@@ -206,9 +207,12 @@ int bwfm_align_batch(const bwfm_index *idx, const bwfm_reads *reads, const bwfm_
 
 /* As bwfm_align_batch, also writing each read's search work -- the number
  * of search states expanded (each expansion issues the two rank queries at
- * k and l + 1), summed over both passes -- to expand (device, n_reads). */
+ * k and l + 1), summed over both passes -- to expand (device, n_reads).
+ * work (device, 3 uint64, or NULL; batched form only) receives the first
+ * pass's loop iterations summed over waves, lane iterations spent on a read,
+ * and lane iterations that issued a rank query. */
 int bwfm_align_batch_counted(const bwfm_index *idx, const bwfm_reads *reads, const bwfm_aln_params *p,
-                             bwfm_aln_result *res, uint32_t *expand, void *hip_stream);
+                             bwfm_aln_result *res, uint32_t *expand, uint64_t *work, void *hip_stream);
 
 /* ------------------------------------------------------------------ */
 /* Locate and pairing ("sampe"; section 2: repeats give several

@@ -121,7 +121,7 @@ def lib():
             "bwfm_index_get_sa_samples": ([P, c_int, P], c_int),
             "bwfm_index_occ": ([P, c_int, u64, P], c_int),
             "bwfm_align_batch": ([P, P, P, P, P], c_int),
-            "bwfm_align_batch_counted": ([P, P, P, P, P, P], c_int),
+            "bwfm_align_batch_counted": ([P, P, P, P, P, P, P], c_int),
             "bwfm_locate": ([P, u32, P, u32, P, P, u64, P], c_int),
             "bwfm_pair_reads": ([P, u32, P, P, P, P, P], c_int),
             "bwfm_estimate_insert": ([P, u64, P], c_int),
@@ -262,6 +262,7 @@ class AlignResult:
     status: object       # uint8 [n]
     n_reads: int
     expand: object = None
+    work: object = None
 
     def _c(self) -> _AlnResult:
         return _AlnResult(_dptr(self.hit_offsets), _dptr(self.hits), self.hits.shape[0], _dptr(self.c1),
@@ -315,12 +316,14 @@ def align_batch(index: Index, bases, offsets, params: Params, max_diff=None, max
                           torch.empty(n, dtype=torch.uint8, device=dev), n)
     if counted and out.expand is None:
         out.expand = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    if counted and getattr(out, "work", None) is None:
+        out.work = torch.zeros(3, dtype=torch.int64, device=dev)
     pc = params._c()
     for attempt in range(2):
         res = out._c()
         if counted:
             rc = lib().bwfm_align_batch_counted(index.handle, ctypes.byref(rd), ctypes.byref(pc), ctypes.byref(res),
-                                                _dptr(out.expand), _stream_ptr(stream))
+                                                _dptr(out.expand), _dptr(out.work), _stream_ptr(stream))
         else:
             rc = lib().bwfm_align_batch(index.handle, ctypes.byref(rd), ctypes.byref(pc), ctypes.byref(res),
                                         _stream_ptr(stream))

@@ -9,8 +9,9 @@
 //
 // Layout.  Each direction of the index is an array of rank lines (64 or
 // 128 bytes): four uint32 counts of A, C, G, T before the line ($ counted as
-// A), then the line's BWT rows packed two bits each, so one rank query is one
-// line fetch plus popcounts within the line.  Row-sampled suffix array values
+// A), then the line's BWT rows as bit planes -- per 32 rows a word of the
+// codes' high bits and a word of their low bits -- so one rank query is one
+// line fetch plus three popcounts per 32 rows.  Row-sampled suffix array values
 // serve locate.
 //
 // Search.  One lane per read, both strands in turn, each strand 5' end
@@ -115,17 +116,13 @@ __device__ __forceinline__ uint32_t line_of(const DevIndex &ix, uint32_t i) {
     return (uint32_t)__umul64hi((uint64_t)i, ix.magic);
 }
 
-__device__ __forceinline__ void count_word(uint64_t x, int valid, uint32_t &cC, uint32_t &cG, uint32_t &cT) {
-    int nv = valid < 0 ? 0 : (valid > 32 ? 32 : valid);
-    uint64_t mask = nv >= 32 ? ~0ULL : ((1ULL << (2 * nv)) - 1);
-    x &= mask;
-    uint64_t lo = x & 0x5555555555555555ULL, hi = (x >> 1) & 0x5555555555555555ULL;
-    cT += __popcll(lo & hi);
-    cG += __popcll(hi & ~lo);
-    cC += __popcll(lo & ~hi);
+// mask of the first t rows of a 32-row group (t may be <= 0 or >= 32)
+__device__ __forceinline__ uint32_t rows_mask(int t) {
+    return t >= 32 ? 0xffffffffu : (t <= 0 ? 0u : ((1u << t) - 1u));
 }
 
-// Occ(a, i) for all four bases (i <= n + 1).
+// Occ(a, i) for all four bases (i <= n + 1).  Per 32-row group: one word of
+// high bits (h) and one of low bits (l); T = h & l, G = h & ~l, C = ~h & l.
 template <int LW>
 __device__ __forceinline__ void occ4(const DevIndex &ix, const DevDir &d, uint32_t i, uint32_t o[4]) {
     uint32_t line = line_of(ix, i);
@@ -136,8 +133,10 @@ __device__ __forceinline__ void occ4(const DevIndex &ix, const DevDir &d, uint32
 #pragma unroll
     for (int q = 0; q < LW / 4 - 1; q++) {
         uint4 v = L[1 + q];
-        count_word((uint64_t)v.x | ((uint64_t)v.y << 32), r - q * 64, cC, cG, cT);
-        count_word((uint64_t)v.z | ((uint64_t)v.w << 32), r - q * 64 - 32, cC, cG, cT);
+        uint32_t m0 = rows_mask(r - q * 64), m1 = rows_mask(r - q * 64 - 32);
+        cT += __popc(v.x & v.y & m0) + __popc(v.z & v.w & m1);
+        cG += __popc(v.x & ~v.y & m0) + __popc(v.z & ~v.w & m1);
+        cC += __popc(~v.x & v.y & m0) + __popc(~v.z & v.w & m1);
     }
     uint32_t cA = (uint32_t)r - cC - cG - cT;
     o[0] = h.x + cA - (i > d.primary ? 1u : 0u);
@@ -153,20 +152,14 @@ __device__ __forceinline__ uint32_t occ1(const DevIndex &ix, const DevDir &d, in
     int r = (int)(i - line * ix.bpl);
     const uint4 *L = reinterpret_cast<const uint4 *>(d.lines) + (size_t)line * (LW / 4);
     uint4 h = L[0];
-    uint64_t pat = 0x5555555555555555ULL * (uint64_t)a;
+    // rows of base a have high bit (a >> 1) and low bit (a & 1)
+    const uint32_t fh = (a & 2) ? 0u : 0xffffffffu, fl = (a & 1) ? 0u : 0xffffffffu;
     uint32_t c = 0;
 #pragma unroll
     for (int q = 0; q < LW / 4 - 1; q++) {
         uint4 v = L[1 + q];
-#pragma unroll
-        for (int half = 0; half < 2; half++) {
-            uint64_t x = half ? ((uint64_t)v.z | ((uint64_t)v.w << 32)) : ((uint64_t)v.x | ((uint64_t)v.y << 32));
-            int nv = r - q * 64 - half * 32;
-            nv = nv < 0 ? 0 : (nv > 32 ? 32 : nv);
-            uint64_t mask = (nv >= 32 ? ~0ULL : ((1ULL << (2 * nv)) - 1)) & 0x5555555555555555ULL;
-            uint64_t y = x ^ pat;
-            c += __popcll(~(y | (y >> 1)) & mask);
-        }
+        c += __popc((v.x ^ fh) & (v.y ^ fl) & rows_mask(r - q * 64));
+        c += __popc((v.z ^ fh) & (v.w ^ fl) & rows_mask(r - q * 64 - 32));
     }
     uint32_t base = a == 0 ? h.x : (a == 1 ? h.y : (a == 2 ? h.z : h.w));
     return base + c - ((a == 0 && i > d.primary) ? 1u : 0u);
@@ -178,43 +171,18 @@ __device__ __forceinline__ uint32_t lf_step(const DevIndex &ix, const DevDir &d,
     uint32_t line = line_of(ix, j);
     uint32_t r = j - line * ix.bpl;
     const uint32_t *L = d.lines + (size_t)line * LW;
-    int a = (L[4 + (r >> 4)] >> (2 * (r & 15))) & 3;
+    int a = (int)((((L[4 + 2 * (r >> 5)] >> (r & 31)) & 1) << 1) | ((L[5 + 2 * (r >> 5)] >> (r & 31)) & 1));
     return sel4(d.C, a) + occ1<LW>(ix, d, a, j);
 }
 
 // ------------------------------------------------------------------ search state
 
-// packed state: x = k, y = l, z = (i + 1) | gs << 10 | nmm << 12 | ngo << 16 | nge << 20 | sd << 24,
-// w = score | len << 10 | lb << 20, where lb = score + minc * D[i] is the
-// state's lower bound on its final score, fixed once D is built
-struct State {
-    uint32_t k, l;
-    int i, gs, nmm, ngo, nge, sd, score, len;
-};
-
-__device__ __forceinline__ uint4 pack(const State &s, int lb) {
-    return make_uint4(s.k, s.l,
-                      (uint32_t)(s.i + 1) | ((uint32_t)s.gs << 10) | ((uint32_t)s.nmm << 12) | ((uint32_t)s.ngo << 16) |
-                          ((uint32_t)s.nge << 20) | ((uint32_t)s.sd << 24),
-                      (uint32_t)s.score | ((uint32_t)s.len << 10) | ((uint32_t)lb << 20));
-}
-
+// Search states are packed in 16 bytes: x = k, y = l,
+// z = (i + 1) | gap state << 10 | n_mm << 12 | n_gapo << 16 | n_gape << 20 | seed diffs << 24,
+// w = score | |X| << 10 | lb << 20, where lb = score + minc * D[i] is the
+// state's lower bound on its final score, fixed once the D-array is built.
+// Every field fits: diffs <= 15, score <= 15 * 63, |X| <= 512 + 15.
 __device__ __forceinline__ int entry_lb(uint4 v) { return (int)(v.w >> 20); }
-
-__device__ __forceinline__ State unpack(uint4 v) {
-    State s;
-    s.k = v.x;
-    s.l = v.y;
-    s.i = (int)(v.z & 1023) - 1;
-    s.gs = (v.z >> 10) & 3;
-    s.nmm = (v.z >> 12) & 15;
-    s.ngo = (v.z >> 16) & 15;
-    s.nge = (v.z >> 20) & 15;
-    s.sd = (v.z >> 24) & 15;
-    s.score = v.w & 1023;
-    s.len = (v.w >> 10) & 1023;
-    return s;
-}
 
 // hit record, same bytes as bwfm_hit
 __device__ __forceinline__ uint4 make_hit(int strand, uint32_t k, uint32_t l, int len, int score, int nmm, int ngo,
@@ -319,24 +287,27 @@ __device__ __forceinline__ Seed seed_of(const Params &P, int m) {
     return s;
 }
 
-__device__ __forceinline__ State root_state(const DevIndex &ix, int m) {
-    State s;
-    s.k = 0;
-    s.l = ix.n;
-    s.i = m - 1;
-    s.gs = GAP_NONE;
-    s.nmm = s.ngo = s.nge = s.sd = s.score = s.len = 0;
-    return s;
+// fields of a packed state (see pack)
+__device__ __forceinline__ int s_i(uint4 s) { return (int)(s.z & 1023) - 1; }
+__device__ __forceinline__ int s_gs(uint4 s) { return (s.z >> 10) & 3; }
+__device__ __forceinline__ int s_nmm(uint4 s) { return (s.z >> 12) & 15; }
+__device__ __forceinline__ int s_ngo(uint4 s) { return (s.z >> 16) & 15; }
+__device__ __forceinline__ int s_nge(uint4 s) { return (s.z >> 20) & 15; }
+__device__ __forceinline__ int s_sd(uint4 s) { return (s.z >> 24) & 15; }
+__device__ __forceinline__ int s_score(uint4 s) { return s.w & 1023; }
+__device__ __forceinline__ int s_len(uint4 s) { return (s.w >> 10) & 1023; }
+
+// the empty string's interval, nothing consumed, lower bound minc * D[m - 1]
+__device__ __forceinline__ uint4 root_state(const DevIndex &ix, int m, int lb) {
+    return make_uint4(0u, ix.n, (uint32_t)m, (uint32_t)lb << 20);
 }
 
 // Advance the search until the current state needs expanding: pop, drop
-// states the BEST bound excludes (a popped entry by its stored lower bound,
-// without unpacking), record completed hits.  At most max_pops entries are
-// popped.  Returns 1 when cur must be expanded (Di = D[cur.i]), 0 when the
-// strand's search is over, 2 when the pop limit was reached first, or
-// -R_CAND when the hit buffer overflowed.
-__device__ int resolve(State &cur, bool &valid, int strand, const Params &P, LaneCtx &c, int phase, int &Di,
-                       int max_pops) {
+// states whose stored lower bound exceeds the BEST bound, record completed
+// hits.  At most max_pops entries are popped.  Returns 1 when cur must be
+// expanded, 0 when the strand's search is over, 2 when the pop limit was
+// reached first, or -R_CAND when the hit buffer overflowed.
+__device__ int resolve(uint4 &cur, bool &valid, int strand, const Params &P, LaneCtx &c, int phase, int max_pops) {
     for (int pops = 0;;) {
         const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
         if (!valid) {
@@ -344,19 +315,19 @@ __device__ int resolve(State &cur, bool &valid, int strand, const Params &P, Lan
             if (pops == max_pops) return 2;
             pops++;
             c.sp--;
-            const uint4 e = c.stack[(size_t)c.sp * c.sstride];
-            if (entry_lb(e) > bound) continue;
-            cur = unpack(e);
+            cur = c.stack[(size_t)c.sp * c.sstride];
             valid = true;
         }
-        Di = pd_d(c, cur.i);
-        if (cur.score + P.minc * Di > bound) {
+        if (entry_lb(cur) > bound) {
             valid = false;
             continue;
         }
-        if (cur.i < 0) {
-            if (cur.score < c.best) c.best = cur.score;
-            int rc = record(c, P, make_hit(strand, cur.k, cur.l, cur.len, cur.score, cur.nmm, cur.ngo, cur.nge), phase);
+        if (s_i(cur) < 0) {
+            const int score = s_score(cur);
+            if (score < c.best) c.best = score;
+            int rc = record(c, P,
+                            make_hit(strand, cur.x, cur.y, s_len(cur), score, s_nmm(cur), s_ngo(cur), s_nge(cur)),
+                            phase);
             if (rc) return -rc;
             valid = false;
             continue;
@@ -366,106 +337,80 @@ __device__ int resolve(State &cur, bool &valid, int strand, const Params &P, Lan
 }
 
 // Children of an expanded state, from the rank counts at k (ok) and l + 1
-// (ol) on the search index: taken in reverse of the fixed order (match,
-// mismatches by base, insertion, deletions by base); the first surviving one
-// becomes cur, the others are pushed.  Returns R_OK or R_STACK.
-__device__ int expand_children(State &cur, bool &valid, const uint32_t (&ok)[4], const uint32_t (&ol)[4],
+// (ol) on the search index, built directly in packed form: each differs
+// from the parent by a few field increments.  They are taken in reverse of
+// the fixed order (match, mismatches by base, insertion, deletions by base);
+// the first surviving one becomes cur, the others are pushed with their
+// lower bounds.  Returns R_OK or R_STACK.
+__device__ int expand_children(uint4 &cur, bool &valid, const uint32_t (&ok)[4], const uint32_t (&ol)[4],
                                const DevDir &sd_, int b, int m, int maxd, int Di, int Dn, const Seed &S,
                                const Params &P, LaneCtx &c) {
-    const int diffs = cur.nmm + cur.ngo + cur.nge;
+    const int i = s_i(cur), gs = s_gs(cur), ngo = s_ngo(cur), nge = s_nge(cur), sd = s_sd(cur);
+    const int score = s_score(cur), len = s_len(cur);
+    const int diffs = s_nmm(cur) + ngo + nge;
     const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
-    State pend;
-    int pend_lb = 0;
+    const uint32_t z0 = cur.z & ~(3u << 10);  // gap state cleared
+    uint4 pend = cur;
     bool have = false;
     int rc = R_OK;
-    auto offer = [&](const State &ch, int lb) {
+    auto offer = [&](uint32_t k, uint32_t l, uint32_t z, uint32_t w) {
         if (have) {
             if (c.sp == c.stack_cap) {
                 rc = R_STACK;
             } else {
-                c.stack[(size_t)c.sp * c.sstride] = pack(pend, pend_lb);
+                c.stack[(size_t)c.sp * c.sstride] = pend;
                 c.sp++;
             }
         }
-        pend = ch;
-        pend_lb = lb;
+        pend = make_uint4(k, l, z, w);
         have = true;
     };
-    // deletions: reference base a between read bases i and i + 1
+    // deletions: reference base a between read bases i and i + 1 (same i)
     {
-        const int bd = cur.i + 1;
-        const bool gap_ok = bd >= P.s1 && bd <= m - P.s1;
-        const bool ext = cur.gs == GAP_DEL;
-        const int nd = diffs + 1, ngo = cur.ngo + (ext ? 0 : 1), nge = cur.nge + (ext ? 1 : 0);
-        const int nsd = cur.sd + ((bd > S.lo && bd < S.hi) ? 1 : 0);
-        const int nsc = cur.score + (ext ? P.s_gape : P.s_gapo);
-        const bool ok_static = gap_ok && nd <= maxd && ngo <= P.max_gapo && (P.max_gape < 0 || nge <= P.max_gape) &&
-                               (S.sl == 0 || nsd <= P.seed_diff) && nd + Di <= maxd && nsc + P.minc * Di <= bound;
-        if (ok_static) {
+        const int bd = i + 1;
+        const bool ext = gs == GAP_DEL;
+        const int nd = diffs + 1, ngo2 = ngo + (ext ? 0 : 1), nge2 = nge + (ext ? 1 : 0);
+        const int in = (bd > S.lo && bd < S.hi) ? 1 : 0;
+        const int nsc = score + (ext ? P.s_gape : P.s_gapo);
+        const int lb = nsc + P.minc * Di;
+        if (bd >= P.s1 && bd <= m - P.s1 && nd <= maxd && ngo2 <= P.max_gapo && (P.max_gape < 0 || nge2 <= P.max_gape) &&
+            (S.sl == 0 || sd + in <= P.seed_diff) && nd + Di <= maxd && lb <= bound) {
+            const uint32_t z = (z0 | ((uint32_t)GAP_DEL << 10)) + (ext ? (1u << 20) : (1u << 16)) + ((uint32_t)in << 24);
+            const uint32_t w = (uint32_t)nsc | ((uint32_t)(len + 1) << 10) | ((uint32_t)lb << 20);
 #pragma unroll
-            for (int a = 3; a >= 0; a--) {
-                if (ok[a] < ol[a]) {
-                    State ch = cur;
-                    ch.k = sd_.C[a] + ok[a];
-                    ch.l = sd_.C[a] + ol[a] - 1;
-                    ch.gs = GAP_DEL;
-                    ch.ngo = ngo;
-                    ch.nge = nge;
-                    ch.sd = nsd;
-                    ch.score = nsc;
-                    ch.len = cur.len + 1;
-                    offer(ch, nsc + P.minc * Di);
-                }
-            }
+            for (int a = 3; a >= 0; a--)
+                if (ok[a] < ol[a]) offer(sd_.C[a] + ok[a], sd_.C[a] + ol[a] - 1, z, w);
         }
     }
-    // insertion: read base w[i] without a reference base
-    if (cur.i >= P.ies && cur.i < m - P.ies) {
-        const bool ext = cur.gs == GAP_INS;
-        const int nd = diffs + 1, ngo = cur.ngo + (ext ? 0 : 1), nge = cur.nge + (ext ? 1 : 0);
-        const int nsd = cur.sd + ((cur.i >= S.lo && cur.i < S.hi) ? 1 : 0);
-        const int nsc = cur.score + (ext ? P.s_gape : P.s_gapo);
-        if (nd <= maxd && ngo <= P.max_gapo && (P.max_gape < 0 || nge <= P.max_gape) &&
-            (S.sl == 0 || nsd <= P.seed_diff) && nd + Dn <= maxd && nsc + P.minc * Dn <= bound) {
-            State ch = cur;
-            ch.i = cur.i - 1;
-            ch.gs = GAP_INS;
-            ch.ngo = ngo;
-            ch.nge = nge;
-            ch.sd = nsd;
-            ch.score = nsc;
-            offer(ch, nsc + P.minc * Dn);
+    const int in_i = (i >= S.lo && i < S.hi) ? 1 : 0;
+    // insertion: read base w[i] without a reference base (same interval)
+    if (i >= P.ies && i < m - P.ies) {
+        const bool ext = gs == GAP_INS;
+        const int nd = diffs + 1, ngo2 = ngo + (ext ? 0 : 1), nge2 = nge + (ext ? 1 : 0);
+        const int nsc = score + (ext ? P.s_gape : P.s_gapo);
+        const int lb = nsc + P.minc * Dn;
+        if (nd <= maxd && ngo2 <= P.max_gapo && (P.max_gape < 0 || nge2 <= P.max_gape) &&
+            (S.sl == 0 || sd + in_i <= P.seed_diff) && nd + Dn <= maxd && lb <= bound) {
+            const uint32_t z =
+                (z0 | ((uint32_t)GAP_INS << 10)) - 1u + (ext ? (1u << 20) : (1u << 16)) + ((uint32_t)in_i << 24);
+            offer(cur.x, cur.y, z, (uint32_t)nsc | ((uint32_t)len << 10) | ((uint32_t)lb << 20));
         }
     }
     // mismatches, then the match (offered last, so it becomes current)
     {
-        const int nsd = cur.sd + ((cur.i >= S.lo && cur.i < S.hi) ? 1 : 0);
-        const int nsc = cur.score + P.s_mm;
-        const bool mm_ok = diffs + 1 <= maxd && (S.sl == 0 || nsd <= P.seed_diff) && diffs + 1 + Dn <= maxd &&
-                           nsc + P.minc * Dn <= bound;
+        const int nsc = score + P.s_mm;
+        const int lb = nsc + P.minc * Dn;
+        if (diffs + 1 <= maxd && (S.sl == 0 || sd + in_i <= P.seed_diff) && diffs + 1 + Dn <= maxd && lb <= bound) {
+            const uint32_t z = z0 - 1u + (1u << 12) + ((uint32_t)in_i << 24);
+            const uint32_t w = (uint32_t)nsc | ((uint32_t)(len + 1) << 10) | ((uint32_t)lb << 20);
 #pragma unroll
-        for (int a = 3; a >= 0; a--) {
-            if (a == b || !(ok[a] < ol[a]) || !mm_ok) continue;
-            State ch = cur;
-            ch.k = sd_.C[a] + ok[a];
-            ch.l = sd_.C[a] + ol[a] - 1;
-            ch.i = cur.i - 1;
-            ch.gs = GAP_NONE;
-            ch.nmm = cur.nmm + 1;
-            ch.sd = nsd;
-            ch.score = nsc;
-            ch.len = cur.len + 1;
-            offer(ch, nsc + P.minc * Dn);
+            for (int a = 3; a >= 0; a--)
+                if (a != b && ok[a] < ol[a]) offer(sd_.C[a] + ok[a], sd_.C[a] + ol[a] - 1, z, w);
         }
-        if (b < 4 && sel4(ok, b) < sel4(ol, b) && diffs + Dn <= maxd && cur.score + P.minc * Dn <= bound) {
-            State ch = cur;
-            ch.k = sel4(sd_.C, b) + sel4(ok, b);
-            ch.l = sel4(sd_.C, b) + sel4(ol, b) - 1;
-            ch.i = cur.i - 1;
-            ch.gs = GAP_NONE;
-            ch.len = cur.len + 1;
-            offer(ch, cur.score + P.minc * Dn);
-        }
+        const int lbm = score + P.minc * Dn;
+        if (b < 4 && sel4(ok, b) < sel4(ol, b) && diffs + Dn <= maxd && lbm <= bound)
+            offer(sel4(sd_.C, b) + sel4(ok, b), sel4(sd_.C, b) + sel4(ol, b) - 1, z0 - 1u,
+                  (uint32_t)score | ((uint32_t)(len + 1) << 10) | ((uint32_t)lbm << 20));
     }
     if (have) cur = pend;
     valid = have;
@@ -504,20 +449,20 @@ template <int LW>
 __device__ int search_strand(const DevIndex &ix, const DevDir &sd_, const uint8_t *W, int m, int strand, int maxd,
                              const Params &P, LaneCtx &c, int phase) {
     const Seed S = seed_of(P, m);
-    State cur = root_state(ix, m);
+    uint4 cur = root_state(ix, m, P.minc * pd_d(c, m - 1));
     bool valid = true;
     c.sp = 0;
     for (;;) {
-        int Di;
-        int rr = resolve(cur, valid, strand, P, c, phase, Di, 0x7fffffff);
+        int rr = resolve(cur, valid, strand, P, c, phase, 0x7fffffff);
         if (rr == 0) return R_OK;
         if (rr < 0) return -rr;
         c.expand++;
         uint32_t ok[4], ol[4];
-        occ4<LW>(ix, sd_, cur.k, ok);
-        occ4<LW>(ix, sd_, cur.l + 1, ol);
-        const int b = pd_base(c, cur.i);
-        const int Dn = pd_d(c, cur.i - 1);
+        occ4<LW>(ix, sd_, cur.x, ok);
+        occ4<LW>(ix, sd_, cur.y + 1, ol);
+        const int i = s_i(cur);
+        const int b = pd_base(c, i);
+        const int Di = pd_d(c, i), Dn = pd_d(c, i - 1);
         int rc = expand_children(cur, valid, ok, ol, sd_, b, m, maxd, Di, Dn, S, P, c);
         if (rc) return rc;
     }
@@ -593,6 +538,8 @@ struct ReadOut {
     uint64_t stage_cap;
     uint64_t *stage_off;             // per read: first staging slot
     uint32_t *expand;                // per read work counter, or NULL
+    unsigned long long *work;        // or NULL: [0] wave iterations, [1] lane iterations with a read,
+                                     // [2] lane iterations that issued a rank query
 };
 
 __device__ __forceinline__ void send_to_second_pass(const ReadOut &O, uint32_t r) {
@@ -691,9 +638,11 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
     int di = 0, dz = 0;
     uint32_t dk = 0, dl = 0;
     // search state
-    State cur;
+    uint4 cur = make_uint4(0, 0, 0, 0);
     bool valid = false;
     Seed S{0, 0, 0};
+    // work statistics (measurement only)
+    unsigned long long w_iters = 0, w_busy = 0, w_query = 0;
 
     for (;;) {
         // refill idle lanes, one atomic per wave
@@ -731,6 +680,10 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
             if (__ballot(!exhausted) == 0) break;
             continue;
         }
+        if (O.work) {
+            w_iters++;
+            w_busy += phase != PZ_IDLE;
+        }
 
         // decide this lane's action and rank queries; a lane that changes
         // phase here acts in its new phase from the next iteration on
@@ -738,7 +691,7 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
         bool query = false;
         int qdir = 0;  // index queried: 0 = T, 1 = reverse(T)
         uint32_t q1 = 0, q2 = 0;
-        int Di = 0, da = 4;
+        int da = 4;
         if (phase == PZ_DSCAN) {
             act = ACT_DSTEP;
             da = pat(W, m, strand, di);
@@ -749,7 +702,7 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
                 q2 = dl + 1;
             }
         } else if (phase == PZ_SEARCH) {
-            int rr = resolve(cur, valid, strand, P, c, PH_FAST, Di, POPS_PER_STEP);
+            int rr = resolve(cur, valid, strand, P, c, PH_FAST, POPS_PER_STEP);
             if (rr == 2) {
                 // pop limit reached: keep popping next iteration
             } else if (rr < 0) {
@@ -772,14 +725,15 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
                 act = ACT_EXPAND;
                 query = true;
                 qdir = strand == 0 ? 1 : 0;
-                q1 = cur.k;
-                q2 = cur.l + 1;
+                q1 = cur.x;
+                q2 = cur.y + 1;
             }
         }
 
         // the shared part: rank counts at q1 and q2 on one index
         uint32_t ok[4] = {0, 0, 0, 0}, ol[4] = {0, 0, 0, 0};
         const DevDir qd = pick_dir(ix, qdir);
+        if (O.work) w_query += query;
         if (query) {
             occ4<LW>(ix, qd, q1, ok);
             occ4<LW>(ix, qd, q2, ol);
@@ -808,7 +762,7 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
             if (skip || di == m) {
                 if (!skip) {
                     phase = PZ_SEARCH;
-                    cur = root_state(ix, m);
+                    cur = root_state(ix, m, P.minc * dz);
                     valid = true;
                     c.sp = 0;
                 } else if (strand == 0) {
@@ -824,8 +778,9 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
             }
         } else if (act == ACT_EXPAND) {
             c.expand++;
-            const int b = pd_base(c, cur.i);
-            const int Dn = pd_d(c, cur.i - 1);
+            const int i = s_i(cur);
+            const int b = pd_base(c, i);
+            const int Di = pd_d(c, i), Dn = pd_d(c, i - 1);
             int rc = expand_children(cur, valid, ok, ol, qd, b, m, maxd, Di, Dn, S, P, c);
             if (rc) {
                 send_to_second_pass(O, r);
@@ -833,6 +788,11 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
                 phase = PZ_IDLE;
             }
         }
+    }
+    if (O.work) {
+        if (lane == 0) atomicAdd(&O.work[0], w_iters);
+        atomicAdd(&O.work[1], w_busy);
+        atomicAdd(&O.work[2], w_query);
     }
 }
 
@@ -1402,7 +1362,7 @@ inline uint32_t block_for(uint32_t stride) {
 
 template <int LW>
 int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, bwfm_aln_result *res,
-               hipStream_t st, uint32_t *expand) {
+               hipStream_t st, uint32_t *expand, uint64_t *work = nullptr) {
     const uint32_t n = rd->n_reads;
     const DevIndex D = dev_index(ix);
     const Params P = make_params(*p);
@@ -1438,7 +1398,10 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     // buffers; persistent lanes drift apart: give each a contiguous run
     LaneBufs lb = plain ? LaneBufs{lstack, lcand, 1, lanes, stack_cap, 1, lanes, FAST_CAND, lstride}
                         : LaneBufs{lstack, lcand, stack_cap, 1, stack_cap, FAST_CAND, 1, FAST_CAND, lstride};
-    ReadOut O{n_rep, res->c1, res->c2, res->status, slow_list, n_slow, stage, stage_used, stage_cap, stage_off, expand};
+    ReadOut O{n_rep,     res->c1,   res->c2,   res->status, slow_list,
+              n_slow,    stage,     stage_used, stage_cap,  stage_off,
+              expand,    reinterpret_cast<unsigned long long *>(work)};
+    if (work) HIPCHK(hipMemsetAsync(work, 0, 24, st));
     CallTimer tm(st);
     if (n) {
         if (plain) {
@@ -1606,7 +1569,7 @@ extern "C" int bwfm_align_batch(const bwfm_index *cix, const bwfm_reads *rd, con
 // Same as bwfm_align_batch, also writing per-read search work (states
 // expanded, summed over both passes) to expand (device, n_reads).
 extern "C" int bwfm_align_batch_counted(const bwfm_index *cix, const bwfm_reads *rd, const bwfm_aln_params *p,
-                                        bwfm_aln_result *res, uint32_t *expand, void *stream) {
+                                        bwfm_aln_result *res, uint32_t *expand, uint64_t *work, void *stream) {
     bwfm_index *ix = const_cast<bwfm_index *>(cix);
     if (!expand) return fail(BWFM_E_INVAL, "align_batch_counted: NULL counter array");
     if (!ix || !rd || !p || !check_result(res, rd->n_reads)) return fail(BWFM_E_INVAL, "align_batch: NULL argument");
@@ -1614,8 +1577,8 @@ extern "C" int bwfm_align_batch_counted(const bwfm_index *cix, const bwfm_reads 
     if (rd->max_len > BWFM_MAX_READ) return fail(BWFM_E_TOOLONG, "align_batch: max_len above 512");
     std::lock_guard<std::mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
-    if (ix->line_bytes == 128) return align_impl<32>(ix, rd, p, res, st, expand);
-    return align_impl<16>(ix, rd, p, res, st, expand);
+    if (ix->line_bytes == 128) return align_impl<32>(ix, rd, p, res, st, expand, work);
+    return align_impl<16>(ix, rd, p, res, st, expand, work);
 }
 
 extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_aln_result *res, uint32_t max_occ,

@@ -4,10 +4,13 @@
 // Suffix sorting uses induced sorting (SA-IS: Nong, Zhang and Chan, "Two
 // efficient algorithms for linear time suffix array construction", IEEE
 // Trans. Computers 2011), written from that description.  The BWT is then
-// packed two bits per row into rank lines: each line starts with the counts
-// of A, C, G and T in the rows before it ($ counted as A, since $ is stored
-// as A in the packed rows) followed by its rows, so one rank query reads one
-// line.  Every sa_sample-th row keeps its suffix array value.
+// packed into rank lines: each line starts with the counts of A, C, G and T
+// in the rows before it ($ counted as A, since $ is stored as A) followed by
+// its rows, so one rank query reads one line.  Rows are stored as bit
+// planes: for every 32 rows one word holds the high bits of their 2-bit
+// codes and the next word the low bits, so a single 32-bit popcount counts
+// a symbol over 32 rows.  Every sa_sample-th row keeps its suffix array
+// value.
 #include <algorithm>
 #include <cstring>
 #include <stdexcept>
@@ -155,7 +158,8 @@ int build_dir(const uint8_t *text, uint64_t n, uint32_t line_bytes, uint32_t bpl
         uint32_t q = SA[j];
         uint32_t c = q == 0 ? 0 : text[q - 1];  // $ stored as A
         if (q == 0) out.primary = j;
-        L[4 + (r >> 4)] |= c << (2 * (r & 15));
+        L[4 + 2 * (r >> 5)] |= (c >> 1) << (r & 31);
+        L[5 + 2 * (r >> 5)] |= (c & 1) << (r & 31);
         cnt[c]++;
         if ((j & (sa_sample - 1)) == 0) out.sa[j / sa_sample] = q;
     }
@@ -169,18 +173,21 @@ int build_dir(const uint8_t *text, uint64_t n, uint32_t line_bytes, uint32_t bpl
     return BWFM_OK;
 }
 
+static inline uint32_t code_at(const uint32_t *L, uint64_t r) {
+    return (((L[4 + 2 * (r >> 5)] >> (r & 31)) & 1) << 1) | ((L[5 + 2 * (r >> 5)] >> (r & 31)) & 1);
+}
+
 uint8_t bwt_host(const HostDir &d, uint32_t lw, uint32_t bpl, uint64_t row) {
     if (row == d.primary) return 4;
     uint64_t line = row / bpl, r = row - line * bpl;
-    const uint32_t *L = &d.lines[line * lw];
-    return (uint8_t)((L[4 + (r >> 4)] >> (2 * (r & 15))) & 3);
+    return (uint8_t)code_at(&d.lines[line * lw], r);
 }
 
 void occ_host(const HostDir &d, uint32_t lw, uint32_t bpl, uint64_t i, uint64_t out[4]) {
     uint64_t line = i / bpl, r = i - line * bpl;
     const uint32_t *L = &d.lines[line * lw];
     for (int a = 0; a < 4; a++) out[a] = L[a];
-    for (uint64_t x = 0; x < r; x++) out[(L[4 + (x >> 4)] >> (2 * (x & 15))) & 3]++;
+    for (uint64_t x = 0; x < r; x++) out[code_at(L, x)]++;
     if (i > d.primary) out[0]--;
 }
 
