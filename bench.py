@@ -4,15 +4,19 @@ Workload: 100 Mbp synthetic genome (41% GC, 40% repeat copies from 500
 families) and 1M read pairs 2 x 100 bp (fragment ~ N(300, 30), 1%
 substitutions, 0.1% indel events), seeded.  One step = the whole path over
 the batch -- align both ends, locate, pair -- with reads and index resident
-in HBM before the timed region.  Two forms are timed and must agree bit for
-bit: plain (one lane per read, one launch per end) and batched (one
-persistent work-stealing launch for both ends); `value` is the batched one.
+in HBM before the timed region.  Three forms are timed and must agree bit
+for bit: plain (one lane per read, one launch per end), batched-eager (one
+persistent work-stealing launch for both ends, then locate and pair, each
+call enqueued by the host) and batched (the same step captured once into a
+hipGraph and replayed); `value` is the batched one.  The batched form's
+residency is picked first by the autotuner on the same batch.
 
 Prints one JSON line.  The roofline entry is for the dominant kernel (the
-persistent search), timed with HIP events on the launch stream inside the
-library; its algorithmic bytes per launch are the oracle's index-line
-touches per read (same traversal order) x line size x reads per launch.  The
-CPU baseline is the oracle itself on a bounded sample of the same pairs.
+persistent search), timed with HIP events around it on its stream (events
+captured into the graph); its algorithmic bytes per launch are the oracle's
+index-line touches per read (same traversal order) x line size x reads per
+launch.  The CPU baseline is the oracle itself on a bounded sample of the
+same pairs.
 """
 from __future__ import annotations
 
@@ -36,6 +40,37 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    """Hash of the search kernel's sources; byte counters are valid only for it."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("bwfm.hip", "bwfm_internal.h"):
+        with open(os.path.join(ROOT, "paper_1505_07855_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM-side bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same
+    counter reads for a device copy of known size), or None when the summary
+    was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_bytes.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("bench-traffic:"):
+                rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+    if not rec or rec.get("kernel") != kernel or rec.get("source") != kernel_source_hash():
+        return None
+    cb = float(rec["copy_bytes"])
+    fetch = float(rec["fetch_kib"]) * 1024 * cb / (float(rec["copy_fetch_kib"]) * 1024)
+    write = float(rec["write_kib"]) * 1024 * cb / (float(rec["copy_write_kib"]) * 1024)
+    return fetch + write
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,10 +78,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--pairs", type=int, default=1_000_000)
     ap.add_argument("--genome", type=int, default=100_000_000)
-    ap.add_argument("--cpu-pairs", type=int, default=100000, help="pairs in the oracle's timed sample")
+    ap.add_argument("--cpu-pairs", type=int, default=250000, help="pairs in the oracle's timed sample (~15 s of host work)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--line-bytes", type=int, default=64)
+    ap.add_argument("--waves-per-simd", type=int, default=0, help="batched-form residency (0 = autotuned)")
+    ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the autotuner (most waves that fit)")
     ap.add_argument("--steps-plain", type=int, default=0, help="steps for the plain form (default: --steps)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -89,8 +126,14 @@ def main():
     both_o = torch.from_numpy(np.concatenate([e1.offsets[:-1], e1.offsets[-1] + e2.offsets]).view(np.int64)).cuda()
     stream = torch.cuda.current_stream()
     p_plain = bw.Params(**configs.PARAMS["C2"], form=bw.FORM_PLAIN)
-    p_batched = bw.Params(**configs.PARAMS["C2"], form=bw.FORM_BATCHED)
-    state = {"plain": [None, None, None], "batched": [None, None]}
+    p_batched = bw.Params(**configs.PARAMS["C2"], form=bw.FORM_BATCHED, waves_per_simd=args.waves_per_simd)
+    tune = None
+    if args.tune and args.waves_per_simd == 0:
+        from paper_1505_07855_amd.tune import tune_batched
+        best, table = tune_batched(ix, both_b, both_o, p_batched, max_len=100, hit_capacity=8 * n, log=log)
+        p_batched.waves_per_simd = best["waves_per_simd"]
+        tune = {"best": best, "table": table}
+    state = {"plain": [None, None, None], "eager": [None, None]}
 
     def step_plain():
         s = state["plain"]
@@ -100,12 +143,25 @@ def main():
         s[2] = bw.pair_reads(ix, s[0], s[1], w["lo"], w["hi"], w["mu"], configs.MAX_OCC, stream=stream, out=s[2])
         return s[0], s[1], s[2]
 
-    def step_batched():
-        s = state["batched"]
+    def step_eager():
+        s = state["eager"]
         s[0] = bw.align_batch(ix, both_b, both_o, p_batched, max_len=100, out=s[0], hit_capacity=8 * n, stream=stream)
         r1, r2 = s[0].window(0, n), s[0].window(n, 2 * n)
         s[1] = bw.pair_reads(ix, r1, r2, w["lo"], w["hi"], w["mu"], configs.MAX_OCC, stream=stream, out=s[1])
         return r1, r2, s[1]
+
+    # the batched form proper: the whole step captured once and replayed
+    pipe = bw.Pipeline(ix, p_batched, w["lo"], w["hi"], w["mu"], configs.MAX_OCC, max_pairs=n, max_len=100,
+                       hit_capacity=8 * n, pos_capacity=128 * n)
+    pipe.set_reads(both_b, both_o, n, max_len=100, stream=stream)
+
+    def step_graph():
+        pipe.run(graph=True, stream=stream)
+        st = pipe.finish(stream=stream)
+        if st["error"]:
+            raise SystemExit(f"pipeline capacity exceeded: {st}")
+        r1, r2, prs, _, _ = pipe.results()
+        return r1, r2, prs
 
     def run(name, fn, steps):
         for i in range(args.warmup):
@@ -143,18 +199,21 @@ def main():
                 "research_reads": research, "paired_fraction": float((flags & bw.PF_PAIRED).astype(bool).mean()),
                 "kernel_ms": kms, "out": out}
 
+    def same(a, b):
+        for x, y in ((a[0], b[0]), (a[1], b[1])):
+            hx, hy = x.to_numpy(), y.to_numpy()
+            if not (all(np.array_equal(u.view(np.uint8), v.view(np.uint8)) for u, v in zip(hx[:4], hy[:4]))
+                    and np.array_equal(hx[4] & 7, hy[4] & 7)):
+                return False
+        return np.array_equal(bw.pairs_numpy(a[2]).view(np.uint8), bw.pairs_numpy(b[2]).view(np.uint8))
+
     plain = run("plain", step_plain, args.steps_plain or args.steps)
-    batched = run("batched", step_batched, args.steps)
-    # both forms must agree exactly
-    a1, a2, ap = plain.pop("out")
-    b1, b2, bp = batched.pop("out")
-    for x, y in ((a1, b1), (a2, b2)):
-        hx, hy = x.to_numpy(), y.to_numpy()
-        same = all(np.array_equal(u.view(np.uint8), v.view(np.uint8)) for u, v in zip(hx[:4], hy[:4]))
-        if not (same and np.array_equal(hx[4] & 7, hy[4] & 7)):
-            raise SystemExit("plain and batched forms disagree")
-    if not np.array_equal(bw.pairs_numpy(ap).view(np.uint8), bw.pairs_numpy(bp).view(np.uint8)):
-        raise SystemExit("plain and batched pair records disagree")
+    eager = run("batched-eager", step_eager, args.steps_plain or args.steps)
+    batched = run("batched", step_graph, args.steps)
+    # every form must agree exactly
+    a_out, e_out, b_out = plain.pop("out"), eager.pop("out"), batched.pop("out")
+    if not same(a_out, b_out) or not same(e_out, b_out):
+        raise SystemExit("plain, eager batched and captured batched forms disagree")
     n_reads = 2 * n
     aligned = batched["aligned"]
     ms_step = batched["ms_per_step"]
@@ -184,14 +243,16 @@ def main():
         # method touches per read (D-array scans + search), same order as the kernel
         touches = np.concatenate([r.counts["touch_s"] + r.counts["touch_d"] for r in ores]).astype(np.float64)
         bytes_per_read = float(touches.mean()) * ix.info()["line_bytes"]
-        kf = kernel_ms.get("align_persistent")
+        kf, timed_in = kernel_ms.get("align_persistent"), "batched (graph replays)"
+        if not kf:
+            kf, timed_in = eager["kernel_ms"].get("align_persistent"), "batched-eager (same kernel and batch)"
         if kf:
             per_launch = bytes_per_read * n_reads
             achieved = per_launch / (kf["avg_ms"] / 1e3) / 1e9
             roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles("k_align_persistent"),
                         "kernel": "k_align_persistent", "bytes_per_read": bytes_per_read,
-                        "reads_per_launch": n_reads, "avg_launch_ms": kf["avg_ms"]}
+                        "reads_per_launch": n_reads, "avg_launch_ms": kf["avg_ms"], "timed_in": timed_in}
 
     out = {
         "metric": METRIC, "value": value, "unit": "aligned reads/s", "n_gpus": 1, "steps": args.steps,
@@ -199,12 +260,14 @@ def main():
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"C2 mid: {args.genome / 1e6:.0f} Mbp synthetic genome (GC 41%, 40% repeats), "
                                f"{args.pairs} pairs 2x100 bp, <=4 diffs, 1 gap open, seed 32/<=2",
-                   "pairs": args.pairs, "reads": n_reads, "form": "batched (one persistent launch for both ends)",
+                   "pairs": args.pairs, "reads": n_reads, "form": "batched: align both ends in one persistent launch, locate, pair; replayed as one captured hipGraph",
+                   "waves_per_simd": p_batched.waves_per_simd,
                    "line_bytes": args.line_bytes, "parallelism": "1 GPU"},
         "p50_ms": batched["p50_ms"], "p99_ms": batched["p99_ms"],
         "reads_per_s": n_reads / (ms_step / 1e3), "pairs_per_s": n / (ms_step / 1e3),
         "aligned_fraction": aligned / n_reads, "paired_fraction": batched["paired_fraction"],
         "plain": {k: v for k, v in plain.items()}, "batched": {k: v for k, v in batched.items()},
+        "batched_eager": {k: v for k, v in eager.items()}, "autotune": tune,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -47,7 +47,8 @@ enum bwfm_err {
     BWFM_E_TOOLONG = -4,  /* reference too long (n + 1 >= 2^32) or read bound above 512 */
     BWFM_E_CAPACITY = -5, /* a caller buffer is too small; see the call for what is reported */
     BWFM_E_DEVICE = -6,   /* a HIP runtime call failed */
-    BWFM_E_STATE = -7     /* index not uploaded to the device */
+    BWFM_E_STATE = -7,    /* index not uploaded to the device */
+    BWFM_E_IO = -8        /* a file could not be read or written, or is not an index file */
 };
 
 /* Longest read and largest per-read difference budget accepted. */
@@ -91,6 +92,18 @@ int bwfm_index_upload(bwfm_index *idx, void *hip_stream);
 
 /* Release host and device memory of the index and its workspace. */
 void bwfm_index_free(bwfm_index *idx);
+
+/* Write the host part of an index to path (created or truncated): a
+ * little-endian header (magic, version, layout, n), then per direction C,
+ * the $ row, the rank lines and the SA samples, then a 64-bit FNV-1a
+ * checksum of everything before it.  Errors: E_INVAL, E_IO. */
+int bwfm_index_save(const bwfm_index *idx, const char *path);
+
+/* Read an index written by bwfm_index_save into a new host-only index
+ * (upload it with bwfm_index_upload).  The checksum and every size are
+ * verified before use.  Errors: E_INVAL (NULL), E_IO (unreadable, short,
+ * corrupt or another version), E_NOMEM. */
+int bwfm_index_load(const char *path, bwfm_index **out);
 
 typedef struct {
     uint64_t n;             /* reference length */
@@ -150,6 +163,9 @@ typedef struct {
     int32_t max_best;       /* BEST: second tier reported only if c1 <= max_best */
     uint32_t max_hits;      /* reads with more candidate hits report none, 1..65536 */
     int32_t form;           /* BWFM_FORM_BATCHED or BWFM_FORM_PLAIN */
+    int32_t waves_per_simd; /* batched form: resident waves per SIMD, 1..8, or
+                               0 = as many as registers and LDS allow.  A
+                               tuning knob: results do not depend on it. */
 } bwfm_aln_params;
 
 /*
@@ -171,6 +187,10 @@ typedef struct {
 #define BWFM_ST_INVALID 4  /* read longer than reads.max_len / 512, or budget above 15 */
 #define BWFM_ST_RESEARCH 8 /* informational: the read's search outgrew the first pass's
                               per-lane buffers and was redone with worst-case buffers */
+#define BWFM_ST_SHARED 16  /* informational (batched form): parts of the read's search
+                              tree were handed to other lanes once the batch ran dry;
+                              results are unaffected, its work counter then covers a
+                              different traversal than one lane's depth-first order */
 
 typedef struct {
     uint64_t *hit_offsets;  /* device, n_reads + 1: hits of read r are [hit_offsets[r], hit_offsets[r+1]) */
@@ -266,6 +286,99 @@ typedef struct {
  */
 int bwfm_pair_reads(const bwfm_index *idx, uint32_t n_pairs, const bwfm_aln_result *r1,
                     const bwfm_aln_result *r2, const bwfm_pair_params *p, bwfm_pair *out, void *hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Captured step: one batch of pairs through align, locate and pairing  */
+/* as a single hipGraph replay                                          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * A pipeline owns fixed-capacity device buffers for one step of the path
+ * over up to max_pairs read pairs -- both ends aligned by one launch of the
+ * batched form, every reported hit located, pairs chosen -- and enqueues the
+ * step with every count read on the device and every capacity checked on
+ * the device, so that no call in it waits for the host.  The step is
+ * captured into a hipGraph at its first run and replayed by later runs; the
+ * eager form enqueues the same kernels one by one.  Results equal those of
+ * bwfm_align_batch (on end 1's reads followed by end 2's) and
+ * bwfm_pair_reads.  Calls on one pipeline must not overlap; runs on one
+ * stream may be queued back to back only if each one's results are read
+ * before the next run is enqueued.
+ */
+typedef struct bwfm_pipeline bwfm_pipeline;
+
+typedef struct {
+    uint32_t max_pairs;    /* most pairs per run */
+    uint32_t max_len;      /* longest read, 1..512 */
+    uint64_t max_bases;    /* most read bases per run, both ends */
+    uint64_t hit_capacity; /* most reported hits per run, both ends */
+    uint64_t pos_capacity; /* most located positions per run, both ends */
+    int32_t paired;        /* 1: each pair has two reads (end 1's, then end 2's);
+                              0: single-end, one read per "pair" record */
+} bwfm_pipeline_params;
+
+/* Allocate the pipeline on the current device (the index must be
+ * uploaded).  ap, pp: search and pairing parameters, fixed for the
+ * pipeline's life.  Errors: E_INVAL, E_STATE, E_TOOLONG, E_NOMEM, E_DEVICE. */
+int bwfm_pipeline_create(const bwfm_index *idx, const bwfm_aln_params *ap, const bwfm_pair_params *pp,
+                         const bwfm_pipeline_params *q, bwfm_pipeline **out);
+
+/* Enqueue on hip_stream a device-to-device copy of the next batch into the
+ * pipeline's own input buffers (and unbind any bound reads):
+ * reads.bases/offsets/max_diff hold 2 * n_pairs reads, end 1's then end
+ * 2's (n_pairs reads single-end), in the bwfm_reads format (CSR offsets
+ * starting at 0; lengths must be NULL; max_diff may be NULL: then every read
+ * takes ap->max_diff).  The source buffers must
+ * stay valid until the copy has run.  Errors: E_INVAL, E_CAPACITY (n_pairs
+ * or the base count above the pipeline's maxima), E_DEVICE. */
+int bwfm_pipeline_set_reads(bwfm_pipeline *pl, const bwfm_reads *reads, uint32_t n_pairs, void *hip_stream);
+
+/* Bind caller-owned device buffers as the pipeline's input instead of its
+ * own: reads->bases, offsets (start offsets when lengths is given, else
+ * CSR offsets), lengths and max_diff (NULL: ap->max_diff for every read)
+ * are read by every later run; reads->n_reads (at least 2 * max_pairs, or
+ * max_pairs single-end) and max_len (at most the pipeline's) bound them.
+ * The caller rewrites their contents between runs (on the run's stream,
+ * before it) and sets the batch size with bwfm_pipeline_set_count.  A
+ * captured graph is dropped and captured again at the next graph run.
+ * Errors: E_INVAL, E_CAPACITY. */
+int bwfm_pipeline_bind_reads(bwfm_pipeline *pl, const bwfm_reads *reads);
+
+/* Batch size of the next run with bound reads.  Errors: E_INVAL, E_CAPACITY. */
+int bwfm_pipeline_set_count(bwfm_pipeline *pl, uint32_t n_pairs);
+
+/* Enqueue one step over the batch last set.  graph: 1 = replay the captured
+ * graph (captured now if this is the first graph run), 0 = enqueue eagerly.
+ * Errors: E_INVAL, E_DEVICE. */
+int bwfm_pipeline_run(bwfm_pipeline *pl, int graph, void *hip_stream);
+
+typedef struct {
+    uint32_t n_pairs;
+    uint32_t error;         /* 0, or BWFM_PIPE_E_* bits: a capacity was too small */
+    uint64_t n_hits;        /* reported hits, both ends (needed size when too small) */
+    uint64_t n_positions;   /* located positions, both ends */
+    double kernel_ms;       /* the batched search kernel's duration in this
+                               run, from HIP events captured around it; 0
+                               when timing is off */
+} bwfm_pipeline_status;
+#define BWFM_PIPE_E_HITS 1
+#define BWFM_PIPE_E_POSITIONS 2
+
+/* Wait for the last run on hip_stream and report it.  With timing enabled
+ * (bwfm_timing_enable) the search kernel's duration is also added to the
+ * timing store under "align_persistent" ("align_plain" for the plain form).
+ * Errors: E_INVAL, E_DEVICE. */
+int bwfm_pipeline_finish(bwfm_pipeline *pl, void *hip_stream, bwfm_pipeline_status *out);
+
+/* Views of the last run's outputs (device memory owned by the pipeline,
+ * valid until the next run): end 0 or 1 as an alignment result whose
+ * hit_offsets index the shared hit array (see bwfm_locate on windows), the
+ * per-hit position offsets (n_hits + 1, over both ends' hits in order) and
+ * positions, and the n_pairs pair records. */
+int bwfm_pipeline_outputs(bwfm_pipeline *pl, int end, bwfm_aln_result *res, uint64_t **pos_offsets,
+                          uint32_t **positions, bwfm_pair **pairs);
+
+void bwfm_pipeline_destroy(bwfm_pipeline *pl);
 
 /* ------------------------------------------------------------------ */
 /* Serving (continuous batching over the path above)                    */

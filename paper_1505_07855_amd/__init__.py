@@ -27,11 +27,13 @@ PAIR_DTYPE = np.dtype([("pos1", "<u4"), ("pos2", "<u4"), ("insert", "<i4"), ("le
                        ("score1", "<u2"), ("score2", "<u2"), ("strand1", "u1"), ("strand2", "u1"),
                        ("flags", "u1"), ("pad", "u1")])
 
-ST_HIT, ST_OVERFLOW, ST_INVALID, ST_RESEARCH = 1, 2, 4, 8
+ST_HIT, ST_OVERFLOW, ST_INVALID, ST_RESEARCH, ST_SHARED = 1, 2, 4, 8, 16
 PF_PAIRED, PF_MAPPED1, PF_MAPPED2, PF_REP1, PF_REP2 = 1, 2, 4, 8, 16
 MODE_ALL, MODE_BEST = 0, 1
 FORM_BATCHED, FORM_PLAIN = 0, 1
 E_CAPACITY = -5
+E_IO = -8
+PIPE_E_HITS, PIPE_E_POSITIONS = 1, 2
 
 
 class BwfmError(RuntimeError):
@@ -60,7 +62,7 @@ class _Reads(ctypes.Structure):
 class _AlnParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("max_diff", "max_gapo", "max_gape", "seed_len", "seed_diff",
                                               "indel_end_skip", "s_mm", "s_gapo", "s_gape", "mode", "max_best")] + [
-        ("max_hits", ctypes.c_uint32), ("form", ctypes.c_int32)]
+        ("max_hits", ctypes.c_uint32), ("form", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
 
 
 class _AlnResult(ctypes.Structure):
@@ -86,13 +88,25 @@ class _PairParams(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_int32), ("hi", ctypes.c_int32), ("mu", ctypes.c_int32), ("max_occ", ctypes.c_uint32)]
 
 
+class _PipeParams(ctypes.Structure):
+    _fields_ = [("max_pairs", ctypes.c_uint32), ("max_len", ctypes.c_uint32), ("max_bases", ctypes.c_uint64),
+                ("hit_capacity", ctypes.c_uint64), ("pos_capacity", ctypes.c_uint64), ("paired", ctypes.c_int32)]
+
+
+class _PipeStatus(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_uint32), ("error", ctypes.c_uint32), ("n_hits", ctypes.c_uint64),
+                ("n_positions", ctypes.c_uint64), ("kernel_ms", ctypes.c_double)]
+
+
 # every function include/bwfm.h declares, plus the counted variant
 SYMBOLS = ("bwfm_build_index", "bwfm_index_upload", "bwfm_index_free", "bwfm_index_get_info", "bwfm_index_get_bwt",
            "bwfm_index_get_sa_samples", "bwfm_index_occ", "bwfm_align_batch", "bwfm_locate", "bwfm_pair_reads",
            "bwfm_estimate_insert", "bwfm_max_diff_rule", "bwfm_last_error", "bwfm_align_batch_counted",
            "bwfm_timing_enable", "bwfm_timing_reset", "bwfm_timing_get", "bwfm_probe_gather",
            "bwfm_server_create", "bwfm_server_submit", "bwfm_server_wait", "bwfm_server_get_stats",
-           "bwfm_server_destroy")
+           "bwfm_server_destroy", "bwfm_index_save", "bwfm_index_load", "bwfm_pipeline_create",
+           "bwfm_pipeline_set_reads", "bwfm_pipeline_run", "bwfm_pipeline_finish", "bwfm_pipeline_outputs",
+           "bwfm_pipeline_destroy", "bwfm_pipeline_bind_reads", "bwfm_pipeline_set_count")
 
 
 def lib():
@@ -115,6 +129,8 @@ def lib():
         sig = {
             "bwfm_build_index": ([P, u64, P, ctypes.POINTER(P)], c_int),
             "bwfm_index_upload": ([P, P], c_int),
+            "bwfm_index_save": ([P, ctypes.c_char_p], c_int),
+            "bwfm_index_load": ([ctypes.c_char_p, ctypes.POINTER(P)], c_int),
             "bwfm_index_free": ([P], None),
             "bwfm_index_get_info": ([P, P], c_int),
             "bwfm_index_get_bwt": ([P, c_int, P], c_int),
@@ -136,6 +152,14 @@ def lib():
             "bwfm_server_wait": ([P, u64, P, P], c_int),
             "bwfm_server_get_stats": ([P, P], c_int),
             "bwfm_server_destroy": ([P], None),
+            "bwfm_pipeline_create": ([P, P, P, P, ctypes.POINTER(P)], c_int),
+            "bwfm_pipeline_set_reads": ([P, P, u32, P], c_int),
+            "bwfm_pipeline_run": ([P, c_int, P], c_int),
+            "bwfm_pipeline_finish": ([P, P, P], c_int),
+            "bwfm_pipeline_outputs": ([P, c_int, P, P, P, P], c_int),
+            "bwfm_pipeline_destroy": ([P], None),
+            "bwfm_pipeline_bind_reads": ([P, P], c_int),
+            "bwfm_pipeline_set_count": ([P, u32], c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -189,6 +213,7 @@ class Params:
     max_best: int = 30
     max_hits: int = 256
     form: int = FORM_BATCHED
+    waves_per_simd: int = 0  # batched form residency (tuning only; 0 = the most that fit)
 
     def _c(self) -> _AlnParams:
         return _AlnParams(*[getattr(self, f.name) for f in fields(self)])
@@ -205,6 +230,20 @@ class Index:
         _check(lib().bwfm_build_index(_np_ptr(ref), len(ref), ctypes.byref(p), ctypes.byref(h)))
         self._h = h
         self.n = len(ref)
+
+    @classmethod
+    def load(cls, path: str) -> "Index":
+        """An index written by save() (bwfm_index_load); host-only until upload()."""
+        h = ctypes.c_void_p()
+        _check(lib().bwfm_index_load(os.fsencode(path), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        self.n = self.info()["n"]
+        return self
+
+    def save(self, path: str) -> None:
+        """Write the index to a file (bwfm_index_save)."""
+        _check(lib().bwfm_index_save(self._h, os.fsencode(path)))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -468,3 +507,92 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class _DeviceView:
+    """A device buffer the library owns, seen by torch without a copy
+    (through the CUDA array interface, which torch's ROCm build reads)."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, False),
+                                         "version": 3}
+
+
+def _view(ptr: int, shape, typestr: str):
+    torch = _torch()
+    if ptr == 0 or 0 in tuple(shape):
+        dt = {"<u8": torch.int64, "<i8": torch.int64, "<i4": torch.int32, "|u1": torch.uint8}[typestr]
+        return torch.empty(shape, dtype=dt, device="cuda")
+    return torch.as_tensor(_DeviceView(ptr, shape, typestr), device="cuda")
+
+
+class Pipeline:
+    """One step of the path (align both ends, locate, pair) over up to
+    max_pairs pairs, captured once into a hipGraph and replayed
+    (bwfm_pipeline_*).  Outputs are views of library-owned device memory,
+    valid until the next run."""
+
+    def __init__(self, index: Index, params: Params, lo: int, hi: int, mu: int, max_occ: int, max_pairs: int,
+                 max_len: int, max_bases: int | None = None, hit_capacity: int | None = None,
+                 pos_capacity: int | None = None, paired: bool = True):
+        self.index = index  # keeps the index alive
+        self.max_pairs = max_pairs
+        self.paired = paired
+        q = _PipeParams(max_pairs, max_len, max_bases if max_bases is not None else 2 * max_pairs * max_len,
+                        hit_capacity if hit_capacity is not None else 8 * max_pairs,
+                        pos_capacity if pos_capacity is not None else 64 * max_pairs, 1 if paired else 0)
+        self.hit_capacity = q.hit_capacity
+        self.pos_capacity = q.pos_capacity
+        ap = params._c()
+        pp = _PairParams(lo, hi, mu, max_occ)
+        h = ctypes.c_void_p()
+        _check(lib().bwfm_pipeline_create(index.handle, ctypes.byref(ap), ctypes.byref(pp), ctypes.byref(q),
+                                          ctypes.byref(h)))
+        self._h = h
+        self.n_pairs = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bwfm_pipeline_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_reads(self, bases, offsets, n_pairs: int, max_len: int, max_diff=None, stream=None):
+        """Copy the next batch (end-1 reads then end-2 reads, device tensors)
+        into the pipeline."""
+        rd = _reads_struct(bases, offsets, max_diff, max_len)
+        _check(lib().bwfm_pipeline_set_reads(self._h, ctypes.byref(rd), n_pairs, _stream_ptr(stream)))
+        self.n_pairs = n_pairs
+
+    def run(self, graph: bool = True, stream=None):
+        _check(lib().bwfm_pipeline_run(self._h, 1 if graph else 0, _stream_ptr(stream)))
+
+    def finish(self, stream=None) -> dict:
+        st = _PipeStatus()
+        _check(lib().bwfm_pipeline_finish(self._h, _stream_ptr(stream), ctypes.byref(st)))
+        return {"n_pairs": st.n_pairs, "error": st.error, "n_hits": st.n_hits, "n_positions": st.n_positions,
+                "kernel_ms": st.kernel_ms}
+
+    def results(self):
+        """(end-1 AlignResult, end-2 AlignResult, pair records uint8 [n, 24],
+        position offsets int64 [n_hits + 1], positions int32) of the last run."""
+        n = self.n_pairs
+        out = []
+        po = ctypes.c_void_p()
+        pos = ctypes.c_void_p()
+        prs = ctypes.c_void_p()
+        for e in ((0, 1) if self.paired else (0,)):
+            r = _AlnResult()
+            _check(lib().bwfm_pipeline_outputs(self._h, e, ctypes.byref(r), ctypes.byref(po), ctypes.byref(pos),
+                                               ctypes.byref(prs)))
+            out.append(AlignResult(_view(r.hit_offsets or 0, (n + 1,), "<i8"),
+                                   _view(r.hits or 0, (r.hit_capacity, 4), "<i4"), _view(r.c1 or 0, (n,), "<i4"),
+                                   _view(r.c2 or 0, (n,), "<i4"), _view(r.status or 0, (n,), "|u1"), n))
+        n_hits = int(out[-1].hit_offsets[n].item()) if n else 0
+        return (out[0], out[1] if self.paired else None, _view(prs.value or 0, (n, PAIR_DTYPE.itemsize), "|u1"),
+                _view(po.value or 0, (n_hits + 1,), "<i8"), _view(pos.value or 0, (self.pos_capacity,), "<i4"))

@@ -33,6 +33,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -65,7 +66,18 @@ struct ReadsView {
     const uint32_t *len;  // per-read lengths, or NULL: read r ends where read r + 1 starts
     const uint8_t *maxd;
     uint32_t n, max_len;
+    const uint64_t *n_dev;  // or NULL; else the batch holds min(*n_dev, n) reads (set on the device)
 };
+
+// number of reads in the batch
+__device__ __forceinline__ uint32_t reads_n(const ReadsView &rd) {
+    return rd.n_dev ? (uint32_t)min(*rd.n_dev, (uint64_t)rd.n) : rd.n;
+}
+
+// a count known on the host (n) or, when n_dev is set, on the device (at most n)
+__device__ __forceinline__ uint64_t count_of(uint64_t n, const uint64_t *n_dev) {
+    return n_dev ? min(*n_dev, n) : n;
+}
 
 // start and length of read r
 __device__ __forceinline__ void read_span(const ReadsView &rd, uint32_t r, uint64_t &o0, uint64_t &len, bool &bad) {
@@ -218,12 +230,13 @@ struct LaneCtx {
     uint4 *stack, *cand;
     uint8_t *pd;  // LDS, per pattern position i: base code | D[i] << 3
     uint32_t sstride, cstride, stack_cap, cand_cap;
-    uint32_t sp, ncand;
+    uint32_t sp, sbase;  // stack entries [sbase, sp) are this lane's pending states
+    uint32_t ncand;
     int best;
     uint32_t expand;
 };
 
-extern __shared__ uint8_t lds_bytes[];
+extern __shared__ __align__(16) uint8_t lds_bytes[];
 
 __device__ __forceinline__ void init_ctx(LaneCtx &c, const LaneBufs &B, uint32_t lane) {
     c.stack = B.stack + (size_t)lane * B.stack_lane_step;
@@ -234,6 +247,7 @@ __device__ __forceinline__ void init_ctx(LaneCtx &c, const LaneBufs &B, uint32_t
     c.stack_cap = B.stack_cap;
     c.cand_cap = B.cand_cap;
     c.sp = 0;
+    c.sbase = 0;
     c.ncand = 0;
     c.best = INF_SCORE;
     c.expand = 0;
@@ -305,13 +319,16 @@ __device__ __forceinline__ uint4 root_state(const DevIndex &ix, int m, int lb) {
 // Advance the search until the current state needs expanding: pop, drop
 // states whose stored lower bound exceeds the BEST bound, record completed
 // hits.  At most max_pops entries are popped.  Returns 1 when cur must be
-// expanded, 0 when the strand's search is over, 2 when the pop limit was
-// reached first, or -R_CAND when the hit buffer overflowed.
-__device__ int resolve(uint4 &cur, bool &valid, int strand, const Params &P, LaneCtx &c, int phase, int max_pops) {
+// expanded, 0 when the lane's part of the strand's search is over, 2 when
+// the pop limit was reached first, 3 when cur is a completed hit left for
+// the caller to record (only with defer), or -R_CAND when the hit buffer
+// overflowed.
+__device__ int resolve(uint4 &cur, bool &valid, int strand, const Params &P, LaneCtx &c, int phase, int max_pops,
+                       bool defer = false) {
     for (int pops = 0;;) {
         const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
         if (!valid) {
-            if (c.sp == 0) return 0;
+            if (c.sp == c.sbase) return 0;
             if (pops == max_pops) return 2;
             pops++;
             c.sp--;
@@ -323,6 +340,7 @@ __device__ int resolve(uint4 &cur, bool &valid, int strand, const Params &P, Lan
             continue;
         }
         if (s_i(cur) < 0) {
+            if (defer) return 3;
             const int score = s_score(cur);
             if (score < c.best) c.best = score;
             int rc = record(c, P,
@@ -355,6 +373,14 @@ __device__ int expand_children(uint4 &cur, bool &valid, const uint32_t (&ok)[4],
     int rc = R_OK;
     auto offer = [&](uint32_t k, uint32_t l, uint32_t z, uint32_t w) {
         if (have) {
+            if (c.sp == c.stack_cap && c.sbase > 0) {
+                // entries below sbase were handed to other lanes: slide the
+                // pending ones down to the bottom
+                for (uint32_t j = c.sbase; j < c.sp; j++)
+                    c.stack[(size_t)(j - c.sbase) * c.sstride] = c.stack[(size_t)j * c.sstride];
+                c.sp -= c.sbase;
+                c.sbase = 0;
+            }
             if (c.sp == c.stack_cap) {
                 rc = R_STACK;
             } else {
@@ -548,24 +574,28 @@ __device__ __forceinline__ void send_to_second_pass(const ReadOut &O, uint32_t r
     O.slow_list[atomicAdd(O.n_slow, 1u)] = r;
 }
 
+// Move a read's nr reported hits (the front of its hit buffer) to the
+// staging arena.  The arena holds as many hits as the caller's output, so
+// running out of it means the output is too small: the count is kept (the
+// offsets scan then reports what is needed) and nothing is copied.
+__device__ void stage_hits(const LaneCtx &c, const ReadOut &O, uint32_t r, uint32_t nr) {
+    if (!nr) return;
+    const unsigned long long off = atomicAdd(O.stage_used, (unsigned long long)nr);
+    if (off + nr > O.stage_cap) return;
+    for (uint32_t j = 0; j < nr; j++) O.stage[off + j] = c.cand[(size_t)j * c.cstride];
+    O.stage_off[r] = off;
+}
+
 // Canonicalise a finished read and move its reported hits to the staging
-// arena; a read whose hits do not fit goes to the second pass.
-__device__ void publish(LaneCtx &c, const Params &P, const ReadOut &O, uint32_t r) {
+// arena.
+__device__ void publish(LaneCtx &c, const Params &P, const ReadOut &O, uint32_t r, uint8_t extra = 0) {
     uint8_t st;
     uint32_t a, b;
     uint32_t nr = finish(c, P, st, a, b);
     if (O.expand) O.expand[r] = c.expand;
-    if (nr) {
-        unsigned long long off = atomicAdd(O.stage_used, (unsigned long long)nr);
-        if (off + nr > O.stage_cap) {
-            send_to_second_pass(O, r);
-            return;
-        }
-        for (uint32_t j = 0; j < nr; j++) O.stage[off + j] = c.cand[(size_t)j * c.cstride];
-        O.stage_off[r] = off;
-    }
+    stage_hits(c, O, r, nr);
     O.n_rep[r] = nr;
-    O.status[r] = st;
+    O.status[r] = st | extra;
     O.c1[r] = a;
     O.c2[r] = b;
 }
@@ -598,7 +628,7 @@ __device__ __forceinline__ int check_read(const ReadsView &rd, const Params &P, 
 template <int LW>
 __global__ __launch_bounds__(BLOCK) void k_align_plain(DevIndex ix, ReadsView rd, Params P, LaneBufs B, ReadOut O) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rd.n) return;
+    if (r >= reads_n(rd)) return;
     int m, maxd;
     uint64_t o0;
     if (check_read(rd, P, O, r, m, maxd, o0)) return;
@@ -613,24 +643,63 @@ __global__ __launch_bounds__(BLOCK) void k_align_plain(DevIndex ix, ReadsView rd
     publish(c, P, O, r);
 }
 
-enum { PZ_IDLE = 0, PZ_DSCAN = 1, PZ_SEARCH = 2 };
+enum { PZ_IDLE = 0, PZ_DSCAN = 1, PZ_SEARCH = 2, PZ_HELP = 3, PZ_WAIT = 4 };
 enum { ACT_NONE = 0, ACT_DSTEP = 1, ACT_EXPAND = 2 };
+enum { SH_FAIL = 1, SH_HELPED = 2 };
+
+// Per-wave block in LDS through which the lanes of a wave share one read's
+// search once the batch's reads are all taken: an idle lane receives the
+// oldest pending state of a busy lane's stack (the root of the largest
+// untouched subtree) and searches it on the owner's pattern, D-array, bound
+// and hit buffer.  Arrays are indexed by the owner lane, the lane that took
+// the read; box and meta pass the donated states, by donor rank.
+struct WaveShare {
+    int best[64];       // best score found so far for the owner's read
+    int ncand[64];      // hits in the owner's hit buffer
+    int pending[64];    // helper lanes still searching donated subtrees
+    int flags[64];      // SH_FAIL: the hit buffer overflowed; SH_HELPED
+    int hexp[64];       // states expanded by helpers
+    uint4 box[64];      // donated states
+    uint32_t meta[64];  // owner lane | strand << 6 | budget << 7 | m << 11
+};
+
+__device__ __forceinline__ int sh_ld(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void sh_st(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// order this wave's earlier LDS and global accesses before its later ones,
+// as seen by the other lanes of the wave
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
 
 // Batched form: a persistent grid whose lanes pull reads from a shared
 // counter.  Each loop iteration performs one rank-query pair per busy lane --
 // a D-array step or a search expansion -- so lanes at different stages of
 // different reads still share the expensive part, and a lane whose read is
 // done takes the next one at once (wave-wide ballot, one atomic per wave).
+// When the counter runs past the batch, idle lanes help the busy lanes of
+// their wave through WaveShare instead of waiting for the slowest one.
 template <int LW>
 __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsView rd, Params P, LaneBufs B, ReadOut O,
                                                             uint32_t *next_read) {
     const uint32_t gl = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
+    const uint32_t wave0 = threadIdx.x & ~63u;  // the wave's first thread in the block
+    const uint32_t n_reads = reads_n(rd);
+    WaveShare &ws = reinterpret_cast<WaveShare *>(lds_bytes + (size_t)blockDim.x * B.lds_stride)[threadIdx.x >> 6];
     LaneCtx c;
     init_ctx(c, B, gl);
+    uint4 *const own_cand = c.cand;
+    uint8_t *const own_pd = c.pd;
 
     int phase = PZ_IDLE;
     bool exhausted = false;
+    bool endgame = false;  // wave-uniform: the batch's reads are all taken
+    int ow = lane;         // owner lane of the read this lane works on
     uint32_t r = 0;
     int m = 0, maxd = 0, strand = 0;
     const uint8_t *W = nullptr;
@@ -655,13 +724,16 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
             base = __shfl(base, leader);
             if (want) {
                 const uint32_t rr = base + (uint32_t)__popcll(wm & ((1ULL << lane) - 1));
-                if (rr >= rd.n) {
+                if (rr >= n_reads) {
                     exhausted = true;
                 } else {
                     r = rr;
                     uint64_t o0;
                     if (!check_read(rd, P, O, r, m, maxd, o0)) {
                         W = rd.bases + o0;
+                        ow = lane;
+                        c.pd = own_pd;
+                        c.cand = own_cand;
                         c.ncand = 0;
                         c.best = INF_SCORE;
                         c.expand = 0;
@@ -672,6 +744,11 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
                         dk = 0;
                         dl = ix.n;
                         S = seed_of(P, m);
+                        sh_st(&ws.best[lane], INF_SCORE);
+                        sh_st(&ws.ncand[lane], 0);
+                        sh_st(&ws.pending[lane], 0);
+                        sh_st(&ws.flags[lane], 0);
+                        sh_st(&ws.hexp[lane], 0);
                     }
                 }
             }
@@ -680,18 +757,75 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
             if (__ballot(!exhausted) == 0) break;
             continue;
         }
+        endgame = endgame || __ballot(exhausted) != 0;
         if (O.work) {
             w_iters++;
-            w_busy += phase != PZ_IDLE;
+            w_busy += phase != PZ_IDLE && phase != PZ_WAIT;
+        }
+
+        if (endgame) {
+            wave_fence();
+            const bool searching = phase == PZ_SEARCH || phase == PZ_HELP;
+            if (searching) {
+                const int sb = sh_ld(&ws.best[ow]);
+                if (sb < c.best) c.best = sb;
+                if (sh_ld(&ws.flags[ow]) & SH_FAIL) {
+                    // the read goes to the second pass: drop this lane's part
+                    valid = false;
+                    c.sp = c.sbase = 0;
+                }
+            }
+            // hand the oldest pending state of busy lanes to idle lanes
+            const int avail = searching ? (int)(c.sp - c.sbase) - (valid ? 0 : 1) : 0;
+            const bool give = avail >= 1;
+            const bool recv = phase == PZ_IDLE;
+            const unsigned long long R = __ballot(recv), G = __ballot(give);
+            if (R && G) {
+                const int n = min(__popcll(R), __popcll(G));
+                const unsigned long long lt = (1ULL << lane) - 1;
+                if (give) {
+                    const int gi = __popcll(G & lt);
+                    if (gi < n) {
+                        ws.box[gi] = c.stack[(size_t)c.sbase * c.sstride];
+                        ws.meta[gi] = (uint32_t)ow | ((uint32_t)strand << 6) | ((uint32_t)maxd << 7) | ((uint32_t)m << 11);
+                        c.sbase++;
+                        atomicAdd(&ws.pending[ow], 1);
+                        atomicOr(&ws.flags[ow], SH_HELPED);
+                    }
+                }
+                wave_fence();
+                if (recv) {
+                    const int ri = __popcll(R & lt);
+                    if (ri < n) {
+                        cur = ws.box[ri];
+                        const uint32_t mt = ws.meta[ri];
+                        ow = (int)(mt & 63);
+                        strand = (int)((mt >> 6) & 1);
+                        maxd = (int)((mt >> 7) & 15);
+                        m = (int)(mt >> 11);
+                        S = seed_of(P, m);
+                        valid = true;
+                        c.sp = c.sbase = 0;
+                        c.pd = lds_bytes + (size_t)(wave0 + ow) * B.lds_stride;
+                        c.cand = B.cand + (size_t)(blockIdx.x * blockDim.x + wave0 + ow) * B.cand_lane_step;
+                        c.best = sh_ld(&ws.best[ow]);
+                        c.expand = 0;
+                        phase = PZ_HELP;
+                    }
+                }
+                wave_fence();
+            }
         }
 
         // decide this lane's action and rank queries; a lane that changes
         // phase here acts in its new phase from the next iteration on
         int act = ACT_NONE;
         bool query = false;
+        bool hit = false;
         int qdir = 0;  // index queried: 0 = T, 1 = reverse(T)
         uint32_t q1 = 0, q2 = 0;
         int da = 4;
+        bool part_done = false;  // this lane's part of the strand's search is over
         if (phase == PZ_DSCAN) {
             act = ACT_DSTEP;
             da = pat(W, m, strand, di);
@@ -701,32 +835,98 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
                 q1 = dk;
                 q2 = dl + 1;
             }
-        } else if (phase == PZ_SEARCH) {
-            int rr = resolve(cur, valid, strand, P, c, PH_FAST, POPS_PER_STEP);
+        } else if (phase == PZ_SEARCH || phase == PZ_HELP) {
+            int rr = resolve(cur, valid, strand, P, c, PH_FAST, POPS_PER_STEP, endgame);
             if (rr == 2) {
                 // pop limit reached: keep popping next iteration
+            } else if (rr == 3) {
+                hit = true;
             } else if (rr < 0) {
+                // only without endgame, so the lane owns its read alone
                 send_to_second_pass(O, r);
                 if (O.expand) O.expand[r] = c.expand;
                 phase = PZ_IDLE;
             } else if (rr == 0) {
-                if (strand == 0) {
-                    strand = 1;
-                    phase = PZ_DSCAN;
-                    di = 0;
-                    dz = 0;
-                    dk = 0;
-                    dl = ix.n;
-                } else {
-                    publish(c, P, O, r);
-                    phase = PZ_IDLE;
-                }
+                part_done = true;
             } else {
                 act = ACT_EXPAND;
                 query = true;
                 qdir = strand == 0 ? 1 : 0;
                 q1 = cur.x;
                 q2 = cur.y + 1;
+            }
+            if (!endgame && phase == PZ_SEARCH) {
+                sh_st(&ws.best[lane], c.best);
+                sh_st(&ws.ncand[lane], (int)c.ncand);
+            }
+        }
+
+        // completed hits found in the endgame, one lane at a time: lanes of
+        // one read share its hit buffer
+        if (endgame) {
+            unsigned long long hm = __ballot(hit);
+            while (hm) {
+                const int L = __ffsll(hm) - 1;
+                if (lane == L) {
+                    c.ncand = (uint32_t)sh_ld(&ws.ncand[ow]);
+                    const int sb = sh_ld(&ws.best[ow]);
+                    if (sb < c.best) c.best = sb;
+                    const int score = s_score(cur);
+                    if (score < c.best) c.best = score;
+                    const int rc = record(c, P,
+                                          make_hit(strand, cur.x, cur.y, s_len(cur), score, s_nmm(cur), s_ngo(cur),
+                                                   s_nge(cur)),
+                                          PH_FAST);
+                    sh_st(&ws.best[ow], c.best);
+                    sh_st(&ws.ncand[ow], (int)c.ncand);
+                    if (rc) {
+                        atomicOr(&ws.flags[ow], SH_FAIL);
+                        c.sp = c.sbase = 0;
+                        part_done = true;
+                    }
+                    valid = false;
+                }
+                wave_fence();
+                hm &= hm - 1;
+            }
+        }
+
+        // the end of a lane's part: a helper reports back; an owner waits
+        // for its helpers before the next strand or the publication
+        if (part_done) {
+            valid = false;
+            c.sp = c.sbase = 0;
+            if (phase == PZ_HELP) {
+                atomicAdd(&ws.hexp[ow], (int)c.expand);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                atomicSub(&ws.pending[ow], 1);
+                phase = PZ_IDLE;
+            } else {
+                phase = PZ_WAIT;
+            }
+        }
+        if (phase == PZ_WAIT && sh_ld(&ws.pending[lane]) == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const int fl = sh_ld(&ws.flags[lane]);
+            if (fl & SH_FAIL) {
+                send_to_second_pass(O, r);
+                if (O.expand) O.expand[r] = c.expand + (uint32_t)sh_ld(&ws.hexp[lane]);
+                phase = PZ_IDLE;
+            } else if (strand == 0) {
+                strand = 1;
+                phase = PZ_DSCAN;
+                di = 0;
+                dz = 0;
+                dk = 0;
+                dl = ix.n;
+            } else {
+                c.ncand = (uint32_t)sh_ld(&ws.ncand[lane]);
+                const int sb = sh_ld(&ws.best[lane]);
+                if (sb < c.best) c.best = sb;
+                c.cand = own_cand;
+                c.expand += (uint32_t)sh_ld(&ws.hexp[lane]);
+                publish(c, P, O, r, (fl & SH_HELPED) ? (uint8_t)BWFM_ST_SHARED : (uint8_t)0);
+                phase = PZ_IDLE;
             }
         }
 
@@ -764,7 +964,7 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
                     phase = PZ_SEARCH;
                     cur = root_state(ix, m, P.minc * dz);
                     valid = true;
-                    c.sp = 0;
+                    c.sp = c.sbase = 0;
                 } else if (strand == 0) {
                     strand = 1;
                     di = 0;
@@ -772,7 +972,14 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
                     dk = 0;
                     dl = ix.n;
                 } else {
-                    publish(c, P, O, r);
+                    // strand - cannot match; the read's helpers, if any,
+                    // were all done before this D scan began
+                    c.ncand = (uint32_t)sh_ld(&ws.ncand[lane]);
+                    const int sb = sh_ld(&ws.best[lane]);
+                    if (sb < c.best) c.best = sb;
+                    c.expand += (uint32_t)sh_ld(&ws.hexp[lane]);
+                    const int fl = sh_ld(&ws.flags[lane]);
+                    publish(c, P, O, r, (fl & SH_HELPED) ? (uint8_t)BWFM_ST_SHARED : (uint8_t)0);
                     phase = PZ_IDLE;
                 }
             }
@@ -783,9 +990,14 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
             const int Di = pd_d(c, i), Dn = pd_d(c, i - 1);
             int rc = expand_children(cur, valid, ok, ol, qd, b, m, maxd, Di, Dn, S, P, c);
             if (rc) {
-                send_to_second_pass(O, r);
-                if (O.expand) O.expand[r] = c.expand;
-                phase = PZ_IDLE;
+                // cannot happen with worst-case stacks; kept as a guard
+                if (endgame) {
+                    atomicOr(&ws.flags[ow], SH_FAIL);  // every lane of the read drops out
+                } else {
+                    send_to_second_pass(O, r);
+                    if (O.expand) O.expand[r] = c.expand;
+                    phase = PZ_IDLE;
+                }
             }
         }
     }
@@ -796,72 +1008,79 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
     }
 }
 
-// Second pass for the reads listed in slow_list: worst-case stack, first the
-// best score S*, then the hits with the bound fixed at S* + s_mm.  Results
-// stay in this pass's lane buffers.
+// Second pass for the reads listed in slow_list (*O.n_slow of them, set by
+// the first pass): a fixed grid pulls them from a counter.  Each read gets
+// the worst-case stack; first the best score S*, then the hits with the
+// bound fixed at S* + s_mm.  The reported hits go to the staging arena like
+// the first pass's.
 template <int LW>
-__global__ __launch_bounds__(BLOCK) void k_align_slow(DevIndex ix, ReadsView rd, Params P, LaneBufs B,
-                                                      const uint32_t *slow_list, uint32_t n_slow, uint32_t *n_rep,
-                                                      uint32_t *c1, uint32_t *c2, uint8_t *status, uint32_t *expand) {
-    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_slow) return;
-    uint32_t r = slow_list[t];
-    uint64_t o0, len;
-    bool bad;
-    read_span(rd, r, o0, len, bad);
-    const int m = (int)len;
-    int maxd = rd.maxd ? rd.maxd[r] : P.max_diff;
+__global__ __launch_bounds__(BLOCK) void k_align_slow(DevIndex ix, ReadsView rd, Params P, LaneBufs B, ReadOut O,
+                                                      uint32_t *slow_next) {
+    const uint32_t gl = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ns = *O.n_slow;
+    if (blockIdx.x * blockDim.x >= ns) return;  // the whole block has nothing to take
     LaneCtx c;
-    init_ctx(c, B, t);
-    align_read<LW>(ix, rd.bases + o0, m, maxd, P, c, PH_BEST);
-    uint8_t st = 0;
-    uint32_t a = 0, b = 0, nr = 0;
-    if (c.best != INF_SCORE) {
-        int rc = align_read<LW>(ix, rd.bases + o0, m, maxd, P, c, PH_COLLECT);
-        if (rc == R_CAND) {
-            st = BWFM_ST_OVERFLOW;
-            a = b = 0xffffffffu;
-        } else {
-            nr = finish(c, P, st, a, b);
+    init_ctx(c, B, gl);
+    for (;;) {
+        const uint32_t t = atomicAdd(slow_next, 1u);
+        if (t >= ns) break;
+        const uint32_t r = O.slow_list[t];
+        uint64_t o0, len;
+        bool bad;
+        read_span(rd, r, o0, len, bad);
+        const int m = (int)len;
+        const int maxd = rd.maxd ? rd.maxd[r] : P.max_diff;
+        c.expand = 0;
+        c.best = INF_SCORE;
+        align_read<LW>(ix, rd.bases + o0, m, maxd, P, c, PH_BEST);
+        uint8_t st = 0;
+        uint32_t a = 0, b = 0, nr = 0;
+        if (c.best != INF_SCORE) {
+            const int rc = align_read<LW>(ix, rd.bases + o0, m, maxd, P, c, PH_COLLECT);
+            if (rc == R_CAND) {
+                st = BWFM_ST_OVERFLOW;
+                a = b = 0xffffffffu;
+            } else {
+                nr = finish(c, P, st, a, b);
+            }
         }
+        stage_hits(c, O, r, nr);
+        O.n_rep[r] = nr;
+        O.status[r] = st | ST_RESEARCH;
+        O.c1[r] = a;
+        O.c2[r] = b;
+        if (O.expand) O.expand[r] += c.expand;
     }
-    n_rep[r] = nr;
-    status[r] = st | ST_RESEARCH;
-    c1[r] = a;
-    c2[r] = b;
-    if (expand) expand[r] += c.expand;
 }
 
-// Copy each read's reported hits to the CSR output: from the staging arena,
-// or from the second pass's lane buffers for the reads it handled.
+// Copy each read's reported hits from the staging arena to the CSR output.
+// Launched only when the output holds them all.
 __global__ void k_compact(uint32_t n, const uint64_t *hoff, const uint4 *stage, const uint64_t *stage_off,
-                          const uint4 *slow, uint32_t slow_stride, const uint32_t *slow_list, uint32_t n_slow,
-                          const uint8_t *status, uint4 *hits) {
-    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    uint64_t o = hoff[r], e = hoff[r + 1];
+                          uint4 *hits, const uint64_t *n_dev, const uint32_t *err) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (err && *err) return;  // the output cannot hold the hits
+    if (r >= count_of(n, n_dev)) return;
+    const uint64_t o = hoff[r], e = hoff[r + 1];
     if (e == o) return;
-    if (status[r] & ST_RESEARCH) {
-        // position of r in the slow list (sorted on the host)
-        uint32_t lo = 0, hi = n_slow;
-        while (lo < hi) {
-            uint32_t mid = (lo + hi) / 2;
-            if (slow_list[mid] < r) lo = mid + 1;
-            else hi = mid;
-        }
-        for (uint64_t j = 0; j < e - o; j++) hits[o + j] = slow[(size_t)j * slow_stride + lo];
-    } else {
-        const uint4 *src = stage + stage_off[r];
-        for (uint64_t j = 0; j < e - o; j++) hits[o + j] = src[j];
-    }
+    const uint4 *src = stage + stage_off[r];
+    for (uint64_t j = 0; j < e - o; j++) hits[o + j] = src[j];
+}
+
+// Fill n words with v (used instead of a memset node, so that a captured
+// sequence replays it reliably).
+__global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ------------------------------------------------------------------ exclusive scan (u32 counts -> u64 offsets)
 
 constexpr int SCAN_BLOCK = 1024;
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const uint32_t *in, uint64_t n, uint64_t *part) {
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const uint32_t *in, uint64_t n, uint64_t *part,
+                                                            const uint64_t *n_dev) {
     __shared__ uint64_t s[SCAN_BLOCK / 64];
+    n = count_of(n, n_dev);
     uint64_t i = (uint64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
     uint64_t v = i < n ? in[i] : 0;
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -901,9 +1120,14 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_parts(uint64_t *part, uint6
 }
 
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const uint32_t *in, uint64_t n, const uint64_t *part,
-                                                           uint64_t *out) {
+                                                           uint64_t *out, const uint64_t *n_dev) {
     __shared__ uint64_t s[SCAN_BLOCK];
+    n = count_of(n, n_dev);
     uint64_t i = (uint64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    if (n == 0) {
+        if (i == 0) out[0] = 0;
+        return;
+    }
     uint64_t v = i < n ? in[i] : 0;
     s[threadIdx.x] = v;
     __syncthreads();
@@ -920,21 +1144,20 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const uint32_t *in, u
 // ------------------------------------------------------------------ locate
 
 // per hit: number of positions to locate (width if <= max_occ, else 0)
-__global__ void k_loc_count(uint64_t n_hits, const uint4 *hits, uint32_t max_occ, uint32_t *cnt) {
+__global__ void k_loc_count(uint64_t n_hits, const uint4 *hits, uint32_t max_occ, uint32_t *cnt,
+                            const uint64_t *n_dev) {
     uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= n_hits) return;
+    if (h >= count_of(n_hits, n_dev)) return;
     uint4 x = hits[h];
     uint64_t w = (uint64_t)x.y - x.x + 1;
     cnt[h] = (x.x <= x.y && w <= max_occ) ? (uint32_t)w : 0;
 }
 
-// one lane per position: find its hit, walk LF to a sampled row
+// position p of the located hits: its hit is the last h with poff[h] <= p
 template <int LW>
-__global__ void k_loc_rows(DevIndex ix, uint64_t n_hits, const uint4 *hits, const uint64_t *poff, uint64_t total,
+__device__ void locate_one(const DevIndex &ix, uint64_t n_hits, const uint4 *hits, const uint64_t *poff, uint64_t p,
                            uint32_t *pos) {
-    uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= total) return;
-    uint64_t lo = 0, hi = n_hits;  // last h with poff[h] <= p
+    uint64_t lo = 0, hi = n_hits;
     while (hi - lo > 1) {
         uint64_t mid = (lo + hi) / 2;
         if (poff[mid] <= p) lo = mid;
@@ -956,11 +1179,22 @@ __global__ void k_loc_rows(DevIndex ix, uint64_t n_hits, const uint4 *hits, cons
     pos[p] = strand == 0 ? ix.n - q - (uint32_t)h_len(x) : q;
 }
 
+// one lane per position (grid-stride): find its hit, walk LF to a sampled row
+template <int LW>
+__global__ void k_loc_rows(DevIndex ix, uint64_t n_hits, const uint4 *hits, const uint64_t *poff, uint64_t total,
+                           uint32_t *pos, const uint64_t *n_hits_dev, const uint64_t *total_dev) {
+    n_hits = count_of(n_hits, n_hits_dev);
+    total = count_of(total, total_dev);
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+         p += (uint64_t)gridDim.x * blockDim.x)
+        locate_one<LW>(ix, n_hits, hits, poff, p, pos);
+}
 // sort each hit's positions: short segments by one lane, long ones by a
 // workgroup running a bitonic network (pairs past the end count as +inf)
-__global__ void k_sort_small(uint64_t n_hits, const uint64_t *poff, uint32_t *pos, uint32_t *big, uint32_t *n_big) {
+__global__ void k_sort_small(uint64_t n_hits, const uint64_t *poff, uint32_t *pos, uint32_t *big, uint32_t *n_big,
+                             const uint64_t *n_dev) {
     uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= n_hits) return;
+    if (h >= count_of(n_hits, n_dev)) return;
     uint64_t o = poff[h], w = poff[h + 1] - o;
     if (w <= 1) return;
     if (w > 32) {
@@ -1051,9 +1285,17 @@ __device__ bool se_primary(const EndView &e, uint32_t q, uint32_t &pos, uint4 &h
     return found;
 }
 
+// One lane per pair.  With n_dev, the pair count is read on the device and
+// end 2's reads follow end 1's in one batch (its offsets start at
+// e1.hoff + n); a nonzero *err (an output was too small) writes nothing.
 __global__ void k_pair(uint32_t n_pairs, EndView e1, EndView e2, int paired, int32_t lo, int32_t hi, int32_t mu,
-                       bwfm_pair *out) {
+                       bwfm_pair *out, const uint64_t *n_dev, const uint32_t *err) {
     uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (err && *err) return;
+    if (n_dev) {
+        n_pairs = (uint32_t)count_of(n_pairs, n_dev);
+        e2.hoff = e1.hoff + n_pairs;
+    }
     if (q >= n_pairs) return;
     bwfm_pair o;
     memset(&o, 0, sizeof(o));
@@ -1316,16 +1558,19 @@ struct Carver {
     }
 };
 
-// exclusive scan of n u32 counts into n + 1 u64 offsets (out[n] = total)
-int scan_counts(const uint32_t *cnt, uint64_t n, uint64_t *out, uint64_t *part, hipStream_t st) {
+// Exclusive scan of n u32 counts into n + 1 u64 offsets (out[n] = total).
+// With n_dev the count is read on the device (at most n; the grid covers n).
+int scan_counts(const uint32_t *cnt, uint64_t n, uint64_t *out, uint64_t *part, hipStream_t st,
+                const uint64_t *n_dev = nullptr) {
     uint64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
     if (n == 0) {
-        HIPCHK(hipMemsetAsync(out, 0, sizeof(uint64_t), st));
+        k_fill_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t *>(out), 2, 0u);
+        HIPCHK(hipGetLastError());
         return BWFM_OK;
     }
-    k_scan_reduce<<<(uint32_t)nb, SCAN_BLOCK, 0, st>>>(cnt, n, part);
+    k_scan_reduce<<<(uint32_t)nb, SCAN_BLOCK, 0, st>>>(cnt, n, part, n_dev);
     k_scan_parts<<<1, SCAN_BLOCK, 0, st>>>(part, nb);
-    k_scan_apply<<<(uint32_t)nb, SCAN_BLOCK, 0, st>>>(cnt, n, part, out);
+    k_scan_apply<<<(uint32_t)nb, SCAN_BLOCK, 0, st>>>(cnt, n, part, out, n_dev);
     HIPCHK(hipGetLastError());
     return BWFM_OK;
 }
@@ -1333,9 +1578,10 @@ int scan_counts(const uint32_t *cnt, uint64_t n, uint64_t *out, uint64_t *part, 
 size_t scan_part_elems(uint64_t n) { return (n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1; }
 
 // Lanes of a persistent grid that fit on the device at once, for a block
-// size and its dynamic LDS.
+// size and its dynamic LDS, at most waves_per_simd waves per SIMD (0 = no
+// cap; a CU has 4 SIMDs).
 template <int LW>
-uint32_t persistent_lanes(uint32_t bs, size_t lds) {
+uint32_t persistent_lanes(uint32_t bs, size_t lds, int waves_per_simd) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -1343,12 +1589,16 @@ uint32_t persistent_lanes(uint32_t bs, size_t lds) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_align_persistent<LW>, (int)bs, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
+    if (waves_per_simd > 0) {
+        const int cap = std::max(1, waves_per_simd * 4 * 64 / (int)bs);
+        per_cu = std::min(per_cu, cap);
+    }
     return (uint32_t)cus * (uint32_t)per_cu * bs;
 }
 
 // LDS bytes per lane for reads up to mlen bases (an odd number of dwords,
 // which spreads the lanes' rows over the banks) and the largest block that
-// keeps a block's LDS within 64 KB.
+// keeps a block's LDS (rows plus the per-wave sharing blocks) within 64 KB.
 inline uint32_t lds_stride_for(uint32_t mlen) {
     uint32_t dw = (mlen + 3) / 4;
     if ((dw & 1) == 0) dw++;
@@ -1356,9 +1606,11 @@ inline uint32_t lds_stride_for(uint32_t mlen) {
 }
 inline uint32_t block_for(uint32_t stride) {
     uint32_t bs = BLOCK;
-    while (bs > 64 && (size_t)bs * stride > 65536) bs /= 2;
+    while (bs > 64 && (size_t)bs * stride + (bs / 64) * sizeof(WaveShare) > 65536) bs /= 2;
     return bs;
 }
+
+constexpr uint32_t SLOW_LANES = 16384;  // most lanes of the second pass
 
 template <int LW>
 int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, bwfm_aln_result *res,
@@ -1366,18 +1618,23 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     const uint32_t n = rd->n_reads;
     const DevIndex D = dev_index(ix);
     const Params P = make_params(*p);
-    ReadsView rv{rd->bases, rd->offsets, rd->lengths, rd->max_diff, rd->n_reads, rd->max_len};
+    ReadsView rv{rd->bases, rd->offsets, rd->lengths, rd->max_diff, rd->n_reads, rd->max_len, nullptr};
     const uint32_t mlen = std::max<uint32_t>(rd->max_len, 1);
     const uint32_t worst_stack = 8 * (mlen + BWFM_MAX_DIFF) + 1;  // never overflows
     const uint32_t lstride = lds_stride_for(mlen);
     const uint32_t bs = block_for(lstride);
-    const size_t lds = (size_t)bs * lstride;
     const bool plain = p->form == BWFM_FORM_PLAIN;
+    const size_t lds = (size_t)bs * lstride + (plain ? 0 : (bs / 64) * sizeof(WaveShare));
     const uint32_t nr_up = ((std::max<uint32_t>(n, 1) + bs - 1) / bs) * bs;
-    const uint32_t lanes = plain ? nr_up : std::min<uint32_t>(persistent_lanes<LW>(bs, lds), nr_up);
+    const uint32_t lanes = plain ? nr_up : std::min<uint32_t>(persistent_lanes<LW>(bs, lds, p->waves_per_simd), nr_up);
     const uint32_t stack_cap = plain ? std::min<uint32_t>(worst_stack, PLAIN_STACK) : worst_stack;
-    const uint64_t stage_cap = std::max<uint64_t>(4ull * n, 4096);
+    // the staging arena holds the reported hits of every read: as many as
+    // the output can take
+    const uint64_t stage_cap = res->hit_capacity;
+    const uint32_t slow_lanes = std::min<uint32_t>(nr_up, SLOW_LANES);
+    const uint32_t scap = P.max_hits + 1;
     size_t need = (size_t)lanes * stack_cap * 16 + (size_t)lanes * FAST_CAND * 16;
+    need += (size_t)slow_lanes * worst_stack * 16 + (size_t)slow_lanes * scap * 16;
     need += (size_t)n * 4 * 2 + (size_t)n * 8 + stage_cap * 16 + scan_part_elems(n) * 8 + 16 * 256;
     void *w;
     int rc = ws_reserve(ix, need, &w);
@@ -1385,15 +1642,17 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     Carver cv{(char *)w};
     uint4 *lstack = cv.take<uint4>((size_t)lanes * stack_cap);
     uint4 *lcand = cv.take<uint4>((size_t)lanes * FAST_CAND);
+    uint4 *sstack = cv.take<uint4>((size_t)slow_lanes * worst_stack);
+    uint4 *scand = cv.take<uint4>((size_t)slow_lanes * scap);
     uint32_t *n_rep = cv.take<uint32_t>(n);
     uint32_t *slow_list = cv.take<uint32_t>(n);
     uint64_t *stage_off = cv.take<uint64_t>(n);
     uint4 *stage = cv.take<uint4>(stage_cap);
     uint64_t *part = cv.take<uint64_t>(scan_part_elems(n));
-    uint32_t *ctl = cv.take<uint32_t>(16);  // n_slow, next_read, stage_used (64-bit)
-    uint32_t *n_slow = ctl, *next_read = ctl + 1;
+    uint32_t *ctl = cv.take<uint32_t>(16);  // n_slow, next_read, stage_used (64-bit), slow_next
+    uint32_t *n_slow = ctl, *next_read = ctl + 1, *slow_next = ctl + 4;
     unsigned long long *stage_used = reinterpret_cast<unsigned long long *>(ctl + 2);
-    HIPCHK(hipMemsetAsync(ctl, 0, 64, st));
+    k_fill_u32<<<1, 64, 0, st>>>(ctl, 16, 0u);
     // plain lanes start together and stay roughly in step: interleave their
     // buffers; persistent lanes drift apart: give each a contiguous run
     LaneBufs lb = plain ? LaneBufs{lstack, lcand, 1, lanes, stack_cap, 1, lanes, FAST_CAND, lstride}
@@ -1401,7 +1660,7 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     ReadOut O{n_rep,     res->c1,   res->c2,   res->status, slow_list,
               n_slow,    stage,     stage_used, stage_cap,  stage_off,
               expand,    reinterpret_cast<unsigned long long *>(work)};
-    if (work) HIPCHK(hipMemsetAsync(work, 0, 24, st));
+    if (work) k_fill_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t *>(work), 6, 0u);
     CallTimer tm(st);
     if (n) {
         if (plain) {
@@ -1413,61 +1672,29 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
             k_align_persistent<LW><<<lanes / bs, bs, lds, st>>>(D, rv, P, lb, O, next_read);
             tm.end(t);
         }
+        // the second pass reads its count on the device: no host round trip
+        const size_t slds = (size_t)bs * lstride;
+        LaneBufs sb{sstack, scand, worst_stack, 1, worst_stack, scap, 1, scap, lstride};
+        int t = tm.begin("align_slow");
+        k_align_slow<LW><<<slow_lanes / bs, bs, slds, st>>>(D, rv, P, sb, O, slow_next);
+        tm.end(t);
         HIPCHK(hipGetLastError());
     }
-    uint32_t ns = 0;
-    HIPCHK(hipMemcpyAsync(&ns, n_slow, 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    void *slow_mem = nullptr;
-    uint4 *scand = nullptr;
-    uint32_t scap = 0;
-    if (ns) {
-        // sort the slow list so the compaction can find each read's slot
-        std::vector<uint32_t> hl(ns);
-        HIPCHK(hipMemcpy(hl.data(), slow_list, 4ull * ns, hipMemcpyDeviceToHost));
-        std::sort(hl.begin(), hl.end());
-        HIPCHK(hipMemcpy(slow_list, hl.data(), 4ull * ns, hipMemcpyHostToDevice));
-        scap = P.max_hits + 1;
-        size_t sbytes = (size_t)ns * worst_stack * 16 + (size_t)ns * scap * 16 + 1024;
-        if (hipMalloc(&slow_mem, sbytes) != hipSuccess) return fail(BWFM_E_NOMEM, "second-pass buffers");
-        Carver sc{(char *)slow_mem};
-        uint4 *sstack = sc.take<uint4>((size_t)ns * worst_stack);
-        scand = sc.take<uint4>((size_t)ns * scap);
-        // hit slots interleaved (stride ns): the compaction reads them that way
-        LaneBufs sb{sstack, scand, worst_stack, 1, worst_stack, 1, ns, scap, lstride};
-        int t = tm.begin("align_slow");
-        k_align_slow<LW><<<blocks(ns, bs), bs, lds, st>>>(D, rv, P, sb, slow_list, ns, n_rep, res->c1, res->c2,
-                                                          res->status, expand);
-        tm.end(t);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) {
-            (void)hipFree(slow_mem);
-            return fail(BWFM_E_DEVICE, std::string("k_align_slow: ") + hipGetErrorString(e));
-        }
-    }
-    int src = scan_counts(n_rep, n, res->hit_offsets, part, st);
-    if (src) { if (slow_mem) (void)hipFree(slow_mem); return src; }
+    rc = scan_counts(n_rep, n, res->hit_offsets, part, st);
+    if (rc) return rc;
     uint64_t total = 0;
-    hipError_t e1 = hipMemcpyAsync(&total, res->hit_offsets + n, 8, hipMemcpyDeviceToHost, st);
-    hipError_t e2 = hipStreamSynchronize(st);
-    if (e1 != hipSuccess || e2 != hipSuccess) {
-        if (slow_mem) (void)hipFree(slow_mem);
-        return fail(BWFM_E_DEVICE, "align: reading the hit total failed");
-    }
-    if (total > res->hit_capacity) {
-        if (slow_mem) (void)hipFree(slow_mem);
+    HIPCHK(hipMemcpyAsync(&total, res->hit_offsets + n, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (total > res->hit_capacity)
         return fail(BWFM_E_CAPACITY, "hit capacity " + std::to_string(res->hit_capacity) + " < " + std::to_string(total));
-    }
-    if (n) {
+    if (n && total) {
         int t = tm.begin("compact");
-        k_compact<<<blocks(n, 256), 256, 0, st>>>(n, res->hit_offsets, stage, stage_off, scand, ns, slow_list, ns,
-                                                  res->status, reinterpret_cast<uint4 *>(res->hits));
+        k_compact<<<blocks(n, 256), 256, 0, st>>>(n, res->hit_offsets, stage, stage_off,
+                                                  reinterpret_cast<uint4 *>(res->hits), nullptr, nullptr);
         tm.end(t);
+        HIPCHK(hipGetLastError());
     }
-    hipError_t e3 = hipGetLastError();
-    hipError_t e4 = hipStreamSynchronize(st);
-    if (slow_mem) (void)hipFree(slow_mem);
-    if (e3 != hipSuccess || e4 != hipSuccess) return fail(BWFM_E_DEVICE, "align: compaction failed");
+    HIPCHK(hipStreamSynchronize(st));
     return BWFM_OK;
 }
 
@@ -1478,7 +1705,7 @@ int locate_impl(bwfm_index *ix, uint64_t n_hits, const uint4 *hits, uint32_t max
                 hipStream_t st, uint64_t *total_out) {
     const DevIndex D = dev_index(ix);
     if (n_hits) {
-        k_loc_count<<<blocks(n_hits, 256), 256, 0, st>>>(n_hits, hits, max_occ, cnt);
+        k_loc_count<<<blocks(n_hits, 256), 256, 0, st>>>(n_hits, hits, max_occ, cnt, nullptr);
         HIPCHK(hipGetLastError());
     }
     int rc = scan_counts(cnt, n_hits, pos_off, part, st);
@@ -1491,12 +1718,13 @@ int locate_impl(bwfm_index *ix, uint64_t n_hits, const uint4 *hits, uint32_t max
     if (total) {
         CallTimer tm(st);
         int t = tm.begin("locate_rows");
-        k_loc_rows<LW><<<blocks(total, 256), 256, 0, st>>>(D, n_hits, hits, pos_off, total, pos);
+        k_loc_rows<LW><<<(uint32_t)std::min<uint64_t>(blocks(total, 256), 65536), 256, 0, st>>>(D, n_hits, hits, pos_off, total,
+                                                                                            pos, nullptr, nullptr);
         tm.end(t);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemsetAsync(n_big, 0, 4, st));
+        k_fill_u32<<<1, 64, 0, st>>>(n_big, 1, 0u);
         t = tm.begin("sort");
-        k_sort_small<<<blocks(n_hits, 256), 256, 0, st>>>(n_hits, pos_off, pos, big, n_big);
+        k_sort_small<<<blocks(n_hits, 256), 256, 0, st>>>(n_hits, pos_off, pos, big, n_big, nullptr);
         k_sort_big<<<1024, 256, 0, st>>>(pos_off, pos, big, n_big);
         tm.end(t);
         HIPCHK(hipGetLastError());
@@ -1547,9 +1775,8 @@ extern "C" void bwfm_index_free(bwfm_index *ix) {
     delete ix;
 }
 
-extern "C" int bwfm_align_batch(const bwfm_index *cix, const bwfm_reads *rd, const bwfm_aln_params *p,
-                                bwfm_aln_result *res, void *stream) {
-    bwfm_index *ix = const_cast<bwfm_index *>(cix);
+// Argument checks shared by the align entry points; 0 or a bwfm_err.
+static int check_align_args(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, const bwfm_aln_result *res) {
     if (!ix || !rd || !p || !check_result(res, rd->n_reads)) return fail(BWFM_E_INVAL, "align_batch: NULL argument");
     if (!check_index(ix)) return fail(BWFM_E_STATE, "align_batch: index not uploaded");
     if (rd->n_reads && (!rd->bases || !rd->offsets)) return fail(BWFM_E_INVAL, "align_batch: NULL reads");
@@ -1557,9 +1784,16 @@ extern "C" int bwfm_align_batch(const bwfm_index *cix, const bwfm_reads *rd, con
     if (p->max_diff < 0 || p->max_diff > BWFM_MAX_DIFF || p->max_gapo < 0 || p->seed_len < 0 || p->seed_diff < 0 ||
         p->indel_end_skip < 0 || p->s_mm < 0 || p->s_gapo < 0 || p->s_gape < 0 ||
         (p->mode != BWFM_MODE_ALL && p->mode != BWFM_MODE_BEST) || p->max_best < 0 || p->max_hits < 1 ||
-        (p->form != BWFM_FORM_BATCHED && p->form != BWFM_FORM_PLAIN) ||
-        p->max_hits > 65536 || p->s_mm > 63 || p->s_gapo > 63 || p->s_gape > 63)
+        (p->form != BWFM_FORM_BATCHED && p->form != BWFM_FORM_PLAIN) || p->waves_per_simd < 0 ||
+        p->waves_per_simd > 8 || p->max_hits > 65536 || p->s_mm > 63 || p->s_gapo > 63 || p->s_gape > 63)
         return fail(BWFM_E_INVAL, "align_batch: parameter out of range");
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_align_batch(const bwfm_index *cix, const bwfm_reads *rd, const bwfm_aln_params *p,
+                                bwfm_aln_result *res, void *stream) {
+    bwfm_index *ix = const_cast<bwfm_index *>(cix);
+    if (int rc = check_align_args(ix, rd, p, res)) return rc;
     std::lock_guard<std::mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
     if (ix->line_bytes == 128) return align_impl<32>(ix, rd, p, res, st, nullptr);
@@ -1572,9 +1806,7 @@ extern "C" int bwfm_align_batch_counted(const bwfm_index *cix, const bwfm_reads 
                                         bwfm_aln_result *res, uint32_t *expand, uint64_t *work, void *stream) {
     bwfm_index *ix = const_cast<bwfm_index *>(cix);
     if (!expand) return fail(BWFM_E_INVAL, "align_batch_counted: NULL counter array");
-    if (!ix || !rd || !p || !check_result(res, rd->n_reads)) return fail(BWFM_E_INVAL, "align_batch: NULL argument");
-    if (!check_index(ix)) return fail(BWFM_E_STATE, "align_batch: index not uploaded");
-    if (rd->max_len > BWFM_MAX_READ) return fail(BWFM_E_TOOLONG, "align_batch: max_len above 512");
+    if (int rc = check_align_args(ix, rd, p, res)) return rc;
     std::lock_guard<std::mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
     if (ix->line_bytes == 128) return align_impl<32>(ix, rd, p, res, st, expand, work);
@@ -1680,7 +1912,8 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
         if (r2) e2 = EndView{r2->hit_offsets, (const uint4 *)r2->hits, poff[1], pos[1], hb[1]};
         CallTimer tm(st);
         int t = tm.begin("pair");
-        k_pair<<<blocks(n_pairs, 256), 256, 0, st>>>(n_pairs, e1, e2, r2 ? 1 : 0, pp->lo, pp->hi, pp->mu, out);
+        k_pair<<<blocks(n_pairs, 256), 256, 0, st>>>(n_pairs, e1, e2, r2 ? 1 : 0, pp->lo, pp->hi, pp->mu, out, nullptr,
+                                                     nullptr);
         tm.end(t);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) rc = fail(BWFM_E_DEVICE, std::string("k_pair: ") + hipGetErrorString(e));
@@ -1785,6 +2018,381 @@ extern "C" int bwfm_probe_gather(const void *buf, uint64_t bytes, uint32_t line_
     if (e != hipSuccess) return fail(BWFM_E_DEVICE, std::string("k_probe_gather: ") + hipGetErrorString(e));
     *ms_out = ms;
     return BWFM_OK;
+}
+
+// ------------------------------------------------------------------ captured pipeline
+
+namespace {
+
+// control words of a pipeline (uint64 indices)
+enum {
+    PC_PAIRS = 0,     // pairs in this run
+    PC_READS = 1,     // reads in this run (2 * pairs)
+    PC_HITS = 2,      // reported hits, 0 when they do not fit
+    PC_POS = 3,       // located positions, 0 when they do not fit
+    PC_NEED_HITS = 4, // reported hits
+    PC_NEED_POS = 5,  // located positions
+    PC_ERR = 6,       // BWFM_PIPE_E_* bits (low 32 bits)
+    PC_BIG = 7,       // hits sorted by a workgroup (low 32 bits)
+    PC_ALIGN = 8,     // 16 uint32 of the align kernels' counters
+    PC_WORDS = 16
+};
+
+__global__ void k_pipe_begin(uint64_t *ctl, uint32_t n_pairs, uint32_t ends) {
+    const uint32_t i = threadIdx.x;
+    if (i < PC_WORDS) ctl[i] = i == PC_PAIRS ? n_pairs : (i == PC_READS ? (uint64_t)ends * n_pairs : 0ull);
+}
+
+// dst = offs[*n_dev], the total of a scan, or 0 with an error bit when it
+// exceeds cap or an earlier stage already failed; need keeps the total
+__global__ void k_take_total(const uint64_t *offs, const uint64_t *n_dev, uint64_t cap, uint64_t *dst, uint64_t *need,
+                             uint32_t *err, uint32_t bit) {
+    if (threadIdx.x != 0) return;
+    const uint64_t t = (*err) ? 0 : offs[*n_dev];
+    *need = t;
+    if (t > cap) *err |= bit;
+    *dst = (*err) ? 0 : t;
+}
+
+}  // namespace
+
+struct bwfm_pipeline {
+    bwfm_index *ix = nullptr;
+    bwfm_aln_params ap{};
+    bwfm_pair_params pp{};
+    bwfm_pipeline_params q{};
+    void *mem = nullptr;
+    // inputs
+    uint8_t *bases = nullptr;
+    uint64_t *offsets = nullptr;
+    uint8_t *maxd = nullptr;
+    // search buffers
+    uint4 *lstack = nullptr, *lcand = nullptr, *sstack = nullptr, *scand = nullptr, *stage = nullptr;
+    uint32_t *n_rep = nullptr, *slow_list = nullptr;
+    uint64_t *stage_off = nullptr, *part = nullptr;
+    // outputs
+    uint64_t *hoff = nullptr, *poff = nullptr;
+    uint4 *hits = nullptr;
+    uint32_t *c1 = nullptr, *c2 = nullptr, *cnt = nullptr, *big = nullptr, *pos = nullptr;
+    uint8_t *status = nullptr;
+    bwfm_pair *pairs = nullptr;
+    uint64_t *ctl = nullptr;
+    // launch shape
+    uint32_t lanes = 0, slow_lanes = 0, bs = 0, lstride = 0, stack_cap = 0, worst_stack = 0, scap = 0;
+    size_t lds = 0;
+    uint32_t n_pairs = 0;  // of the batch last set
+    uint32_t ends = 2;     // reads per pair record
+    bool bound = false;    // input from caller-owned buffers
+    bwfm_reads in{};       // the bound input
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipStream_t cap = nullptr;  // capture only: nothing runs on it
+    bool timed_graph = false, timed_last = false;
+};
+
+namespace {
+
+// Enqueue the step.  Every count comes from the control words.
+template <int LW>
+int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed) {
+    const DevIndex D = dev_index(pl->ix);
+    const Params P = make_params(pl->ap);
+    const uint32_t nmax = pl->ends * pl->q.max_pairs;
+    uint64_t *ctl = pl->ctl;
+    uint32_t *actl = reinterpret_cast<uint32_t *>(ctl + PC_ALIGN);
+    uint32_t *err = reinterpret_cast<uint32_t *>(ctl + PC_ERR);
+    ReadsView rv = pl->bound ? ReadsView{pl->in.bases, pl->in.offsets, pl->in.lengths, pl->in.max_diff, nmax,
+                                         pl->in.max_len, ctl + PC_READS}
+                             : ReadsView{pl->bases, pl->offsets, nullptr, pl->maxd, nmax, pl->q.max_len, ctl + PC_READS};
+    const bool plain = pl->ap.form == BWFM_FORM_PLAIN;
+    LaneBufs lb = plain ? LaneBufs{pl->lstack, pl->lcand, 1, pl->lanes, pl->stack_cap, 1, pl->lanes, FAST_CAND, pl->lstride}
+                        : LaneBufs{pl->lstack, pl->lcand, pl->stack_cap, 1, pl->stack_cap, FAST_CAND, 1, FAST_CAND,
+                                   pl->lstride};
+    ReadOut O{pl->n_rep, pl->c1, pl->c2, pl->status, pl->slow_list, actl, pl->stage,
+              reinterpret_cast<unsigned long long *>(actl + 2), pl->q.hit_capacity, pl->stage_off, nullptr, nullptr};
+    if (timed) HIPCHK(hipEventRecord(pl->ev[0], st));
+    if (plain)
+        k_align_plain<LW><<<pl->lanes / pl->bs, pl->bs, pl->lds, st>>>(D, rv, P, lb, O);
+    else
+        k_align_persistent<LW><<<pl->lanes / pl->bs, pl->bs, pl->lds, st>>>(D, rv, P, lb, O, actl + 1);
+    if (timed) HIPCHK(hipEventRecord(pl->ev[1], st));
+    LaneBufs sb{pl->sstack, pl->scand, pl->worst_stack, 1, pl->worst_stack, pl->scap, 1, pl->scap, pl->lstride};
+    k_align_slow<LW><<<pl->slow_lanes / pl->bs, pl->bs, (size_t)pl->bs * pl->lstride, st>>>(D, rv, P, sb, O, actl + 4);
+    HIPCHK(hipGetLastError());
+    int rc = scan_counts(pl->n_rep, nmax, pl->hoff, pl->part, st, ctl + PC_READS);
+    if (rc) return rc;
+    k_take_total<<<1, 64, 0, st>>>(pl->hoff, ctl + PC_READS, pl->q.hit_capacity, ctl + PC_HITS, ctl + PC_NEED_HITS, err,
+                                   BWFM_PIPE_E_HITS);
+    k_compact<<<blocks(nmax, 256), 256, 0, st>>>(nmax, pl->hoff, pl->stage, pl->stage_off, pl->hits, ctl + PC_READS,
+                                                 err);
+    // every hit of both ends is located in one pass
+    const uint64_t hcap = std::max<uint64_t>(pl->q.hit_capacity, 1);
+    k_loc_count<<<blocks(hcap, 256), 256, 0, st>>>(hcap, pl->hits, pl->pp.max_occ, pl->cnt, ctl + PC_HITS);
+    rc = scan_counts(pl->cnt, hcap, pl->poff, pl->part, st, ctl + PC_HITS);
+    if (rc) return rc;
+    k_take_total<<<1, 64, 0, st>>>(pl->poff, ctl + PC_HITS, pl->q.pos_capacity, ctl + PC_POS, ctl + PC_NEED_POS, err,
+                                   BWFM_PIPE_E_POSITIONS);
+    k_loc_rows<LW><<<2048, 256, 0, st>>>(D, hcap, pl->hits, pl->poff, pl->q.pos_capacity, pl->pos, ctl + PC_HITS,
+                                         ctl + PC_POS);
+    uint32_t *n_big = reinterpret_cast<uint32_t *>(ctl + PC_BIG);
+    k_sort_small<<<blocks(hcap, 256), 256, 0, st>>>(hcap, pl->poff, pl->pos, pl->big, n_big, ctl + PC_HITS);
+    k_sort_big<<<1024, 256, 0, st>>>(pl->poff, pl->pos, pl->big, n_big);
+    EndView e1{pl->hoff, pl->hits, pl->poff, pl->pos, 0};
+    EndView e2{pl->hoff, pl->hits, pl->poff, pl->pos, 0};  // offsets moved by n on the device
+    k_pair<<<blocks(pl->q.max_pairs, 256), 256, 0, st>>>(pl->q.max_pairs, e1, e2, pl->ends == 2 ? 1 : 0, pl->pp.lo,
+                                                         pl->pp.hi, pl->pp.mu, pl->pairs, ctl + PC_PAIRS, err);
+    HIPCHK(hipGetLastError());
+    return BWFM_OK;
+}
+
+int pipe_enqueue_any(bwfm_pipeline *pl, hipStream_t st, bool timed) {
+    return pl->ix->line_bytes == 128 ? pipe_enqueue<32>(pl, st, timed) : pipe_enqueue<16>(pl, st, timed);
+}
+
+}  // namespace
+
+namespace {
+
+void drop_graph(bwfm_pipeline *pl) {
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    pl->exec = nullptr;
+    pl->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params *ap, const bwfm_pair_params *pp,
+                                    const bwfm_pipeline_params *q, bwfm_pipeline **out) {
+    bwfm_index *ix = const_cast<bwfm_index *>(cix);
+    if (!out) return fail(BWFM_E_INVAL, "pipeline_create: NULL argument");
+    *out = nullptr;
+    if (!ix || !ap || !pp || !q) return fail(BWFM_E_INVAL, "pipeline_create: NULL argument");
+    if (!check_index(ix)) return fail(BWFM_E_STATE, "pipeline_create: index not uploaded");
+    if (q->max_pairs == 0 || q->max_len == 0 || q->max_bases == 0 || q->max_pairs > (1u << 30))
+        return fail(BWFM_E_INVAL, "pipeline_create: empty or oversized capacity");
+    if (q->max_len > BWFM_MAX_READ) return fail(BWFM_E_TOOLONG, "pipeline_create: max_len above 512");
+    if (pp->lo > pp->hi) return fail(BWFM_E_INVAL, "pipeline_create: lo > hi");
+    {
+        bwfm_reads probe{nullptr, nullptr, nullptr, 0, q->max_len, nullptr};
+        bwfm_aln_result r0{nullptr, nullptr, 0, nullptr, nullptr, nullptr};
+        if (int rc = check_align_args(ix, &probe, ap, &r0)) return rc;
+    }
+    std::unique_ptr<bwfm_pipeline> pl(new (std::nothrow) bwfm_pipeline);
+    if (!pl) return fail(BWFM_E_NOMEM, "out of host memory");
+    pl->ix = ix;
+    pl->ap = *ap;
+    pl->pp = *pp;
+    pl->q = *q;
+    pl->ends = q->paired ? 2 : 1;
+    const uint32_t nmax = pl->ends * q->max_pairs;
+    const uint32_t mlen = q->max_len;
+    pl->worst_stack = 8 * (mlen + BWFM_MAX_DIFF) + 1;
+    pl->lstride = lds_stride_for(mlen);
+    pl->bs = block_for(pl->lstride);
+    const bool plain = ap->form == BWFM_FORM_PLAIN;
+    pl->lds = (size_t)pl->bs * pl->lstride + (plain ? 0 : (pl->bs / 64) * sizeof(WaveShare));
+    const uint32_t nr_up = ((nmax + pl->bs - 1) / pl->bs) * pl->bs;
+    pl->lanes = plain ? nr_up
+                      : std::min<uint32_t>(ix->line_bytes == 128 ? persistent_lanes<32>(pl->bs, pl->lds, ap->waves_per_simd)
+                                                                 : persistent_lanes<16>(pl->bs, pl->lds, ap->waves_per_simd),
+                                           nr_up);
+    pl->stack_cap = plain ? std::min<uint32_t>(pl->worst_stack, PLAIN_STACK) : pl->worst_stack;
+    pl->slow_lanes = std::min<uint32_t>(nr_up, SLOW_LANES);
+    pl->scap = ap->max_hits + 1;
+    const uint64_t hcap = std::max<uint64_t>(q->hit_capacity, 1);
+    const uint64_t pcap = std::max<uint64_t>(q->pos_capacity, 1);
+    size_t need = 0;
+    auto add = [&](size_t b) { need += (b + 255) & ~size_t(255); };
+    add(q->max_bases); add((size_t)(nmax + 1) * 8); add(nmax);
+    add((size_t)pl->lanes * pl->stack_cap * 16); add((size_t)pl->lanes * FAST_CAND * 16);
+    add((size_t)pl->slow_lanes * pl->worst_stack * 16); add((size_t)pl->slow_lanes * pl->scap * 16);
+    add((size_t)nmax * 4); add((size_t)nmax * 4); add((size_t)nmax * 8); add(hcap * 16);
+    add(scan_part_elems(std::max<uint64_t>(nmax, hcap)) * 8);
+    add((size_t)(nmax + 1) * 8); add(hcap * 16); add((size_t)nmax * 4); add((size_t)nmax * 4); add(nmax);
+    add(hcap * 4); add(hcap * 4); add((hcap + 1) * 8); add(pcap * 4); add((size_t)q->max_pairs * sizeof(bwfm_pair));
+    add(PC_WORDS * 8);
+    need += 4096;
+    if (hipMalloc(&pl->mem, need) != hipSuccess) return fail(BWFM_E_NOMEM, "pipeline: device allocation failed");
+    Carver cv{(char *)pl->mem};
+    pl->bases = cv.take<uint8_t>(q->max_bases);
+    pl->offsets = cv.take<uint64_t>(nmax + 1);
+    pl->maxd = cv.take<uint8_t>(nmax);
+    pl->lstack = cv.take<uint4>((size_t)pl->lanes * pl->stack_cap);
+    pl->lcand = cv.take<uint4>((size_t)pl->lanes * FAST_CAND);
+    pl->sstack = cv.take<uint4>((size_t)pl->slow_lanes * pl->worst_stack);
+    pl->scand = cv.take<uint4>((size_t)pl->slow_lanes * pl->scap);
+    pl->n_rep = cv.take<uint32_t>(nmax);
+    pl->slow_list = cv.take<uint32_t>(nmax);
+    pl->stage_off = cv.take<uint64_t>(nmax);
+    pl->stage = cv.take<uint4>(hcap);
+    pl->part = cv.take<uint64_t>(scan_part_elems(std::max<uint64_t>(nmax, hcap)));
+    pl->hoff = cv.take<uint64_t>(nmax + 1);
+    pl->hits = cv.take<uint4>(hcap);
+    pl->c1 = cv.take<uint32_t>(nmax);
+    pl->c2 = cv.take<uint32_t>(nmax);
+    pl->status = cv.take<uint8_t>(nmax);
+    pl->cnt = cv.take<uint32_t>(hcap);
+    pl->big = cv.take<uint32_t>(hcap);
+    pl->poff = cv.take<uint64_t>(hcap + 1);
+    pl->pos = cv.take<uint32_t>(pcap);
+    pl->pairs = cv.take<bwfm_pair>(q->max_pairs);
+    pl->ctl = cv.take<uint64_t>(PC_WORDS);
+    if (hipEventCreate(&pl->ev[0]) != hipSuccess || hipEventCreate(&pl->ev[1]) != hipSuccess ||
+        hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess) {
+        bwfm_pipeline_destroy(pl.release());
+        return fail(BWFM_E_DEVICE, "pipeline: event or stream creation failed");
+    }
+    *out = pl.release();
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_pipeline_set_reads(bwfm_pipeline *pl, const bwfm_reads *rd, uint32_t n_pairs, void *stream) {
+    if (!pl || !rd) return fail(BWFM_E_INVAL, "pipeline_set_reads: NULL argument");
+    if (rd->lengths) return fail(BWFM_E_INVAL, "pipeline_set_reads: lengths must be NULL");
+    if (rd->n_reads != pl->ends * n_pairs)
+        return fail(BWFM_E_INVAL, "pipeline_set_reads: n_reads must be n_pairs times the reads per pair");
+    if (n_pairs > pl->q.max_pairs) return fail(BWFM_E_CAPACITY, "pipeline_set_reads: more pairs than max_pairs");
+    if (rd->max_len > pl->q.max_len) return fail(BWFM_E_CAPACITY, "pipeline_set_reads: max_len above the pipeline's");
+    if (n_pairs && (!rd->bases || !rd->offsets)) return fail(BWFM_E_INVAL, "pipeline_set_reads: NULL reads");
+    hipStream_t st = (hipStream_t)stream;
+    const uint32_t n = pl->ends * n_pairs;
+    if (pl->bound) drop_graph(pl);
+    pl->bound = false;
+    if (n) {
+        uint64_t o[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(&o[0], rd->offsets, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&o[1], rd->offsets + n, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (o[0] != 0) return fail(BWFM_E_INVAL, "pipeline_set_reads: offsets must start at 0");
+        if (o[1] > pl->q.max_bases) return fail(BWFM_E_CAPACITY, "pipeline_set_reads: more bases than max_bases");
+        if (o[1]) HIPCHK(hipMemcpyAsync(pl->bases, rd->bases, o[1], hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(pl->offsets, rd->offsets, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, st));
+        if (rd->max_diff)
+            HIPCHK(hipMemcpyAsync(pl->maxd, rd->max_diff, n, hipMemcpyDeviceToDevice, st));
+        else
+            HIPCHK(hipMemsetAsync(pl->maxd, pl->ap.max_diff, n, st));
+    }
+    pl->n_pairs = n_pairs;
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_pipeline_bind_reads(bwfm_pipeline *pl, const bwfm_reads *rd) {
+    if (!pl || !rd || !rd->bases || !rd->offsets) return fail(BWFM_E_INVAL, "pipeline_bind_reads: NULL argument");
+    if (rd->n_reads < pl->ends * pl->q.max_pairs)
+        return fail(BWFM_E_CAPACITY, "pipeline_bind_reads: fewer read slots than the pipeline's maximum");
+    if (rd->max_len > pl->q.max_len) return fail(BWFM_E_CAPACITY, "pipeline_bind_reads: max_len above the pipeline's");
+    drop_graph(pl);
+    pl->in = *rd;
+    pl->in.max_len = pl->q.max_len;  // reads longer than the LDS rows allow are flagged invalid
+    pl->bound = true;
+    pl->n_pairs = 0;
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_pipeline_set_count(bwfm_pipeline *pl, uint32_t n_pairs) {
+    if (!pl || !pl->bound) return fail(BWFM_E_INVAL, "pipeline_set_count: no bound reads");
+    if (n_pairs > pl->q.max_pairs) return fail(BWFM_E_CAPACITY, "pipeline_set_count: more pairs than max_pairs");
+    pl->n_pairs = n_pairs;
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_pipeline_run(bwfm_pipeline *pl, int graph, void *stream) {
+    if (!pl) return fail(BWFM_E_INVAL, "pipeline_run: NULL pipeline");
+    hipStream_t st = (hipStream_t)stream;
+    bool timed;
+    {
+        std::lock_guard<std::mutex> g(timing().mu);
+        timed = timing().on;
+    }
+    // the batch size goes in by a launch of its own: the graph's kernels
+    // read it from the control words
+    k_pipe_begin<<<1, 64, 0, st>>>(pl->ctl, pl->n_pairs, pl->ends);
+    HIPCHK(hipGetLastError());
+    if (!graph) {
+        pl->timed_last = timed;
+        return pipe_enqueue_any(pl, st, timed);
+    }
+    if (pl->exec && pl->timed_graph != timed) drop_graph(pl);
+    if (!pl->exec) {
+        // recorded on the pipeline's own stream (the caller's may be the
+        // null stream, which cannot be captured); launched on the caller's
+        HIPCHK(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+        int rc = pipe_enqueue_any(pl, pl->cap, timed);
+        hipGraph_t gph = nullptr;
+        hipError_t e = hipStreamEndCapture(pl->cap, &gph);
+        if (rc) {
+            if (gph) (void)hipGraphDestroy(gph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(BWFM_E_DEVICE, std::string("pipeline capture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(gph);
+            return fail(BWFM_E_DEVICE, std::string("pipeline graph instantiation: ") + hipGetErrorString(e));
+        }
+        pl->graph = gph;
+        pl->exec = ex;
+        pl->timed_graph = timed;
+    }
+    pl->timed_last = pl->timed_graph;
+    HIPCHK(hipGraphLaunch(pl->exec, st));
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_pipeline_finish(bwfm_pipeline *pl, void *stream, bwfm_pipeline_status *out) {
+    if (!pl || !out) return fail(BWFM_E_INVAL, "pipeline_finish: NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t c[PC_WORDS];
+    HIPCHK(hipMemcpyAsync(c, pl->ctl, sizeof c, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    out->n_pairs = (uint32_t)c[PC_PAIRS];
+    out->error = (uint32_t)c[PC_ERR];
+    out->n_hits = c[PC_NEED_HITS];
+    out->n_positions = c[PC_NEED_POS];
+    out->kernel_ms = 0;
+    if (pl->timed_last) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, pl->ev[0], pl->ev[1]) == hipSuccess) {
+            out->kernel_ms = ms;
+            std::lock_guard<std::mutex> g(timing().mu);
+            auto &e = timing().acc[pl->ap.form == BWFM_FORM_PLAIN ? "align_plain" : "align_persistent"];
+            e.first += ms;
+            e.second += 1;
+        }
+    }
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_pipeline_outputs(bwfm_pipeline *pl, int end, bwfm_aln_result *res, uint64_t **pos_offsets,
+                                     uint32_t **positions, bwfm_pair **pairs) {
+    if (!pl || (end != 0 && end != 1)) return fail(BWFM_E_INVAL, "pipeline_outputs: bad argument");
+    if (end == 1 && pl->ends == 1) return fail(BWFM_E_INVAL, "pipeline_outputs: single-end pipeline has no end 2");
+    const uint64_t base = end ? pl->n_pairs : 0;
+    if (res) {
+        res->hit_offsets = pl->hoff + base;
+        res->hits = reinterpret_cast<bwfm_hit *>(pl->hits);
+        res->hit_capacity = pl->q.hit_capacity;
+        res->c1 = pl->c1 + base;
+        res->c2 = pl->c2 + base;
+        res->status = pl->status + base;
+    }
+    if (pos_offsets) *pos_offsets = pl->poff;
+    if (positions) *positions = pl->pos;
+    if (pairs) *pairs = pl->pairs;
+    return BWFM_OK;
+}
+
+extern "C" void bwfm_pipeline_destroy(bwfm_pipeline *pl) {
+    if (!pl) return;
+    drop_graph(pl);
+    for (auto &e : pl->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (pl->cap) (void)hipStreamDestroy(pl->cap);
+    if (pl->mem) (void)hipFree(pl->mem);
+    delete pl;
 }
 
 extern "C" const char *bwfm_last_error(void) { return last_error().c_str(); }

@@ -12,6 +12,8 @@
 // a symbol over 32 rows.  Every sa_sample-th row keeps its suffix array
 // value.
 #include <algorithm>
+#include <cstdio>
+#include <memory>
 #include <cstring>
 #include <stdexcept>
 #include <thread>
@@ -288,5 +290,138 @@ extern "C" int bwfm_index_get_sa_samples(const bwfm_index *ix, int which, uint32
 extern "C" int bwfm_index_occ(const bwfm_index *ix, int which, uint64_t i, uint64_t *out) {
     if (!ix || !out || which < 0 || which > 1 || i > ix->n + 1) return fail(BWFM_E_INVAL, "occ: bad argument");
     occ_host(ix->dir[which], ix->line_bytes / 4, ix->bpl, i, out);
+    return BWFM_OK;
+}
+
+// ------------------------------------------------------------------ index files
+
+namespace {
+
+constexpr char FILE_MAGIC[8] = {'B', 'W', 'F', 'M', 'I', 'D', 'X', 0};
+constexpr uint32_t FILE_VERSION = 1;
+
+struct Fnv {
+    uint64_t h = 1469598103934665603ULL;
+    void add(const void *p, size_t n) {
+        const uint8_t *b = static_cast<const uint8_t *>(p);
+        for (size_t i = 0; i < n; i++) {
+            h ^= b[i];
+            h *= 1099511628211ULL;
+        }
+    }
+};
+
+struct Writer {
+    FILE *f;
+    Fnv sum;
+    bool ok = true;
+    void put(const void *p, size_t n) {
+        if (!ok || n == 0) return;
+        sum.add(p, n);
+        ok = std::fwrite(p, 1, n, f) == n;
+    }
+    template <class T> void val(T v) { put(&v, sizeof v); }
+};
+
+struct Reader {
+    FILE *f;
+    Fnv sum;
+    bool ok = true;
+    void get(void *p, size_t n) {
+        if (!ok || n == 0) return;
+        ok = std::fread(p, 1, n, f) == n;
+        if (ok) sum.add(p, n);
+    }
+    template <class T> T val() {
+        T v{};
+        get(&v, sizeof v);
+        return v;
+    }
+};
+
+}  // namespace
+
+extern "C" int bwfm_index_save(const bwfm_index *ix, const char *path) {
+    if (!ix || !path) return fail(BWFM_E_INVAL, "index_save: NULL argument");
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(BWFM_E_IO, std::string("index_save: cannot open ") + path);
+    Writer w{f};
+    w.put(FILE_MAGIC, 8);
+    w.val<uint32_t>(FILE_VERSION);
+    w.val<uint32_t>(ix->line_bytes);
+    w.val<uint32_t>(ix->bpl);
+    w.val<uint32_t>(ix->sa_sample);
+    w.val<uint64_t>(ix->n);
+    w.val<uint64_t>(ix->n_lines);
+    w.val<uint64_t>(ix->n_samples);
+    for (int d = 0; d < 2; d++) {
+        const HostDir &h = ix->dir[d];
+        for (int a = 0; a < 4; a++) w.val<uint64_t>(h.C[a]);
+        w.val<uint64_t>(h.primary);
+        w.val<uint64_t>(h.lines.size());
+        w.put(h.lines.data(), h.lines.size() * 4);
+        w.val<uint64_t>(h.sa.size());
+        w.put(h.sa.data(), h.sa.size() * 4);
+    }
+    const uint64_t sum = w.sum.h;
+    if (w.ok) w.ok = std::fwrite(&sum, 1, 8, f) == 8;
+    const bool closed = std::fclose(f) == 0;
+    if (!w.ok || !closed) return fail(BWFM_E_IO, std::string("index_save: write failed on ") + path);
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_index_load(const char *path, bwfm_index **out) {
+    if (!path || !out) return fail(BWFM_E_INVAL, "index_load: NULL argument");
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(BWFM_E_IO, std::string("index_load: cannot open ") + path);
+    std::unique_ptr<FILE, int (*)(FILE *)> guard(f, std::fclose);
+    std::fseek(f, 0, SEEK_END);
+    const long fsize = std::ftell(f);
+    std::fseek(f, 0, SEEK_SET);
+    Reader r{f};
+    char magic[8];
+    r.get(magic, 8);
+    if (!r.ok || std::memcmp(magic, FILE_MAGIC, 8) != 0) return fail(BWFM_E_IO, "index_load: not an index file");
+    if (r.val<uint32_t>() != FILE_VERSION) return fail(BWFM_E_IO, "index_load: unsupported file version");
+    std::unique_ptr<bwfm_index> ix(new (std::nothrow) bwfm_index);
+    if (!ix) return fail(BWFM_E_NOMEM, "out of host memory");
+    ix->line_bytes = r.val<uint32_t>();
+    ix->bpl = r.val<uint32_t>();
+    ix->sa_sample = r.val<uint32_t>();
+    ix->n = r.val<uint64_t>();
+    ix->n_lines = r.val<uint64_t>();
+    ix->n_samples = r.val<uint64_t>();
+    // the layout must be one the builder could have made, and the sizes
+    // must follow from it, before anything is allocated
+    const bool layout_ok = (ix->line_bytes == 64 || ix->line_bytes == 128) && ix->bpl % 32 == 0 && ix->bpl >= 32 &&
+                           ix->bpl <= (ix->line_bytes - 16) * 4 && ix->sa_sample >= 1 && ix->sa_sample <= 1024 &&
+                           (ix->sa_sample & (ix->sa_sample - 1)) == 0 && ix->n >= 1 && ix->n + 1 < (1ULL << 32) &&
+                           ix->n_lines == (ix->n + 1) / ix->bpl + 1 && ix->n_samples == ix->n / ix->sa_sample + 1;
+    if (!r.ok || !layout_ok) return fail(BWFM_E_IO, "index_load: corrupt header");
+    const uint64_t words = ix->n_lines * (ix->line_bytes / 4);
+    const uint64_t expect = 8 + 4 * 4 + 3 * 8 + 2 * (6 * 8 + words * 4 + 8 + ix->n_samples * 4) + 8;
+    if (fsize < 0 || (uint64_t)fsize != expect) return fail(BWFM_E_IO, "index_load: file size does not match header");
+    try {
+        for (int d = 0; d < 2; d++) {
+            HostDir &h = ix->dir[d];
+            for (int a = 0; a < 4; a++) h.C[a] = r.val<uint64_t>();
+            h.primary = r.val<uint64_t>();
+            if (r.val<uint64_t>() != words) return fail(BWFM_E_IO, "index_load: corrupt rank-line count");
+            h.lines.resize(words);
+            r.get(h.lines.data(), words * 4);
+            if (r.val<uint64_t>() != ix->n_samples) return fail(BWFM_E_IO, "index_load: corrupt SA sample count");
+            h.sa.resize(ix->n_samples);
+            r.get(h.sa.data(), ix->n_samples * 4);
+            if (h.primary > ix->n) return fail(BWFM_E_IO, "index_load: corrupt $ row");
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(BWFM_E_NOMEM, "out of host memory");
+    }
+    const uint64_t sum = r.sum.h;
+    uint64_t stored = 0;
+    if (!r.ok || std::fread(&stored, 1, 8, f) != 8) return fail(BWFM_E_IO, "index_load: truncated file");
+    if (stored != sum) return fail(BWFM_E_IO, "index_load: checksum mismatch");
+    *out = ix.release();
     return BWFM_OK;
 }

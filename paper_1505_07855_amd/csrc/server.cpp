@@ -107,6 +107,9 @@ struct bwfm_server {
     uint32_t *d_c1 = nullptr, *d_c2 = nullptr;
     uint8_t *d_status = nullptr;
     bwfm_pair *d_pairs = nullptr;
+    // the step as a captured graph over the buffers above (NULL: eager calls)
+    bwfm_pipeline *pipe = nullptr;
+    uint64_t pipe_hits = 0, pipe_pos = 0;
     // host staging
     std::vector<uint64_t> h_off;
     std::vector<uint32_t> h_len;
@@ -130,7 +133,31 @@ struct bwfm_server {
 
 namespace {
 
+// (Re)create the step pipeline with the given capacities, reading the
+// server's own step buffers: the arena, start offsets, lengths, budgets.
+int make_pipeline(bwfm_server *s, uint64_t hits, uint64_t pos) {
+    if (s->pipe) bwfm_pipeline_destroy(s->pipe);
+    s->pipe = nullptr;
+    const bool paired = s->sp.paired != 0;
+    bwfm_pipeline_params q{s->sp.step_pairs, s->sp.max_len, 256, hits, pos, paired ? 1 : 0};
+    int rc = bwfm_pipeline_create(s->ix, &s->ap, &s->pp, &q, &s->pipe);
+    if (rc) return rc;
+    const uint32_t R = (paired ? 2u : 1u) * s->sp.step_pairs;
+    bwfm_reads rd{s->arena_mem, s->d_off, s->sp.budget_rule ? s->d_md : nullptr, R, s->sp.max_len, s->d_len};
+    rc = bwfm_pipeline_bind_reads(s->pipe, &rd);
+    if (rc) {
+        bwfm_pipeline_destroy(s->pipe);
+        s->pipe = nullptr;
+        return rc;
+    }
+    s->pipe_hits = hits;
+    s->pipe_pos = pos;
+    return BWFM_OK;
+}
+
 void release_device(bwfm_server *s) {
+    if (s->pipe) bwfm_pipeline_destroy(s->pipe);
+    s->pipe = nullptr;
     void *ptrs[] = {s->arena_mem, s->d_off, s->d_len, s->d_md,   s->d_hoff,
                     s->d_hits,      s->d_c1,  s->d_c2,  s->d_status, s->d_pairs};
     for (void *p : ptrs)
@@ -138,8 +165,20 @@ void release_device(bwfm_server *s) {
     if (s->stream) (void)hipStreamDestroy(s->stream);
 }
 
+using Chunks = std::vector<std::tuple<std::shared_ptr<Request>, uint32_t, uint32_t>>;
+
+// hand the step's pair records (in chunk order) to their requests
+void scatter_pairs(bwfm_server *s, const Chunks &chunks) {
+    uint32_t o = 0;
+    for (auto &c : chunks) {
+        Request &q = *std::get<0>(c);
+        std::memcpy(q.out.data() + std::get<1>(c), s->h_pairs.data() + o, sizeof(bwfm_pair) * std::get<2>(c));
+        o += std::get<2>(c);
+    }
+}
+
 // One scheduling step over the chunks (request, first pair, pair count).
-int run_step(bwfm_server *s, std::vector<std::tuple<std::shared_ptr<Request>, uint32_t, uint32_t>> &chunks) {
+int run_step(bwfm_server *s, Chunks &chunks) {
     uint32_t P = 0;
     for (auto &c : chunks) P += std::get<2>(c);
     const bool paired = s->sp.paired != 0;
@@ -162,6 +201,29 @@ int run_step(bwfm_server *s, std::vector<std::tuple<std::shared_ptr<Request>, ui
         hipMemcpyAsync(s->d_len, s->h_len.data(), 4ull * n, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         (rule && hipMemcpyAsync(s->d_md, s->h_md.data(), n, hipMemcpyHostToDevice, s->stream) != hipSuccess))
         return fail(BWFM_E_DEVICE, "server: step upload failed");
+    // the captured step over the uploaded buffers; a step that outgrows its
+    // capacities is redone by eager calls, and the pipeline is grown
+    if (s->pipe) {
+        int rc = bwfm_pipeline_set_count(s->pipe, P);
+        if (!rc) rc = bwfm_pipeline_run(s->pipe, 1, s->stream);
+        bwfm_pipeline_status ps{};
+        if (!rc) rc = bwfm_pipeline_finish(s->pipe, s->stream, &ps);
+        if (rc) return rc;
+        if (!ps.error) {
+            bwfm_pair *dp = nullptr;
+            rc = bwfm_pipeline_outputs(s->pipe, 0, nullptr, nullptr, nullptr, &dp);
+            if (rc) return rc;
+            if (hipMemcpyAsync(s->h_pairs.data(), dp, sizeof(bwfm_pair) * P, hipMemcpyDeviceToHost, s->stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(s->stream) != hipSuccess)
+                return fail(BWFM_E_DEVICE, "server: result download failed");
+            scatter_pairs(s, chunks);
+            return BWFM_OK;
+        }
+        rc = make_pipeline(s, std::max(s->pipe_hits, ps.n_hits + ps.n_hits / 4 + 1024),
+                           std::max(s->pipe_pos, ps.n_positions + ps.n_positions / 4 + 4096));
+        if (rc) return rc;
+    }
     bwfm_reads rd{s->arena_mem, s->d_off, rule ? s->d_md : nullptr, n, s->sp.max_len, s->d_len};
     bwfm_aln_result res{s->d_hoff, reinterpret_cast<bwfm_hit *>(s->d_hits), s->hit_cap, s->d_c1, s->d_c2, s->d_status};
     int rc = bwfm_align_batch(s->ix, &rd, &s->ap, &res, s->stream);
@@ -189,12 +251,7 @@ int run_step(bwfm_server *s, std::vector<std::tuple<std::shared_ptr<Request>, ui
             hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return fail(BWFM_E_DEVICE, "server: result download failed");
-    uint32_t o = 0;
-    for (auto &c : chunks) {
-        Request &q = *std::get<0>(c);
-        std::memcpy(q.out.data() + std::get<1>(c), s->h_pairs.data() + o, sizeof(bwfm_pair) * std::get<2>(c));
-        o += std::get<2>(c);
-    }
+    scatter_pairs(s, chunks);
     return BWFM_OK;
 }
 
@@ -321,6 +378,10 @@ extern "C" int bwfm_server_create(const bwfm_index *ix, const bwfm_aln_params *a
     for (uint32_t L = 0; L <= BWFM_MAX_READ; L++)
         s->rule[L] = (uint8_t)std::min(bwfm_max_diff_rule(L, 0.02, 0.04), BWFM_MAX_DIFF);
     s->h_pairs.resize(sp->step_pairs);
+    if (int rc = make_pipeline(s.get(), s->hit_cap, 64 * R + 4096)) {
+        release_device(s.get());
+        return rc;
+    }
     bwfm_server *raw = s.release();
     raw->worker = std::thread(worker_main, raw);
     *out = raw;

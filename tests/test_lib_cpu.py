@@ -90,3 +90,35 @@ def test_align_without_upload_is_a_state_error():
     ix = bw.Index(np.zeros(100, np.uint8))
     assert not ix.info()["uploaded"]
     ix.close()
+
+
+def test_index_save_load_roundtrip_and_corruption(rng, tmp_path):
+    t = rng.integers(0, 4, 7000).astype(np.uint8)
+    t[3000:4000] = t[100:1100]
+    ix = bw.Index(t, line_bytes=64, sa_sample=8)
+    path = str(tmp_path / "x.bwfm")
+    ix.save(path)
+    iy = bw.Index.load(path)
+    a, b = ix.info(), iy.info()
+    for k in ("n", "primary", "C", "lines", "sa_samples", "line_bytes", "bases_per_line", "sa_sample"):
+        assert a[k] == b[k], k
+    assert not b["uploaded"]
+    for which in (0, 1):
+        assert np.array_equal(ix.bwt(which), iy.bwt(which))
+        assert np.array_equal(ix.sa_samples(which), iy.sa_samples(which))
+        for i in rng.integers(0, len(t) + 2, 50):
+            assert ix.occ(int(i), which).tolist() == iy.occ(int(i), which).tolist()
+    iy.close()
+    raw = bytearray(open(path, "rb").read())
+    # a flipped byte in a rank line, a truncated file, another file format
+    for name, data in (("flip", raw[:200] + bytes([raw[200] ^ 1]) + raw[201:]), ("short", raw[:-9]),
+                       ("magic", b"NOTANIDX" + raw[8:])):
+        bad = str(tmp_path / f"{name}.bwfm")
+        open(bad, "wb").write(bytes(data))
+        with pytest.raises(bw.BwfmError) as e:
+            bw.Index.load(bad)
+        assert e.value.code == bw.E_IO, name
+    with pytest.raises(bw.BwfmError) as e:
+        bw.Index.load(str(tmp_path / "missing.bwfm"))
+    assert e.value.code == bw.E_IO
+    ix.close()
