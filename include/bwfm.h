@@ -86,6 +86,17 @@ typedef struct {
  */
 int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index_params *p, bwfm_index **out);
 
+/* The same index built on the current device: the suffix arrays of T$ and
+ * reverse(T)$ by prefix doubling over device radix sorts (first keys of 21
+ * symbols, then (rank, rank h further) pairs until all ranks differ), then
+ * the rank lines and SA samples in device memory.  The result is uploaded
+ * already and holds host copies too, byte for byte equal to
+ * bwfm_build_index's.  Device scratch: about 30 bytes per reference base,
+ * released before return.  ref is a host array.  Synchronises hip_stream.
+ * Errors: as bwfm_build_index, plus E_DEVICE. */
+int bwfm_build_index_device(const uint8_t *ref, uint64_t n, const bwfm_index_params *p, void *hip_stream,
+                            bwfm_index **out);
+
 /* Copy the index to the current device's memory (once; later calls are
  * no-ops).  Synchronises hip_stream.  Errors: E_INVAL, E_NOMEM, E_DEVICE. */
 int bwfm_index_upload(bwfm_index *idx, void *hip_stream);

@@ -106,7 +106,8 @@ SYMBOLS = ("bwfm_build_index", "bwfm_index_upload", "bwfm_index_free", "bwfm_ind
            "bwfm_server_create", "bwfm_server_submit", "bwfm_server_wait", "bwfm_server_get_stats",
            "bwfm_server_destroy", "bwfm_index_save", "bwfm_index_load", "bwfm_pipeline_create",
            "bwfm_pipeline_set_reads", "bwfm_pipeline_run", "bwfm_pipeline_finish", "bwfm_pipeline_outputs",
-           "bwfm_pipeline_destroy", "bwfm_pipeline_bind_reads", "bwfm_pipeline_set_count")
+           "bwfm_pipeline_destroy", "bwfm_pipeline_bind_reads", "bwfm_pipeline_set_count",
+           "bwfm_build_index_device")
 
 
 def lib():
@@ -129,6 +130,7 @@ def lib():
         sig = {
             "bwfm_build_index": ([P, u64, P, ctypes.POINTER(P)], c_int),
             "bwfm_index_upload": ([P, P], c_int),
+            "bwfm_build_index_device": ([P, u64, P, P, ctypes.POINTER(P)], c_int),
             "bwfm_index_save": ([P, ctypes.c_char_p], c_int),
             "bwfm_index_load": ([ctypes.c_char_p, ctypes.POINTER(P)], c_int),
             "bwfm_index_free": ([P], None),
@@ -230,6 +232,21 @@ class Index:
         _check(lib().bwfm_build_index(_np_ptr(ref), len(ref), ctypes.byref(p), ctypes.byref(h)))
         self._h = h
         self.n = len(ref)
+
+    @classmethod
+    def build_device(cls, ref: np.ndarray, line_bytes: int = 128, bases_per_line: int = 0, sa_sample: int = 32,
+                     stream=None) -> "Index":
+        """The same index built on the current GPU (bwfm_build_index_device);
+        it comes back uploaded."""
+        ref = np.ascontiguousarray(ref, np.uint8)
+        h = ctypes.c_void_p()
+        p = _IndexParams(line_bytes, bases_per_line, sa_sample, 0)
+        _check(lib().bwfm_build_index_device(_np_ptr(ref), len(ref), ctypes.byref(p), _stream_ptr(stream),
+                                             ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        self.n = len(ref)
+        return self
 
     @classmethod
     def load(cls, path: str) -> "Index":

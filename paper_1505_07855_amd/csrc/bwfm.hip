@@ -1775,12 +1775,8 @@ extern "C" void bwfm_index_free(bwfm_index *ix) {
     delete ix;
 }
 
-// Argument checks shared by the align entry points; 0 or a bwfm_err.
-static int check_align_args(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, const bwfm_aln_result *res) {
-    if (!ix || !rd || !p || !check_result(res, rd->n_reads)) return fail(BWFM_E_INVAL, "align_batch: NULL argument");
-    if (!check_index(ix)) return fail(BWFM_E_STATE, "align_batch: index not uploaded");
-    if (rd->n_reads && (!rd->bases || !rd->offsets)) return fail(BWFM_E_INVAL, "align_batch: NULL reads");
-    if (rd->max_len > BWFM_MAX_READ) return fail(BWFM_E_TOOLONG, "align_batch: max_len above 512");
+// Search parameters in range; 0 or a bwfm_err.
+static int check_aln_params(const bwfm_aln_params *p) {
     if (p->max_diff < 0 || p->max_diff > BWFM_MAX_DIFF || p->max_gapo < 0 || p->seed_len < 0 || p->seed_diff < 0 ||
         p->indel_end_skip < 0 || p->s_mm < 0 || p->s_gapo < 0 || p->s_gape < 0 ||
         (p->mode != BWFM_MODE_ALL && p->mode != BWFM_MODE_BEST) || p->max_best < 0 || p->max_hits < 1 ||
@@ -1788,6 +1784,15 @@ static int check_align_args(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln
         p->waves_per_simd > 8 || p->max_hits > 65536 || p->s_mm > 63 || p->s_gapo > 63 || p->s_gape > 63)
         return fail(BWFM_E_INVAL, "align_batch: parameter out of range");
     return BWFM_OK;
+}
+
+// Argument checks shared by the align entry points; 0 or a bwfm_err.
+static int check_align_args(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, const bwfm_aln_result *res) {
+    if (!ix || !rd || !p || !check_result(res, rd->n_reads)) return fail(BWFM_E_INVAL, "align_batch: NULL argument");
+    if (!check_index(ix)) return fail(BWFM_E_STATE, "align_batch: index not uploaded");
+    if (rd->n_reads && (!rd->bases || !rd->offsets)) return fail(BWFM_E_INVAL, "align_batch: NULL reads");
+    if (rd->max_len > BWFM_MAX_READ) return fail(BWFM_E_TOOLONG, "align_batch: max_len above 512");
+    return check_aln_params(p);
 }
 
 extern "C" int bwfm_align_batch(const bwfm_index *cix, const bwfm_reads *rd, const bwfm_aln_params *p,
@@ -2174,11 +2179,7 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
         return fail(BWFM_E_INVAL, "pipeline_create: empty or oversized capacity");
     if (q->max_len > BWFM_MAX_READ) return fail(BWFM_E_TOOLONG, "pipeline_create: max_len above 512");
     if (pp->lo > pp->hi) return fail(BWFM_E_INVAL, "pipeline_create: lo > hi");
-    {
-        bwfm_reads probe{nullptr, nullptr, nullptr, 0, q->max_len, nullptr};
-        bwfm_aln_result r0{nullptr, nullptr, 0, nullptr, nullptr, nullptr};
-        if (int rc = check_align_args(ix, &probe, ap, &r0)) return rc;
-    }
+    if (int rc = check_aln_params(ap)) return rc;
     std::unique_ptr<bwfm_pipeline> pl(new (std::nothrow) bwfm_pipeline);
     if (!pl) return fail(BWFM_E_NOMEM, "out of host memory");
     pl->ix = ix;

@@ -45,6 +45,10 @@ struct Workspace {
 std::string &last_error();
 int fail(int code, const std::string &msg);
 
+// Validate a layout (filling in bases_per_line = 0) for a reference of n
+// bases; 0 or a bwfm_err with the message set.
+int check_index_params(bwfm_index_params &q, uint64_t n);
+
 // Host index builder and inspection (index_host.cpp).
 int build_dir(const uint8_t *text, uint64_t n, uint32_t line_bytes, uint32_t bpl, uint32_t sa_sample,
               HostDir &out);

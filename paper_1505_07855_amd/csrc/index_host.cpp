@@ -207,10 +207,9 @@ int fail(int code, const std::string &msg) {
 
 using namespace bwfm;
 
-extern "C" int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index_params *p, bwfm_index **out) {
-    if (!ref || !out) return fail(BWFM_E_INVAL, "build_index: NULL argument");
-    *out = nullptr;
-    bwfm_index_params q = p ? *p : bwfm_index_params{128, 0, 32, 0};
+namespace bwfm {
+
+int check_index_params(bwfm_index_params &q, uint64_t n) {
     if (q.line_bytes != 64 && q.line_bytes != 128) return fail(BWFM_E_INVAL, "line_bytes must be 64 or 128");
     uint32_t maxb = (q.line_bytes - 16) * 4;
     if (q.bases_per_line == 0) q.bases_per_line = maxb;
@@ -220,6 +219,16 @@ extern "C" int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index
         return fail(BWFM_E_INVAL, "sa_sample must be a power of two in [1, 1024]");
     if (n < 1) return fail(BWFM_E_INVAL, "empty reference");
     if (n + 1 >= (1ULL << 32)) return fail(BWFM_E_TOOLONG, "reference too long for 32-bit positions");
+    return BWFM_OK;
+}
+
+}  // namespace bwfm
+
+extern "C" int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index_params *p, bwfm_index **out) {
+    if (!ref || !out) return fail(BWFM_E_INVAL, "build_index: NULL argument");
+    *out = nullptr;
+    bwfm_index_params q = p ? *p : bwfm_index_params{128, 0, 32, 0};
+    if (int rc = check_index_params(q, n)) return rc;
     for (uint64_t i = 0; i < n; i++)
         if (ref[i] > 3) return fail(BWFM_E_BASE, "reference holds a code outside 0..3 at " + std::to_string(i));
     bwfm_index *ix = new (std::nothrow) bwfm_index;

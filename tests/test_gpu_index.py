@@ -1,0 +1,66 @@
+"""The device index builder against the host builder, byte for byte (rank
+lines, SA samples, C, the $ row), on texts that stress a suffix sort: random,
+one symbol repeated, short periods, long exact repeats, and a C2-shaped
+genome; and its index aligns like the host one."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import paper_1505_07855_amd as bw
+from gen import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _texts():
+    rng = np.random.default_rng(5)
+    yield "one", np.array([2], np.uint8)
+    yield "random", rng.integers(0, 4, 100_003).astype(np.uint8)
+    yield "allA", np.zeros(5000, np.uint8)
+    yield "period5", np.resize(np.array([0, 1, 2, 3, 3], np.uint8), 30_001)
+    yield "binary", rng.integers(0, 2, 20_000).astype(np.uint8)
+    t = rng.integers(0, 4, 200_000).astype(np.uint8)
+    t[100_000:150_000] = t[10_000:60_000]  # a 50 kbp exact repeat: many doubling rounds
+    yield "repeat", t
+    yield "c2", configs.c2_genome(3_000_000, seed=61).seq
+
+
+def _host_bytes(ix):
+    info = ix.info()
+    out = [info["primary"], info["C"], info["lines"], info["sa_samples"]]
+    for which in (0, 1):
+        out.append(ix.bwt(which).tobytes())
+        out.append(ix.sa_samples(which).tobytes())
+    return out
+
+
+@pytest.mark.parametrize("layout", [(64, 0, 32), (128, 0, 32), (64, 128, 8)])
+def test_device_index_equals_host_index(layout):
+    lb, bpl, sas = layout
+    rng = np.random.default_rng(9)
+    for name, t in _texts():
+        a = bw.Index(t, line_bytes=lb, bases_per_line=bpl, sa_sample=sas)
+        b = bw.Index.build_device(t, line_bytes=lb, bases_per_line=bpl, sa_sample=sas)
+        assert b.info()["uploaded"]
+        assert _host_bytes(a) == _host_bytes(b), name
+        for which in (0, 1):
+            for i in np.unique(np.concatenate([rng.integers(0, len(t) + 2, 40), [0, len(t), len(t) + 1]])):
+                assert a.occ(int(i), which).tolist() == b.occ(int(i), which).tolist(), (name, which, i)
+        a.close()
+        b.close()
+
+
+def test_device_index_aligns_like_host_index():
+    g = configs.c2_genome(2_000_000, seed=62)
+    pairs = configs.c2_pairs(g, 1000, seed=63)
+    p = bw.Params(**configs.PARAMS["C2"])
+    out = []
+    for ix in (bw.Index(g.seq, **configs.LAYOUT["C2"]).upload(), bw.Index.build_device(g.seq, **configs.LAYOUT["C2"])):
+        e = pairs.end1
+        res = bw.align_batch(ix, torch.from_numpy(e.bases).cuda(), torch.from_numpy(e.offsets.view(np.int64)).cuda(), p,
+                             max_len=100)
+        out.append([x.tobytes() for x in res.to_numpy()])
+    assert out[0] == out[1]
