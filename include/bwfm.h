@@ -174,9 +174,12 @@ typedef struct {
     int32_t max_best;       /* BEST: second tier reported only if c1 <= max_best */
     uint32_t max_hits;      /* reads with more candidate hits report none, 1..65536 */
     int32_t form;           /* BWFM_FORM_BATCHED or BWFM_FORM_PLAIN */
-    int32_t waves_per_simd; /* batched form: resident waves per SIMD, 1..8, or
-                               0 = as many as registers and LDS allow.  A
-                               tuning knob: results do not depend on it. */
+    int32_t waves_per_simd; /* batched form residency, 0..8.  0 or >= 4: the
+                               kernel build held to 128 VGPRs, 4 waves per
+                               SIMD; 3: the compiler's own register budget
+                               (3 waves); 1, 2: that build capped at 1 or 2
+                               waves per SIMD.  A tuning knob: results do not
+                               depend on it. */
 } bwfm_aln_params;
 
 /*

@@ -684,8 +684,8 @@ __device__ __forceinline__ void wave_fence() {
 // When the counter runs past the batch, idle lanes help the busy lanes of
 // their wave through WaveShare instead of waiting for the slowest one.
 template <int LW>
-__global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsView rd, Params P, LaneBufs B, ReadOut O,
-                                                            uint32_t *next_read) {
+__device__ __forceinline__ void persistent_body(const DevIndex &ix, const ReadsView &rd, const Params &P,
+                                                const LaneBufs &B, const ReadOut &O, uint32_t *next_read) {
     const uint32_t gl = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const uint32_t wave0 = threadIdx.x & ~63u;  // the wave's first thread in the block
@@ -1006,6 +1006,31 @@ __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsVi
         atomicAdd(&O.work[1], w_busy);
         atomicAdd(&O.work[2], w_query);
     }
+}
+
+// Two builds of the batched kernel: the compiler's own register budget
+// (about 144 VGPRs: 3 waves per SIMD) and one held to 128 VGPRs so that 4
+// waves stay resident per SIMD.  The search is latency-bound, so the second
+// is faster on the benchmark batch (122 ms against 134); a build held to 96
+// VGPRs spills to scratch and is slower still (205 ms).  The autotuner picks.
+template <int LW>
+__global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsView rd, Params P, LaneBufs B, ReadOut O,
+                                                            uint32_t *next_read) {
+    persistent_body<LW>(ix, rd, P, B, O, next_read);
+}
+template <int LW>
+__global__ __launch_bounds__(BLOCK, 4) void k_align_persistent4(DevIndex ix, ReadsView rd, Params P, LaneBufs B,
+                                                               ReadOut O, uint32_t *next_read) {
+    persistent_body<LW>(ix, rd, P, B, O, next_read);
+}
+
+using PersistentKernel = void (*)(DevIndex, ReadsView, Params, LaneBufs, ReadOut, uint32_t *);
+
+// the build serving a waves_per_simd setting: 0 and >= 4 take the 4-wave
+// build, 1-3 the compiler's own
+template <int LW>
+PersistentKernel persistent_kernel(int waves_per_simd) {
+    return (waves_per_simd == 0 || waves_per_simd >= 4) ? k_align_persistent4<LW> : k_align_persistent<LW>;
 }
 
 // Second pass for the reads listed in slow_list (*O.n_slow of them, set by
@@ -1586,7 +1611,8 @@ uint32_t persistent_lanes(uint32_t bs, size_t lds, int waves_per_simd) {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_align_persistent<LW>, (int)bs, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<LW>(waves_per_simd), (int)bs, lds) !=
+            hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     if (waves_per_simd > 0) {
@@ -1669,7 +1695,8 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
             tm.end(t);
         } else {
             int t = tm.begin("align_persistent");
-            k_align_persistent<LW><<<lanes / bs, bs, lds, st>>>(D, rv, P, lb, O, next_read);
+            hipLaunchKernelGGL(persistent_kernel<LW>(p->waves_per_simd), dim3(lanes / bs), dim3(bs), lds, st, D, rv, P,
+                               lb, O, next_read);
             tm.end(t);
         }
         // the second pass reads its count on the device: no host round trip
@@ -2094,13 +2121,14 @@ struct bwfm_pipeline {
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipStream_t cap = nullptr;  // capture only: nothing runs on it
     bool timed_graph = false, timed_last = false;
+    bool timing_uncapturable = false;  // a capture with event nodes failed once
 };
 
 namespace {
 
 // Enqueue the step.  Every count comes from the control words.
 template <int LW>
-int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed) {
+int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed, bool capture) {
     const DevIndex D = dev_index(pl->ix);
     const Params P = make_params(pl->ap);
     const uint32_t nmax = pl->ends * pl->q.max_pairs;
@@ -2116,12 +2144,17 @@ int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed) {
                                    pl->lstride};
     ReadOut O{pl->n_rep, pl->c1, pl->c2, pl->status, pl->slow_list, actl, pl->stage,
               reinterpret_cast<unsigned long long *>(actl + 2), pl->q.hit_capacity, pl->stage_off, nullptr, nullptr};
-    if (timed) HIPCHK(hipEventRecord(pl->ev[0], st));
+    // under capture the events become event-record nodes of the graph
+    auto mark = [&](hipEvent_t e) {
+        return capture ? hipEventRecordWithFlags(e, st, hipEventRecordExternal) : hipEventRecord(e, st);
+    };
+    if (timed) HIPCHK(mark(pl->ev[0]));
     if (plain)
         k_align_plain<LW><<<pl->lanes / pl->bs, pl->bs, pl->lds, st>>>(D, rv, P, lb, O);
     else
-        k_align_persistent<LW><<<pl->lanes / pl->bs, pl->bs, pl->lds, st>>>(D, rv, P, lb, O, actl + 1);
-    if (timed) HIPCHK(hipEventRecord(pl->ev[1], st));
+        hipLaunchKernelGGL(persistent_kernel<LW>(pl->ap.waves_per_simd), dim3(pl->lanes / pl->bs), dim3(pl->bs),
+                           pl->lds, st, D, rv, P, lb, O, actl + 1);
+    if (timed) HIPCHK(mark(pl->ev[1]));
     LaneBufs sb{pl->sstack, pl->scand, pl->worst_stack, 1, pl->worst_stack, pl->scap, 1, pl->scap, pl->lstride};
     k_align_slow<LW><<<pl->slow_lanes / pl->bs, pl->bs, (size_t)pl->bs * pl->lstride, st>>>(D, rv, P, sb, O, actl + 4);
     HIPCHK(hipGetLastError());
@@ -2151,8 +2184,9 @@ int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed) {
     return BWFM_OK;
 }
 
-int pipe_enqueue_any(bwfm_pipeline *pl, hipStream_t st, bool timed) {
-    return pl->ix->line_bytes == 128 ? pipe_enqueue<32>(pl, st, timed) : pipe_enqueue<16>(pl, st, timed);
+int pipe_enqueue_any(bwfm_pipeline *pl, hipStream_t st, bool timed, bool capture) {
+    return pl->ix->line_bytes == 128 ? pipe_enqueue<32>(pl, st, timed, capture)
+                                     : pipe_enqueue<16>(pl, st, timed, capture);
 }
 
 }  // namespace
@@ -2313,22 +2347,32 @@ extern "C" int bwfm_pipeline_run(bwfm_pipeline *pl, int graph, void *stream) {
     HIPCHK(hipGetLastError());
     if (!graph) {
         pl->timed_last = timed;
-        return pipe_enqueue_any(pl, st, timed);
+        return pipe_enqueue_any(pl, st, timed, false);
     }
+    if (pl->timing_uncapturable) timed = false;
     if (pl->exec && pl->timed_graph != timed) drop_graph(pl);
     if (!pl->exec) {
         // recorded on the pipeline's own stream (the caller's may be the
         // null stream, which cannot be captured); launched on the caller's
-        HIPCHK(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
-        int rc = pipe_enqueue_any(pl, pl->cap, timed);
         hipGraph_t gph = nullptr;
-        hipError_t e = hipStreamEndCapture(pl->cap, &gph);
-        if (rc) {
+        for (;;) {
+            HIPCHK(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+            int rc = pipe_enqueue_any(pl, pl->cap, timed, true);
+            hipError_t e = hipStreamEndCapture(pl->cap, &gph);
+            (void)hipGetLastError();
+            if (!rc && e == hipSuccess) break;
             if (gph) (void)hipGraphDestroy(gph);
-            return rc;
+            gph = nullptr;
+            if (!timed) {
+                if (rc) return rc;
+                return fail(BWFM_E_DEVICE, std::string("pipeline capture: ") + hipGetErrorString(e));
+            }
+            // without event nodes: the step still runs, its kernel time is not taken
+            pl->timing_uncapturable = true;
+            timed = false;
         }
-        if (e != hipSuccess) return fail(BWFM_E_DEVICE, std::string("pipeline capture: ") + hipGetErrorString(e));
         hipGraphExec_t ex = nullptr;
+        hipError_t e;
         e = hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             (void)hipGraphDestroy(gph);

@@ -1,9 +1,10 @@
 """Autotuner for the batched form.
 
 The batched form's speed depends on launch knobs that do not change its
-results: how many waves stay resident per SIMD (fewer resident lanes means
-more reads per lane and a shorter tail of lanes left waiting on one slow
-read, but less latency hiding) and the rank-line size of the index (64- or
+results: the kernel build and how many waves stay resident per SIMD (a
+build held to 128 registers keeps 4 waves per SIMD for latency hiding; the
+compiler's own budget keeps 3 with fewer instructions; fewer resident lanes
+also means more reads per lane) and the rank-line size of the index (64- or
 128-byte lines: bytes per rank query against popcount work per query).
 `tune_batched` times one batched call per candidate on the caller's own
 batch, checks that every candidate returns the same bytes, and returns the
@@ -24,7 +25,7 @@ def _digest(res):
 
 
 def tune_batched(indexes: dict[int, Index] | Index, bases, offsets, params: Params, max_len: int, max_diff=None,
-                 waves=(0, 3, 2, 1), repeats: int = 1, hit_capacity: int | None = None, log=None):
+                 waves=(0, 3), repeats: int = 1, hit_capacity: int | None = None, log=None):
     """Time the batched form for every (rank-line size, waves per SIMD)
     candidate.  `indexes` maps line bytes to an uploaded index of the same
     reference (or is a single index).  Returns (best, table): best is a dict

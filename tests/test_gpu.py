@@ -236,8 +236,8 @@ def test_c3_shape_per_read_budgets_parity(form):
         _compare_align(res, ores)
 
 
-@pytest.mark.parametrize("form", FORMS)
-def test_c5_shape_stress_parity(form):
+@pytest.mark.parametrize("form,wps", [(bw.FORM_BATCHED, 0), (bw.FORM_BATCHED, 3), (bw.FORM_PLAIN, 0)])
+def test_c5_shape_stress_parity(form, wps):
     """250 bp reads, 6 differences with gaps, a tenth from repeat copies: a few
     reads expand hundreds of thousands of states.  In the batched form their
     trees are split across the lanes of a wave once the batch runs dry."""
@@ -246,6 +246,7 @@ def test_c5_shape_stress_parity(form):
     ox = oracle.Index(g.seq)
     ix = bw.Index(g.seq, **{k: v for k, v in configs.LAYOUT["C5"].items()}).upload()
     p, op = _params_pair(form=form, **configs.PARAMS["C5"])
+    p.waves_per_simd = wps  # every build of the batched kernel
     op.bases_per_line = ix.info()["bases_per_line"]
     res = _gpu_align(ix, reads, p, counted=True)
     ores = oracle.align(ox, reads.bases, reads.offsets, op, threads=8)

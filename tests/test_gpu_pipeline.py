@@ -84,6 +84,13 @@ def test_pipeline_eager_and_graph_replays_equal_oracle(setup, form):
         x = torch.arange(1 << 20, device="cuda", dtype=torch.int64)
         assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
         torch.cuda.synchronize()
+    # a replay with the search kernel timed by events captured into the graph
+    bw.timing_enable(True)
+    try:
+        pl.run(graph=True)
+        _check_run(pl, N, exp)
+    finally:
+        bw.timing_enable(False)
     # a smaller batch replays the same graph
     n2 = 777
     b2, o2 = _both(pairs, n2)
