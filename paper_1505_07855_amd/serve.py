@@ -79,12 +79,16 @@ def main():
     ap.add_argument("--max-pairs", type=int, default=200_000)
     ap.add_argument("--step-pairs", type=int, default=131072)
     ap.add_argument("--arena-mib", type=int, default=2048)
+    ap.add_argument("--device-index", action="store_true", help="build the index on the GPU (for 3.1 Gbp)")
     args = ap.parse_args()
 
     import paper_1505_07855_amd as bw
     from gen import configs
+    t0 = time.perf_counter()
     g = configs.c2_genome(args.genome)
-    ix = bw.Index(g.seq).upload()
+    ix = (bw.Index.build_device(g.seq, **configs.LAYOUT["C3"]) if args.device_index
+          else bw.Index(g.seq, **configs.LAYOUT["C3"]).upload())
+    print(f"[serve] {args.genome} bp genome and index in {time.perf_counter() - t0:.0f}s", file=sys.stderr, flush=True)
     w = configs.PAIR_WINDOW
     params = bw.Params(**configs.PARAMS["C3"])
     srv = bw.Server(ix, params, w["lo"], w["hi"], w["mu"], configs.MAX_OCC, arena_bytes=args.arena_mib << 20,
@@ -95,7 +99,7 @@ def main():
     lat, wall = replay(srv, burst, 0.0, 1)
     cap_pairs = sum(r[4] for r in burst) / wall
     mean_size = (args.max_pairs - args.min_pairs) / np.log(args.max_pairs / args.min_pairs)
-    out = {"capacity_pairs_per_s": cap_pairs, "mean_request_pairs": mean_size, "rates": []}
+    out = {"genome": args.genome, "capacity_pairs_per_s": cap_pairs, "mean_request_pairs": mean_size, "rates": []}
     print(f"[serve] capacity {cap_pairs:.0f} pairs/s", file=sys.stderr, flush=True)
     for k, rho in enumerate(args.rates):
         reqs = make_requests(g, args.requests, 5000 + k, args.min_pairs, args.max_pairs)
