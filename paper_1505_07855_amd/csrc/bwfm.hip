@@ -683,16 +683,33 @@ __device__ __forceinline__ void wave_fence() {
 // done takes the next one at once (wave-wide ballot, one atomic per wave).
 // When the counter runs past the batch, idle lanes help the busy lanes of
 // their wave through WaveShare instead of waiting for the slowest one.
+// Arguments of the batched kernel that are used only at read boundaries:
+// kept in device memory and loaded where used, so that they do not occupy
+// scalar registers across the loop (the spills of a full argument list
+// cost more vector instructions than the loop's own work).
+struct PersistentArgs {
+    ReadsView rd;
+    LaneBufs B;
+    ReadOut O;
+    uint32_t *next_read;
+};
+
+__global__ void k_set_args(PersistentArgs *dst, PersistentArgs a) {
+    if (threadIdx.x == 0) *dst = a;
+}
+
 template <int LW>
-__device__ __forceinline__ void persistent_body(const DevIndex &ix, const ReadsView &rd, const Params &P,
-                                                const LaneBufs &B, const ReadOut &O, uint32_t *next_read) {
+__device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params &P, const PersistentArgs *A) {
     const uint32_t gl = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const uint32_t wave0 = threadIdx.x & ~63u;  // the wave's first thread in the block
-    const uint32_t n_reads = reads_n(rd);
-    WaveShare &ws = reinterpret_cast<WaveShare *>(lds_bytes + (size_t)blockDim.x * B.lds_stride)[threadIdx.x >> 6];
+    const uint32_t n_reads = reads_n(A->rd);
+    const uint32_t lds_stride = A->B.lds_stride;
+    WaveShare &ws = reinterpret_cast<WaveShare *>(lds_bytes + (size_t)blockDim.x * lds_stride)[threadIdx.x >> 6];
     LaneCtx c;
-    init_ctx(c, B, gl);
+    init_ctx(c, A->B, gl);
+    c.sstride = 1;  // persistent lanes own contiguous runs
+    c.cstride = 1;
     uint4 *const own_cand = c.cand;
     uint8_t *const own_pd = c.pd;
 
@@ -714,6 +731,12 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const ReadsV
     unsigned long long w_iters = 0, w_busy = 0, w_query = 0;
 
     for (;;) {
+        // an opaque step on the pointer keeps the argument loads inside the
+        // loop, next to their uses
+        asm volatile("" : "+s"(A));
+        const ReadsView &rd = A->rd;
+        const ReadOut &O = A->O;
+        uint32_t *const next_read = A->next_read;
         // refill idle lanes, one atomic per wave
         const bool want = phase == PZ_IDLE && !exhausted;
         const unsigned long long wm = __ballot(want);
@@ -806,8 +829,8 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const ReadsV
                         S = seed_of(P, m);
                         valid = true;
                         c.sp = c.sbase = 0;
-                        c.pd = lds_bytes + (size_t)(wave0 + ow) * B.lds_stride;
-                        c.cand = B.cand + (size_t)(blockIdx.x * blockDim.x + wave0 + ow) * B.cand_lane_step;
+                        c.pd = lds_bytes + (size_t)(wave0 + ow) * lds_stride;
+                        c.cand = own_cand + ((int)ow - lane) * (ptrdiff_t)FAST_CAND;
                         c.best = sh_ld(&ws.best[ow]);
                         c.expand = 0;
                         phase = PZ_HELP;
@@ -1001,10 +1024,10 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const ReadsV
             }
         }
     }
-    if (O.work) {
-        if (lane == 0) atomicAdd(&O.work[0], w_iters);
-        atomicAdd(&O.work[1], w_busy);
-        atomicAdd(&O.work[2], w_query);
+    if (A->O.work) {
+        if (lane == 0) atomicAdd(&A->O.work[0], w_iters);
+        atomicAdd(&A->O.work[1], w_busy);
+        atomicAdd(&A->O.work[2], w_query);
     }
 }
 
@@ -1014,17 +1037,15 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const ReadsV
 // is faster on the benchmark batch (122 ms against 134); a build held to 96
 // VGPRs spills to scratch and is slower still (205 ms).  The autotuner picks.
 template <int LW>
-__global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, ReadsView rd, Params P, LaneBufs B, ReadOut O,
-                                                            uint32_t *next_read) {
-    persistent_body<LW>(ix, rd, P, B, O, next_read);
+__global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, Params P, const PersistentArgs *A) {
+    persistent_body<LW>(ix, P, A);
 }
 template <int LW>
-__global__ __launch_bounds__(BLOCK, 4) void k_align_persistent4(DevIndex ix, ReadsView rd, Params P, LaneBufs B,
-                                                               ReadOut O, uint32_t *next_read) {
-    persistent_body<LW>(ix, rd, P, B, O, next_read);
+__global__ __launch_bounds__(BLOCK, 4) void k_align_persistent4(DevIndex ix, Params P, const PersistentArgs *A) {
+    persistent_body<LW>(ix, P, A);
 }
 
-using PersistentKernel = void (*)(DevIndex, ReadsView, Params, LaneBufs, ReadOut, uint32_t *);
+using PersistentKernel = void (*)(DevIndex, Params, const PersistentArgs *);
 
 // the build serving a waves_per_simd setting: 0 and >= 4 take the 4-wave
 // build, 1-3 the compiler's own
@@ -1662,6 +1683,7 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     size_t need = (size_t)lanes * stack_cap * 16 + (size_t)lanes * FAST_CAND * 16;
     need += (size_t)slow_lanes * worst_stack * 16 + (size_t)slow_lanes * scap * 16;
     need += (size_t)n * 4 * 2 + (size_t)n * 8 + stage_cap * 16 + scan_part_elems(n) * 8 + 16 * 256;
+    need += sizeof(PersistentArgs) + 256;
     void *w;
     int rc = ws_reserve(ix, need, &w);
     if (rc) return rc;
@@ -1675,6 +1697,7 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     uint64_t *stage_off = cv.take<uint64_t>(n);
     uint4 *stage = cv.take<uint4>(stage_cap);
     uint64_t *part = cv.take<uint64_t>(scan_part_elems(n));
+    PersistentArgs *pargs = cv.take<PersistentArgs>(1);
     uint32_t *ctl = cv.take<uint32_t>(16);  // n_slow, next_read, stage_used (64-bit), slow_next
     uint32_t *n_slow = ctl, *next_read = ctl + 1, *slow_next = ctl + 4;
     unsigned long long *stage_used = reinterpret_cast<unsigned long long *>(ctl + 2);
@@ -1694,9 +1717,10 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
             k_align_plain<LW><<<nr_up / bs, bs, lds, st>>>(D, rv, P, lb, O);
             tm.end(t);
         } else {
+            k_set_args<<<1, 64, 0, st>>>(pargs, PersistentArgs{rv, lb, O, next_read});
             int t = tm.begin("align_persistent");
-            hipLaunchKernelGGL(persistent_kernel<LW>(p->waves_per_simd), dim3(lanes / bs), dim3(bs), lds, st, D, rv, P,
-                               lb, O, next_read);
+            hipLaunchKernelGGL(persistent_kernel<LW>(p->waves_per_simd), dim3(lanes / bs), dim3(bs), lds, st, D, P,
+                               (const PersistentArgs *)pargs);
             tm.end(t);
         }
         // the second pass reads its count on the device: no host round trip
@@ -2109,6 +2133,7 @@ struct bwfm_pipeline {
     uint8_t *status = nullptr;
     bwfm_pair *pairs = nullptr;
     uint64_t *ctl = nullptr;
+    PersistentArgs *pargs = nullptr;
     // launch shape
     uint32_t lanes = 0, slow_lanes = 0, bs = 0, lstride = 0, stack_cap = 0, worst_stack = 0, scap = 0;
     size_t lds = 0;
@@ -2148,12 +2173,13 @@ int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed, bool capture) {
     auto mark = [&](hipEvent_t e) {
         return capture ? hipEventRecordWithFlags(e, st, hipEventRecordExternal) : hipEventRecord(e, st);
     };
+    if (!plain) k_set_args<<<1, 64, 0, st>>>(pl->pargs, PersistentArgs{rv, lb, O, actl + 1});
     if (timed) HIPCHK(mark(pl->ev[0]));
     if (plain)
         k_align_plain<LW><<<pl->lanes / pl->bs, pl->bs, pl->lds, st>>>(D, rv, P, lb, O);
     else
         hipLaunchKernelGGL(persistent_kernel<LW>(pl->ap.waves_per_simd), dim3(pl->lanes / pl->bs), dim3(pl->bs),
-                           pl->lds, st, D, rv, P, lb, O, actl + 1);
+                           pl->lds, st, D, P, (const PersistentArgs *)pl->pargs);
     if (timed) HIPCHK(mark(pl->ev[1]));
     LaneBufs sb{pl->sstack, pl->scand, pl->worst_stack, 1, pl->worst_stack, pl->scap, 1, pl->scap, pl->lstride};
     k_align_slow<LW><<<pl->slow_lanes / pl->bs, pl->bs, (size_t)pl->bs * pl->lstride, st>>>(D, rv, P, sb, O, actl + 4);
@@ -2248,6 +2274,7 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
     add((size_t)(nmax + 1) * 8); add(hcap * 16); add((size_t)nmax * 4); add((size_t)nmax * 4); add(nmax);
     add(hcap * 4); add(hcap * 4); add((hcap + 1) * 8); add(pcap * 4); add((size_t)q->max_pairs * sizeof(bwfm_pair));
     add(PC_WORDS * 8);
+    add(sizeof(PersistentArgs));
     need += 4096;
     if (hipMalloc(&pl->mem, need) != hipSuccess) return fail(BWFM_E_NOMEM, "pipeline: device allocation failed");
     Carver cv{(char *)pl->mem};
@@ -2274,6 +2301,7 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
     pl->pos = cv.take<uint32_t>(pcap);
     pl->pairs = cv.take<bwfm_pair>(q->max_pairs);
     pl->ctl = cv.take<uint64_t>(PC_WORDS);
+    pl->pargs = cv.take<PersistentArgs>(1);
     if (hipEventCreate(&pl->ev[0]) != hipSuccess || hipEventCreate(&pl->ev[1]) != hipSuccess ||
         hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess) {
         bwfm_pipeline_destroy(pl.release());
