@@ -289,6 +289,30 @@ __device__ __forceinline__ int pat(const uint8_t *W, int m, int strand, int i) {
     return (strand == 0 || b > 3) ? b : 3 - b;
 }
 
+// Copy read W (m bases) into an LDS row reversed, row[i] = W[m - 1 - i]:
+// the strand + pattern, whose D-array scan then rewrites each byte in place
+// as base | D << 3 (strand -: the complement of the same low bits).  Whole
+// aligned dwords are loaded 8 at a time, so a read costs a few memory round
+// trips instead of one per D-array step; only dwords holding read bases are
+// touched.
+__device__ __forceinline__ void stage_read(uint8_t *row, const uint8_t *W, int m) {
+    const uint32_t *A = reinterpret_cast<const uint32_t *>(reinterpret_cast<uintptr_t>(W) & ~uintptr_t(3));
+    const int off = (int)(reinterpret_cast<uintptr_t>(W) & 3);
+    const int ndw = (off + m + 3) >> 2;
+    for (int k0 = 0; k0 < ndw; k0 += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) v[j] = k0 + j < ndw ? A[k0 + j] : 0u;
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int i = 4 * (k0 + j) + q - off;
+                if (i >= 0 && i < m) row[m - 1 - i] = (uint8_t)(v[j] >> (8 * q));
+            }
+    }
+}
+
 // seed window of the strand pattern: the read's 5' end, consumed first
 struct Seed {
     int sl, lo, hi;
@@ -719,7 +743,6 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
     int ow = lane;         // owner lane of the read this lane works on
     uint32_t r = 0;
     int m = 0, maxd = 0, strand = 0;
-    const uint8_t *W = nullptr;
     // D scan state
     int di = 0, dz = 0;
     uint32_t dk = 0, dl = 0;
@@ -753,7 +776,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                     r = rr;
                     uint64_t o0;
                     if (!check_read(rd, P, O, r, m, maxd, o0)) {
-                        W = rd.bases + o0;
+                        stage_read(own_pd, rd.bases + o0, m);
                         ow = lane;
                         c.pd = own_pd;
                         c.cand = own_cand;
@@ -851,7 +874,10 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
         bool part_done = false;  // this lane's part of the strand's search is over
         if (phase == PZ_DSCAN) {
             act = ACT_DSTEP;
-            da = pat(W, m, strand, di);
+            {
+                const int b = own_pd[di] & 7;  // the staged base (strand +)
+                da = (strand == 0 || b > 3) ? b : 3 - b;
+            }
             if (da < 4) {
                 query = true;
                 qdir = strand == 0 ? 0 : 1;
