@@ -52,7 +52,8 @@ constexpr int INF_SCORE = 0x7fffffff;
 constexpr uint32_t PLAIN_STACK = 320;  // stack entries per lane, plain form first pass
 constexpr uint32_t FAST_CAND = 64;     // hit slots per lane, first pass
 constexpr int BLOCK = 256;
-constexpr int POPS_PER_STEP = 4;  // stack pops per lane per persistent iteration
+constexpr int POPS_PER_STEP = 1;  // stack pops per lane per persistent iteration (more costs the
+                                  // whole wave a pass of the pop code; measured best at 1)
 
 struct Params {
     int max_diff, max_gapo, max_gape, seed_len, seed_diff, ies, s_mm, s_gapo, s_gape, mode, max_best;
@@ -392,25 +393,26 @@ __device__ int expand_children(uint4 &cur, bool &valid, const uint32_t (&ok)[4],
     const int diffs = s_nmm(cur) + ngo + nge;
     const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
     const uint32_t z0 = cur.z & ~(3u << 10);  // gap state cleared
+    // room for the at most 8 states pushed below: checked once per
+    // expansion.  Entries below sbase were handed to other lanes; sliding
+    // the pending ones down makes room when the top of the stack is reached.
+    if (c.sp + 8 > c.stack_cap && c.sbase > 0) {
+        for (uint32_t j = c.sbase; j < c.sp; j++)
+            c.stack[(size_t)(j - c.sbase) * c.sstride] = c.stack[(size_t)j * c.sstride];
+        c.sp -= c.sbase;
+        c.sbase = 0;
+    }
+    if (c.sp + 8 > c.stack_cap) {
+        valid = false;
+        return R_STACK;
+    }
     uint4 pend = cur;
     bool have = false;
-    int rc = R_OK;
+    const int rc = R_OK;
     auto offer = [&](uint32_t k, uint32_t l, uint32_t z, uint32_t w) {
         if (have) {
-            if (c.sp == c.stack_cap && c.sbase > 0) {
-                // entries below sbase were handed to other lanes: slide the
-                // pending ones down to the bottom
-                for (uint32_t j = c.sbase; j < c.sp; j++)
-                    c.stack[(size_t)(j - c.sbase) * c.sstride] = c.stack[(size_t)j * c.sstride];
-                c.sp -= c.sbase;
-                c.sbase = 0;
-            }
-            if (c.sp == c.stack_cap) {
-                rc = R_STACK;
-            } else {
-                c.stack[(size_t)c.sp * c.sstride] = pend;
-                c.sp++;
-            }
+            c.stack[(size_t)c.sp * c.sstride] = pend;
+            c.sp++;
         }
         pend = make_uint4(k, l, z, w);
         have = true;
