@@ -63,10 +63,10 @@ enum bwfm_err {
 typedef struct bwfm_index bwfm_index;
 
 typedef struct {
-    uint32_t line_bytes;     /* rank line size: 64 or 128 bytes */
+    uint32_t line_bytes;     /* rank line size: 32, 64 or 128 bytes */
     uint32_t bases_per_line; /* BWT rows per rank line: a multiple of 32 in
                                 [32, (line_bytes - 16) * 4]; 0 = the maximum
-                                (192 for 64-byte lines, 448 for 128) */
+                                (64 for 32-byte lines, 192 for 64, 448 for 128) */
     uint32_t sa_sample;      /* rows r with r % sa_sample == 0 keep SA[r];
                                 a power of two in [1, 1024] */
     uint32_t n_threads;      /* host threads for the build; 0 = all cores */
@@ -490,7 +490,7 @@ int bwfm_timing_get(const char *kernel, double *total_ms, uint64_t *launches);
  * Random-line probe: the achievable rate of dependent random line fetches,
  * the access pattern of the search (each rank query is one line at an index
  * the previous query decided).  lanes (a multiple of 256) each perform iters
- * dependent fetches of whole line_bytes (64 or 128) lines at pseudo-random
+ * dependent fetches of whole line_bytes (32, 64 or 128) lines at pseudo-random
  * line indices within buf (device, bytes long; contents arbitrary).  sink:
  * device, lanes uint32 (defeats dead-code removal).  *ms_out receives the
  * kernel time from HIP events on hip_stream.  Synchronous.  Lines/s =

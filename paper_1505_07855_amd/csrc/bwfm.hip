@@ -1926,6 +1926,7 @@ extern "C" int bwfm_align_batch(const bwfm_index *cix, const bwfm_reads *rd, con
     std::lock_guard<std::mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
     if (ix->line_bytes == 128) return align_impl<32>(ix, rd, p, res, st, nullptr);
+    if (ix->line_bytes == 32) return align_impl<8>(ix, rd, p, res, st, nullptr);
     return align_impl<16>(ix, rd, p, res, st, nullptr);
 }
 
@@ -1939,6 +1940,7 @@ extern "C" int bwfm_align_batch_counted(const bwfm_index *cix, const bwfm_reads 
     std::lock_guard<std::mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
     if (ix->line_bytes == 128) return align_impl<32>(ix, rd, p, res, st, expand, work);
+    if (ix->line_bytes == 32) return align_impl<8>(ix, rd, p, res, st, expand, work);
     return align_impl<16>(ix, rd, p, res, st, expand, work);
 }
 
@@ -1968,6 +1970,8 @@ extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_a
     const uint4 *hits = (const uint4 *)res->hits + h0;
     if (ix->line_bytes == 128)
         rc = locate_impl<32>(ix, n_hits, hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st, &total);
+    else if (ix->line_bytes == 32)
+        rc = locate_impl<8>(ix, n_hits, hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st, &total);
     else
         rc = locate_impl<16>(ix, n_hits, hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st, &total);
     if (rc) return rc;
@@ -2019,6 +2023,8 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
         uint64_t total = 0;
         rc = ix->line_bytes == 128
                  ? locate_impl<32>(ix, nh[e], hits, pp->max_occ, poff[e], nullptr, 0, cnt, part, big, n_big, st, &total)
+             : ix->line_bytes == 32
+                 ? locate_impl<8>(ix, nh[e], hits, pp->max_occ, poff[e], nullptr, 0, cnt, part, big, n_big, st, &total)
                  : locate_impl<16>(ix, nh[e], hits, pp->max_occ, poff[e], nullptr, 0, cnt, part, big, n_big, st, &total);
         if (rc == BWFM_E_CAPACITY || (rc == BWFM_OK && total == 0)) {
             rc = BWFM_OK;
@@ -2031,6 +2037,9 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
                 rc = ix->line_bytes == 128
                          ? locate_impl<32>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total, cnt, part, big, n_big,
                                            st, &total)
+                     : ix->line_bytes == 32
+                         ? locate_impl<8>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total, cnt, part, big, n_big,
+                                          st, &total)
                          : locate_impl<16>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total, cnt, part, big, n_big,
                                            st, &total);
         }
@@ -2124,7 +2133,8 @@ extern "C" int bwfm_timing_get(const char *kernel, double *total_ms, uint64_t *l
 
 extern "C" int bwfm_probe_gather(const void *buf, uint64_t bytes, uint32_t line_bytes, uint32_t lanes, uint32_t iters,
                                  uint32_t *sink, double *ms_out, void *stream) {
-    if (!buf || !sink || !ms_out || (line_bytes != 64 && line_bytes != 128) || lanes == 0 || lanes % 256 ||
+    if (!buf || !sink || !ms_out || (line_bytes != 32 && line_bytes != 64 && line_bytes != 128) || lanes == 0 ||
+        lanes % 256 ||
         bytes < line_bytes)
         return fail(BWFM_E_INVAL, "probe_gather: bad argument");
     hipStream_t st = (hipStream_t)stream;
@@ -2135,6 +2145,8 @@ extern "C" int bwfm_probe_gather(const void *buf, uint64_t bytes, uint32_t line_
     HIPCHK(hipEventRecord(a, st));
     if (line_bytes == 128)
         k_probe_gather<32><<<lanes / 256, 256, 0, st>>>((const uint4 *)buf, n_lines, iters, sink);
+    else if (line_bytes == 32)
+        k_probe_gather<8><<<lanes / 256, 256, 0, st>>>((const uint4 *)buf, n_lines, iters, sink);
     else
         k_probe_gather<16><<<lanes / 256, 256, 0, st>>>((const uint4 *)buf, n_lines, iters, sink);
     hipError_t e = hipGetLastError();
@@ -2284,8 +2296,9 @@ int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed, bool capture) {
 }
 
 int pipe_enqueue_any(bwfm_pipeline *pl, hipStream_t st, bool timed, bool capture) {
-    return pl->ix->line_bytes == 128 ? pipe_enqueue<32>(pl, st, timed, capture)
-                                     : pipe_enqueue<16>(pl, st, timed, capture);
+    if (pl->ix->line_bytes == 128) return pipe_enqueue<32>(pl, st, timed, capture);
+    if (pl->ix->line_bytes == 32) return pipe_enqueue<8>(pl, st, timed, capture);
+    return pipe_enqueue<16>(pl, st, timed, capture);
 }
 
 }  // namespace
@@ -2329,8 +2342,9 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
     pl->lds = (size_t)pl->bs * pl->lstride + (plain ? 0 : (pl->bs / 64) * sizeof(WaveShare));
     const uint32_t nr_up = ((nmax + pl->bs - 1) / pl->bs) * pl->bs;
     pl->lanes = plain ? nr_up
-                      : std::min<uint32_t>(ix->line_bytes == 128 ? persistent_lanes<32>(pl->bs, pl->lds, ap->waves_per_simd)
-                                                                 : persistent_lanes<16>(pl->bs, pl->lds, ap->waves_per_simd),
+                      : std::min<uint32_t>(ix->line_bytes == 128  ? persistent_lanes<32>(pl->bs, pl->lds, ap->waves_per_simd)
+                                           : ix->line_bytes == 32 ? persistent_lanes<8>(pl->bs, pl->lds, ap->waves_per_simd)
+                                                                  : persistent_lanes<16>(pl->bs, pl->lds, ap->waves_per_simd),
                                            nr_up);
     pl->stack_cap = plain ? std::min<uint32_t>(pl->worst_stack, PLAIN_STACK) : pl->worst_stack;
     pl->slow_lanes = std::min<uint32_t>(nr_up, SLOW_LANES);

@@ -210,7 +210,8 @@ using namespace bwfm;
 namespace bwfm {
 
 int check_index_params(bwfm_index_params &q, uint64_t n) {
-    if (q.line_bytes != 64 && q.line_bytes != 128) return fail(BWFM_E_INVAL, "line_bytes must be 64 or 128");
+    if (q.line_bytes != 32 && q.line_bytes != 64 && q.line_bytes != 128)
+        return fail(BWFM_E_INVAL, "line_bytes must be 32, 64 or 128");
     uint32_t maxb = (q.line_bytes - 16) * 4;
     if (q.bases_per_line == 0) q.bases_per_line = maxb;
     if (q.bases_per_line % 32 || q.bases_per_line < 32 || q.bases_per_line > maxb)
@@ -403,7 +404,8 @@ extern "C" int bwfm_index_load(const char *path, bwfm_index **out) {
     ix->n_samples = r.val<uint64_t>();
     // the layout must be one the builder could have made, and the sizes
     // must follow from it, before anything is allocated
-    const bool layout_ok = (ix->line_bytes == 64 || ix->line_bytes == 128) && ix->bpl % 32 == 0 && ix->bpl >= 32 &&
+    const bool layout_ok = (ix->line_bytes == 32 || ix->line_bytes == 64 || ix->line_bytes == 128) && ix->bpl % 32 == 0 &&
+                           ix->bpl >= 32 &&
                            ix->bpl <= (ix->line_bytes - 16) * 4 && ix->sa_sample >= 1 && ix->sa_sample <= 1024 &&
                            (ix->sa_sample & (ix->sa_sample - 1)) == 0 && ix->n >= 1 && ix->n + 1 < (1ULL << 32) &&
                            ix->n_lines == (ix->n + 1) / ix->bpl + 1 && ix->n_samples == ix->n / ix->sa_sample + 1;

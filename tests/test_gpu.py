@@ -94,7 +94,7 @@ def c2_small():
 
 
 @pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("layout", [(128, 448, 32), (64, 192, 16)])
+@pytest.mark.parametrize("layout", [(128, 448, 32), (64, 192, 16), (32, 64, 32)])
 def test_c2_shape_parity_align_locate_pair(c2_small, layout, form):
     g, pairs, ox = c2_small
     ix = bw.Index(g.seq, line_bytes=layout[0], bases_per_line=layout[1], sa_sample=layout[2]).upload()

@@ -37,7 +37,7 @@ def _host_bytes(ix):
     return out
 
 
-@pytest.mark.parametrize("layout", [(64, 0, 32), (128, 0, 32), (64, 128, 8)])
+@pytest.mark.parametrize("layout", [(64, 0, 32), (128, 0, 32), (64, 128, 8), (32, 0, 32)])
 def test_device_index_equals_host_index(layout):
     lb, bpl, sas = layout
     rng = np.random.default_rng(9)

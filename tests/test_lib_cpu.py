@@ -39,7 +39,7 @@ def _texts(rng):
 
 
 @pytest.mark.parametrize("layout", [(128, 0, 32), (64, 0, 32), (64, 128, 32), (128, 64, 1), (64, 32, 8),
-                                    (128, 448, 1024)])
+                                    (128, 448, 1024), (32, 0, 32), (32, 32, 4)])
 def test_host_index_equals_oracle_index(layout, rng):
     lb, bpl, sas = layout
     for name, t in _texts(rng):
