@@ -131,10 +131,7 @@ __device__ __forceinline__ uint32_t line_of(const DevIndex &ix, uint32_t i) {
 
 // mask of the first t rows of a 32-row group (t may be <= 0 or >= 32)
 __device__ __forceinline__ uint32_t rows_mask(int t) {
-    // clamp to [0, 32], then the low word of 2^t - 1 (a 64-bit shift, so
-    // that t = 32 gives all ones): three instructions, no selects
-    const uint32_t x = (uint32_t)min(max(t, 0), 32);
-    return (uint32_t)(1ull << x) - 1u;
+    return t >= 32 ? 0xffffffffu : (t <= 0 ? 0u : ((1u << t) - 1u));
 }
 
 // Occ(a, i) for all four bases (i <= n + 1).  Per 32-row group: one word of
