@@ -246,6 +246,19 @@ def main():
         kf, timed_in = kernel_ms.get("align_persistent"), "batched (graph replays)"
         if not kf:
             kf, timed_in = eager["kernel_ms"].get("align_persistent"), "batched-eager (same kernel and batch)"
+        # the achievable rate of dependent random line fetches on a buffer
+        # the size of the index's rank lines (the same access pattern with
+        # no search around it), measured here, for a second fraction
+        probe = None
+        try:
+            lb = ix.info()["line_bytes"]
+            buf = torch.zeros(2 * ix.info()["lines"] * lb, dtype=torch.uint8, device="cuda")
+            bw.probe_gather(buf, lb, iters=16)
+            probe_lps = bw.probe_gather(buf, lb)
+            del buf
+            probe = {"lines_per_s": probe_lps, "line_bytes": lb}
+        except Exception as e:  # the probe is context; the bench line stands without it
+            log(f"gather probe skipped: {e}")
         if kf:
             per_launch = bytes_per_read * n_reads
             achieved = per_launch / (kf["avg_ms"] / 1e3) / 1e9
@@ -253,6 +266,13 @@ def main():
                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles("k_align_persistent"),
                         "kernel": "k_align_persistent", "bytes_per_read": bytes_per_read,
                         "reads_per_launch": n_reads, "avg_launch_ms": kf["avg_ms"], "timed_in": timed_in}
+            if probe:
+                lines_ps = per_launch / ix.info()["line_bytes"] / (kf["avg_ms"] / 1e3)
+                roofline["random_line_ceiling"] = {
+                    "probe_lines_per_s": probe["lines_per_s"], "kernel_lines_per_s": lines_ps,
+                    "frac": lines_ps / probe["lines_per_s"],
+                    "note": "algorithmic rank-line fetches/s against a dependent random-line gather on an "
+                            "index-sized buffer (paper_1505_07855_amd.probes)"}
 
     out = {
         "metric": METRIC, "value": value, "unit": "aligned reads/s", "n_gpus": 1, "steps": args.steps,
