@@ -73,6 +73,9 @@ def _lib(name: str):
             L.orc_locate.argtypes = [P, P, i64, u32, P, ctypes.POINTER(P), P, u32]
             L.orc_locate.restype = i64
             L.orc_pair_reads.argtypes = [i64, P, P, P, P, P, P, P, P, i32, i32, i32, P]
+            L.orc_rescue_mates.argtypes = [i64, P, i64, P, P, P, P, P, i32, i32, i32, i32, i32, i32, i32, P]
+            L.orc_local_best.argtypes = [P, i32, P, i32, i32, i32, i32, i32, i32, P, P]
+            L.orc_local_best.restype = i32
             L.orc_max_diff_rule.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
             L.orc_max_diff_rule.restype = ctypes.c_int
             L.orc_estimate_insert.argtypes = [P, i64, P]
@@ -241,6 +244,37 @@ def pair(r1: AlnResult, po1, pos1, r2: AlnResult | None, po2, pos2, lo: int, hi:
                                   _p(r2.hit_off) if r2 else None, _p(r2.hits) if r2 else None,
                                   _p(po2) if r2 else None, _p(pos2) if r2 else None, lo, hi, mu, _p(out))
     return out
+
+
+RESCUE_DTYPE = np.dtype([("pos", "<u4"), ("len", "<u2"), ("score", "<i2"), ("insert", "<i4"), ("end", "u1"),
+                         ("strand", "u1"), ("pad", "u1", 2)])
+# local-alignment scores of the rescue (a reading: BWA-MEM's documented defaults)
+RESCUE_SCORES = dict(match=1, mismatch=4, gap_open=6, gap_extend=1)
+
+
+def rescue(ref: np.ndarray, end1, end2, pairs: np.ndarray, lo: int, hi: int, min_score: int = 20,
+           match: int = 1, mismatch: int = 4, gap_open: int = 6, gap_extend: int = 1) -> np.ndarray:
+    """Mate rescue for the pairs without a proper pair (see oracle.c):
+    end1/end2 are (bases, offsets) of the two ends, pairs the pair records."""
+    t = np.ascontiguousarray(ref, np.uint8)
+    b1, o1 = np.ascontiguousarray(end1[0], np.uint8), np.ascontiguousarray(end1[1], np.uint64)
+    b2, o2 = np.ascontiguousarray(end2[0], np.uint8), np.ascontiguousarray(end2[1], np.uint64)
+    pr = np.ascontiguousarray(pairs)
+    n = len(pr)
+    out = np.zeros(n, RESCUE_DTYPE)
+    _lib("oracle").orc_rescue_mates(n, _p(t), len(t), _p(b1), _p(o1), _p(b2), _p(o2), _p(pr), lo, hi, match, mismatch,
+                                    gap_open, gap_extend, min_score, _p(out))
+    return out
+
+
+def local_best(q, r, e_min: int = 0, match: int = 1, mismatch: int = 4, gap_open: int = 6, gap_extend: int = 1):
+    """(score, end column, start column) of the rescue's local alignment of q
+    in r, ending at column >= e_min (score 0: none)."""
+    qa, ra = np.ascontiguousarray(q, np.uint8), np.ascontiguousarray(r, np.uint8)
+    je, js = ctypes.c_int(), ctypes.c_int()
+    sc = _lib("oracle").orc_local_best(_p(qa), len(qa), _p(ra), len(ra), e_min, match, mismatch, gap_open, gap_extend,
+                                       ctypes.byref(je), ctypes.byref(js))
+    return sc, je.value, js.value
 
 
 def max_diff_rule(L: int, err: float = 0.02, thres: float = 0.04) -> int:

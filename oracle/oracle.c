@@ -1012,3 +1012,178 @@ int orc_estimate_insert(const int32_t *ins, int64_t N, int32_t *out)
     free(s);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Mate rescue                                                          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * A pair left without a proper pair, with a primary for at least one end,
+ * gets a second chance for the other end (the mate): the best local
+ * alignment of the mate inside the reference window that the fragment
+ * length allows around the primary (the anchor; with primaries for both
+ * ends, the one of lower score, end 1 on ties).  This is the sampe step the
+ * paper's pipeline ends with (section 3.7), here a reading: affine-gap local
+ * alignment (match +a, mismatch -b, a gap of g bases -(o + e g); a read N
+ * mismatches everything), kept only when its score reaches min_score.
+ *
+ *  anchor on +, at pf: the mate is on - (revcomp(mate) aligns), window
+ *    [pf, pf + hi) clipped to the reference; the alignment must end at
+ *    window column >= lo - 1, so that insert = pr + lr - pf lies in [lo, hi].
+ *  anchor on -, at pr with length lr: the mate is on + and must start at
+ *    pf <= pr + lr - lo inside [pr + lr - hi, pr + lr).  Reversing both the
+ *    mate and the window turns this into the first case's constraint on the
+ *    end column, so one routine serves both.
+ *
+ * The routine fills a column of the local-alignment matrices per reference
+ * base, carrying with every cell the window column where its alignment
+ * starts.  Ties: a cell prefers the diagonal move, then the gap along the
+ * reference, then the gap along the read, over 0 (no alignment); a gap
+ * prefers opening over extending.  The reported alignment is the first
+ * cell of highest score in column order (smallest end column, then
+ * smallest read row) among the columns allowed.
+ */
+
+typedef struct {
+    uint32_t pos;    /* leftmost reference base of the rescued alignment */
+    uint16_t len;    /* reference bases it spans */
+    int16_t score;   /* its local alignment score */
+    int32_t insert;  /* pr + lr - pf of the rescued pair */
+    uint8_t end;     /* 0: nothing rescued, else the rescued end (1 or 2) */
+    uint8_t strand;  /* strand of the rescued end */
+    uint8_t pad[2];
+} orc_rescue;
+
+#define RESCUE_NEG (-1000000000)
+
+/* best local alignment of q (m) in r (w) ending at column >= e_min:
+ * returns the score (0: none), sets *jend and *jstart */
+static int local_best(const uint8_t *q, int m, const uint8_t *r, int w, int e_min, int a, int b, int o, int e,
+                      int *jend, int *jstart)
+{
+    int *Hp = malloc(sizeof(int) * (m + 1) * 4);
+    int *Ep = Hp + (m + 1), *HpO = Ep + (m + 1), *EpO = HpO + (m + 1);
+    for (int i = 0; i <= m; i++) {
+        Hp[i] = 0;
+        Ep[i] = RESCUE_NEG;
+        HpO[i] = EpO[i] = 0;
+    }
+    int best = 0;
+    *jend = *jstart = -1;
+    for (int j = 0; j < w; j++) {
+        int F = RESCUE_NEG, FO = 0;
+        int Hdiag = 0, HdiagO = 0; /* H[i-1][j-1] */
+        int Hup = 0, HupO = 0;     /* H[i-1][j] */
+        for (int i = 1; i <= m; i++) {
+            /* gap along the reference (E), from the previous column */
+            int eo = Hp[i] - (o + e), ee = Ep[i] - e, E, EO;
+            if (eo >= ee) {
+                E = eo;
+                EO = HpO[i];
+            } else {
+                E = ee;
+                EO = EpO[i];
+            }
+            /* gap along the read (F), from the row above */
+            int fo = Hup - (o + e), fe = F - e;
+            if (fo >= fe) {
+                F = fo;
+                FO = HupO;
+            } else {
+                F = fe;
+            }
+            int s = (q[i - 1] < 4 && q[i - 1] == r[j]) ? a : -b;
+            int diag = Hdiag + s, diagO = Hdiag > 0 ? HdiagO : j;
+            int H = 0, HO = 0;
+            if (diag > H) {
+                H = diag;
+                HO = diagO;
+            }
+            if (E > H) {
+                H = E;
+                HO = EO;
+            }
+            if (F > H) {
+                H = F;
+                HO = FO;
+            }
+            Hdiag = Hp[i];
+            HdiagO = HpO[i];
+            Hp[i] = H;
+            HpO[i] = HO;
+            Ep[i] = E;
+            EpO[i] = EO;
+            Hup = H;
+            HupO = HO;
+            if (j >= e_min && H > best) {
+                best = H;
+                *jend = j;
+                *jstart = HO;
+            }
+        }
+    }
+    free(Hp);
+    return best;
+}
+
+void orc_rescue_mates(int64_t n_pairs, const uint8_t *ref, int64_t n, const uint8_t *b1, const uint64_t *o1,
+                      const uint8_t *b2, const uint64_t *o2, const orc_pair *pairs, int32_t lo, int32_t hi,
+                      int32_t a, int32_t b, int32_t o, int32_t e, int32_t min_score, orc_rescue *out)
+{
+    uint8_t *q = malloc(MAX_READ), *win = malloc(hi > 0 ? (size_t)hi : 1);
+    for (int64_t p = 0; p < n_pairs; p++) {
+        orc_rescue *res = &out[p];
+        memset(res, 0, sizeof(*res));
+        const orc_pair *pr = &pairs[p];
+        const int m1 = (pr->flags & 2) != 0, m2 = (pr->flags & 4) != 0;
+        if ((pr->flags & 1) || (!m1 && !m2)) continue;
+        const int anchor = (m1 && m2) ? (pr->score1 <= pr->score2 ? 1 : 2) : (m1 ? 1 : 2);
+        const int mate = 3 - anchor;
+        const int64_t pa = anchor == 1 ? pr->pos1 : pr->pos2;
+        const int la = anchor == 1 ? pr->len1 : pr->len2;
+        const int sa = anchor == 1 ? pr->strand1 : pr->strand2;
+        const uint8_t *W = mate == 1 ? b1 + o1[p] : b2 + o2[p];
+        const int m = (int)(mate == 1 ? o1[p + 1] - o1[p] : o2[p + 1] - o2[p]);
+        if (m == 0 || m > MAX_READ) continue;
+        int64_t w0, w1;
+        if (sa == 0) {
+            w0 = pa;
+            w1 = pa + hi < n ? pa + hi : n;
+            for (int i = 0; i < m; i++) { /* revcomp(mate) */
+                uint8_t c = W[m - 1 - i];
+                q[i] = c < 4 ? (uint8_t)(3 - c) : c;
+            }
+        } else {
+            w1 = pa + la;
+            w0 = w1 - hi > 0 ? w1 - hi : 0;
+            for (int i = 0; i < m; i++) q[i] = W[m - 1 - i]; /* reverse(mate) */
+        }
+        const int w = (int)(w1 - w0);
+        if (w <= 0) continue;
+        for (int j = 0; j < w; j++) win[j] = sa == 0 ? ref[w0 + j] : ref[w1 - 1 - j];
+        int jend, jstart;
+        const int sc = local_best(q, m, win, w, lo - 1, a, b, o, e, &jend, &jstart);
+        if (sc <= 0 || sc < min_score) continue;
+        res->end = (uint8_t)mate;
+        res->score = (int16_t)sc;
+        res->len = (uint16_t)(jend - jstart + 1);
+        if (sa == 0) {
+            res->strand = 1;
+            res->pos = (uint32_t)(w0 + jstart);
+            res->insert = jend + 1;
+        } else {
+            res->strand = 0;
+            res->pos = (uint32_t)(w1 - 1 - jend);
+            res->insert = jend + 1;
+        }
+    }
+    free(q);
+    free(win);
+}
+
+/* the local alignment routine alone, for the tests that pin it */
+int orc_local_best(const uint8_t *q, int m, const uint8_t *r, int w, int e_min, int a, int b, int o, int e, int *jend,
+                   int *jstart)
+{
+    return local_best(q, m, r, w, e_min, a, b, o, e, jend, jstart);
+}

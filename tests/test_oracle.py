@@ -431,3 +431,157 @@ def test_threads_do_not_change_results():
     b = oracle.align(ix, reads.bases, reads.offsets, p, threads=7)
     for f in ("hit_off", "hits", "c1", "c2", "status", "counts"):
         assert np.array_equal(getattr(a, f), getattr(b, f))
+
+
+# ------------------------------------------------------------------ mate rescue
+
+def _global_affine(q, r, a, b, o, e):
+    """Best score aligning all of q with all of r: match +a, mismatch -b, a
+    gap of g bases -(o + e g).  Textbook three-state recursion (ends in a
+    match/mismatch, in a gap along r, in a gap along q), written out
+    independently of the oracle's local routine."""
+    NEG = -10 ** 9
+    m, w = len(q), len(r)
+    M = [[NEG] * (w + 1) for _ in range(m + 1)]
+    X = [[NEG] * (w + 1) for _ in range(m + 1)]  # last op consumes r only
+    Y = [[NEG] * (w + 1) for _ in range(m + 1)]  # last op consumes q only
+    M[0][0] = 0
+    for i in range(m + 1):
+        for j in range(w + 1):
+            if i and j:
+                s = a if (q[i - 1] < 4 and q[i - 1] == r[j - 1]) else -b
+                M[i][j] = max(M[i - 1][j - 1], X[i - 1][j - 1], Y[i - 1][j - 1]) + s
+            if j:
+                X[i][j] = max(max(M[i][j - 1], Y[i][j - 1]) - (o + e), X[i][j - 1] - e)
+            if i:
+                Y[i][j] = max(max(M[i - 1][j], X[i - 1][j]) - (o + e), Y[i - 1][j] - e)
+    return max(M[m][w], X[m][w], Y[m][w])
+
+
+def _brute_local(q, r, e_min, a=1, b=4, o=6, e=1):
+    """(best, smallest end column reaching it) over every pair of non-empty
+    substrings q[i0:i1], r[j0:j1] with j1 - 1 >= e_min."""
+    best, bend = 0, -1
+    for j1 in range(1, len(r) + 1):
+        if j1 - 1 < e_min:
+            continue
+        for j0 in range(j1):
+            for i0 in range(len(q)):
+                for i1 in range(i0 + 1, len(q) + 1):
+                    s = _global_affine(q[i0:i1], r[j0:j1], a, b, o, e)
+                    if s > best:
+                        best, bend = s, j1 - 1
+    return best, bend
+
+
+def test_local_alignment_against_substring_enumeration(rng):
+    for t in range(60):
+        m, w = int(rng.integers(1, 6)), int(rng.integers(1, 9))
+        q = rng.integers(0, 5 if t % 5 == 0 else 4, m).astype(np.uint8)  # some reads carry N
+        r = rng.integers(0, 4, w).astype(np.uint8)
+        if t % 3 == 0 and w >= m:  # plant q (with a change) so that gaps and mismatches matter
+            p = int(rng.integers(0, w - m + 1))
+            r[p:p + m] = np.where(q < 4, q, 0)
+            if m > 2:
+                r[p + m // 2] = (r[p + m // 2] + 1) % 4
+        e_min = int(rng.integers(-1, w))
+        for sc in (dict(a=1, b=4, o=6, e=1), dict(a=2, b=1, o=1, e=1)):
+            got, jend, jstart = oracle.local_best(q, r, e_min, sc["a"], sc["b"], sc["o"], sc["e"])
+            want, wend = _brute_local(q, r, e_min, **sc)
+            assert got == want, (q, r, e_min, sc)
+            if want > 0:
+                assert jend == wend and 0 <= jstart <= jend
+                # the reported reference span holds an alignment of that score
+                assert max(_global_affine(q[i0:i1], r[jstart:jend + 1], sc["a"], sc["b"], sc["o"], sc["e"])
+                           for i0 in range(m) for i1 in range(i0 + 1, m + 1)) == want
+
+
+def test_local_alignment_closed_cases():
+    q = np.array([0, 1, 2, 3, 3, 2, 1, 0, 0, 2, 1, 3, 3, 0, 1, 2, 2, 1, 0, 3], np.uint8)
+    r = np.concatenate([np.full(5, 1, np.uint8), q, np.full(6, 2, np.uint8)])
+    assert oracle.local_best(q, r, 0) == (20, 24, 5)  # exact: score m, span 5..24
+    r2 = r.copy()
+    r2[15] = (r2[15] + 1) % 4  # one mismatch mid-read: 20 - 1 - 4 beats either side (10, 9)
+    assert oracle.local_best(q, r2, 0) == (15, 24, 5)
+    assert oracle.local_best(q, r, 25)[0] < 20  # end forced past the exact copy
+    assert oracle.local_best(np.array([4, 4], np.uint8), r, 0) == (0, -1, -1)  # N matches nothing
+
+
+def _pair_rec(pos1, len1, s1, score1, pos2, len2, s2, score2, flags):
+    p = np.zeros(1, oracle.PAIR_DTYPE)
+    p["pos1"], p["len1"], p["strand1"], p["score1"] = pos1, len1, s1, score1
+    p["pos2"], p["len2"], p["strand2"], p["score2"] = pos2, len2, s2, score2
+    p["flags"] = flags
+    return p
+
+
+def test_rescue_finds_planted_mates(rng):
+    g = rng.integers(0, 4, 20000).astype(np.uint8)
+    lo, hi = 180, 420
+    L = 60
+    for anchor_strand in (0, 1):
+        for ins in (200, 300, 419):
+            if anchor_strand == 0:
+                pf = 5000
+                pr = pf + ins - L
+                mate = gen.revcomp(g[pr:pr + L]).copy()  # end 2 on -: its revcomp is g[pr:pr+L]
+                mate[10] = (mate[10] + 1) % 4
+                rec = _pair_rec(pf, L, 0, 0, 0xFFFFFFFF, 0, 0, 0, 2)  # end 1 mapped, end 2 not
+                want = (pr, L, 1, ins)
+            else:
+                pr = 9000
+                pf = pr + L - ins
+                mate = g[pf:pf + L].copy()  # end 2 on +
+                mate[30] = (mate[30] + 1) % 4
+                rec = _pair_rec(pr, L, 1, 0, 0xFFFFFFFF, 0, 0, 0, 2)
+                want = (pf, L, 0, ins)
+            e1 = (np.zeros(L, np.uint8), np.array([0, L], np.uint64))
+            e2 = (mate, np.array([0, L], np.uint64))
+            out = oracle.rescue(g, e1, e2, rec, lo, hi)
+            assert out[0]["end"] == 2, (anchor_strand, ins)
+            assert (int(out[0]["pos"]), int(out[0]["len"]), int(out[0]["strand"]), int(out[0]["insert"])) == want
+            assert out[0]["score"] == L - 1 - 4
+    # a pair already proper, or with no primary, is left alone
+    rec = _pair_rec(5000, L, 0, 0, 5200, L, 1, 0, 1 | 2 | 4)
+    e = (np.zeros(L, np.uint8), np.array([0, L], np.uint64))
+    assert oracle.rescue(g, e, e, rec, lo, hi)[0]["end"] == 0
+    rec = _pair_rec(0xFFFFFFFF, 0, 0, 0, 0xFFFFFFFF, 0, 0, 0, 0)
+    assert oracle.rescue(g, e, e, rec, lo, hi)[0]["end"] == 0
+    # below min_score nothing is rescued: a random mate
+    rec = _pair_rec(5000, L, 0, 0, 0xFFFFFFFF, 0, 0, 0, 2)
+    rnd = (rng.integers(0, 4, L).astype(np.uint8), np.array([0, L], np.uint64))
+    assert oracle.rescue(g, e, rnd, rec, lo, hi)[0]["end"] == 0
+
+
+def test_rescue_anchor_choice_and_insert_bounds(rng):
+    g = rng.integers(0, 4, 20000).astype(np.uint8)
+    lo, hi, L = 180, 420, 60
+    e_rand = (rng.integers(0, 4, L).astype(np.uint8), np.array([0, L], np.uint64))
+    # both ends mapped, not paired: the end of lower penalty anchors; here end 2
+    # (on + at 7000) anchors and end 1 is rescued on - at 7000 + 250 - L
+    pr = 7000 + 250 - L
+    e1 = (gen.revcomp(g[pr:pr + L]).copy(), np.array([0, L], np.uint64))
+    e2 = (g[7000:7000 + L].copy(), np.array([0, L], np.uint64))
+    rec = _pair_rec(100, L, 0, 3, 7000, L, 0, 1, 2 | 4)
+    out = oracle.rescue(g, e1, e2, rec, lo, hi)[0]
+    assert (out["end"], out["pos"], out["strand"], out["insert"], out["score"]) == (1, pr, 1, 250, L)
+    # equal penalties: end 1 anchors (at 100, nothing there for end 2's copy)
+    rec = _pair_rec(100, L, 0, 1, 7000, L, 0, 1, 2 | 4)
+    assert oracle.rescue(g, e1, e2, rec, lo, hi)[0]["end"] != 1
+    # the copy lies at insert 150 < lo: no rescue at that place
+    pf = 5000
+    pr = pf + 150 - L
+    e2 = (gen.revcomp(g[pr:pr + L]).copy(), np.array([0, L], np.uint64))
+    rec = _pair_rec(pf, L, 0, 0, 0xFFFFFFFF, 0, 0, 0, 2)
+    out = oracle.rescue(g, e_rand, e2, rec, lo, hi)[0]
+    assert out["end"] == 0 or (out["score"] < L and out["insert"] >= lo)
+    assert oracle.rescue(g, e_rand, e2, rec, 150, hi)[0]["insert"] == 150  # allowed once lo admits it
+    # the window is clipped at both reference ends
+    rec = _pair_rec(len(g) - 2 * L, L, 0, 0, 0xFFFFFFFF, 0, 0, 0, 2)
+    tail = gen.revcomp(g[len(g) - L:]).copy()
+    out = oracle.rescue(g, e_rand, (tail, np.array([0, L], np.uint64)), rec, 100, hi)[0]
+    assert (out["end"], out["pos"], out["insert"]) == (2, len(g) - L, 2 * L)
+    rec = _pair_rec(10, L, 1, 0, 0xFFFFFFFF, 0, 0, 0, 2)
+    head = g[0:L].copy()
+    out = oracle.rescue(g, e_rand, (head, np.array([0, L], np.uint64)), rec, 60, hi)[0]
+    assert (out["end"], out["pos"], out["strand"], out["insert"]) == (2, 0, 0, 10 + L)
