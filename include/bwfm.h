@@ -81,8 +81,10 @@ typedef struct {
  * ("primary"), C[a] = 1 + #symbols < a, rank lines (4 x uint32 counts of
  * A, C, G, T before the line, $ counted as A, then the line's rows as bit
  * planes: for each 32 rows a uint32 of the 2-bit codes' high bits followed
- * by a uint32 of their low bits), and SA samples.  Errors: E_INVAL (NULL or bad
- * layout), E_BASE, E_TOOLONG (n + 1 >= 2^32), E_NOMEM.
+ * by a uint32 of their low bits), and SA samples.  The index also keeps T
+ * itself, two bits per base (16 bases per uint32, base i in bits 2 (i % 16)
+ * of word i / 16), for mate rescue.  Errors: E_INVAL (NULL or bad layout),
+ * E_BASE, E_TOOLONG (n + 1 >= 2^32), E_NOMEM.
  */
 int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index_params *p, bwfm_index **out);
 
@@ -105,9 +107,10 @@ int bwfm_index_upload(bwfm_index *idx, void *hip_stream);
 void bwfm_index_free(bwfm_index *idx);
 
 /* Write the host part of an index to path (created or truncated): a
- * little-endian header (magic, version, layout, n), then per direction C,
- * the $ row, the rank lines and the SA samples, then a 64-bit FNV-1a
- * checksum of everything before it.  Errors: E_INVAL, E_IO. */
+ * little-endian header (magic, version 2, layout, n), then per direction C,
+ * the $ row, the rank lines and the SA samples, then the packed reference,
+ * then a 64-bit FNV-1a checksum of everything before it.  Errors: E_INVAL,
+ * E_IO. */
 int bwfm_index_save(const bwfm_index *idx, const char *path);
 
 /* Read an index written by bwfm_index_save into a new host-only index
@@ -137,6 +140,9 @@ int bwfm_index_get_info(const bwfm_index *idx, bwfm_index_info *out);
 int bwfm_index_get_bwt(const bwfm_index *idx, int which, uint8_t *out);
 int bwfm_index_get_sa_samples(const bwfm_index *idx, int which, uint32_t *out);
 int bwfm_index_occ(const bwfm_index *idx, int which, uint64_t i, uint64_t *out);
+/*   get_ref: out (host, len bytes) <- T[start, start + len), codes 0..3,
+ *        decoded from the index's packed copy; start + len <= n. */
+int bwfm_index_get_ref(const bwfm_index *idx, uint64_t start, uint64_t len, uint8_t *out);
 
 /* ------------------------------------------------------------------ */
 /* Alignment ("aln"; section 2: per-read search with backtracking)     */
@@ -300,6 +306,65 @@ typedef struct {
  */
 int bwfm_pair_reads(const bwfm_index *idx, uint32_t n_pairs, const bwfm_aln_result *r1,
                     const bwfm_aln_result *r2, const bwfm_pair_params *p, bwfm_pair *out, void *hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Mate rescue (section 3.7: the pipeline ends with BWA's pairing step,  */
+/* which gives an end without a partner a local alignment near its mate) */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t match;       /* score of a matching base, 1..32 */
+    int32_t mismatch;    /* penalty of a mismatch (a read N mismatches everything), 0..64 */
+    int32_t gap_open;    /* a gap of g bases costs gap_open + g * gap_extend; 0..64 each */
+    int32_t gap_extend;
+    int32_t min_score;   /* an alignment is reported when its score reaches this (>= 1) */
+} bwfm_rescue_params;
+
+/* the defaults: BWA-MEM's documented local-alignment scores, 20 to report */
+#define BWFM_RESCUE_DEFAULTS {1, 4, 6, 1, 20}
+/* largest fragment window (hi) rescue accepts */
+#define BWFM_RESCUE_MAX_WINDOW 8192
+
+typedef struct {
+    uint32_t pos;      /* leftmost reference base of the rescued alignment */
+    uint16_t len;      /* reference bases it spans */
+    int16_t score;     /* its local alignment score */
+    int32_t insert;    /* pr + lr - pf of the pair it forms (lo <= insert <= hi) */
+    uint8_t end;       /* 0: nothing rescued; else the end rescued (1 or 2) */
+    uint8_t strand;    /* strand of the rescued end (1: its reverse complement aligned) */
+    uint8_t pad[2];
+} bwfm_rescue;
+
+/*
+ * For every pair without a proper pair (BWFM_PF_PAIRED clear) and with a
+ * primary for at least one end, align the other end (the mate) locally
+ * inside the reference window the insert bounds allow around the primary
+ * (the anchor; with primaries for both ends the one of lower score, end 1 on
+ * ties):
+ *   anchor on + at pf:            window [pf, pf + hi), mate on -;
+ *   anchor on - at pr, length lr: window [pr + lr - hi, pr + lr), mate on +;
+ * both clipped to the reference, and the alignment must give an insert of at
+ * least lo.  Affine-gap local alignment (bwfm_rescue_params); among the best
+ * cells the one of smallest insert, then smallest mate base, is reported; a
+ * cell prefers the diagonal, then the gap along the reference, then the gap
+ * along the read, and a gap prefers opening over extending, which fixes the
+ * reported start.  Pairs that are proper, have no primary, or whose best score
+ * is below min_score get end = 0.
+ *   idx:   uploaded index (its packed reference is read).
+ *   end1, end2: device, the pairs' reads (n_reads >= n_pairs each; the
+ *          budgets are ignored); max_len bounds both ends' lengths.
+ *   pairs: device, n_pairs records from bwfm_pair_reads.
+ *   pp:    lo, hi as given to bwfm_pair_reads (hi <= BWFM_RESCUE_MAX_WINDOW).
+ *   rp:    scores; NULL = BWFM_RESCUE_DEFAULTS.
+ *   out:   device, n_pairs records (every one written).
+ * Allocates nothing and does not wait: the work is enqueued on hip_stream.
+ * Errors: E_INVAL (NULL, lo > hi, hi above the maximum, scores out of
+ * range), E_TOOLONG (max_len above 512), E_STATE (index not uploaded),
+ * E_DEVICE.
+ */
+int bwfm_rescue_mates(const bwfm_index *idx, const bwfm_reads *end1, const bwfm_reads *end2, uint32_t n_pairs,
+                      const bwfm_pair *pairs, const bwfm_pair_params *pp, const bwfm_rescue_params *rp,
+                      bwfm_rescue *out, void *hip_stream);
 
 /* ------------------------------------------------------------------ */
 /* Captured step: one batch of pairs through align, locate and pairing  */

@@ -26,6 +26,8 @@ HIT_DTYPE = np.dtype([("k", "<u4"), ("l", "<u4"), ("len", "<u2"), ("score", "<u2
 PAIR_DTYPE = np.dtype([("pos1", "<u4"), ("pos2", "<u4"), ("insert", "<i4"), ("len1", "<u2"), ("len2", "<u2"),
                        ("score1", "<u2"), ("score2", "<u2"), ("strand1", "u1"), ("strand2", "u1"),
                        ("flags", "u1"), ("pad", "u1")])
+RESCUE_DTYPE = np.dtype([("pos", "<u4"), ("len", "<u2"), ("score", "<i2"), ("insert", "<i4"), ("end", "u1"),
+                         ("strand", "u1"), ("pad", "u1", 2)])
 
 ST_HIT, ST_OVERFLOW, ST_INVALID, ST_RESEARCH, ST_SHARED = 1, 2, 4, 8, 16
 PF_PAIRED, PF_MAPPED1, PF_MAPPED2, PF_REP1, PF_REP2 = 1, 2, 4, 8, 16
@@ -88,6 +90,10 @@ class _PairParams(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_int32), ("hi", ctypes.c_int32), ("mu", ctypes.c_int32), ("max_occ", ctypes.c_uint32)]
 
 
+class _RescueParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("match", "mismatch", "gap_open", "gap_extend", "min_score")]
+
+
 class _PipeParams(ctypes.Structure):
     _fields_ = [("max_pairs", ctypes.c_uint32), ("max_len", ctypes.c_uint32), ("max_bases", ctypes.c_uint64),
                 ("hit_capacity", ctypes.c_uint64), ("pos_capacity", ctypes.c_uint64), ("paired", ctypes.c_int32)]
@@ -107,7 +113,7 @@ SYMBOLS = ("bwfm_build_index", "bwfm_index_upload", "bwfm_index_free", "bwfm_ind
            "bwfm_server_destroy", "bwfm_index_save", "bwfm_index_load", "bwfm_pipeline_create",
            "bwfm_pipeline_set_reads", "bwfm_pipeline_run", "bwfm_pipeline_finish", "bwfm_pipeline_outputs",
            "bwfm_pipeline_destroy", "bwfm_pipeline_bind_reads", "bwfm_pipeline_set_count",
-           "bwfm_build_index_device")
+           "bwfm_build_index_device", "bwfm_index_get_ref", "bwfm_rescue_mates")
 
 
 def lib():
@@ -138,6 +144,8 @@ def lib():
             "bwfm_index_get_bwt": ([P, c_int, P], c_int),
             "bwfm_index_get_sa_samples": ([P, c_int, P], c_int),
             "bwfm_index_occ": ([P, c_int, u64, P], c_int),
+            "bwfm_index_get_ref": ([P, u64, u64, P], c_int),
+            "bwfm_rescue_mates": ([P, P, P, u32, P, P, P, P, P], c_int),
             "bwfm_align_batch": ([P, P, P, P, P], c_int),
             "bwfm_align_batch_counted": ([P, P, P, P, P, P, P], c_int),
             "bwfm_locate": ([P, u32, P, u32, P, P, u64, P], c_int),
@@ -303,6 +311,13 @@ class Index:
         _check(lib().bwfm_index_occ(self._h, which, i, _np_ptr(out)))
         return out
 
+    def ref(self, start: int = 0, length: int | None = None) -> np.ndarray:
+        """T[start, start + length) decoded from the index's packed copy."""
+        length = self.n - start if length is None else length
+        out = np.empty(max(length, 1), np.uint8)
+        _check(lib().bwfm_index_get_ref(self._h, start, length, _np_ptr(out)))
+        return out[:length]
+
 
 def build_index(ref: np.ndarray, **kw) -> Index:
     return Index(ref, **kw)
@@ -427,6 +442,43 @@ def pair_reads(index: Index, r1: AlignResult, r2: AlignResult | None, lo: int, h
     _check(lib().bwfm_pair_reads(index.handle, n, ctypes.byref(a), ctypes.byref(b) if b is not None else None,
                                  ctypes.byref(pp), _dptr(out), _stream_ptr(stream)))
     return out
+
+
+@dataclass
+class RescueParams:
+    """Local-alignment scores of mate rescue (bwfm_rescue_params); defaults
+    are BWA-MEM's documented ones, reporting from score 20."""
+    match: int = 1
+    mismatch: int = 4
+    gap_open: int = 6
+    gap_extend: int = 1
+    min_score: int = 20
+
+    def _c(self) -> _RescueParams:
+        return _RescueParams(self.match, self.mismatch, self.gap_open, self.gap_extend, self.min_score)
+
+
+def rescue_mates(index: Index, end1, end2, pairs, lo: int, hi: int, max_len: int,
+                 params: RescueParams | None = None, stream=None, out=None):
+    """Mate rescue for the pairs without a proper pair (bwfm_rescue_mates).
+    end1/end2: (device uint8 bases, device int64 offsets [n + 1]) of the two
+    ends; pairs: device uint8 [n, 24] records from pair_reads.  Returns a
+    device uint8 tensor [n, 16] of bwfm_rescue records; does not synchronise."""
+    torch = _torch()
+    n = end1[1].shape[0] - 1
+    if out is None:
+        out = torch.empty((max(n, 1), RESCUE_DTYPE.itemsize), dtype=torch.uint8, device=end1[1].device)
+    r1 = _reads_struct(end1[0], end1[1], None, max_len)
+    r2 = _reads_struct(end2[0], end2[1], None, max_len)
+    pp = _PairParams(lo, hi, 0, 0)
+    rp = (params or RescueParams())._c()
+    _check(lib().bwfm_rescue_mates(index.handle, ctypes.byref(r1), ctypes.byref(r2), n, _dptr(pairs) if n else None,
+                                   ctypes.byref(pp), ctypes.byref(rp), _dptr(out), _stream_ptr(stream)))
+    return out
+
+
+def rescue_numpy(t) -> np.ndarray:
+    return t.cpu().numpy().view(RESCUE_DTYPE).reshape(-1)
 
 
 def pairs_numpy(t) -> np.ndarray:

@@ -1880,6 +1880,11 @@ extern "C" int bwfm_index_upload(bwfm_index *ix, void *stream) {
         HIPCHK(hipMemcpyAsync(ix->d_sa[d], ix->dir[d].sa.data(), sb, hipMemcpyHostToDevice, st));
         bytes += lb + sb;
     }
+    const size_t pb = std::max<size_t>(ix->pac.size(), 1) * 4;
+    if (hipMalloc(&ix->d_pac, pb) != hipSuccess) return fail(BWFM_E_NOMEM, "index upload: device allocation failed");
+    if (!ix->pac.empty())
+        HIPCHK(hipMemcpyAsync(ix->d_pac, ix->pac.data(), ix->pac.size() * 4, hipMemcpyHostToDevice, st));
+    bytes += pb;
     HIPCHK(hipStreamSynchronize(st));
     ix->device_bytes = bytes;
     ix->device = dev;
@@ -1892,6 +1897,7 @@ extern "C" void bwfm_index_free(bwfm_index *ix) {
         if (ix->d_lines[d]) (void)hipFree(ix->d_lines[d]);
         if (ix->d_sa[d]) (void)hipFree(ix->d_sa[d]);
     }
+    if (ix->d_pac) (void)hipFree(ix->d_pac);
     if (ix->ws.ptr) (void)hipFree(ix->ws.ptr);
     delete ix;
 }

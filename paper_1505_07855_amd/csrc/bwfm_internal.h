@@ -53,6 +53,9 @@ int check_index_params(bwfm_index_params &q, uint64_t n);
 int build_dir(const uint8_t *text, uint64_t n, uint32_t line_bytes, uint32_t bpl, uint32_t sa_sample,
               HostDir &out);
 void occ_host(const HostDir &d, uint32_t line_words, uint32_t bpl, uint64_t i, uint64_t out[4]);
+// T packed two bits per base, 16 bases per word, base i in bits 2 (i % 16)
+// of word i / 16 (unused high bits of the last word zero)
+void pack_ref(const uint8_t *text, uint64_t n, std::vector<uint32_t> &out);
 uint8_t bwt_host(const HostDir &d, uint32_t line_words, uint32_t bpl, uint64_t row);
 
 }  // namespace bwfm
@@ -62,10 +65,12 @@ struct bwfm_index {
     uint32_t line_bytes = 128, bpl = 448, sa_sample = 32;
     uint64_t n_lines = 0, n_samples = 0;
     bwfm::HostDir dir[2];
+    std::vector<uint32_t> pac;  // the reference itself (pack_ref), for mate rescue
     // device copies (valid when uploaded)
     int device = -1;
     void *d_lines[2] = {nullptr, nullptr};
     void *d_sa[2] = {nullptr, nullptr};
+    void *d_pac = nullptr;
     uint64_t device_bytes = 0;
     std::mutex mu;
     bwfm::Workspace ws;

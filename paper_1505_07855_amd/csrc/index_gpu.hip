@@ -44,6 +44,17 @@ __global__ void k_reverse(const uint8_t *t, uint64_t n, uint8_t *r) {
         r[i] = t[n - 1 - i];
 }
 
+// the reference two bits per base, 16 bases per word (base i in bits 2 (i % 16) of word i / 16)
+__global__ void k_pack_ref(const uint8_t *t, uint64_t n, uint32_t *pac) {
+    const uint64_t words = (n + 15) / 16;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t v = 0;
+        const uint64_t i0 = w * 16;
+        for (int k = 0; k < 16 && i0 + k < n; k++) v |= (uint32_t)(t[i0 + k] & 3) << (2 * k);
+        pac[w] = v;
+    }
+}
+
 // first-round keys: the 21 symbols from i, each code + 1, 0 from $ on
 __global__ void k_sa_init(const uint8_t *t, uint64_t n, uint64_t N, uint64_t *key, uint32_t *val) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -270,6 +281,18 @@ extern "C" int bwfm_build_index_device(const uint8_t *ref, uint64_t n, const bwf
     int rc = BWFM_OK;
     if (hipMemcpyAsync(t, ref, n, hipMemcpyHostToDevice, st) != hipSuccess)
         rc = fail(BWFM_E_DEVICE, "index build: text upload");
+    const uint64_t pac_words = (n + 15) / 16;
+    if (!rc && hipMalloc(&ix->d_pac, pac_words * 4) != hipSuccess) rc = fail(BWFM_E_NOMEM, "index build: packed text");
+    if (!rc) {
+        k_pack_ref<<<grid_for(pac_words, 256), 256, 0, st>>>(t, n, (uint32_t *)ix->d_pac);
+        try {
+            ix->pac.resize(pac_words);
+        } catch (const std::bad_alloc &) {
+            rc = fail(BWFM_E_NOMEM, "out of host memory");
+        }
+        if (!rc && hipMemcpyAsync(ix->pac.data(), ix->d_pac, pac_words * 4, hipMemcpyDeviceToHost, st) != hipSuccess)
+            rc = fail(BWFM_E_DEVICE, "index build: packed text copy");
+    }
     if (!rc) rc = build_dir_device(t, n, q.line_bytes, q.bases_per_line, q.sa_sample, ix->dir[0], ix->d_lines[0],
                                    ix->d_sa[0], st);
     if (!rc) {
@@ -291,11 +314,14 @@ extern "C" int bwfm_build_index_device(const uint8_t *ref, uint64_t n, const bwf
             if (ix->d_sa[d]) (void)hipFree(ix->d_sa[d]);
             ix->d_lines[d] = ix->d_sa[d] = nullptr;
         }
+        if (ix->d_pac) (void)hipFree(ix->d_pac);
+        ix->d_pac = nullptr;
         return rc;
     }
     ix->device = dev;
     ix->device_bytes = 0;
     for (int d = 0; d < 2; d++) ix->device_bytes += ix->dir[d].lines.size() * 4 + ix->dir[d].sa.size() * 4;
+    ix->device_bytes += pac_words * 4;
     *out = ix.release();
     return BWFM_OK;
 }

@@ -223,6 +223,11 @@ int check_index_params(bwfm_index_params &q, uint64_t n) {
     return BWFM_OK;
 }
 
+void pack_ref(const uint8_t *text, uint64_t n, std::vector<uint32_t> &out) {
+    out.assign((n + 15) / 16, 0u);
+    for (uint64_t i = 0; i < n; i++) out[i >> 4] |= (uint32_t)(text[i] & 3) << (2 * (i & 15));
+}
+
 }  // namespace bwfm
 
 extern "C" int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index_params *p, bwfm_index **out) {
@@ -263,6 +268,12 @@ extern "C" int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index
         delete ix;
         return fail(rc[0] ? rc[0] : rc[1], "index build failed (out of memory)");
     }
+    try {
+        pack_ref(ref, n, ix->pac);
+    } catch (const std::bad_alloc &) {
+        delete ix;
+        return fail(BWFM_E_NOMEM, "index build failed (out of memory)");
+    }
     *out = ix;
     return BWFM_OK;
 }
@@ -297,6 +308,15 @@ extern "C" int bwfm_index_get_sa_samples(const bwfm_index *ix, int which, uint32
     return BWFM_OK;
 }
 
+extern "C" int bwfm_index_get_ref(const bwfm_index *ix, uint64_t start, uint64_t len, uint8_t *out) {
+    if (!ix || (!out && len) || start > ix->n || len > ix->n - start) return fail(BWFM_E_INVAL, "get_ref: bad argument");
+    for (uint64_t i = 0; i < len; i++) {
+        const uint64_t p = start + i;
+        out[i] = (uint8_t)((ix->pac[p >> 4] >> (2 * (p & 15))) & 3);
+    }
+    return BWFM_OK;
+}
+
 extern "C" int bwfm_index_occ(const bwfm_index *ix, int which, uint64_t i, uint64_t *out) {
     if (!ix || !out || which < 0 || which > 1 || i > ix->n + 1) return fail(BWFM_E_INVAL, "occ: bad argument");
     occ_host(ix->dir[which], ix->line_bytes / 4, ix->bpl, i, out);
@@ -308,7 +328,7 @@ extern "C" int bwfm_index_occ(const bwfm_index *ix, int which, uint64_t i, uint6
 namespace {
 
 constexpr char FILE_MAGIC[8] = {'B', 'W', 'F', 'M', 'I', 'D', 'X', 0};
-constexpr uint32_t FILE_VERSION = 1;
+constexpr uint32_t FILE_VERSION = 2;
 
 struct Fnv {
     uint64_t h = 1469598103934665603ULL;
@@ -373,6 +393,8 @@ extern "C" int bwfm_index_save(const bwfm_index *ix, const char *path) {
         w.val<uint64_t>(h.sa.size());
         w.put(h.sa.data(), h.sa.size() * 4);
     }
+    w.val<uint64_t>(ix->pac.size());
+    w.put(ix->pac.data(), ix->pac.size() * 4);
     const uint64_t sum = w.sum.h;
     if (w.ok) w.ok = std::fwrite(&sum, 1, 8, f) == 8;
     const bool closed = std::fclose(f) == 0;
@@ -411,7 +433,9 @@ extern "C" int bwfm_index_load(const char *path, bwfm_index **out) {
                            ix->n_lines == (ix->n + 1) / ix->bpl + 1 && ix->n_samples == ix->n / ix->sa_sample + 1;
     if (!r.ok || !layout_ok) return fail(BWFM_E_IO, "index_load: corrupt header");
     const uint64_t words = ix->n_lines * (ix->line_bytes / 4);
-    const uint64_t expect = 8 + 4 * 4 + 3 * 8 + 2 * (6 * 8 + words * 4 + 8 + ix->n_samples * 4) + 8;
+    const uint64_t pac_words = (ix->n + 15) / 16;
+    const uint64_t expect =
+        8 + 4 * 4 + 3 * 8 + 2 * (6 * 8 + words * 4 + 8 + ix->n_samples * 4) + 8 + pac_words * 4 + 8;
     if (fsize < 0 || (uint64_t)fsize != expect) return fail(BWFM_E_IO, "index_load: file size does not match header");
     try {
         for (int d = 0; d < 2; d++) {
@@ -426,6 +450,9 @@ extern "C" int bwfm_index_load(const char *path, bwfm_index **out) {
             r.get(h.sa.data(), ix->n_samples * 4);
             if (h.primary > ix->n) return fail(BWFM_E_IO, "index_load: corrupt $ row");
         }
+        if (r.val<uint64_t>() != pac_words) return fail(BWFM_E_IO, "index_load: corrupt reference size");
+        ix->pac.resize(pac_words);
+        r.get(ix->pac.data(), pac_words * 4);
     } catch (const std::bad_alloc &) {
         return fail(BWFM_E_NOMEM, "out of host memory");
     }

@@ -1,0 +1,300 @@
+// Mate rescue on the device: the end of a pair left without a partner is
+// aligned locally (affine gaps) inside the reference window that the insert
+// bounds allow around its mate's primary (section 3.7 closes the pipeline
+// with BWA's pairing step, of which this is the rescue part).
+//
+// One wave per rescued pair.  The mate's m bases are the rows of the
+// dynamic-programming matrix, R consecutive rows per lane; the window's
+// reference bases are its columns.  The wave sweeps the columns in skewed
+// order -- lane l works on column t - l at step t -- so each lane receives
+// the values of the row above its first row (H and F of the previous lane's
+// last row, with the window columns their alignments start at) one step
+// after they were made, through a one-lane shift.  Every cell is computed
+// once; a step costs R cells per lane.  The window is decoded from the packed
+// reference into LDS first.  Work per pair is m x window cells, a few hundred
+// steps: the kernel is bound by integer ALU work, not memory.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "bwfm_internal.h"
+
+using namespace bwfm;
+
+namespace {
+
+constexpr int RB = 256;  // threads per block: 4 waves, each takes 64 pairs
+constexpr int NEG = -1000000000;
+
+struct EndView {
+    const uint8_t *bases;
+    const uint64_t *off;
+    const uint32_t *len;  // or NULL: read r ends where read r + 1 starts
+};
+
+struct Scores {
+    int a, b, o, e, min_score;
+};
+
+__device__ __forceinline__ void end_span(const EndView &v, uint32_t r, uint64_t &o0, int &m) {
+    o0 = v.off[r];
+    if (v.len) {
+        m = (int)min(v.len[r], 1u << 20);
+    } else {
+        const uint64_t o1 = v.off[r + 1];
+        m = o1 < o0 ? -1 : (int)min(o1 - o0, (uint64_t)1 << 20);
+    }
+}
+
+// order this wave's LDS writes before its later reads by other lanes
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int shift_down(int v) { return __shfl_up(v, 1); }
+
+// Rescue one pair with the whole wave (all arguments wave-uniform).
+template <int R>
+__device__ void rescue_one(const uint32_t *pac, uint64_t n, const EndView &ev, uint32_t pair, int mate, uint32_t pa,
+                           int la, int sa, int lo, int hi, int max_len, const Scores &S, uint8_t *win,
+                           bwfm_rescue *out) {
+    const int lane = threadIdx.x & 63;
+    uint64_t o0;
+    int m;
+    end_span(ev, pair, o0, m);
+    int64_t w0, w1;
+    if (sa == 0) {
+        w0 = pa;
+        w1 = std::min<int64_t>((int64_t)pa + hi, (int64_t)n);
+    } else {
+        w1 = std::min<int64_t>((int64_t)pa + la, (int64_t)n);
+        w0 = std::max<int64_t>(w1 - hi, 0);
+    }
+    const int w = (int)std::max<int64_t>(w1 - w0, 0);
+    bwfm_rescue res;
+    std::memset(&res, 0, sizeof res);
+    if (m <= 0 || m > max_len || m > 64 * R || w <= 0) {
+        if (lane == 0) out[pair] = res;
+        return;
+    }
+    // the window, in the orientation the query reads it: forward after a +
+    // anchor, reversed (from pr + lr - 1 down) after a - anchor
+    for (int j = lane; j < w; j += 64) {
+        const uint64_t p = sa == 0 ? (uint64_t)(w0 + j) : (uint64_t)(w1 - 1 - j);
+        win[j] = (uint8_t)((pac[p >> 4] >> (2 * (p & 15))) & 3);
+    }
+    // this lane's rows: query base i is mate base m - 1 - i, complemented
+    // after a + anchor (the mate then lies on -)
+    uint8_t q[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int i = lane * R + r;
+        uint8_t c = 5;  // rows past the mate: match nothing, never reported
+        if (i < m) {
+            c = ev.bases[o0 + (uint64_t)(m - 1 - i)];
+            if (sa == 0 && c < 4) c = (uint8_t)(3 - c);
+        }
+        q[r] = c;
+    }
+    wave_sync();
+    const int used = (m + R - 1) / R;  // lanes holding rows
+    const int e_min = lo > 0 ? lo - 1 : -1;  // the alignment must end at column >= lo - 1
+    const int oe = S.o + S.e;
+    int Hp[R], HpO[R], Ep[R], EpO[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        Hp[r] = 0;
+        HpO[r] = 0;
+        Ep[r] = NEG;
+        EpO[r] = 0;
+    }
+    int outH = 0, outHO = 0, outF = NEG, outFO = 0;  // last row of this lane, current column
+    int prevH = 0, prevHO = 0;                       // row above, previous column
+    int best = 0, bj = -1, bi = 0, bO = 0;
+    const bool rows = lane < used;
+    const int steps = w + used - 1;
+    for (int t = 0; t < steps; t++) {
+        int upH = shift_down(outH), upHO = shift_down(outHO), upF = shift_down(outF), upFO = shift_down(outFO);
+        if (lane == 0) {
+            upH = 0;
+            upHO = 0;
+            upF = NEG;
+            upFO = 0;
+        }
+        const int j = t - lane;
+        if (rows && j >= 0 && j < w) {
+            const uint8_t rj = win[j];
+            int Hd = prevH, HdO = prevHO;  // H of the row above, previous column
+            int Hu = upH, HuO = upHO;      // H of the row above, this column
+            int F = upF, FO = upFO;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                // gap along the reference, from the previous column
+                const int eo = Hp[r] - oe, ee = Ep[r] - S.e;
+                const int E = eo >= ee ? eo : ee, EO = eo >= ee ? HpO[r] : EpO[r];
+                // gap along the read, from the row above
+                const int fo = Hu - oe, fe = F - S.e;
+                if (fo >= fe) {
+                    F = fo;
+                    FO = HuO;
+                } else {
+                    F = fe;
+                }
+                const int s = (q[r] < 4 && q[r] == rj) ? S.a : -S.b;
+                const int dg = Hd + s, dgO = Hd > 0 ? HdO : j;
+                int H = 0, HO = 0;
+                if (dg > H) {
+                    H = dg;
+                    HO = dgO;
+                }
+                if (E > H) {
+                    H = E;
+                    HO = EO;
+                }
+                if (F > H) {
+                    H = F;
+                    HO = FO;
+                }
+                Hd = Hp[r];
+                HdO = HpO[r];
+                Hp[r] = H;
+                HpO[r] = HO;
+                Ep[r] = E;
+                EpO[r] = EO;
+                Hu = H;
+                HuO = HO;
+                const int i = lane * R + r + 1;
+                if (j >= e_min && i <= m && H > best) {
+                    best = H;
+                    bj = j;
+                    bi = i;
+                    bO = HO;
+                }
+            }
+            outH = Hu;
+            outHO = HuO;
+            outF = F;
+            outFO = FO;
+        }
+        prevH = upH;
+        prevHO = upHO;
+    }
+    // the first best cell in column order: highest score, then smallest
+    // column, then smallest row (each cell lives in exactly one lane)
+    uint64_t key = best > 0 ? ((uint64_t)(uint32_t)best << 32) | ((uint64_t)(0xFFFFu - (uint32_t)bj) << 16) |
+                                  (uint64_t)(0xFFFFu - (uint32_t)bi)
+                            : 0;
+    uint64_t top = key;
+    for (int k = 32; k > 0; k >>= 1) {
+        const uint64_t o = __shfl_xor(top, k);
+        top = o > top ? o : top;
+    }
+    const unsigned long long who = __ballot(key == top && top != 0);
+    if (who) {
+        const int src = __ffsll((long long)who) - 1;
+        best = __shfl(best, src);
+        bj = __shfl(bj, src);
+        bO = __shfl(bO, src);
+        if (best >= S.min_score) {
+            res.end = (uint8_t)mate;
+            res.score = (int16_t)best;
+            res.len = (uint16_t)(bj - bO + 1);
+            res.insert = bj + 1;
+            if (sa == 0) {
+                res.strand = 1;
+                res.pos = (uint32_t)(w0 + bO);
+            } else {
+                res.strand = 0;
+                res.pos = (uint32_t)(w1 - 1 - bj);
+            }
+        }
+    }
+    if (lane == 0) out[pair] = res;
+}
+
+template <int R>
+__global__ __launch_bounds__(RB) void k_rescue(const uint32_t *pac, uint64_t n, EndView e1, EndView e2,
+                                               const bwfm_pair *pairs, uint32_t n_pairs, int lo, int hi, int max_len,
+                                               Scores S, int win_stride, bwfm_rescue *out) {
+    extern __shared__ uint8_t lds[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint8_t *win = lds + (size_t)wv * win_stride;
+    const uint32_t base = ((uint32_t)blockIdx.x * (RB / 64) + (uint32_t)wv) * 64u;
+    const uint32_t p = base + (uint32_t)lane;
+    bool cand = false;
+    int mate = 0, la = 0, sa = 0;
+    uint32_t pa = 0;
+    if (p < n_pairs) {
+        const bwfm_pair pr = pairs[p];
+        const bool m1 = (pr.flags & BWFM_PF_MAPPED1) != 0, m2 = (pr.flags & BWFM_PF_MAPPED2) != 0;
+        cand = !(pr.flags & BWFM_PF_PAIRED) && (m1 || m2);
+        // the anchor: the mapped end, or of two the lower search score (end 1 on ties)
+        const int anchor = (m1 && m2) ? (pr.score1 <= pr.score2 ? 1 : 2) : (m1 ? 1 : 2);
+        mate = 3 - anchor;
+        pa = anchor == 1 ? pr.pos1 : pr.pos2;
+        la = anchor == 1 ? pr.len1 : pr.len2;
+        sa = anchor == 1 ? pr.strand1 : pr.strand2;
+        if (!cand) {
+            bwfm_rescue z;
+            std::memset(&z, 0, sizeof z);
+            out[p] = z;
+        }
+    }
+    unsigned long long todo = __ballot(cand);
+    while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const int c_mate = __shfl(mate, src), c_la = __shfl(la, src), c_sa = __shfl(sa, src);
+        const uint32_t c_pa = (uint32_t)__shfl((int)pa, src);
+        rescue_one<R>(pac, n, c_mate == 1 ? e1 : e2, base + (uint32_t)src, c_mate, c_pa, c_la, c_sa, lo, hi, max_len,
+                      S, win, out);
+        wave_sync();  // the window is rewritten for the next pair
+    }
+}
+
+}  // namespace
+
+extern "C" int bwfm_rescue_mates(const bwfm_index *ix, const bwfm_reads *end1, const bwfm_reads *end2,
+                                 uint32_t n_pairs, const bwfm_pair *pairs, const bwfm_pair_params *pp,
+                                 const bwfm_rescue_params *rp, bwfm_rescue *out, void *stream) {
+    if (!ix || !end1 || !end2 || !pp || (n_pairs && (!pairs || !out)))
+        return fail(BWFM_E_INVAL, "rescue_mates: NULL argument");
+    if (ix->device < 0 || !ix->d_pac) return fail(BWFM_E_STATE, "rescue_mates: index not uploaded");
+    if (n_pairs && (!end1->bases || !end1->offsets || !end2->bases || !end2->offsets))
+        return fail(BWFM_E_INVAL, "rescue_mates: NULL reads");
+    if (end1->n_reads < n_pairs || end2->n_reads < n_pairs)
+        return fail(BWFM_E_INVAL, "rescue_mates: fewer reads than pairs");
+    if (pp->lo > pp->hi) return fail(BWFM_E_INVAL, "rescue_mates: lo > hi");
+    if (pp->hi > BWFM_RESCUE_MAX_WINDOW) return fail(BWFM_E_INVAL, "rescue_mates: hi above the largest window");
+    const bwfm_rescue_params q = rp ? *rp : bwfm_rescue_params BWFM_RESCUE_DEFAULTS;
+    if (q.match < 1 || q.match > 32 || q.mismatch < 0 || q.mismatch > 64 || q.gap_open < 0 || q.gap_open > 64 ||
+        q.gap_extend < 0 || q.gap_extend > 64 || q.min_score < 1)
+        return fail(BWFM_E_INVAL, "rescue_mates: scores out of range");
+    const uint32_t max_len = std::max(end1->max_len, end2->max_len);
+    if (max_len > BWFM_MAX_READ) return fail(BWFM_E_TOOLONG, "rescue_mates: max_len above 512");
+    if (n_pairs == 0) return BWFM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const EndView e1{end1->bases, end1->offsets, end1->lengths}, e2{end2->bases, end2->offsets, end2->lengths};
+    const Scores S{q.match, q.mismatch, q.gap_open, q.gap_extend, q.min_score};
+    const int hi = std::max(pp->hi, 0);
+    const int win_stride = std::max((hi + 15) & ~15, 16);
+    const uint32_t grid = (uint32_t)(((uint64_t)n_pairs + RB - 1) / RB);
+    const size_t lds = (size_t)(RB / 64) * win_stride;
+    const uint32_t *pac = (const uint32_t *)ix->d_pac;
+    const int ml = (int)max_len;
+    if (max_len <= 64)
+        k_rescue<1><<<grid, RB, lds, st>>>(pac, ix->n, e1, e2, pairs, n_pairs, pp->lo, hi, ml, S, win_stride, out);
+    else if (max_len <= 128)
+        k_rescue<2><<<grid, RB, lds, st>>>(pac, ix->n, e1, e2, pairs, n_pairs, pp->lo, hi, ml, S, win_stride, out);
+    else if (max_len <= 256)
+        k_rescue<4><<<grid, RB, lds, st>>>(pac, ix->n, e1, e2, pairs, n_pairs, pp->lo, hi, ml, S, win_stride, out);
+    else
+        k_rescue<8><<<grid, RB, lds, st>>>(pac, ix->n, e1, e2, pairs, n_pairs, pp->lo, hi, ml, S, win_stride, out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(BWFM_E_DEVICE, std::string("rescue_mates: launch: ") + hipGetErrorString(e));
+    return BWFM_OK;
+}

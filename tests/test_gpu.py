@@ -324,13 +324,22 @@ def test_c2_full_size_sampled_parity(c2_full):
         so[1:] = np.cumsum(np.diff(offs)[sample])
         ores = oracle.align(ox, sb, so, op, threads=16)
         _compare_align(res, ores, rows=sample)
-        res_e.append((res, ores))
+        res_e.append((res, ores, (sb, so)))
     # pairs of the sampled reads
     w = configs.PAIR_WINDOW
-    gp = bw.pairs_numpy(bw.pair_reads(ix, res_e[0][0], res_e[1][0], w["lo"], w["hi"], w["mu"], configs.MAX_OCC))
+    gpd = bw.pair_reads(ix, res_e[0][0], res_e[1][0], w["lo"], w["hi"], w["mu"], configs.MAX_OCC)
+    gp = bw.pairs_numpy(gpd)
     po1, pos1 = oracle.locate(ox, res_e[0][1].hits, configs.MAX_OCC)
     po2, pos2 = oracle.locate(ox, res_e[1][1].hits, configs.MAX_OCC)
     op_ = oracle.pair(res_e[0][1], po1, pos1, res_e[1][1], po2, pos2, w["lo"], w["hi"], w["mu"])
     assert np.array_equal(gp[sample].view(np.uint8), op_.view(np.uint8))
     # whole-batch properties: every pair got a record, most pair properly
     assert (gp["flags"] & bw.PF_PAIRED).mean() > 0.8
+    # mate rescue over the whole batch; the sampled pairs against the oracle's
+    # rescue of its own pair records
+    ends = [(_dev(e.bases), _dev(e.offsets.view(np.int64))) for e in (pairs.end1, pairs.end2)]
+    gr = bw.rescue_numpy(bw.rescue_mates(ix, ends[0], ends[1], gpd, w["lo"], w["hi"], max_len=100))
+    orr = oracle.rescue(g.seq, res_e[0][2], res_e[1][2], op_, w["lo"], w["hi"])
+    assert np.array_equal(gr[sample].view(np.uint8), orr.view(np.uint8))
+    unpaired = (gp["flags"] & bw.PF_PAIRED) == 0
+    assert (gr["end"][~unpaired] == 0).all() and (gr["end"][unpaired] != 0).sum() > 0

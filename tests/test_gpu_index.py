@@ -34,6 +34,7 @@ def _host_bytes(ix):
     for which in (0, 1):
         out.append(ix.bwt(which).tobytes())
         out.append(ix.sa_samples(which).tobytes())
+    out.append(ix.ref().tobytes())
     return out
 
 

@@ -1,0 +1,196 @@
+"""GPU parity of mate rescue (bwfm_rescue_mates) against the oracle, bit for
+bit on every record field.  Pair records fed to both sides come from the
+generator's truth (every scenario: proper, one end mapped, both mapped
+apart, none, anchors displaced or at the reference ends) or from the oracle's
+own alignment, locate and pairing of a seeded batch; nothing the GPU computes
+is an input to the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_1505_07855_amd as bw
+from gen import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+UNPLACED = 0xFFFFFFFF
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _end_dev(reads):
+    return _dev(reads.bases), _dev(reads.offsets.view(np.int64))
+
+
+def _truth_records(pairs: gen.PairedReads, n_ref: int, seed: int) -> np.ndarray:
+    """Pair records of every rescue scenario, placed from the generator's truth."""
+    rng = np.random.default_rng(seed)
+    n = pairs.end1.n
+    t1, t2 = pairs.end1.truth, pairs.end2.truth
+    rec = np.zeros(n, oracle.PAIR_DTYPE)
+    rec["pos1"], rec["len1"], rec["strand1"] = t1.pos, t1.ref_len, t1.strand
+    rec["pos2"], rec["len2"], rec["strand2"] = t2.pos, t2.ref_len, t2.strand
+    rec["score1"] = rng.integers(0, 20, n)
+    rec["score2"] = rng.integers(0, 20, n)
+    kind = np.arange(n) % 7
+    flags = np.zeros(n, np.uint8)
+    flags[kind == 0] = 1 | 2 | 4                      # proper: left alone
+    flags[kind == 1] = 2                              # end 2 to rescue
+    flags[kind == 2] = 4                              # end 1 to rescue
+    flags[kind == 3] = 2 | 4                          # both placed, apart: the lower score anchors
+    far = kind == 3
+    rec["pos2"][far] = rng.integers(0, n_ref - 400, far.sum())
+    rec["strand2"][far] = rng.integers(0, 2, far.sum())
+    flags[kind == 4] = 0                              # nothing placed
+    flags[kind == 5] = 2                              # anchor displaced: usually nothing to find
+    d = kind == 5
+    rec["pos1"][d] = rng.integers(0, n_ref - 400, d.sum())
+    flags[kind == 6] = 2 | 4                          # both placed, equal scores: end 1 anchors
+    rec["score2"][kind == 6] = rec["score1"][kind == 6]
+    rec["flags"] = flags
+    for k in np.flatnonzero(~(flags & 2).astype(bool)):
+        rec["pos1"][k], rec["len1"][k] = UNPLACED, 0
+    for k in np.flatnonzero(~(flags & 4).astype(bool)):
+        rec["pos2"][k], rec["len2"][k] = UNPLACED, 0
+    # anchors at both reference ends (window clipping)
+    for k, (pos, strand) in enumerate([(0, 0), (5, 1), (n_ref - 30, 0), (n_ref - 90, 1), (n_ref - 1, 0)]):
+        if k < n:
+            rec["flags"][k], rec["pos1"][k], rec["len1"][k], rec["strand1"][k] = 2, pos, 30, strand
+            rec["pos2"][k], rec["len2"][k] = UNPLACED, 0
+    return rec
+
+
+def _run_both(ix, g, pairs, rec, lo, hi, params=None):
+    max_len = int(max(np.diff(pairs.end1.offsets).max(), np.diff(pairs.end2.offsets).max(), 1))
+    rp = params or bw.RescueParams()
+    out = bw.rescue_mates(ix, _end_dev(pairs.end1), _end_dev(pairs.end2), _dev(rec.view(np.uint8)), lo, hi,
+                          max_len, params=rp)
+    torch.cuda.synchronize()
+    got = bw.rescue_numpy(out)[:pairs.end1.n]
+    want = oracle.rescue(g.seq, (pairs.end1.bases, pairs.end1.offsets), (pairs.end2.bases, pairs.end2.offsets),
+                         rec, lo, hi, min_score=rp.min_score, match=rp.match, mismatch=rp.mismatch,
+                         gap_open=rp.gap_open, gap_extend=rp.gap_extend)
+    return got, want
+
+
+@pytest.fixture(scope="module")
+def genome():
+    g = configs.c2_genome(1_000_000, seed=91)
+    return g, bw.Index(g.seq, **configs.LAYOUT["C2"]).upload()
+
+
+@pytest.mark.parametrize("length", [36, 100, "c3", 300])
+def test_rescue_truth_records_parity(genome, length):
+    """One build per rows-per-lane (36 -> 1, 100 -> 2, up to 150 -> 4, 300 -> 8)."""
+    g, ix = genome
+    if length == "c3":
+        pairs = configs.c3_pairs(g, 2100, seed=92)
+    else:
+        pairs = gen.reads_pe(93, g, 2100, length, frag_mu=300 if length < 300 else 700, frag_sd=30, frag_min=100,
+                             ps=0.02, indel_ratio=0.2)
+    rec = _truth_records(pairs, len(g.seq), seed=94)
+    lo, hi = (180, 420) if length != 300 else (580, 820)
+    got, want = _run_both(ix, g, pairs, rec, lo, hi)
+    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+    # the rescue finds the true mate when one end alone was placed from the truth
+    kind = np.arange(pairs.end1.n) % 7
+    one = (kind == 1)
+    one[:5] = False
+    hit = want["end"][one] == 2
+    assert hit.mean() > 0.9
+    assert np.mean(want["pos"][one][hit] == pairs.end2.truth.pos[one][hit]) > 0.8
+    assert (want["end"][5:][kind[5:] == 0] == 0).all() and (want["end"][5:][kind[5:] == 4] == 0).all()
+
+
+def test_rescue_other_scores_and_bounds(genome):
+    g, ix = genome
+    pairs = configs.c2_pairs(g, 1400, seed=95)
+    rec = _truth_records(pairs, len(g.seq), seed=96)
+    for params, lo, hi in [(bw.RescueParams(2, 1, 1, 1, 30), 180, 420),
+                           (bw.RescueParams(1, 4, 6, 1, 90), 180, 420),   # a high bar: few kept
+                           (bw.RescueParams(), 0, 64),                    # windows shorter than the fragment
+                           (bw.RescueParams(), 300, 300),                 # a single admissible insert
+                           (bw.RescueParams(1, 0, 0, 0, 1), -5, 1000)]:   # free gaps, lo below 0
+        got, want = _run_both(ix, g, pairs, rec, lo, hi, params)
+        assert np.array_equal(got.view(np.uint8), want.view(np.uint8)), (params, lo, hi)
+
+
+def test_rescue_pairs_from_oracle_pipeline():
+    """C2-shaped pairs aligned, located and paired by the oracle, then rescued
+    on both sides."""
+    g = configs.c2_genome(2_000_000, seed=97)
+    pairs = configs.c2_pairs(g, 3000, seed=98)
+    # a tenth of end 2 reads scrambled so that they do not align: their mates anchor
+    rng = np.random.default_rng(99)
+    b2 = pairs.end2.bases.copy()
+    for r in range(0, pairs.end2.n, 10):
+        o0, o1 = pairs.end2.offsets[r], pairs.end2.offsets[r + 1]
+        b2[o0:o1] = rng.integers(0, 4, int(o1 - o0))
+    pairs = gen.PairedReads(pairs.end1, gen.Reads(b2, pairs.end2.offsets, pairs.end2.truth), pairs.frag)
+    ox = oracle.Index(g.seq)
+    op = oracle.Params(**configs.PARAMS["C2"])
+    o1 = oracle.align(ox, pairs.end1.bases, pairs.end1.offsets, op, threads=8)
+    o2 = oracle.align(ox, pairs.end2.bases, pairs.end2.offsets, op, threads=8)
+    po1, pos1 = oracle.locate(ox, o1.hits, configs.MAX_OCC)
+    po2, pos2 = oracle.locate(ox, o2.hits, configs.MAX_OCC)
+    w = configs.PAIR_WINDOW
+    rec = oracle.pair(o1, po1, pos1, o2, po2, pos2, w["lo"], w["hi"], w["mu"])
+    ix = bw.Index(g.seq, **configs.LAYOUT["C2"]).upload()
+    got, want = _run_both(ix, g, pairs, rec, w["lo"], w["hi"])
+    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+    assert (want["end"] != 0).sum() > 0
+    # scrambled mates are random sequence: the rescue must not invent them
+    scrambled = np.zeros(pairs.end1.n, bool)
+    scrambled[::10] = True
+    assert (want["end"][scrambled] == 0).mean() > 0.95
+
+
+def test_rescue_edge_cases(genome):
+    g, ix = genome
+    n_ref = len(g.seq)
+    L = 80
+    # mates: empty, all N, one base, exact copy at the window's far end, N
+    # inside, and exact copies against both reference ends (clipped windows)
+    cp = g.seq[60000 + 420 - L:60000 + 420]
+    nm = gen.revcomp(cp).copy()
+    nm[[5, 40, 41]] = 4
+    mates = [np.zeros(0, np.uint8), np.full(L, 4, np.uint8), np.array([2], np.uint8), gen.revcomp(cp), nm,
+             gen.revcomp(g.seq[n_ref - L:]), g.seq[:L].copy()]
+    anchors = [(60000, 0)] * 5 + [(n_ref - 200, 0), (200, 1)]
+    n = len(mates)
+    o2 = np.zeros(n + 1, np.uint64)
+    o2[1:] = np.cumsum([len(m) for m in mates])
+    end2 = gen.Reads(np.concatenate(mates), o2)
+    end1 = gen.Reads(np.zeros(n * L, np.uint8), np.arange(n + 1, dtype=np.uint64) * L)
+    rec = np.zeros(n, oracle.PAIR_DTYPE)
+    rec["pos1"] = [a[0] for a in anchors]
+    rec["strand1"] = [a[1] for a in anchors]
+    rec["len1"], rec["flags"] = L, 2
+    rec["pos2"] = UNPLACED
+    pairs = gen.PairedReads(end1, end2, np.zeros((n, 3), np.uint32))
+    got, want = _run_both(ix, g, pairs, rec, 180, 420)
+    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+    assert list(want["end"]) == [0, 0, 0, 2, 2, 2, 2]
+    assert want[3]["pos"] == 60000 + 420 - L and want[3]["insert"] == 420 and want[3]["score"] == L
+    assert (want[5]["pos"], want[5]["insert"], want[5]["strand"]) == (n_ref - L, 200, 1)
+    assert (want[6]["pos"], want[6]["insert"], want[6]["strand"]) == (0, 200 + L, 0)
+    # an empty batch writes nothing and returns
+    e0 = (torch.zeros(0, dtype=torch.uint8, device="cuda:0"), torch.zeros(1, dtype=torch.int64, device="cuda:0"))
+    bw.rescue_mates(ix, e0, e0, torch.zeros((0, 24), dtype=torch.uint8, device="cuda:0"), 180, 420, 100)
+    # argument errors are reported, nothing launched
+    ed = _end_dev(end1)
+    recd = _dev(rec.view(np.uint8))
+    for kw in [dict(lo=500, hi=400), dict(lo=0, hi=100000), dict(params=bw.RescueParams(0, 4, 6, 1, 20)),
+               dict(params=bw.RescueParams(1, 4, 6, 1, 0)), dict(max_len=513)]:
+        args = dict(lo=180, hi=420, max_len=L)
+        args.update(kw)
+        with pytest.raises(bw.BwfmError):
+            bw.rescue_mates(ix, ed, ed, recd, **args)
+    assert n_ref > 0

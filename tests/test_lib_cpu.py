@@ -56,6 +56,10 @@ def test_host_index_equals_oracle_index(layout, rng):
             rows = np.unique(np.concatenate([rng.integers(0, len(t) + 2, 60), [0, 1, len(t), len(t) + 1]]))
             for i in rows:
                 assert ix.occ(int(i), which).tolist() == ox.occ4(int(i), which).tolist(), (name, which, i)
+        # the packed reference the index keeps for mate rescue
+        assert np.array_equal(ix.ref(), t), name
+        if len(t) > 20:
+            assert np.array_equal(ix.ref(len(t) - 17, 17), t[-17:])
         ix.close()
 
 
@@ -108,10 +112,15 @@ def test_index_save_load_roundtrip_and_corruption(rng, tmp_path):
         assert np.array_equal(ix.sa_samples(which), iy.sa_samples(which))
         for i in rng.integers(0, len(t) + 2, 50):
             assert ix.occ(int(i), which).tolist() == iy.occ(int(i), which).tolist()
+    assert np.array_equal(iy.ref(), t)
+    with pytest.raises(bw.BwfmError):
+        iy.ref(len(t) - 5, 6)
     iy.close()
     raw = bytearray(open(path, "rb").read())
     # a flipped byte in a rank line, a truncated file, another file format
     for name, data in (("flip", raw[:200] + bytes([raw[200] ^ 1]) + raw[201:]), ("short", raw[:-9]),
+                       ("flip_ref", raw[:-20] + bytes([raw[-20] ^ 4]) + raw[-19:]),
+                       ("version", raw[:8] + bytes([1, 0, 0, 0]) + raw[12:]),
                        ("magic", b"NOTANIDX" + raw[8:])):
         bad = str(tmp_path / f"{name}.bwfm")
         open(bad, "wb").write(bytes(data))
