@@ -34,17 +34,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "aligned reads/s (2x100bp, <=4 diffs) on 1 MI355X, batched vs plain; p99 ms"
 HBM_PEAK_GBS = 8000.0
+# 32-bit integer vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one op per lane per clock
+INT_ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# integer operations of the affine local-alignment recurrence per cell: the
+# gap along the reference (2 subtractions, 1 max), the gap along the read
+# (same), the substitution score (compare, select, add) and H (3 maxes)
+RESCUE_OPS_PER_CELL = 12
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    """Hash of the search kernel's sources; byte counters are valid only for it."""
+# sources each profiled kernel is built from; a counter summary is valid only for them
+KERNEL_SOURCES = {"k_align_persistent": ("bwfm.hip", "bwfm_internal.h"),
+                  "k_rescue": ("rescue.hip", "bwfm_internal.h")}
+
+
+def kernel_source_hash(kernel: str = "k_align_persistent") -> str:
+    """Hash of a kernel's sources; byte counters are valid only for it."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("bwfm.hip", "bwfm_internal.h"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1505_07855_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -63,12 +74,50 @@ def traffic_from_profiles(kernel: str):
         for line in fh:
             if line.startswith("bench-traffic:"):
                 rec = dict(kv.split("=", 1) for kv in line.split()[1:])
-    if not rec or rec.get("kernel") != kernel or rec.get("source") != kernel_source_hash():
+    if not rec or rec.get("kernel") != kernel or rec.get("source") != kernel_source_hash(kernel):
         return None
     cb = float(rec["copy_bytes"])
     fetch = float(rec["fetch_kib"]) * 1024 * cb / (float(rec["copy_fetch_kib"]) * 1024)
     write = float(rec["write_kib"]) * 1024 * cb / (float(rec["copy_write_kib"]) * 1024)
     return fetch + write
+
+
+def rescue_leg(bw, torch, ix, ends, prs, n, w, stream, launches, n_ref):
+    """Mate rescue over the step's pair records, timed alone with HIP events
+    on its stream; the work is m x window cells per rescued-for pair."""
+    out = bw.rescue_mates(ix, ends[0], ends[1], prs, w["lo"], w["hi"], max_len=100, stream=stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(launches):
+        bw.rescue_mates(ix, ends[0], ends[1], prs, w["lo"], w["hi"], max_len=100, stream=stream, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / launches
+    res = bw.rescue_numpy(out)[:n]
+    pr = bw.pairs_numpy(prs)[:n]
+    f = pr["flags"]
+    m1, m2 = (f & bw.PF_MAPPED1) != 0, (f & bw.PF_MAPPED2) != 0
+    cand = ((f & bw.PF_PAIRED) == 0) & (m1 | m2)
+    a1 = m1 & (~m2 | (pr["score1"] <= pr["score2"]))
+    pa = np.where(a1, pr["pos1"], pr["pos2"]).astype(np.int64)
+    la = np.where(a1, pr["len1"], pr["len2"]).astype(np.int64)
+    sa = np.where(a1, pr["strand1"], pr["strand2"])
+    w_fwd = np.minimum(pa + w["hi"], n_ref) - pa
+    w1 = np.minimum(pa + la, n_ref)
+    w_rev = w1 - np.maximum(w1 - w["hi"], 0)
+    width = np.clip(np.where(sa == 0, w_fwd, w_rev), 0, None)
+    lens = [np.diff(e[1].cpu().numpy()) for e in ends]
+    m = np.where(a1, lens[1], lens[0])
+    cells = float((m * width)[cand].sum())
+    cps = cells / (ms / 1e3)
+    achieved = cps * RESCUE_OPS_PER_CELL / 1e12
+    return {"kernel": "k_rescue", "candidates": int(cand.sum()), "rescued": int((res["end"] != 0).sum()),
+            "avg_launch_ms": ms, "launches": launches, "cells": cells, "gcups": cps / 1e9,
+            "pairs_per_s": n / (ms / 1e3),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": INT_ALU_PEAK_TOPS, "unit": "Tops/s",
+                         "frac": achieved / INT_ALU_PEAK_TOPS, "traffic": traffic_from_profiles("k_rescue"),
+                         "ops_per_cell": RESCUE_OPS_PER_CELL}}
 
 
 def main():
@@ -84,6 +133,8 @@ def main():
     ap.add_argument("--line-bytes", type=int, default=64)
     ap.add_argument("--waves-per-simd", type=int, default=0, help="batched-form residency (0 = autotuned)")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the autotuner (most waves that fit)")
+    ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue measurement")
+    ap.add_argument("--rescue-launches", type=int, default=10)
     ap.add_argument("--steps-plain", type=int, default=0, help="steps for the plain form (default: --steps)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -220,6 +271,12 @@ def main():
     value = batched["aligned_reads_per_s"]
     kernel_ms = batched["kernel_ms"]
 
+    rescue = None
+    if not args.no_rescue:
+        rescue = rescue_leg(bw, torch, ix, ends, b_out[2], n, w, stream, args.rescue_launches, len(g.seq))
+        log(f"rescue: {rescue['candidates']} candidates, {rescue['rescued']} rescued, "
+            f"{rescue['avg_launch_ms']:.3f} ms per launch")
+
     roofline = None
     cpu = None
     if want_cpu:
@@ -288,7 +345,7 @@ def main():
         "aligned_fraction": aligned / n_reads, "paired_fraction": batched["paired_fraction"],
         "plain": {k: v for k, v in plain.items()}, "batched": {k: v for k, v in batched.items()},
         "batched_eager": {k: v for k, v in eager.items()}, "autotune": tune,
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "rescue": rescue,
     }
     print(json.dumps(out), flush=True)
 
