@@ -76,6 +76,7 @@ def _lib(name: str):
             L.orc_rescue_mates.argtypes = [i64, P, i64, P, P, P, P, P, i32, i32, i32, i32, i32, i32, i32, P]
             L.orc_local_best.argtypes = [P, i32, P, i32, i32, i32, i32, i32, i32, P, P]
             L.orc_local_best.restype = i32
+            L.orc_mapq.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, i32, P, P, i32, i32, i32, i32, P]
             L.orc_max_diff_rule.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
             L.orc_max_diff_rule.restype = ctypes.c_int
             L.orc_estimate_insert.argtypes = [P, i64, P]
@@ -275,6 +276,29 @@ def local_best(q, r, e_min: int = 0, match: int = 1, mismatch: int = 4, gap_open
     sc = _lib("oracle").orc_local_best(_p(qa), len(qa), _p(ra), len(ra), e_min, match, mismatch, gap_open, gap_extend,
                                        ctypes.byref(je), ctypes.byref(js))
     return sc, je.value, js.value
+
+
+# mapping-quality constants (a reading): phred weight of a tier-2 placement,
+# single-end cap, cap when the best hits spend the whole budget, proper-pair cap
+MAPQ_DEFAULTS = dict(q_tier=22, q_unique=37, q_budget=25, q_pair=60)
+
+
+def mapq(r1: AlnResult, r2: AlnResult | None, pairs: np.ndarray, rescue: np.ndarray | None = None,
+         budgets1=None, budgets2=None, max_diff: int = 4, q_tier: int = 22, q_unique: int = 37, q_budget: int = 25,
+         q_pair: int = 60) -> np.ndarray:
+    """uint8 [n_pairs, 2]: MAPQ of end 1 and end 2 of every pair (see oracle.c)."""
+    n = len(r1.hit_off) - 1
+    out = np.zeros((n, 2), np.uint8)
+    pr = np.ascontiguousarray(pairs)
+    b1 = None if budgets1 is None else np.ascontiguousarray(budgets1, np.uint8)
+    b2 = None if budgets2 is None else np.ascontiguousarray(budgets2, np.uint8)
+    rs = None if rescue is None else np.ascontiguousarray(rescue)
+    L = _lib("oracle")
+    L.orc_mapq(n, _p(r1.hit_off), _p(r1.hits), _p(r1.c1), _p(r1.c2), _p(r1.status), _p(b1) if b1 is not None else None,
+               _p(r2.hit_off) if r2 else None, _p(r2.hits) if r2 else None, _p(r2.c1) if r2 else None,
+               _p(r2.c2) if r2 else None, _p(r2.status) if r2 else None, _p(b2) if b2 is not None else None,
+               max_diff, _p(pr), _p(rs) if rs is not None else None, q_tier, q_unique, q_budget, q_pair, _p(out))
+    return out
 
 
 def max_diff_rule(L: int, err: float = 0.02, thres: float = 0.04) -> int:

@@ -60,6 +60,11 @@
  *    strand1, pos1, len1, pos2, len2).  Without one, each end takes its
  *    single-end primary, the minimum (score, diffs, strand, pos, len).
  *
+ *  - Mate rescue and mapping quality, the rest of the pairing step that
+ *    closes the pipeline (section 3.7); the paper gives no details, so both
+ *    are readings, stated where they are computed (orc_rescue_mates,
+ *    orc_mapq).
+ *
  * The search visits children in a fixed order -- match, mismatches by base,
  * insertion, deletions by base -- and, in BEST mode, drops a state whose
  * score plus min(s_mm, s_gapo, s_gape) * D[i] exceeds best-so-far + s_mm.
@@ -1186,4 +1191,82 @@ int orc_local_best(const uint8_t *q, int m, const uint8_t *r, int w, int e_min, 
                    int *jstart)
 {
     return local_best(q, m, r, w, e_min, a, b, o, e, jend, jstart);
+}
+
+/* ------------------------------------------------------------------ */
+/* Mapping quality                                                      */
+/* ------------------------------------------------------------------ */
+
+/*
+ * MAPQ, phred-scaled confidence that an end's reported placement is right
+ * (a reading: the paper has no such output).  Each placement the search
+ * reported weighs 1 when it is in tier 1 and r = 10^(-q_tier / 10) when it is
+ * in tier 2 (one mismatch-penalty step worse); the chosen placement's share
+ * of the total weight c1 + c2 r is the probability it is right:
+ *
+ *     P = w / (c1 + c2 r),  w = 1 (its score is the read's best) or r,
+ *     Q_se = round(-10 log10(1 - P)), at most q_unique; q_unique when P = 1;
+ *
+ * with Q_se at most q_budget when every tier-1 hit spends the read's whole
+ * difference budget (a placement just past the budget was not searched),
+ * and 0 for an end that is not placed or whose candidate set overflowed.
+ * An end of a proper pair is wrong only if both placements are, so both
+ * ends of a proper pair get min(q_pair, Q_se(end 1) + Q_se(end 2)).  A
+ * rescued mate is placed relative to its anchor and takes the anchor's
+ * Q_se.  Rounding is half up, in double precision.
+ */
+static int mapq_se(const orc_pair *pr, int e, const uint64_t *hoff, const orc_hit *hits, const uint32_t *c1,
+                   const uint32_t *c2, const uint8_t *st, int64_t p, int budget, double r, int q_unique,
+                   int q_budget)
+{
+    const uint32_t pos = e == 1 ? pr->pos1 : pr->pos2;
+    const int score = e == 1 ? pr->score1 : pr->score2;
+    if (pos == 0xFFFFFFFFu || (st[p] & 2) || c1[p] == 0 || hoff[p + 1] == hoff[p]) return 0;
+    const orc_hit *h = hits + hoff[p];
+    const int64_t nh = (int64_t)(hoff[p + 1] - hoff[p]);
+    /* tier 1: the leading hits of the best score (hits are ordered by score first) */
+    int dmin = 1 << 30;
+    for (int64_t i = 0; i < nh && h[i].score == h[0].score; i++) {
+        const int d = h[i].n_mm + h[i].n_gapo + h[i].n_gape;
+        if (d < dmin) dmin = d;
+    }
+    const double w = score == h[0].score ? 1.0 : r;
+    const double den = (double)c1[p] + (double)c2[p] * r;
+    int q;
+    if (den - w <= 0.0) {
+        q = q_unique;
+    } else {
+        q = (int)floor(-10.0 * log10((den - w) / den) + 0.5);
+        if (q > q_unique) q = q_unique;
+        if (q < 0) q = 0;
+    }
+    if (dmin >= budget && q > q_budget) q = q_budget;
+    return q;
+}
+
+void orc_mapq(int64_t n_pairs, const uint64_t *hoff1, const orc_hit *hits1, const uint32_t *c1_1,
+              const uint32_t *c2_1, const uint8_t *st1, const uint8_t *bud1, const uint64_t *hoff2,
+              const orc_hit *hits2, const uint32_t *c1_2, const uint32_t *c2_2, const uint8_t *st2,
+              const uint8_t *bud2, int32_t max_diff, const orc_pair *pairs, const orc_rescue *rescue,
+              int32_t q_tier, int32_t q_unique, int32_t q_budget, int32_t q_pair, uint8_t *out)
+{
+    const double r = pow(10.0, -q_tier / 10.0);
+    for (int64_t p = 0; p < n_pairs; p++) {
+        const orc_pair *pr = &pairs[p];
+        int q1 = mapq_se(pr, 1, hoff1, hits1, c1_1, c2_1, st1, p, bud1 ? bud1[p] : max_diff, r, q_unique, q_budget);
+        int q2 = hoff2 ? mapq_se(pr, 2, hoff2, hits2, c1_2, c2_2, st2, p, bud2 ? bud2[p] : max_diff, r, q_unique,
+                                 q_budget)
+                       : 0;
+        int o1 = q1, o2 = q2;
+        if (pr->flags & 1) {
+            const int s = q1 + q2 < q_pair ? q1 + q2 : q_pair;
+            o1 = o2 = s;
+        } else if (rescue && rescue[p].end == 2) {
+            o2 = q1;
+        } else if (rescue && rescue[p].end == 1) {
+            o1 = q2;
+        }
+        out[2 * p] = (uint8_t)o1;
+        out[2 * p + 1] = (uint8_t)o2;
+    }
 }

@@ -585,3 +585,79 @@ def test_rescue_anchor_choice_and_insert_bounds(rng):
     head = g[0:L].copy()
     out = oracle.rescue(g, e_rand, (head, np.array([0, L], np.uint64)), rec, 60, hi)[0]
     assert (out["end"], out["pos"], out["strand"], out["insert"]) == (2, 0, 0, 10 + L)
+
+
+# ------------------------------------------------------------------ mapping quality
+
+def _one_read_result(c1, c2, hits, status=oracle.ST_HIT):
+    """An AlnResult of one read with the given tiers and hit list
+    [(score, n_mm, n_gapo, n_gape), ...] (ordered by score)."""
+    h = np.zeros(len(hits), oracle.HIT_DTYPE)
+    for i, (sc, mm, go, ge) in enumerate(hits):
+        h[i]["score"], h[i]["n_mm"], h[i]["n_gapo"], h[i]["n_gape"] = sc, mm, go, ge
+        h[i]["k"], h[i]["l"], h[i]["len"] = 10 + i, 10 + i, 50
+    return oracle.AlnResult(np.array([0, len(hits)], np.uint64), h, np.array([c1], np.uint32),
+                            np.array([c2], np.uint32), np.array([status], np.uint8), np.zeros(1, oracle.COUNT_DTYPE))
+
+
+def _se_q(c1, c2, hits, pair_score=None, max_diff=4, placed=True, status=oracle.ST_HIT):
+    r = _one_read_result(c1, c2, hits, status)
+    pr = _pair_rec(1000 if placed else 0xFFFFFFFF, 50, 0, hits[0][0] if pair_score is None else pair_score,
+                   0xFFFFFFFF, 0, 0, 0, 2 if placed else 0)
+    return int(oracle.mapq(r, None, pr, max_diff=max_diff)[0, 0])
+
+
+def test_mapq_closed_forms():
+    # unique best placement, nothing in tier 2: P = 1, the single-end cap
+    assert _se_q(1, 0, [(3, 1, 0, 0)]) == 37
+    # one tier-2 placement: 1 - P = r / (1 + r), Q = 10 log10(1 + 10^2.2) = 22.03
+    assert _se_q(1, 1, [(0, 0, 0, 0), (3, 1, 0, 0)]) == 22
+    # ten of them: 1 - P = 10 r / (1 + 10 r), Q = 10 log10(1 + 10^1.2) = 12.27
+    assert _se_q(1, 10, [(0, 0, 0, 0), (3, 1, 0, 0)]) == 12
+    # two equal best placements: P = 1/2, Q = 10 log10 2 = 3.01; three: 10 log10 1.5 = 1.76
+    assert _se_q(2, 0, [(0, 0, 0, 0), (0, 0, 0, 0)]) == 3
+    assert _se_q(3, 0, [(0, 0, 0, 0)] * 3) == 2
+    # the chosen placement itself in tier 2 (say, the one that pairs): P = r / (1 + r),
+    # 1 - P = 1 / (1 + r), Q = 10 log10(1 + 10^-2.2) = 0.027
+    assert _se_q(1, 1, [(0, 0, 0, 0), (3, 1, 0, 0)], pair_score=3) == 0
+    # every best hit spends the whole budget: at most 25; one hit under it lifts the cap
+    assert _se_q(1, 0, [(12, 4, 0, 0)]) == 25
+    assert _se_q(1, 0, [(12, 2, 1, 1)]) == 25  # diffs = mismatches + gap opens + extensions
+    assert _se_q(2, 0, [(12, 4, 0, 0), (12, 3, 0, 0)]) == 3
+    assert _se_q(1, 0, [(12, 4, 0, 0)], max_diff=5) == 37
+    # not placed, or an overflowed candidate set: 0
+    assert _se_q(1, 0, [(0, 0, 0, 0)], placed=False) == 0
+    assert _se_q(0xFFFFFFFF, 0xFFFFFFFF, [(0, 0, 0, 0)], status=oracle.ST_OVERFLOW) == 0
+
+
+def test_mapq_pairs_and_rescue():
+    a = _one_read_result(1, 0, [(0, 0, 0, 0)])              # Q_se 37
+    b = _one_read_result(2, 0, [(0, 0, 0, 0), (0, 0, 0, 0)])  # Q_se 3
+    # a proper pair: both ends get min(60, q1 + q2)
+    pr = _pair_rec(1000, 50, 0, 0, 1200, 50, 1, 0, 1 | 2 | 4)
+    assert oracle.mapq(a, a, pr).tolist() == [[60, 60]]
+    assert oracle.mapq(b, a, pr).tolist() == [[40, 40]]
+    assert oracle.mapq(b, b, pr).tolist() == [[6, 6]]
+    # not paired: each end its own
+    pr = _pair_rec(1000, 50, 0, 0, 9000, 50, 1, 0, 2 | 4)
+    assert oracle.mapq(a, b, pr).tolist() == [[37, 3]]
+    # a rescued mate takes its anchor's single-end quality
+    pr = _pair_rec(1000, 50, 0, 0, 0xFFFFFFFF, 0, 0, 0, 2)
+    resc = np.zeros(1, oracle.RESCUE_DTYPE)
+    resc["end"] = 2
+    assert oracle.mapq(b, a, pr, rescue=resc).tolist() == [[3, 3]]
+    assert oracle.mapq(b, a, pr).tolist() == [[3, 0]]
+    # per-read budgets replace the uniform one
+    c = _one_read_result(1, 0, [(6, 2, 0, 0)])
+    pr = _pair_rec(1000, 50, 0, 6, 0xFFFFFFFF, 0, 0, 0, 2)
+    assert oracle.mapq(c, None, pr, budgets1=np.array([2], np.uint8)).tolist() == [[25, 0]]
+    assert oracle.mapq(c, None, pr, budgets1=np.array([3], np.uint8)).tolist() == [[37, 0]]
+
+
+def test_mapq_monotone_in_competition():
+    """More competing placements never raise the quality."""
+    qs = [[_se_q(c1, c2, [(0, 0, 0, 0), (3, 1, 0, 0)]) for c2 in range(0, 40)] for c1 in (1, 2, 5)]
+    for row in qs:
+        assert all(x >= y for x, y in zip(row, row[1:]))
+    for a_, b_ in zip(qs, qs[1:]):
+        assert all(x >= y for x, y in zip(a_, b_))
