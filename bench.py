@@ -82,9 +82,10 @@ def traffic_from_profiles(kernel: str):
     return fetch + write
 
 
-def rescue_leg(bw, torch, ix, ends, prs, n, w, stream, launches, n_ref):
-    """Mate rescue over the step's pair records, timed alone with HIP events
-    on its stream; the work is m x window cells per rescued-for pair."""
+def rescue_leg(bw, torch, ix, ends, results, prs, n, w, stream, launches, n_ref, max_diff):
+    """Mate rescue, then mapping quality, over the step's pair records, each
+    timed alone with HIP events on its stream; rescue work is m x window cells
+    per rescued-for pair."""
     out = bw.rescue_mates(ix, ends[0], ends[1], prs, w["lo"], w["hi"], max_len=100, stream=stream)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -112,12 +113,31 @@ def rescue_leg(bw, torch, ix, ends, prs, n, w, stream, launches, n_ref):
     cells = float((m * width)[cand].sum())
     cps = cells / (ms / 1e3)
     achieved = cps * RESCUE_OPS_PER_CELL / 1e12
+    # mapping quality of both ends over the same records (a streaming kernel)
+    mq = bw.mapq(results[0], results[1], prs, rescue=out, max_diff=max_diff, stream=stream)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(launches):
+        bw.mapq(results[0], results[1], prs, rescue=out, max_diff=max_diff, stream=stream, out=mq)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    mq_ms = ev0.elapsed_time(ev1) / launches
+    # per pair: its record (24 B), rescue record (16 B), two MAPQ bytes, and per
+    # end an offset (8 B), c1, c2, status (9 B) and at least one hit (16 B)
+    mq_bytes = n * (24 + 16 + 2 + 2 * (8 + 9 + 16))
+    mq_gbs = mq_bytes / (mq_ms / 1e3) / 1e9
+    q = mq.cpu().numpy()[:n]
     return {"kernel": "k_rescue", "candidates": int(cand.sum()), "rescued": int((res["end"] != 0).sum()),
             "avg_launch_ms": ms, "launches": launches, "cells": cells, "gcups": cps / 1e9,
             "pairs_per_s": n / (ms / 1e3),
             "roofline": {"bound": "alu", "achieved": achieved, "peak": INT_ALU_PEAK_TOPS, "unit": "Tops/s",
                          "frac": achieved / INT_ALU_PEAK_TOPS, "traffic": traffic_from_profiles("k_rescue"),
-                         "ops_per_cell": RESCUE_OPS_PER_CELL}}
+                         "ops_per_cell": RESCUE_OPS_PER_CELL},
+            "mapq": {"kernel": "k_mapq", "avg_launch_ms": mq_ms, "launches": launches,
+                     "q60_fraction": float((q == 60).mean()), "q0_fraction": float((q == 0).mean()),
+                     "roofline": {"bound": "hbm", "achieved": mq_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": mq_gbs / HBM_PEAK_GBS, "traffic": None,
+                                  "bytes_per_launch": mq_bytes}}}
 
 
 def main():
@@ -273,7 +293,8 @@ def main():
 
     rescue = None
     if not args.no_rescue:
-        rescue = rescue_leg(bw, torch, ix, ends, b_out[2], n, w, stream, args.rescue_launches, len(g.seq))
+        rescue = rescue_leg(bw, torch, ix, ends, b_out[:2], b_out[2], n, w, stream, args.rescue_launches, len(g.seq),
+                            configs.PARAMS["C2"]["max_diff"])
         log(f"rescue: {rescue['candidates']} candidates, {rescue['rescued']} rescued, "
             f"{rescue['avg_launch_ms']:.3f} ms per launch")
 

@@ -367,6 +367,44 @@ int bwfm_rescue_mates(const bwfm_index *idx, const bwfm_reads *end1, const bwfm_
                       bwfm_rescue *out, void *hip_stream);
 
 /* ------------------------------------------------------------------ */
+/* Mapping quality (the pairing step of section 3.7 reports one per end; */
+/* the paper gives no formula, so this is a stated reading)             */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t q_tier;    /* phred weight of a tier-2 placement against a tier-1 one, 1..60 */
+    int32_t q_unique;  /* single-end cap (a unique placement), 0..60 */
+    int32_t q_budget;  /* cap when every tier-1 hit spends the whole budget, 0..60 */
+    int32_t q_pair;    /* cap for the ends of a proper pair, 0..254 */
+} bwfm_mapq_params;
+
+#define BWFM_MAPQ_DEFAULTS {22, 37, 25, 60}
+
+/*
+ * MAPQ of both ends of n_pairs pairs.  Each placement the search reported
+ * weighs 1 in tier 1 and r = 10^(-q_tier / 10) in tier 2; an end placed by a
+ * hit of its read's best score has P = 1 / (c1 + c2 r) of being right (r /
+ * (c1 + c2 r) when placed by a tier-2 hit), and Q = round(-10 log10(1 - P))
+ * (half up, double precision), at most q_unique, and at most q_budget when
+ * every hit of the best score has diffs (mismatches + gap opens + gap
+ * extensions) >= the read's budget.  0 for an end not placed in its pair
+ * record or whose candidate set overflowed.  Both ends of a proper pair get
+ * min(q_pair, Q1 + Q2); an end rescued by bwfm_rescue_mates takes its
+ * anchor's Q.
+ *   r1, r2:  the alignments the pairs were made from (r2 NULL: single-end,
+ *            end 2 gets 0); windows of a larger result are fine.
+ *   budget1, budget2: device, per-read difference budgets, or NULL: max_diff.
+ *   pairs:   device, n_pairs records from bwfm_pair_reads.
+ *   rescue:  device, n_pairs records from bwfm_rescue_mates, or NULL.
+ *   mp:      NULL = BWFM_MAPQ_DEFAULTS.
+ *   out:     device, 2 n_pairs bytes: end 1's then end 2's MAPQ per pair.
+ * Allocates nothing and does not wait.  Errors: E_INVAL, E_DEVICE.
+ */
+int bwfm_mapq(uint32_t n_pairs, const bwfm_aln_result *r1, const bwfm_aln_result *r2, const uint8_t *budget1,
+              const uint8_t *budget2, uint32_t max_diff, const bwfm_pair *pairs, const bwfm_rescue *rescue,
+              const bwfm_mapq_params *mp, uint8_t *out, void *hip_stream);
+
+/* ------------------------------------------------------------------ */
 /* Captured step: one batch of pairs through align, locate and pairing  */
 /* as a single hipGraph replay                                          */
 /* ------------------------------------------------------------------ */

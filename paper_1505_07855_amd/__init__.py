@@ -94,6 +94,10 @@ class _RescueParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("match", "mismatch", "gap_open", "gap_extend", "min_score")]
 
 
+class _MapqParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("q_tier", "q_unique", "q_budget", "q_pair")]
+
+
 class _PipeParams(ctypes.Structure):
     _fields_ = [("max_pairs", ctypes.c_uint32), ("max_len", ctypes.c_uint32), ("max_bases", ctypes.c_uint64),
                 ("hit_capacity", ctypes.c_uint64), ("pos_capacity", ctypes.c_uint64), ("paired", ctypes.c_int32)]
@@ -113,7 +117,7 @@ SYMBOLS = ("bwfm_build_index", "bwfm_index_upload", "bwfm_index_free", "bwfm_ind
            "bwfm_server_destroy", "bwfm_index_save", "bwfm_index_load", "bwfm_pipeline_create",
            "bwfm_pipeline_set_reads", "bwfm_pipeline_run", "bwfm_pipeline_finish", "bwfm_pipeline_outputs",
            "bwfm_pipeline_destroy", "bwfm_pipeline_bind_reads", "bwfm_pipeline_set_count",
-           "bwfm_build_index_device", "bwfm_index_get_ref", "bwfm_rescue_mates")
+           "bwfm_build_index_device", "bwfm_index_get_ref", "bwfm_rescue_mates", "bwfm_mapq")
 
 
 def lib():
@@ -146,6 +150,7 @@ def lib():
             "bwfm_index_occ": ([P, c_int, u64, P], c_int),
             "bwfm_index_get_ref": ([P, u64, u64, P], c_int),
             "bwfm_rescue_mates": ([P, P, P, u32, P, P, P, P, P], c_int),
+            "bwfm_mapq": ([u32, P, P, P, P, u32, P, P, P, P, P], c_int),
             "bwfm_align_batch": ([P, P, P, P, P], c_int),
             "bwfm_align_batch_counted": ([P, P, P, P, P, P, P], c_int),
             "bwfm_locate": ([P, u32, P, u32, P, P, u64, P], c_int),
@@ -474,6 +479,27 @@ def rescue_mates(index: Index, end1, end2, pairs, lo: int, hi: int, max_len: int
     rp = (params or RescueParams())._c()
     _check(lib().bwfm_rescue_mates(index.handle, ctypes.byref(r1), ctypes.byref(r2), n, _dptr(pairs) if n else None,
                                    ctypes.byref(pp), ctypes.byref(rp), _dptr(out), _stream_ptr(stream)))
+    return out
+
+
+def mapq(r1: AlignResult, r2: AlignResult | None, pairs, rescue=None, budgets1=None, budgets2=None,
+         max_diff: int = 4, q_tier: int = 22, q_unique: int = 37, q_budget: int = 25, q_pair: int = 60,
+         stream=None, out=None):
+    """MAPQ of both ends of every pair (bwfm_mapq): device uint8 [n, 2].
+    pairs/rescue: device records from pair_reads / rescue_mates; budgets:
+    device uint8 per read or None (max_diff for all).  Does not synchronise."""
+    torch = _torch()
+    n = r1.n_reads
+    if out is None:
+        out = torch.empty((max(n, 1), 2), dtype=torch.uint8, device=r1.hit_offsets.device)
+    a = r1._c()
+    b = r2._c() if r2 is not None else None
+    mp = _MapqParams(q_tier, q_unique, q_budget, q_pair)
+    _check(lib().bwfm_mapq(n, ctypes.byref(a), ctypes.byref(b) if b is not None else None,
+                           _dptr(budgets1) if budgets1 is not None else None,
+                           _dptr(budgets2) if budgets2 is not None else None, max_diff,
+                           _dptr(pairs) if n else None, _dptr(rescue) if rescue is not None else None,
+                           ctypes.byref(mp), _dptr(out), _stream_ptr(stream)))
     return out
 
 

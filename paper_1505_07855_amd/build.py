@@ -31,7 +31,7 @@ def build() -> str:
     o = os.path.join(OUT, "index_host.o")
     _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "index_host.cpp"), "-o", o])
     objs.append(o)
-    for src in ("bwfm.hip", "index_gpu.hip", "rescue.hip", "server.cpp"):
+    for src in ("bwfm.hip", "index_gpu.hip", "rescue.hip", "mapq.hip", "server.cpp"):
         o = os.path.join(OUT, os.path.splitext(src)[0] + ".o")
         _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)

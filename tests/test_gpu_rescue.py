@@ -1,5 +1,5 @@
-"""GPU parity of mate rescue (bwfm_rescue_mates) against the oracle, bit for
-bit on every record field.  Pair records fed to both sides come from the
+"""GPU parity of mate rescue (bwfm_rescue_mates) and mapping quality
+(bwfm_mapq) against the oracle, bit for bit on every record field.  Pair records fed to both sides come from the
 generator's truth (every scenario: proper, one end mapped, both mapped
 apart, none, anchors displaced or at the reference ends) or from the oracle's
 own alignment, locate and pairing of a seeded batch; nothing the GPU computes
@@ -194,3 +194,87 @@ def test_rescue_edge_cases(genome):
         with pytest.raises(bw.BwfmError):
             bw.rescue_mates(ix, ed, ed, recd, **args)
     assert n_ref > 0
+
+
+# ------------------------------------------------------------------ mapping quality
+
+def _upload_result(o):
+    """The oracle's alignment result as device tensors in the library's layout."""
+    hits = o.hits.view(np.uint8).reshape(-1, 16) if len(o.hits) else np.zeros((1, 16), np.uint8)
+    return bw.AlignResult(_dev(o.hit_off.view(np.int64)), _dev(hits.view(np.int32).reshape(-1, 4)),
+                          _dev(o.c1.view(np.int32)), _dev(o.c2.view(np.int32)), _dev(o.status), len(o.c1))
+
+
+def _oracle_chain(g, pairs, budgets=None, params=None):
+    ox = oracle.Index(g.seq)
+    op = oracle.Params(**(params or configs.PARAMS["C2"]))
+    o = [oracle.align(ox, e.bases, e.offsets, op, max_diff=budgets[k] if budgets else None, threads=8)
+         for k, e in enumerate((pairs.end1, pairs.end2))]
+    loc = [oracle.locate(ox, r.hits, configs.MAX_OCC) for r in o]
+    w = configs.PAIR_WINDOW
+    rec = oracle.pair(o[0], loc[0][0], loc[0][1], o[1], loc[1][0], loc[1][1], w["lo"], w["hi"], w["mu"])
+    resc = oracle.rescue(g.seq, (pairs.end1.bases, pairs.end1.offsets), (pairs.end2.bases, pairs.end2.offsets), rec,
+                         w["lo"], w["hi"])
+    return o, rec, resc
+
+
+@pytest.mark.parametrize("genome_kind", ["c2", "close_repeats"])
+def test_mapq_kernel_on_oracle_results(genome_kind):
+    """The kernel alone, fed the oracle's own alignments, pairs and rescues;
+    the close-repeat genome gives many reads several best placements and a
+    second tier."""
+    if genome_kind == "c2":
+        g = configs.c2_genome(2_000_000, seed=101)
+    else:
+        g = gen.genome_repeats(105, 2_000_000, gc=0.41, repeat_frac=0.6, n_fam=200, min_len=300, max_len=3000,
+                               div_lo=0.0, div_hi=0.03)
+    pairs = configs.c2_pairs(g, 3000, seed=102)
+    o, rec, resc = _oracle_chain(g, pairs)
+    r1, r2 = _upload_result(o[0]), _upload_result(o[1])
+    recd, rescd = _dev(rec.view(np.uint8)), _dev(resc.view(np.uint8))
+    md = configs.PARAMS["C2"]["max_diff"]
+    for rs, kw in [(None, {}), (resc, {}), (resc, dict(q_tier=10, q_unique=60, q_budget=30, q_pair=99))]:
+        got = bw.mapq(r1, r2, recd, rescue=rescd if rs is not None else None, max_diff=md, **kw).cpu().numpy()
+        want = oracle.mapq(o[0], o[1], rec, rescue=rs, max_diff=md, **kw)
+        assert np.array_equal(got[:len(want)], want), kw
+    # single-end
+    got = bw.mapq(r1, None, recd, max_diff=md).cpu().numpy()
+    assert np.array_equal(got[:len(rec)], oracle.mapq(o[0], None, rec, max_diff=md))
+    q = oracle.mapq(o[0], o[1], rec, rescue=resc, max_diff=md)
+    assert len(np.unique(q)) >= 4
+
+
+def test_mapq_full_chain_on_gpu_with_budgets():
+    """Align, pair, rescue and MAPQ on the GPU against the oracle's chain, with
+    per-read budgets (C3-shaped lengths)."""
+    g = configs.c2_genome(1_500_000, seed=103)
+    pairs = configs.c3_pairs(g, 2000, seed=104)
+    budgets = [np.array([oracle.max_diff_rule(int(L)) for L in np.diff(e.offsets)], np.uint8)
+               for e in (pairs.end1, pairs.end2)]
+    o, rec, resc = _oracle_chain(g, pairs, budgets=budgets, params=configs.PARAMS["C3"])
+    ix = bw.Index(g.seq, **configs.LAYOUT["C3"]).upload()
+    p = bw.Params(**configs.PARAMS["C3"])
+    res = []
+    for e, b in zip((pairs.end1, pairs.end2), budgets):
+        res.append(bw.align_batch(ix, _dev(e.bases), _dev(e.offsets.view(np.int64)), p, max_diff=_dev(b),
+                                  max_len=150))
+    w = configs.PAIR_WINDOW
+    gp = bw.pair_reads(ix, res[0], res[1], w["lo"], w["hi"], w["mu"], configs.MAX_OCC)
+    gr = bw.rescue_mates(ix, _end_dev(pairs.end1), _end_dev(pairs.end2), gp, w["lo"], w["hi"], max_len=150)
+    gq = bw.mapq(res[0], res[1], gp, rescue=gr, budgets1=_dev(budgets[0]), budgets2=_dev(budgets[1])).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(bw.pairs_numpy(gp).view(np.uint8), rec.view(np.uint8))
+    assert np.array_equal(bw.rescue_numpy(gr)[:len(resc)].view(np.uint8), resc.view(np.uint8))
+    want = oracle.mapq(o[0], o[1], rec, rescue=resc, budgets1=budgets[0], budgets2=budgets[1])
+    assert np.array_equal(gq[:len(want)], want)
+
+
+def test_mapq_argument_errors():
+    o = oracle.AlnResult(np.array([0, 0], np.uint64), np.zeros(0, oracle.HIT_DTYPE), np.zeros(1, np.uint32),
+                         np.zeros(1, np.uint32), np.zeros(1, np.uint8), np.zeros(1, oracle.COUNT_DTYPE))
+    r = _upload_result(o)
+    recd = _dev(np.zeros(1, oracle.PAIR_DTYPE).view(np.uint8))
+    for kw in [dict(q_tier=0), dict(q_unique=61), dict(q_pair=300)]:
+        with pytest.raises(bw.BwfmError):
+            bw.mapq(r, None, recd, **kw)
+    assert bw.mapq(r, None, recd).cpu().numpy().tolist() == [[0, 0]]
