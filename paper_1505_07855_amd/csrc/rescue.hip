@@ -3,16 +3,19 @@
 // bounds allow around its mate's primary (section 3.7 closes the pipeline
 // with BWA's pairing step, of which this is the rescue part).
 //
-// One wave per rescued pair.  The mate's m bases are the rows of the
-// dynamic-programming matrix, R consecutive rows per lane; the window's
-// reference bases are its columns.  The wave sweeps the columns in skewed
-// order -- lane l works on column t - l at step t -- so each lane receives
-// the values of the row above its first row (H and F of the previous lane's
-// last row, with the window columns their alignments start at) one step
-// after they were made, through a one-lane shift.  Every cell is computed
-// once; a step costs R cells per lane.  The window is decoded from the packed
-// reference into LDS first.  Work per pair is m x window cells, a few hundred
-// steps: the kernel is bound by integer ALU work, not memory.
+// One wave per rescued pair (a wave takes a few pair records and works
+// through those that need a rescue, one after another).  The mate's m bases
+// are the rows of the dynamic-programming matrices, R consecutive rows per
+// lane; the window's reference bases are its columns.  The wave sweeps the
+// columns in skewed order -- lane l works on column t - l at step t -- so
+// each lane receives the row above its first row (the previous lane's last
+// row) one step after it was made, through a one-lane DPP shift.  Every cell
+// is computed once; a step costs R cells per lane.  A cell is one int32 key
+// holding its score, the move it prefers on ties and the window column its
+// alignment starts at, so the recurrence's maxima carry the tie order and
+// the start along at no extra cost.  The window is decoded from the packed
+// reference into LDS first.  Work per pair is m x window cells, a few
+// hundred steps: the kernel is bound by integer ALU work, not memory.
 
 #include <hip/hip_runtime.h>
 
@@ -26,8 +29,11 @@ using namespace bwfm;
 
 namespace {
 
-constexpr int RB = 256;  // threads per block: 4 waves, each takes 64 pairs
-constexpr int NEG = -1000000000;
+constexpr int RB = 64;   // threads per block: one wave, so the hardware hands out work one wave at a time
+constexpr int PPW = 4;   // pair records a wave takes (lanes 0 .. PPW - 1): few, so waves end evenly
+// cell keys: score * KS + preference * KP + start column
+constexpr int KS = 1 << 15, KP = 1 << 13;
+constexpr int NEGK = -(1 << 30);  // no alignment can end here (score -32768)
 
 struct EndView {
     const uint8_t *bases;
@@ -55,7 +61,11 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ int shift_down(int v) { return __shfl_up(v, 1); }
+// v from the previous lane of the wave (a DPP shift right by one lane);
+// lane 0, which has no previous lane, gets 0
+__device__ __forceinline__ int row_above(int v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+}
 
 // Rescue one pair with the whole wave (all arguments wave-uniform).
 template <int R>
@@ -83,108 +93,89 @@ __device__ void rescue_one(const uint32_t *pac, uint64_t n, const EndView &ev, u
     }
     // the window, in the orientation the query reads it: forward after a +
     // anchor, reversed (from pr + lr - 1 down) after a - anchor
+    // (each base stored times 8: the bit offset of its score in a row's profile)
     for (int j = lane; j < w; j += 64) {
         const uint64_t p = sa == 0 ? (uint64_t)(w0 + j) : (uint64_t)(w1 - 1 - j);
-        win[j] = (uint8_t)((pac[p >> 4] >> (2 * (p & 15))) & 3);
+        win[j] = (uint8_t)(8 * ((pac[p >> 4] >> (2 * (p & 15))) & 3));
     }
     // this lane's rows: query base i is mate base m - 1 - i, complemented
-    // after a + anchor (the mate then lies on -)
-    uint8_t q[R];
+    // after a + anchor (the mate then lies on -).  Each row keeps its
+    // substitution scores against A, C, G, T as four signed bytes.
+    int prof[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int i = lane * R + r;
-        uint8_t c = 5;  // rows past the mate: match nothing, never reported
+        int c = 5;  // rows past the mate: match nothing, never reported
         if (i < m) {
             c = ev.bases[o0 + (uint64_t)(m - 1 - i)];
-            if (sa == 0 && c < 4) c = (uint8_t)(3 - c);
+            if (sa == 0 && c < 4) c = 3 - c;
         }
-        q[r] = c;
+        uint32_t pk = 0;
+        for (int b = 0; b < 4; b++) pk |= (uint32_t)(uint8_t)(int8_t)(c == b ? S.a : -S.b) << (8 * b);
+        prof[r] = (int)pk;
     }
     wave_sync();
-    const int used = (m + R - 1) / R;  // lanes holding rows
+    const int used = (m + R - 1) / R;        // lanes holding rows
     const int e_min = lo > 0 ? lo - 1 : -1;  // the alignment must end at column >= lo - 1
-    const int oe = S.o + S.e;
-    int Hp[R], HpO[R], Ep[R], EpO[R];
+    // Cells are int32 keys: score * 2^15 + preference * 2^13 + the window
+    // column the cell's alignment starts at (< 2^13).  One max over keys then
+    // takes the highest score and, on equal scores, the preferred move
+    // (diagonal 3 > gap along the reference 2 > gap along the read 1 > no
+    // alignment 0), carrying the start column along.  H keys are kept with
+    // preference 3, so a gap opened from H arrives with preference 3 and
+    // beats the extension of a gap (E kept at 2, F at 1) on equal scores;
+    // clearing one bit then brings E back to 2 and F back to 1.  The edge
+    // row and column are key 0; cells of score 0 or below never pass their
+    // start column on to a cell of positive score, so their keys' low bits
+    // do not matter.
+    const int oek = (S.o + S.e) * KS, ek = S.e * KS;
+    int Hp[R], Ep[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        Hp[r] = 0;
-        HpO[r] = 0;
-        Ep[r] = NEG;
-        EpO[r] = 0;
+        Hp[r] = 3 * KP;
+        Ep[r] = NEGK;
     }
-    int outH = 0, outHO = 0, outF = NEG, outFO = 0;  // last row of this lane, current column
-    int prevH = 0, prevHO = 0;                       // row above, previous column
-    int best = 0, bj = -1, bi = 0, bO = 0;
-    const bool rows = lane < used;
+    int outH = 0, outF = 0;  // last row of this lane, current column
+    int prevH = 0;           // row above, previous column
+    int bestK = 0, bj = -1, bi = 0;
+    int bestT = KS;  // a cell reports when its key reaches this: a score above the best
     const int steps = w + used - 1;
-    for (int t = 0; t < steps; t++) {
-        int upH = shift_down(outH), upHO = shift_down(outHO), upF = shift_down(outF), upFO = shift_down(outFO);
-        if (lane == 0) {
-            upH = 0;
-            upHO = 0;
-            upF = NEG;
-            upFO = 0;
-        }
-        const int j = t - lane;
-        if (rows && j >= 0 && j < w) {
-            const uint8_t rj = win[j];
-            int Hd = prevH, HdO = prevHO;  // H of the row above, previous column
-            int Hu = upH, HuO = upHO;      // H of the row above, this column
-            int F = upF, FO = upFO;
+    const bool holds = lane < used;
+    int j = -lane;
+    for (int t = 0; t < steps; t++, j++) {
+        // the row above this lane's first row, from the previous lane
+        const int upH = row_above(outH), upF = row_above(outF);
+        if (holds && (unsigned)j < (unsigned)w) {
+            const int sh = win[j];
+            const bool elig = j >= e_min;
+            int Hd = prevH, Hu = upH, F = upF;
+            const int j3 = j + 3 * KP;
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                // gap along the reference, from the previous column
-                const int eo = Hp[r] - oe, ee = Ep[r] - S.e;
-                const int E = eo >= ee ? eo : ee, EO = eo >= ee ? HpO[r] : EpO[r];
-                // gap along the read, from the row above
-                const int fo = Hu - oe, fe = F - S.e;
-                if (fo >= fe) {
-                    F = fo;
-                    FO = HuO;
-                } else {
-                    F = fe;
-                }
-                const int s = (q[r] < 4 && q[r] == rj) ? S.a : -S.b;
-                const int dg = Hd + s, dgO = Hd > 0 ? HdO : j;
-                int H = 0, HO = 0;
-                if (dg > H) {
-                    H = dg;
-                    HO = dgO;
-                }
-                if (E > H) {
-                    H = E;
-                    HO = EO;
-                }
-                if (F > H) {
-                    H = F;
-                    HO = FO;
-                }
+                const int E = max(Hp[r] - oek, Ep[r] - ek) & ~KP;
+                F = max(Hu - oek, F - ek) & ~(2 * KP);
+                const int base = Hd >= KS ? Hd : j3;  // extend a positive cell, or start here
+                const int dg = base + __builtin_amdgcn_sbfe(prof[r], sh, 8) * KS;
+                const int H = max(max(dg, E), max(F, 0)) | (3 * KP);
                 Hd = Hp[r];
-                HdO = HpO[r];
                 Hp[r] = H;
-                HpO[r] = HO;
                 Ep[r] = E;
-                EpO[r] = EO;
                 Hu = H;
-                HuO = HO;
-                const int i = lane * R + r + 1;
-                if (j >= e_min && i <= m && H > best) {
-                    best = H;
+                if (elig && H >= bestT && lane * R + r < m) {
+                    bestK = H;
+                    bestT = (H & ~(KS - 1)) + KS;
                     bj = j;
-                    bi = i;
-                    bO = HO;
+                    bi = lane * R + r + 1;
                 }
             }
             outH = Hu;
-            outHO = HuO;
             outF = F;
-            outFO = FO;
         }
         prevH = upH;
-        prevHO = upHO;
     }
     // the first best cell in column order: highest score, then smallest
     // column, then smallest row (each cell lives in exactly one lane)
+    const int best = bestK >> 15;
     uint64_t key = best > 0 ? ((uint64_t)(uint32_t)best << 32) | ((uint64_t)(0xFFFFu - (uint32_t)bj) << 16) |
                                   (uint64_t)(0xFFFFu - (uint32_t)bi)
                             : 0;
@@ -196,20 +187,20 @@ __device__ void rescue_one(const uint32_t *pac, uint64_t n, const EndView &ev, u
     const unsigned long long who = __ballot(key == top && top != 0);
     if (who) {
         const int src = __ffsll((long long)who) - 1;
-        best = __shfl(best, src);
-        bj = __shfl(bj, src);
-        bO = __shfl(bO, src);
-        if (best >= S.min_score) {
+        const int sbest = __shfl(best, src);
+        const int sbj = __shfl(bj, src);
+        const int sbO = __shfl(bestK & (KP - 1), src);
+        if (sbest >= S.min_score) {
             res.end = (uint8_t)mate;
-            res.score = (int16_t)best;
-            res.len = (uint16_t)(bj - bO + 1);
-            res.insert = bj + 1;
+            res.score = (int16_t)sbest;
+            res.len = (uint16_t)(sbj - sbO + 1);
+            res.insert = sbj + 1;
             if (sa == 0) {
                 res.strand = 1;
-                res.pos = (uint32_t)(w0 + bO);
+                res.pos = (uint32_t)(w0 + sbO);
             } else {
                 res.strand = 0;
-                res.pos = (uint32_t)(w1 - 1 - bj);
+                res.pos = (uint32_t)(w1 - 1 - sbj);
             }
         }
     }
@@ -223,12 +214,14 @@ __global__ __launch_bounds__(RB) void k_rescue(const uint32_t *pac, uint64_t n, 
     extern __shared__ uint8_t lds[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint8_t *win = lds + (size_t)wv * win_stride;
-    const uint32_t base = ((uint32_t)blockIdx.x * (RB / 64) + (uint32_t)wv) * 64u;
+    // the wave's first pair (uniform across the wave; said so, so that the
+    // per-pair values derived from it live in scalar registers)
+    const uint32_t base = __builtin_amdgcn_readfirstlane(((uint32_t)blockIdx.x * (RB / 64) + (uint32_t)wv) * PPW);
     const uint32_t p = base + (uint32_t)lane;
     bool cand = false;
     int mate = 0, la = 0, sa = 0;
     uint32_t pa = 0;
-    if (p < n_pairs) {
+    if (lane < PPW && p < n_pairs) {
         const bwfm_pair pr = pairs[p];
         const bool m1 = (pr.flags & BWFM_PF_MAPPED1) != 0, m2 = (pr.flags & BWFM_PF_MAPPED2) != 0;
         cand = !(pr.flags & BWFM_PF_PAIRED) && (m1 || m2);
@@ -248,8 +241,9 @@ __global__ __launch_bounds__(RB) void k_rescue(const uint32_t *pac, uint64_t n, 
     while (todo) {
         const int src = __ffsll((long long)todo) - 1;
         todo &= todo - 1;
-        const int c_mate = __shfl(mate, src), c_la = __shfl(la, src), c_sa = __shfl(sa, src);
-        const uint32_t c_pa = (uint32_t)__shfl((int)pa, src);
+        const int c_mate = __builtin_amdgcn_readlane(mate, src), c_la = __builtin_amdgcn_readlane(la, src),
+                  c_sa = __builtin_amdgcn_readlane(sa, src);
+        const uint32_t c_pa = (uint32_t)__builtin_amdgcn_readlane((int)pa, src);
         rescue_one<R>(pac, n, c_mate == 1 ? e1 : e2, base + (uint32_t)src, c_mate, c_pa, c_la, c_sa, lo, hi, max_len,
                       S, win, out);
         wave_sync();  // the window is rewritten for the next pair
@@ -282,7 +276,8 @@ extern "C" int bwfm_rescue_mates(const bwfm_index *ix, const bwfm_reads *end1, c
     const Scores S{q.match, q.mismatch, q.gap_open, q.gap_extend, q.min_score};
     const int hi = std::max(pp->hi, 0);
     const int win_stride = std::max((hi + 15) & ~15, 16);
-    const uint32_t grid = (uint32_t)(((uint64_t)n_pairs + RB - 1) / RB);
+    const uint64_t per_block = (uint64_t)(RB / 64) * PPW;
+    const uint32_t grid = (uint32_t)(((uint64_t)n_pairs + per_block - 1) / per_block);
     const size_t lds = (size_t)(RB / 64) * win_stride;
     const uint32_t *pac = (const uint32_t *)ix->d_pac;
     const int ml = (int)max_len;
