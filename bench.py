@@ -151,6 +151,7 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--line-bytes", type=int, default=64)
+    ap.add_argument("--rank-format", type=int, default=0, help="0: counts + bit planes; 1: sub-counted 160-row lines")
     ap.add_argument("--waves-per-simd", type=int, default=0, help="batched-form residency (0 = autotuned)")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the autotuner (most waves that fit)")
     ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue measurement")
@@ -185,7 +186,7 @@ def main():
     if want_cpu:
         th.start()
     t0 = time.time()
-    ix = bw.Index(g.seq, line_bytes=args.line_bytes, sa_sample=32).upload()
+    ix = bw.Index(g.seq, line_bytes=args.line_bytes, sa_sample=32, rank_format=args.rank_format).upload()
     log(f"library index built and uploaded in {time.time() - t0:.1f}s ({ix.info()['device_bytes'] / 1e6:.1f} MB)")
 
     w = configs.PAIR_WINDOW
@@ -360,7 +361,7 @@ def main():
                                f"{args.pairs} pairs 2x100 bp, <=4 diffs, 1 gap open, seed 32/<=2",
                    "pairs": args.pairs, "reads": n_reads, "form": "batched: align both ends in one persistent launch, locate, pair; replayed as one captured hipGraph",
                    "waves_per_simd": p_batched.waves_per_simd,
-                   "line_bytes": args.line_bytes, "parallelism": "1 GPU"},
+                   "line_bytes": args.line_bytes, "rank_format": args.rank_format, "parallelism": "1 GPU"},
         "p50_ms": batched["p50_ms"], "p99_ms": batched["p99_ms"],
         "reads_per_s": n_reads / (ms_step / 1e3), "pairs_per_s": n / (ms_step / 1e3),
         "aligned_fraction": aligned / n_reads, "paired_fraction": batched["paired_fraction"],

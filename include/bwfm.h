@@ -70,12 +70,24 @@ typedef struct {
     uint32_t sa_sample;      /* rows r with r % sa_sample == 0 keep SA[r];
                                 a power of two in [1, 1024] */
     uint32_t n_threads;      /* host threads for the build; 0 = all cores */
+    uint32_t rank_format;    /* BWFM_RANK_PLANES or BWFM_RANK_SUBCOUNTS */
 } bwfm_index_params;
+
+/* Rank-line formats.  PLANES: 16 bytes of counts (A, C, G, T before the
+ * line), then the rows.  SUBCOUNTS (64-byte lines of 160 rows only): 12
+ * bytes of counts (C, G, T before the line; A follows from the row number),
+ * then for each of C, G and T a uint32 of four bytes, byte g - 1 counting
+ * that base in the line's first 32 g rows (g = 1..4), then the rows; a rank
+ * query then counts bits in one 32-row group only.  Rows in both: for each
+ * 32 rows a uint32 of the 2-bit codes' high bits, then one of their low
+ * bits. */
+#define BWFM_RANK_PLANES 0
+#define BWFM_RANK_SUBCOUNTS 1
 
 /*
  * Build the FM-index of T = ref[0, n) and of reverse(T) on the host.
  *   ref: host, n codes 0..3 (borrowed for the call only).
- *   p:   layout; NULL = {128, 0, 32, 0}.
+ *   p:   layout; NULL = {128, 0, 32, 0, BWFM_RANK_PLANES}.
  *   out: receives a new index (host part only; see bwfm_index_upload).
  * Each direction holds the BWT of S$ with $ stored as A, the row of $
  * ("primary"), C[a] = 1 + #symbols < a, rank lines (4 x uint32 counts of
@@ -126,7 +138,7 @@ typedef struct {
     uint64_t lines;         /* rank lines per direction */
     uint64_t sa_samples;    /* SA samples per direction */
     uint64_t device_bytes;  /* device memory the uploaded index occupies */
-    uint32_t line_bytes, bases_per_line, sa_sample, uploaded;
+    uint32_t line_bytes, bases_per_line, sa_sample, uploaded, rank_format;
 } bwfm_index_info;
 
 int bwfm_index_get_info(const bwfm_index *idx, bwfm_index_info *out);

@@ -36,6 +36,7 @@ FORM_BATCHED, FORM_PLAIN = 0, 1
 E_CAPACITY = -5
 E_IO = -8
 PIPE_E_HITS, PIPE_E_POSITIONS = 1, 2
+RANK_PLANES, RANK_SUBCOUNTS = 0, 1  # rank-line formats (bwfm_index_params.rank_format)
 
 
 class BwfmError(RuntimeError):
@@ -46,14 +47,14 @@ class BwfmError(RuntimeError):
 
 class _IndexParams(ctypes.Structure):
     _fields_ = [("line_bytes", ctypes.c_uint32), ("bases_per_line", ctypes.c_uint32),
-                ("sa_sample", ctypes.c_uint32), ("n_threads", ctypes.c_uint32)]
+                ("sa_sample", ctypes.c_uint32), ("n_threads", ctypes.c_uint32), ("rank_format", ctypes.c_uint32)]
 
 
 class _IndexInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("primary", ctypes.c_uint64 * 2), ("C", (ctypes.c_uint64 * 4) * 2),
                 ("lines", ctypes.c_uint64), ("sa_samples", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
                 ("line_bytes", ctypes.c_uint32), ("bases_per_line", ctypes.c_uint32),
-                ("sa_sample", ctypes.c_uint32), ("uploaded", ctypes.c_uint32)]
+                ("sa_sample", ctypes.c_uint32), ("uploaded", ctypes.c_uint32), ("rank_format", ctypes.c_uint32)]
 
 
 class _Reads(ctypes.Structure):
@@ -238,22 +239,22 @@ class Index:
     """Packed FM-index of a reference and of its reverse (bwfm_build_index)."""
 
     def __init__(self, ref: np.ndarray, line_bytes: int = 128, bases_per_line: int = 0, sa_sample: int = 32,
-                 threads: int = 0):
+                 threads: int = 0, rank_format: int = RANK_PLANES):
         ref = np.ascontiguousarray(ref, np.uint8)
         h = ctypes.c_void_p()
-        p = _IndexParams(line_bytes, bases_per_line, sa_sample, threads)
+        p = _IndexParams(line_bytes, bases_per_line, sa_sample, threads, rank_format)
         _check(lib().bwfm_build_index(_np_ptr(ref), len(ref), ctypes.byref(p), ctypes.byref(h)))
         self._h = h
         self.n = len(ref)
 
     @classmethod
     def build_device(cls, ref: np.ndarray, line_bytes: int = 128, bases_per_line: int = 0, sa_sample: int = 32,
-                     stream=None) -> "Index":
+                     stream=None, rank_format: int = RANK_PLANES) -> "Index":
         """The same index built on the current GPU (bwfm_build_index_device);
         it comes back uploaded."""
         ref = np.ascontiguousarray(ref, np.uint8)
         h = ctypes.c_void_p()
-        p = _IndexParams(line_bytes, bases_per_line, sa_sample, 0)
+        p = _IndexParams(line_bytes, bases_per_line, sa_sample, 0, rank_format)
         _check(lib().bwfm_build_index_device(_np_ptr(ref), len(ref), ctypes.byref(p), _stream_ptr(stream),
                                              ctypes.byref(h)))
         self = cls.__new__(cls)
@@ -299,7 +300,7 @@ class Index:
         _check(lib().bwfm_index_get_info(self._h, ctypes.byref(i)))
         return dict(n=i.n, primary=list(i.primary), C=[list(c) for c in i.C], lines=i.lines, sa_samples=i.sa_samples,
                     device_bytes=i.device_bytes, line_bytes=i.line_bytes, bases_per_line=i.bases_per_line,
-                    sa_sample=i.sa_sample, uploaded=bool(i.uploaded))
+                    sa_sample=i.sa_sample, uploaded=bool(i.uploaded), rank_format=i.rank_format)
 
     def bwt(self, which: int = 0) -> np.ndarray:
         out = np.empty(self.n + 1, np.uint8)

@@ -129,6 +129,78 @@ __device__ __forceinline__ uint32_t line_of(const DevIndex &ix, uint32_t i) {
     return (uint32_t)__umul64hi((uint64_t)i, ix.magic);
 }
 
+// Rank-line format as a template tag: 8, 16 or 32 = lines of that many
+// uint32 words with counts then bit planes; LW_SUB = 64-byte sub-counted
+// lines of 160 rows (counts of C, G, T, then per base the counts at the
+// first four 32-row boundaries as bytes, then the bit planes).
+constexpr int LW_SUB = 17;
+template <int LW> constexpr int line_words() { return LW == LW_SUB ? 16 : LW; }
+
+// Occ of all four bases at row i of a sub-counted line: the counts before
+// the line, the count at the boundary of row i's 32-row group, and a count
+// of bits in that one group.  A is what the rows leave ($ excluded).
+__device__ __forceinline__ void occ4_sub(const DevIndex &ix, const DevDir &d, uint32_t i, uint32_t o[4]) {
+    const uint32_t line = line_of(ix, i);
+    const uint32_t r = i - line * 160u, g = r >> 5;
+    const uint32_t *L = d.lines + (size_t)line * 16;
+    const uint4 h = *reinterpret_cast<const uint4 *>(L);       // C, G, T before the line; C boundaries
+    const uint2 b = *reinterpret_cast<const uint2 *>(L + 4);   // G, T boundaries
+    const uint2 w = *reinterpret_cast<const uint2 *>(L + 6 + 2 * g);
+    const uint32_t m = (1u << (r & 31)) - 1u;
+    uint32_t cC = __popc(~w.x & w.y & m), cG = __popc(w.x & ~w.y & m), cT = __popc(w.x & w.y & m);
+    if (g) {
+        const uint32_t sh = 8 * (g - 1);
+        cC += (h.w >> sh) & 255u;
+        cG += (b.x >> sh) & 255u;
+        cT += (b.y >> sh) & 255u;
+    }
+    o[1] = h.x + cC;
+    o[2] = h.y + cG;
+    o[3] = h.z + cT;
+    o[0] = i - o[1] - o[2] - o[3] - (i > d.primary ? 1u : 0u);
+}
+
+// Occ at rows i1 and i2 of sub-counted lines, for the search loop, where
+// line requests cost more than bit counting: whole lines are fetched (four
+// 16-byte loads, once when both rows fall in one line) and each row's
+// group is picked from registers.
+__device__ __forceinline__ void occ4_sub_pair(const DevIndex &ix, const DevDir &d, uint32_t i1, uint32_t i2,
+                                              uint32_t o1[4], uint32_t o2[4]) {
+    const uint32_t l1 = line_of(ix, i1), l2 = line_of(ix, i2);
+    const uint4 *L1 = reinterpret_cast<const uint4 *>(d.lines) + (size_t)l1 * 4;
+    const uint4 *L2 = reinterpret_cast<const uint4 *>(d.lines) + (size_t)l2 * 4;
+    uint4 a[4], b[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) a[q] = L1[q];
+    if (l1 != l2) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) b[q] = L2[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; q++) b[q] = a[q];
+    }
+    auto count = [&](const uint4(&v)[4], uint32_t i, uint32_t line, uint32_t o[4]) {
+        const uint32_t r = i - line * 160u, g = r >> 5;
+        // the group's two plane words: words 6 + 2 g and 7 + 2 g of the line
+        const uint32_t hi = g == 0 ? v[1].z : g == 1 ? v[2].x : g == 2 ? v[2].z : g == 3 ? v[3].x : v[3].z;
+        const uint32_t lo = g == 0 ? v[1].w : g == 1 ? v[2].y : g == 2 ? v[2].w : g == 3 ? v[3].y : v[3].w;
+        const uint32_t m = (1u << (r & 31)) - 1u;
+        uint32_t cC = __popc(~hi & lo & m), cG = __popc(hi & ~lo & m), cT = __popc(hi & lo & m);
+        if (g) {
+            const uint32_t sh = 8 * (g - 1);
+            cC += (v[0].w >> sh) & 255u;
+            cG += (v[1].x >> sh) & 255u;
+            cT += (v[1].y >> sh) & 255u;
+        }
+        o[1] = v[0].x + cC;
+        o[2] = v[0].y + cG;
+        o[3] = v[0].z + cT;
+        o[0] = i - o[1] - o[2] - o[3] - (i > d.primary ? 1u : 0u);
+    };
+    count(a, i1, l1, o1);
+    count(b, i2, l2, o2);
+}
+
 // mask of the first t rows of a 32-row group (t may be <= 0 or >= 32)
 __device__ __forceinline__ uint32_t rows_mask(int t) {
     return t >= 32 ? 0xffffffffu : (t <= 0 ? 0u : ((1u << t) - 1u));
@@ -138,6 +210,10 @@ __device__ __forceinline__ uint32_t rows_mask(int t) {
 // high bits (h) and one of low bits (l); T = h & l, G = h & ~l, C = ~h & l.
 template <int LW>
 __device__ __forceinline__ void occ4(const DevIndex &ix, const DevDir &d, uint32_t i, uint32_t o[4]) {
+    if constexpr (LW == LW_SUB) {
+        occ4_sub(ix, d, i, o);
+        return;
+    }
     uint32_t line = line_of(ix, i);
     int r = (int)(i - line * ix.bpl);
     const uint4 *L = reinterpret_cast<const uint4 *>(d.lines) + (size_t)line * (LW / 4);
@@ -166,6 +242,10 @@ __device__ __forceinline__ void occ4(const DevIndex &ix, const DevDir &d, uint32
 template <int LW>
 __device__ __forceinline__ void occ4_pair(const DevIndex &ix, const DevDir &d, uint32_t i1, uint32_t i2, uint32_t o1[4],
                                           uint32_t o2[4]) {
+    if constexpr (LW == LW_SUB) {
+        occ4_sub_pair(ix, d, i1, i2, o1, o2);
+        return;
+    }
     const uint32_t l1 = line_of(ix, i1), l2 = line_of(ix, i2);
     const uint4 *L1 = reinterpret_cast<const uint4 *>(d.lines) + (size_t)l1 * (LW / 4);
     const uint4 *L2 = reinterpret_cast<const uint4 *>(d.lines) + (size_t)l2 * (LW / 4);
@@ -206,6 +286,11 @@ __device__ __forceinline__ void occ4_pair(const DevIndex &ix, const DevDir &d, u
 // Occ(a, i) for one base a.
 template <int LW>
 __device__ __forceinline__ uint32_t occ1(const DevIndex &ix, const DevDir &d, int a, uint32_t i) {
+    if constexpr (LW == LW_SUB) {
+        uint32_t o[4];
+        occ4_sub(ix, d, i, o);
+        return sel4(o, a);
+    }
     uint32_t line = line_of(ix, i);
     int r = (int)(i - line * ix.bpl);
     const uint4 *L = reinterpret_cast<const uint4 *>(d.lines) + (size_t)line * (LW / 4);
@@ -228,8 +313,9 @@ template <int LW>
 __device__ __forceinline__ uint32_t lf_step(const DevIndex &ix, const DevDir &d, uint32_t j) {
     uint32_t line = line_of(ix, j);
     uint32_t r = j - line * ix.bpl;
-    const uint32_t *L = d.lines + (size_t)line * LW;
-    int a = (int)((((L[4 + 2 * (r >> 5)] >> (r & 31)) & 1) << 1) | ((L[5 + 2 * (r >> 5)] >> (r & 31)) & 1));
+    const uint32_t *L = d.lines + (size_t)line * line_words<LW>();
+    constexpr int po = LW == LW_SUB ? 6 : 4;  // first word of the bit planes
+    int a = (int)((((L[po + 2 * (r >> 5)] >> (r & 31)) & 1) << 1) | ((L[po + 1 + 2 * (r >> 5)] >> (r & 31)) & 1));
     return sel4(d.C, a) + occ1<LW>(ix, d, a, j);
 }
 
@@ -1862,6 +1948,14 @@ int check_result(const bwfm_aln_result *r, uint32_t n) {
 
 }  // namespace
 
+// Call f with the index's rank-line format as a compile-time tag.
+template <class F> auto by_layout(const bwfm_index *ix, F &&f) {
+    if (ix->rank_format == BWFM_RANK_SUBCOUNTS) return f(std::integral_constant<int, LW_SUB>());
+    if (ix->line_bytes == 128) return f(std::integral_constant<int, 32>());
+    if (ix->line_bytes == 32) return f(std::integral_constant<int, 8>());
+    return f(std::integral_constant<int, 16>());
+}
+
 // ===================================================================== C ABI
 
 extern "C" int bwfm_index_upload(bwfm_index *ix, void *stream) {
@@ -1928,9 +2022,7 @@ extern "C" int bwfm_align_batch(const bwfm_index *cix, const bwfm_reads *rd, con
     if (int rc = check_align_args(ix, rd, p, res)) return rc;
     std::lock_guard<std::mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
-    if (ix->line_bytes == 128) return align_impl<32>(ix, rd, p, res, st, nullptr);
-    if (ix->line_bytes == 32) return align_impl<8>(ix, rd, p, res, st, nullptr);
-    return align_impl<16>(ix, rd, p, res, st, nullptr);
+    return by_layout(ix, [&](auto lw) { return align_impl<decltype(lw)::value>(ix, rd, p, res, st, nullptr); });
 }
 
 // Same as bwfm_align_batch, also writing per-read search work (states
@@ -1942,9 +2034,7 @@ extern "C" int bwfm_align_batch_counted(const bwfm_index *cix, const bwfm_reads 
     if (int rc = check_align_args(ix, rd, p, res)) return rc;
     std::lock_guard<std::mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
-    if (ix->line_bytes == 128) return align_impl<32>(ix, rd, p, res, st, expand, work);
-    if (ix->line_bytes == 32) return align_impl<8>(ix, rd, p, res, st, expand, work);
-    return align_impl<16>(ix, rd, p, res, st, expand, work);
+    return by_layout(ix, [&](auto lw) { return align_impl<decltype(lw)::value>(ix, rd, p, res, st, expand, work); });
 }
 
 extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_aln_result *res, uint32_t max_occ,
@@ -1971,12 +2061,10 @@ extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_a
     uint32_t *n_big = cv.take<uint32_t>(1);
     uint64_t total = 0;
     const uint4 *hits = (const uint4 *)res->hits + h0;
-    if (ix->line_bytes == 128)
-        rc = locate_impl<32>(ix, n_hits, hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st, &total);
-    else if (ix->line_bytes == 32)
-        rc = locate_impl<8>(ix, n_hits, hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st, &total);
-    else
-        rc = locate_impl<16>(ix, n_hits, hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big, st, &total);
+    rc = by_layout(ix, [&](auto lw) {
+        return locate_impl<decltype(lw)::value>(ix, n_hits, hits, max_occ, pos_off, pos, cap, cnt, part, big, n_big,
+                                                st, &total);
+    });
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(st));
     return BWFM_OK;
@@ -2024,11 +2112,10 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
         const uint4 *hits = (const uint4 *)rr[e]->hits + hb[e];
         // count pass (capacity 0 reports the total)
         uint64_t total = 0;
-        rc = ix->line_bytes == 128
-                 ? locate_impl<32>(ix, nh[e], hits, pp->max_occ, poff[e], nullptr, 0, cnt, part, big, n_big, st, &total)
-             : ix->line_bytes == 32
-                 ? locate_impl<8>(ix, nh[e], hits, pp->max_occ, poff[e], nullptr, 0, cnt, part, big, n_big, st, &total)
-                 : locate_impl<16>(ix, nh[e], hits, pp->max_occ, poff[e], nullptr, 0, cnt, part, big, n_big, st, &total);
+        rc = by_layout(ix, [&](auto lw) {
+            return locate_impl<decltype(lw)::value>(ix, nh[e], hits, pp->max_occ, poff[e], nullptr, 0, cnt, part, big,
+                                                    n_big, st, &total);
+        });
         if (rc == BWFM_E_CAPACITY || (rc == BWFM_OK && total == 0)) {
             rc = BWFM_OK;
             if (hipMalloc(&posmem[e], std::max<uint64_t>(total, 1) * 4) != hipSuccess) {
@@ -2037,14 +2124,10 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
             }
             pos[e] = (uint32_t *)posmem[e];
             if (total)
-                rc = ix->line_bytes == 128
-                         ? locate_impl<32>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total, cnt, part, big, n_big,
-                                           st, &total)
-                     : ix->line_bytes == 32
-                         ? locate_impl<8>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total, cnt, part, big, n_big,
-                                          st, &total)
-                         : locate_impl<16>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total, cnt, part, big, n_big,
-                                           st, &total);
+                rc = by_layout(ix, [&](auto lw) {
+                    return locate_impl<decltype(lw)::value>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total, cnt,
+                                                            part, big, n_big, st, &total);
+                });
         }
     }
     if (rc == BWFM_OK && n_pairs) {
@@ -2299,9 +2382,7 @@ int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed, bool capture) {
 }
 
 int pipe_enqueue_any(bwfm_pipeline *pl, hipStream_t st, bool timed, bool capture) {
-    if (pl->ix->line_bytes == 128) return pipe_enqueue<32>(pl, st, timed, capture);
-    if (pl->ix->line_bytes == 32) return pipe_enqueue<8>(pl, st, timed, capture);
-    return pipe_enqueue<16>(pl, st, timed, capture);
+    return by_layout(pl->ix, [&](auto lw) { return pipe_enqueue<decltype(lw)::value>(pl, st, timed, capture); });
 }
 
 }  // namespace
@@ -2345,9 +2426,11 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
     pl->lds = (size_t)pl->bs * pl->lstride + (plain ? 0 : (pl->bs / 64) * sizeof(WaveShare));
     const uint32_t nr_up = ((nmax + pl->bs - 1) / pl->bs) * pl->bs;
     pl->lanes = plain ? nr_up
-                      : std::min<uint32_t>(ix->line_bytes == 128  ? persistent_lanes<32>(pl->bs, pl->lds, ap->waves_per_simd)
-                                           : ix->line_bytes == 32 ? persistent_lanes<8>(pl->bs, pl->lds, ap->waves_per_simd)
-                                                                  : persistent_lanes<16>(pl->bs, pl->lds, ap->waves_per_simd),
+                      : std::min<uint32_t>(by_layout(ix,
+                                                     [&](auto lw) {
+                                                         return persistent_lanes<decltype(lw)::value>(
+                                                             pl->bs, pl->lds, ap->waves_per_simd);
+                                                     }),
                                            nr_up);
     pl->stack_cap = plain ? std::min<uint32_t>(pl->worst_stack, PLAIN_STACK) : pl->worst_stack;
     pl->slow_lanes = std::min<uint32_t>(nr_up, SLOW_LANES);

@@ -51,18 +51,21 @@ int check_index_params(bwfm_index_params &q, uint64_t n);
 
 // Host index builder and inspection (index_host.cpp).
 int build_dir(const uint8_t *text, uint64_t n, uint32_t line_bytes, uint32_t bpl, uint32_t sa_sample,
-              HostDir &out);
-void occ_host(const HostDir &d, uint32_t line_words, uint32_t bpl, uint64_t i, uint64_t out[4]);
+              uint32_t rank_format, HostDir &out);
+// rewrite planar 64-byte lines of 160 rows as sub-counted ones, in place
+void subcount_lines(uint32_t *lines, uint64_t n_lines);
+void occ_host(const HostDir &d, uint32_t line_words, uint32_t bpl, uint32_t rank_format, uint64_t i,
+              uint64_t out[4]);
+uint8_t bwt_host(const HostDir &d, uint32_t line_words, uint32_t bpl, uint32_t rank_format, uint64_t row);
 // T packed two bits per base, 16 bases per word, base i in bits 2 (i % 16)
 // of word i / 16 (unused high bits of the last word zero)
 void pack_ref(const uint8_t *text, uint64_t n, std::vector<uint32_t> &out);
-uint8_t bwt_host(const HostDir &d, uint32_t line_words, uint32_t bpl, uint64_t row);
 
 }  // namespace bwfm
 
 struct bwfm_index {
     uint64_t n = 0;
-    uint32_t line_bytes = 128, bpl = 448, sa_sample = 32;
+    uint32_t line_bytes = 128, bpl = 448, sa_sample = 32, rank_format = BWFM_RANK_PLANES;
     uint64_t n_lines = 0, n_samples = 0;
     bwfm::HostDir dir[2];
     std::vector<uint32_t> pac;  // the reference itself (pack_ref), for mate rescue

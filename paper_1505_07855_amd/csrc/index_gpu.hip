@@ -55,6 +55,36 @@ __global__ void k_pack_ref(const uint8_t *t, uint64_t n, uint32_t *pac) {
     }
 }
 
+// planar 64-byte lines of 160 rows rewritten in place as sub-counted ones:
+// counts of C, G, T before the line, per base a word of the counts in the
+// first 32, 64, 96 and 128 rows (a byte each), then the ten row words
+__global__ void k_ix_subcount(uint32_t *lines, uint64_t n_lines) {
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n_lines; x += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t *L = lines + x * 16;
+        uint32_t P[16];
+        for (int w = 0; w < 16; w++) P[w] = L[w];
+        uint32_t cC = 0, cG = 0, cT = 0, sC = 0, sG = 0, sT = 0;
+        for (int g = 0; g < 5; g++) {
+            if (g > 0) {
+                sC |= cC << (8 * (g - 1));
+                sG |= cG << (8 * (g - 1));
+                sT |= cT << (8 * (g - 1));
+            }
+            const uint32_t h = P[4 + 2 * g], l = P[5 + 2 * g];
+            cC += __popc(~h & l);
+            cG += __popc(h & ~l);
+            cT += __popc(h & l);
+        }
+        L[0] = P[1];
+        L[1] = P[2];
+        L[2] = P[3];
+        L[3] = sC;
+        L[4] = sG;
+        L[5] = sT;
+        for (int w = 0; w < 10; w++) L[6 + w] = P[4 + w];
+    }
+}
+
 // first-round keys: the 21 symbols from i, each code + 1, 0 from $ on
 __global__ void k_sa_init(const uint8_t *t, uint64_t n, uint64_t N, uint64_t *key, uint32_t *val) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -202,7 +232,7 @@ int suffix_sort(const uint8_t *t, uint64_t n, uint32_t *sa, hipStream_t st) {
 // One direction: suffix sort, then rank lines and samples straight into
 // the index's device buffers, and host copies of both.
 int build_dir_device(const uint8_t *t, uint64_t n, uint32_t line_bytes, uint32_t bpl, uint32_t sa_sample,
-                     HostDir &out, void *&d_lines, void *&d_sa, hipStream_t st) {
+                     uint32_t rank_format, HostDir &out, void *&d_lines, void *&d_sa, hipStream_t st) {
     const uint64_t N = n + 1;
     const uint32_t lw = line_bytes / 4;
     const uint64_t n_lines = N / bpl + 1, n_samples = n / sa_sample + 1, n_groups = (N + 31) / 32;
@@ -231,6 +261,7 @@ int build_dir_device(const uint8_t *t, uint64_t n, uint32_t line_bytes, uint32_t
                                      rocprim::plus<uint64_t>(), st));
     }
     k_ix_heads<<<grid_for(n_lines, B), B, 0, st>>>(off, n_lines, lw, lines);
+    if (rank_format == BWFM_RANK_SUBCOUNTS) k_ix_subcount<<<grid_for(n_lines, B), B, 0, st>>>(lines, n_lines);
     DCHK(hipGetLastError());
     // totals per base ($ counted as A) and the $ row
     uint64_t last_off[4];
@@ -261,7 +292,7 @@ extern "C" int bwfm_build_index_device(const uint8_t *ref, uint64_t n, const bwf
                                        bwfm_index **out) {
     if (!ref || !out) return fail(BWFM_E_INVAL, "build_index_device: NULL argument");
     *out = nullptr;
-    bwfm_index_params q = p ? *p : bwfm_index_params{128, 0, 32, 0};
+    bwfm_index_params q = p ? *p : bwfm_index_params{128, 0, 32, 0, BWFM_RANK_PLANES};
     if (int rc = check_index_params(q, n)) return rc;
     for (uint64_t i = 0; i < n; i++)
         if (ref[i] > 3) return fail(BWFM_E_BASE, "reference holds a code outside 0..3 at " + std::to_string(i));
@@ -271,6 +302,7 @@ extern "C" int bwfm_build_index_device(const uint8_t *ref, uint64_t n, const bwf
     ix->line_bytes = q.line_bytes;
     ix->bpl = q.bases_per_line;
     ix->sa_sample = q.sa_sample;
+    ix->rank_format = q.rank_format;
     ix->n_lines = (n + 1) / q.bases_per_line + 1;
     ix->n_samples = n / q.sa_sample + 1;
     hipStream_t st = (hipStream_t)stream;
@@ -293,7 +325,8 @@ extern "C" int bwfm_build_index_device(const uint8_t *ref, uint64_t n, const bwf
         if (!rc && hipMemcpyAsync(ix->pac.data(), ix->d_pac, pac_words * 4, hipMemcpyDeviceToHost, st) != hipSuccess)
             rc = fail(BWFM_E_DEVICE, "index build: packed text copy");
     }
-    if (!rc) rc = build_dir_device(t, n, q.line_bytes, q.bases_per_line, q.sa_sample, ix->dir[0], ix->d_lines[0],
+    if (!rc) rc = build_dir_device(t, n, q.line_bytes, q.bases_per_line, q.sa_sample, q.rank_format, ix->dir[0],
+                                   ix->d_lines[0],
                                    ix->d_sa[0], st);
     if (!rc) {
         // reverse(T) in place of T
@@ -301,7 +334,8 @@ extern "C" int bwfm_build_index_device(const uint8_t *ref, uint64_t n, const bwf
             rc = fail(BWFM_E_NOMEM, "index build: device text");
         } else {
             k_reverse<<<grid_for(n, 256), 256, 0, st>>>(t, n, r);
-            rc = build_dir_device(r, n, q.line_bytes, q.bases_per_line, q.sa_sample, ix->dir[1], ix->d_lines[1],
+            rc = build_dir_device(r, n, q.line_bytes, q.bases_per_line, q.sa_sample, q.rank_format, ix->dir[1],
+                                  ix->d_lines[1],
                                   ix->d_sa[1], st);
         }
     }

@@ -133,7 +133,7 @@ void sais(const Ch *s, uint32_t *SA, uint64_t n, uint64_t K) {
 }  // namespace
 
 int build_dir(const uint8_t *text, uint64_t n, uint32_t line_bytes, uint32_t bpl, uint32_t sa_sample,
-              HostDir &out) {
+              uint32_t rank_format, HostDir &out) {
     const uint64_t N = n + 1;
     std::vector<uint8_t> s(N);
     for (uint64_t i = 0; i < n; i++) s[i] = (uint8_t)(text[i] + 1);
@@ -172,24 +172,60 @@ int build_dir(const uint8_t *text, uint64_t n, uint32_t line_bytes, uint32_t bpl
     cnt[0] -= 1;  // the $ row was counted as A
     out.C[0] = 1;
     for (int a = 1; a < 4; a++) out.C[a] = out.C[a - 1] + cnt[a - 1];
+    if (rank_format == BWFM_RANK_SUBCOUNTS) subcount_lines(out.lines.data(), n_lines);
     return BWFM_OK;
 }
 
-static inline uint32_t code_at(const uint32_t *L, uint64_t r) {
-    return (((L[4 + 2 * (r >> 5)] >> (r & 31)) & 1) << 1) | ((L[5 + 2 * (r >> 5)] >> (r & 31)) & 1);
+void subcount_lines(uint32_t *lines, uint64_t n_lines) {
+    for (uint64_t x = 0; x < n_lines; x++) {
+        uint32_t *L = lines + x * 16, P[16];
+        std::memcpy(P, L, sizeof P);
+        uint32_t cum[3] = {0, 0, 0}, sub[3] = {0, 0, 0};
+        for (int g = 0; g < 5; g++) {
+            const uint32_t h = P[4 + 2 * g], l = P[5 + 2 * g];
+            if (g > 0)
+                for (int b = 0; b < 3; b++) sub[b] |= cum[b] << (8 * (g - 1));
+            cum[0] += (uint32_t)__builtin_popcount(~h & l);  // C
+            cum[1] += (uint32_t)__builtin_popcount(h & ~l);  // G
+            cum[2] += (uint32_t)__builtin_popcount(h & l);   // T
+        }
+        L[0] = P[1];
+        L[1] = P[2];
+        L[2] = P[3];
+        for (int b = 0; b < 3; b++) L[3 + b] = sub[b];
+        for (int w = 0; w < 10; w++) L[6 + w] = P[4 + w];
+    }
 }
 
-uint8_t bwt_host(const HostDir &d, uint32_t lw, uint32_t bpl, uint64_t row) {
+static inline uint32_t planes_at(uint32_t rank_format) { return rank_format == BWFM_RANK_SUBCOUNTS ? 6 : 4; }
+
+static inline uint32_t code_at(const uint32_t *L, uint32_t po, uint64_t r) {
+    return (((L[po + 2 * (r >> 5)] >> (r & 31)) & 1) << 1) | ((L[po + 1 + 2 * (r >> 5)] >> (r & 31)) & 1);
+}
+
+uint8_t bwt_host(const HostDir &d, uint32_t lw, uint32_t bpl, uint32_t rank_format, uint64_t row) {
     if (row == d.primary) return 4;
     uint64_t line = row / bpl, r = row - line * bpl;
-    return (uint8_t)code_at(&d.lines[line * lw], r);
+    return (uint8_t)code_at(&d.lines[line * lw], planes_at(rank_format), r);
 }
 
-void occ_host(const HostDir &d, uint32_t lw, uint32_t bpl, uint64_t i, uint64_t out[4]) {
+void occ_host(const HostDir &d, uint32_t lw, uint32_t bpl, uint32_t rank_format, uint64_t i, uint64_t out[4]) {
     uint64_t line = i / bpl, r = i - line * bpl;
     const uint32_t *L = &d.lines[line * lw];
+    if (rank_format == BWFM_RANK_SUBCOUNTS) {
+        // counts before the line, then at the start of row r's 32-row group
+        // (the stored bytes), then the group's rows before r; A is the rest
+        const uint64_t g = r >> 5;
+        for (int b = 0; b < 3; b++) out[1 + b] = L[b] + (g ? (L[3 + b] >> (8 * (g - 1))) & 255u : 0u);
+        for (uint64_t x = 32 * g; x < r; x++) {
+            const uint32_t c = code_at(L, planes_at(rank_format), x);
+            if (c) out[c]++;
+        }
+        out[0] = i - out[1] - out[2] - out[3] - (i > d.primary ? 1 : 0);
+        return;
+    }
     for (int a = 0; a < 4; a++) out[a] = L[a];
-    for (uint64_t x = 0; x < r; x++) out[code_at(L, x)]++;
+    for (uint64_t x = 0; x < r; x++) out[code_at(L, planes_at(rank_format), x)]++;
     if (i > d.primary) out[0]--;
 }
 
@@ -212,6 +248,13 @@ namespace bwfm {
 int check_index_params(bwfm_index_params &q, uint64_t n) {
     if (q.line_bytes != 32 && q.line_bytes != 64 && q.line_bytes != 128)
         return fail(BWFM_E_INVAL, "line_bytes must be 32, 64 or 128");
+    if (q.rank_format != BWFM_RANK_PLANES && q.rank_format != BWFM_RANK_SUBCOUNTS)
+        return fail(BWFM_E_INVAL, "unknown rank_format");
+    if (q.rank_format == BWFM_RANK_SUBCOUNTS) {
+        if (q.bases_per_line == 0) q.bases_per_line = 160;
+        if (q.line_bytes != 64 || q.bases_per_line != 160)
+            return fail(BWFM_E_INVAL, "sub-counted rank lines are 64 bytes of 160 rows");
+    }
     uint32_t maxb = (q.line_bytes - 16) * 4;
     if (q.bases_per_line == 0) q.bases_per_line = maxb;
     if (q.bases_per_line % 32 || q.bases_per_line < 32 || q.bases_per_line > maxb)
@@ -233,7 +276,7 @@ void pack_ref(const uint8_t *text, uint64_t n, std::vector<uint32_t> &out) {
 extern "C" int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index_params *p, bwfm_index **out) {
     if (!ref || !out) return fail(BWFM_E_INVAL, "build_index: NULL argument");
     *out = nullptr;
-    bwfm_index_params q = p ? *p : bwfm_index_params{128, 0, 32, 0};
+    bwfm_index_params q = p ? *p : bwfm_index_params{128, 0, 32, 0, BWFM_RANK_PLANES};
     if (int rc = check_index_params(q, n)) return rc;
     for (uint64_t i = 0; i < n; i++)
         if (ref[i] > 3) return fail(BWFM_E_BASE, "reference holds a code outside 0..3 at " + std::to_string(i));
@@ -243,6 +286,7 @@ extern "C" int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index
     ix->line_bytes = q.line_bytes;
     ix->bpl = q.bases_per_line;
     ix->sa_sample = q.sa_sample;
+    ix->rank_format = q.rank_format;
     ix->n_lines = (n + 1) / q.bases_per_line + 1;
     ix->n_samples = n / q.sa_sample + 1;
     std::vector<uint8_t> rev(ref, ref + n);
@@ -250,7 +294,8 @@ extern "C" int bwfm_build_index(const uint8_t *ref, uint64_t n, const bwfm_index
     int rc[2] = {BWFM_OK, BWFM_OK};
     auto job = [&](int d) {
         try {
-            rc[d] = build_dir(d == 0 ? ref : rev.data(), n, q.line_bytes, q.bases_per_line, q.sa_sample, ix->dir[d]);
+            rc[d] = build_dir(d == 0 ? ref : rev.data(), n, q.line_bytes, q.bases_per_line, q.sa_sample,
+                              q.rank_format, ix->dir[d]);
         } catch (const std::bad_alloc &) {
             rc[d] = BWFM_E_NOMEM;
         }
@@ -293,12 +338,14 @@ extern "C" int bwfm_index_get_info(const bwfm_index *ix, bwfm_index_info *o) {
     o->bases_per_line = ix->bpl;
     o->sa_sample = ix->sa_sample;
     o->uploaded = ix->device >= 0;
+    o->rank_format = ix->rank_format;
     return BWFM_OK;
 }
 
 extern "C" int bwfm_index_get_bwt(const bwfm_index *ix, int which, uint8_t *out) {
     if (!ix || !out || which < 0 || which > 1) return fail(BWFM_E_INVAL, "get_bwt: bad argument");
-    for (uint64_t r = 0; r <= ix->n; r++) out[r] = bwt_host(ix->dir[which], ix->line_bytes / 4, ix->bpl, r);
+    for (uint64_t r = 0; r <= ix->n; r++)
+        out[r] = bwt_host(ix->dir[which], ix->line_bytes / 4, ix->bpl, ix->rank_format, r);
     return BWFM_OK;
 }
 
@@ -319,7 +366,7 @@ extern "C" int bwfm_index_get_ref(const bwfm_index *ix, uint64_t start, uint64_t
 
 extern "C" int bwfm_index_occ(const bwfm_index *ix, int which, uint64_t i, uint64_t *out) {
     if (!ix || !out || which < 0 || which > 1 || i > ix->n + 1) return fail(BWFM_E_INVAL, "occ: bad argument");
-    occ_host(ix->dir[which], ix->line_bytes / 4, ix->bpl, i, out);
+    occ_host(ix->dir[which], ix->line_bytes / 4, ix->bpl, ix->rank_format, i, out);
     return BWFM_OK;
 }
 
@@ -381,6 +428,7 @@ extern "C" int bwfm_index_save(const bwfm_index *ix, const char *path) {
     w.val<uint32_t>(ix->line_bytes);
     w.val<uint32_t>(ix->bpl);
     w.val<uint32_t>(ix->sa_sample);
+    w.val<uint32_t>(ix->rank_format);
     w.val<uint64_t>(ix->n);
     w.val<uint64_t>(ix->n_lines);
     w.val<uint64_t>(ix->n_samples);
@@ -421,6 +469,7 @@ extern "C" int bwfm_index_load(const char *path, bwfm_index **out) {
     ix->line_bytes = r.val<uint32_t>();
     ix->bpl = r.val<uint32_t>();
     ix->sa_sample = r.val<uint32_t>();
+    ix->rank_format = r.val<uint32_t>();
     ix->n = r.val<uint64_t>();
     ix->n_lines = r.val<uint64_t>();
     ix->n_samples = r.val<uint64_t>();
@@ -430,12 +479,14 @@ extern "C" int bwfm_index_load(const char *path, bwfm_index **out) {
                            ix->bpl >= 32 &&
                            ix->bpl <= (ix->line_bytes - 16) * 4 && ix->sa_sample >= 1 && ix->sa_sample <= 1024 &&
                            (ix->sa_sample & (ix->sa_sample - 1)) == 0 && ix->n >= 1 && ix->n + 1 < (1ULL << 32) &&
+                           (ix->rank_format == BWFM_RANK_PLANES ||
+                            (ix->rank_format == BWFM_RANK_SUBCOUNTS && ix->line_bytes == 64 && ix->bpl == 160)) &&
                            ix->n_lines == (ix->n + 1) / ix->bpl + 1 && ix->n_samples == ix->n / ix->sa_sample + 1;
     if (!r.ok || !layout_ok) return fail(BWFM_E_IO, "index_load: corrupt header");
     const uint64_t words = ix->n_lines * (ix->line_bytes / 4);
     const uint64_t pac_words = (ix->n + 15) / 16;
     const uint64_t expect =
-        8 + 4 * 4 + 3 * 8 + 2 * (6 * 8 + words * 4 + 8 + ix->n_samples * 4) + 8 + pac_words * 4 + 8;
+        8 + 5 * 4 + 3 * 8 + 2 * (6 * 8 + words * 4 + 8 + ix->n_samples * 4) + 8 + pac_words * 4 + 8;
     if (fsize < 0 || (uint64_t)fsize != expect) return fail(BWFM_E_IO, "index_load: file size does not match header");
     try {
         for (int d = 0; d < 2; d++) {

@@ -68,11 +68,12 @@ FORMS = [bw.FORM_BATCHED, bw.FORM_PLAIN]
 
 
 @pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("layout", [(64, 128), (128, 448)])
+@pytest.mark.parametrize("layout", [(64, 128), (128, 448), (64, 160, bw.RANK_SUBCOUNTS)])
 @pytest.mark.parametrize("mode", [bw.MODE_BEST, bw.MODE_ALL])
 def test_c1_shape_parity(c1_small, layout, mode, form):
     g, reads, ox = c1_small
-    ix = bw.Index(g.seq, line_bytes=layout[0], bases_per_line=layout[1], sa_sample=32).upload()
+    ix = bw.Index(g.seq, line_bytes=layout[0], bases_per_line=layout[1], sa_sample=32,
+                  rank_format=layout[2] if len(layout) > 2 else bw.RANK_PLANES).upload()
     p, op = _params_pair(**configs.PARAMS["C1"], mode=mode)
     p.form = form
     res = _gpu_align(ix, reads, p, counted=True)
@@ -94,10 +95,11 @@ def c2_small():
 
 
 @pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("layout", [(128, 448, 32), (64, 192, 16), (32, 64, 32)])
+@pytest.mark.parametrize("layout", [(128, 448, 32), (64, 192, 16), (32, 64, 32), (64, 160, 32, bw.RANK_SUBCOUNTS)])
 def test_c2_shape_parity_align_locate_pair(c2_small, layout, form):
     g, pairs, ox = c2_small
-    ix = bw.Index(g.seq, line_bytes=layout[0], bases_per_line=layout[1], sa_sample=layout[2]).upload()
+    ix = bw.Index(g.seq, line_bytes=layout[0], bases_per_line=layout[1], sa_sample=layout[2],
+                  rank_format=layout[3] if len(layout) > 3 else bw.RANK_PLANES).upload()
     p, op = _params_pair(form=form, **configs.PARAMS["C2"])
     r = []
     for end in (pairs.end1, pairs.end2):
@@ -236,15 +238,17 @@ def test_c3_shape_per_read_budgets_parity(form):
         _compare_align(res, ores)
 
 
-@pytest.mark.parametrize("form,wps", [(bw.FORM_BATCHED, 0), (bw.FORM_BATCHED, 3), (bw.FORM_PLAIN, 0)])
-def test_c5_shape_stress_parity(form, wps):
+@pytest.mark.parametrize("form,wps,fmt", [(bw.FORM_BATCHED, 0, bw.RANK_PLANES), (bw.FORM_BATCHED, 3, bw.RANK_PLANES),
+                                          (bw.FORM_PLAIN, 0, bw.RANK_PLANES), (bw.FORM_BATCHED, 0, bw.RANK_SUBCOUNTS)])
+def test_c5_shape_stress_parity(form, wps, fmt):
     """250 bp reads, 6 differences with gaps, a tenth from repeat copies: a few
     reads expand hundreds of thousands of states.  In the batched form their
     trees are split across the lanes of a wave once the batch runs dry."""
     g = configs.c2_genome(2_000_000, seed=55)
     reads = configs.c5_reads(g, 2000, seed=56)
     ox = oracle.Index(g.seq)
-    ix = bw.Index(g.seq, **{k: v for k, v in configs.LAYOUT["C5"].items()}).upload()
+    lay = dict(configs.LAYOUT["C5"]) if fmt == bw.RANK_PLANES else dict(line_bytes=64, sa_sample=32)
+    ix = bw.Index(g.seq, **lay, rank_format=fmt).upload()
     p, op = _params_pair(form=form, **configs.PARAMS["C5"])
     p.waves_per_simd = wps  # every build of the batched kernel
     op.bases_per_line = ix.info()["bases_per_line"]

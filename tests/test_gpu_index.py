@@ -38,13 +38,15 @@ def _host_bytes(ix):
     return out
 
 
-@pytest.mark.parametrize("layout", [(64, 0, 32), (128, 0, 32), (64, 128, 8), (32, 0, 32)])
+@pytest.mark.parametrize("layout", [(64, 0, 32), (128, 0, 32), (64, 128, 8), (32, 0, 32),
+                                    (64, 0, 32, bw.RANK_SUBCOUNTS)])
 def test_device_index_equals_host_index(layout):
-    lb, bpl, sas = layout
+    lb, bpl, sas = layout[:3]
+    fmt = layout[3] if len(layout) > 3 else bw.RANK_PLANES
     rng = np.random.default_rng(9)
     for name, t in _texts():
-        a = bw.Index(t, line_bytes=lb, bases_per_line=bpl, sa_sample=sas)
-        b = bw.Index.build_device(t, line_bytes=lb, bases_per_line=bpl, sa_sample=sas)
+        a = bw.Index(t, line_bytes=lb, bases_per_line=bpl, sa_sample=sas, rank_format=fmt)
+        b = bw.Index.build_device(t, line_bytes=lb, bases_per_line=bpl, sa_sample=sas, rank_format=fmt)
         assert b.info()["uploaded"]
         assert _host_bytes(a) == _host_bytes(b), name
         for which in (0, 1):
@@ -54,12 +56,14 @@ def test_device_index_equals_host_index(layout):
         b.close()
 
 
-def test_device_index_aligns_like_host_index():
+@pytest.mark.parametrize("fmt", [bw.RANK_PLANES, bw.RANK_SUBCOUNTS])
+def test_device_index_aligns_like_host_index(fmt):
     g = configs.c2_genome(2_000_000, seed=62)
     pairs = configs.c2_pairs(g, 1000, seed=63)
     p = bw.Params(**configs.PARAMS["C2"])
     out = []
-    for ix in (bw.Index(g.seq, **configs.LAYOUT["C2"]).upload(), bw.Index.build_device(g.seq, **configs.LAYOUT["C2"])):
+    lay = dict(configs.LAYOUT["C2"]) if fmt == bw.RANK_PLANES else dict(line_bytes=64, sa_sample=32)
+    for ix in (bw.Index(g.seq, **lay, rank_format=fmt).upload(), bw.Index.build_device(g.seq, **lay, rank_format=fmt)):
         e = pairs.end1
         res = bw.align_batch(ix, torch.from_numpy(e.bases).cuda(), torch.from_numpy(e.offsets.view(np.int64)).cuda(), p,
                              max_len=100)

@@ -39,11 +39,14 @@ def _texts(rng):
 
 
 @pytest.mark.parametrize("layout", [(128, 0, 32), (64, 0, 32), (64, 128, 32), (128, 64, 1), (64, 32, 8),
-                                    (128, 448, 1024), (32, 0, 32), (32, 32, 4)])
+                                    (128, 448, 1024), (32, 0, 32), (32, 32, 4), (64, 0, 32, bw.RANK_SUBCOUNTS),
+                                    (64, 160, 1, bw.RANK_SUBCOUNTS)])
 def test_host_index_equals_oracle_index(layout, rng):
-    lb, bpl, sas = layout
+    lb, bpl, sas = layout[:3]
+    fmt = layout[3] if len(layout) > 3 else bw.RANK_PLANES
     for name, t in _texts(rng):
-        ix = bw.Index(t, line_bytes=lb, bases_per_line=bpl, sa_sample=sas)
+        ix = bw.Index(t, line_bytes=lb, bases_per_line=bpl, sa_sample=sas, rank_format=fmt)
+        assert ix.info()["rank_format"] == fmt
         ox = oracle.Index(t)
         info = ix.info()
         for which in (0, 1):
@@ -78,6 +81,12 @@ def test_build_index_errors():
     assert e.value.code == -1
     with pytest.raises(bw.BwfmError):
         bw.Index(np.zeros(0, np.uint8))
+    for kw in (dict(line_bytes=128), dict(line_bytes=64, bases_per_line=192), dict(line_bytes=32)):
+        with pytest.raises(bw.BwfmError) as e:  # sub-counted lines are 64 bytes of 160 rows
+            bw.Index(np.zeros(10, np.uint8), rank_format=bw.RANK_SUBCOUNTS, **kw)
+        assert e.value.code == -1
+    with pytest.raises(bw.BwfmError):
+        bw.Index(np.zeros(10, np.uint8), rank_format=7)
 
 
 def test_host_helpers_match_oracle(rng):
@@ -96,15 +105,16 @@ def test_align_without_upload_is_a_state_error():
     ix.close()
 
 
-def test_index_save_load_roundtrip_and_corruption(rng, tmp_path):
+@pytest.mark.parametrize("fmt", [bw.RANK_PLANES, bw.RANK_SUBCOUNTS])
+def test_index_save_load_roundtrip_and_corruption(rng, tmp_path, fmt):
     t = rng.integers(0, 4, 7000).astype(np.uint8)
     t[3000:4000] = t[100:1100]
-    ix = bw.Index(t, line_bytes=64, sa_sample=8)
+    ix = bw.Index(t, line_bytes=64, sa_sample=8, rank_format=fmt)
     path = str(tmp_path / "x.bwfm")
     ix.save(path)
     iy = bw.Index.load(path)
     a, b = ix.info(), iy.info()
-    for k in ("n", "primary", "C", "lines", "sa_samples", "line_bytes", "bases_per_line", "sa_sample"):
+    for k in ("n", "primary", "C", "lines", "sa_samples", "line_bytes", "bases_per_line", "sa_sample", "rank_format"):
         assert a[k] == b[k], k
     assert not b["uploaded"]
     for which in (0, 1):
