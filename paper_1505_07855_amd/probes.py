@@ -2,6 +2,7 @@
 
     python -m paper_1505_07855_amd.probes copy   [MiB]   # one device copy of known size
     python -m paper_1505_07855_amd.probes gather [MiB]   # random-line rates
+    python -m paper_1505_07855_amd.probes gather_occupancy [MiB]   # the same against resident waves
 
 `copy` gives the reference against which hardware byte counters
 (FETCH_SIZE, WRITE_SIZE under rocprofv3 --pmc) are scaled: a plain copy of
@@ -39,7 +40,25 @@ def gather(mib: int = 2048) -> dict:
     return out
 
 
+def gather_occupancy(mib: int = 64) -> dict:
+    """The gather rate of 64-byte lines against the number of resident
+    waves per SIMD (1 to 16 over 256 CUs x 4 SIMDs): whether dependent random
+    line fetches are bound by latency (the rate grows with waves) or by the
+    memory system's throughput (it does not)."""
+    import torch
+
+    import paper_1505_07855_amd as bw
+    buf = torch.zeros(mib << 20, dtype=torch.uint8, device="cuda")
+    out = {"probe": "gather_occupancy", "buffer_mib": mib, "line_bytes": 64, "lines_per_s": {}}
+    for w in (1, 2, 4, 8, 16):
+        lanes = 256 * 4 * 64 * w
+        bw.probe_gather(buf, 64, lanes=lanes, iters=16)  # warm
+        out["lines_per_s"][w] = max(bw.probe_gather(buf, 64, lanes=lanes) for _ in range(3))
+    return out
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "gather"
-    size = int(sys.argv[2]) if len(sys.argv) > 2 else (1024 if what == "copy" else 2048)
-    print(json.dumps(copy(size) if what == "copy" else gather(size)), flush=True)
+    size = int(sys.argv[2]) if len(sys.argv) > 2 else (1024 if what == "copy" else 2048 if what == "gather" else 64)
+    fn = {"copy": copy, "gather": gather, "gather_occupancy": gather_occupancy}[what]
+    print(json.dumps(fn(size)), flush=True)
