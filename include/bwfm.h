@@ -535,6 +535,10 @@ typedef struct {
     int32_t budget_rule;   /* 1: each read's difference budget is
                               bwfm_max_diff_rule(length, 0.02, 0.04);
                               0: ap->max_diff for every read */
+    int32_t rescue_mapq;   /* 1: after pairing, rescue mates (paired servers;
+                              bwfm_rescue_mates with default scores, pp->hi
+                              <= BWFM_RESCUE_MAX_WINDOW) and assign MAPQ
+                              (bwfm_mapq, default qualities) */
 } bwfm_server_params;
 
 typedef struct {
@@ -560,10 +564,13 @@ int bwfm_server_create(const bwfm_index *idx, const bwfm_aln_params *ap, const b
 int bwfm_server_submit(bwfm_server *srv, const uint8_t *bases1, const uint64_t *offsets1, const uint8_t *bases2,
                        const uint64_t *offsets2, uint32_t n_pairs, uint64_t *ticket);
 
-/* Block until the request is done; copy its n_pairs pair records to out
- * (host, may be NULL) and its times to *times (may be NULL).  Each ticket
- * can be waited for once. */
-int bwfm_server_wait(bwfm_server *srv, uint64_t ticket, bwfm_pair *out, bwfm_request_times *times);
+/* Block until the request is done; copy its n_pairs pair records to out,
+ * with rescue_mapq its n_pairs rescue records to rescue and its 2 n_pairs
+ * MAPQ bytes (end 1, end 2 per pair) to mapq, and its times to *times (host
+ * buffers; each may be NULL; rescue and mapq are left untouched without
+ * rescue_mapq).  Each ticket can be waited for once. */
+int bwfm_server_wait(bwfm_server *srv, uint64_t ticket, bwfm_pair *out, bwfm_rescue *rescue, uint8_t *mapq,
+                     bwfm_request_times *times);
 
 int bwfm_server_get_stats(bwfm_server *srv, bwfm_server_stats *out);
 

@@ -75,7 +75,7 @@ class _AlnResult(ctypes.Structure):
 
 class _ServerParams(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_uint64), ("step_pairs", ctypes.c_uint32), ("max_len", ctypes.c_uint32),
-                ("paired", ctypes.c_int32), ("budget_rule", ctypes.c_int32)]
+                ("paired", ctypes.c_int32), ("budget_rule", ctypes.c_int32), ("rescue_mapq", ctypes.c_int32)]
 
 
 class _Times(ctypes.Structure):
@@ -165,7 +165,7 @@ def lib():
             "bwfm_probe_gather": ([P, u64, u32, u32, u32, P, P, P], c_int),
             "bwfm_server_create": ([P, P, P, P, ctypes.POINTER(P)], c_int),
             "bwfm_server_submit": ([P, P, P, P, P, u32, P], c_int),
-            "bwfm_server_wait": ([P, u64, P, P], c_int),
+            "bwfm_server_wait": ([P, u64, P, P, P, P], c_int),
             "bwfm_server_get_stats": ([P, P], c_int),
             "bwfm_server_destroy": ([P], None),
             "bwfm_pipeline_create": ([P, P, P, P, ctypes.POINTER(P)], c_int),
@@ -558,16 +558,18 @@ class Server:
 
     def __init__(self, index: Index, params: Params, lo: int, hi: int, mu: int, max_occ: int,
                  arena_bytes: int = 1 << 30, step_pairs: int = 65536, max_len: int = 150, paired: bool = True,
-                 budget_rule: bool = False):
+                 budget_rule: bool = False, rescue_mapq: bool = False):
         self._index = index  # keep the index alive
         h = ctypes.c_void_p()
         ap = params._c()
         pp = _PairParams(lo, hi, mu, max_occ)
-        sp = _ServerParams(arena_bytes, step_pairs, max_len, 1 if paired else 0, 1 if budget_rule else 0)
+        sp = _ServerParams(arena_bytes, step_pairs, max_len, 1 if paired else 0, 1 if budget_rule else 0,
+                           1 if rescue_mapq else 0)
         _check(lib().bwfm_server_create(index.handle, ctypes.byref(ap), ctypes.byref(pp), ctypes.byref(sp),
                                         ctypes.byref(h)))
         self._h = h
         self.paired = paired
+        self.rescue_mapq = rescue_mapq
 
     def submit(self, bases1: np.ndarray, offsets1: np.ndarray, bases2: np.ndarray | None = None,
                offsets2: np.ndarray | None = None) -> int:
@@ -581,12 +583,20 @@ class Server:
                                         _np_ptr(o2) if o2 is not None else None, len(o1) - 1, ctypes.byref(t)))
         return t.value
 
-    def wait(self, ticket: int, n_pairs: int):
-        """(pair records PAIR_DTYPE[n_pairs], {queued_ms, service_ms, latency_ms})."""
-        out = np.zeros(n_pairs, PAIR_DTYPE)
+    def wait(self, ticket: int, n_pairs: int, extras: bool = False):
+        """(pair records PAIR_DTYPE[n_pairs], {queued_ms, service_ms, latency_ms});
+        with extras (a rescue_mapq server), also the rescue records
+        RESCUE_DTYPE[n_pairs] and the MAPQ bytes uint8[n_pairs, 2]."""
+        out = np.zeros(max(n_pairs, 1), PAIR_DTYPE)
+        resc = np.zeros(max(n_pairs, 1), RESCUE_DTYPE)
+        mq = np.zeros((max(n_pairs, 1), 2), np.uint8)
         tm = _Times()
-        _check(lib().bwfm_server_wait(self._h, ticket, _np_ptr(out), ctypes.byref(tm)))
-        return out, {"queued_ms": tm.queued_ms, "service_ms": tm.service_ms, "latency_ms": tm.latency_ms}
+        _check(lib().bwfm_server_wait(self._h, ticket, _np_ptr(out), _np_ptr(resc) if extras else None,
+                                      _np_ptr(mq) if extras else None, ctypes.byref(tm)))
+        times = {"queued_ms": tm.queued_ms, "service_ms": tm.service_ms, "latency_ms": tm.latency_ms}
+        if extras:
+            return out[:n_pairs], resc[:n_pairs], mq[:n_pairs], times
+        return out[:n_pairs], times
 
     def stats(self) -> dict:
         s = _ServerStats()

@@ -47,6 +47,8 @@ struct Request {
     uint32_t next_pair = 0;         // first pair not yet scheduled
     uint32_t done_pairs = 0;
     std::vector<bwfm_pair> out;
+    std::vector<bwfm_rescue> resc;  // with rescue_mapq
+    std::vector<uint8_t> mapq;      // with rescue_mapq: 2 per pair
     double t_submit = 0, t_admit = 0, t_done = 0;
     int state = 0;  // 0 queued, 1 admitted, 2 done, 3 failed
     int err = 0;
@@ -107,6 +109,8 @@ struct bwfm_server {
     uint32_t *d_c1 = nullptr, *d_c2 = nullptr;
     uint8_t *d_status = nullptr;
     bwfm_pair *d_pairs = nullptr;
+    bwfm_rescue *d_resc = nullptr;  // with rescue_mapq
+    uint8_t *d_mapq = nullptr;
     // the step as a captured graph over the buffers above (NULL: eager calls)
     bwfm_pipeline *pipe = nullptr;
     uint64_t pipe_hits = 0, pipe_pos = 0;
@@ -116,6 +120,8 @@ struct bwfm_server {
     std::vector<uint8_t> h_md;
     uint8_t rule[BWFM_MAX_READ + 1];
     std::vector<bwfm_pair> h_pairs;
+    std::vector<bwfm_rescue> h_resc;
+    std::vector<uint8_t> h_mapq;
     // state
     Arena arena{0};
     std::mutex mu;
@@ -158,8 +164,8 @@ int make_pipeline(bwfm_server *s, uint64_t hits, uint64_t pos) {
 void release_device(bwfm_server *s) {
     if (s->pipe) bwfm_pipeline_destroy(s->pipe);
     s->pipe = nullptr;
-    void *ptrs[] = {s->arena_mem, s->d_off, s->d_len, s->d_md,   s->d_hoff,
-                    s->d_hits,      s->d_c1,  s->d_c2,  s->d_status, s->d_pairs};
+    void *ptrs[] = {s->arena_mem, s->d_off, s->d_len,    s->d_md,    s->d_hoff, s->d_hits,
+                    s->d_c1,      s->d_c2,  s->d_status, s->d_pairs, s->d_resc, s->d_mapq};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -167,14 +173,49 @@ void release_device(bwfm_server *s) {
 
 using Chunks = std::vector<std::tuple<std::shared_ptr<Request>, uint32_t, uint32_t>>;
 
-// hand the step's pair records (in chunk order) to their requests
+// hand the step's records (in chunk order) to their requests
 void scatter_pairs(bwfm_server *s, const Chunks &chunks) {
     uint32_t o = 0;
     for (auto &c : chunks) {
         Request &q = *std::get<0>(c);
-        std::memcpy(q.out.data() + std::get<1>(c), s->h_pairs.data() + o, sizeof(bwfm_pair) * std::get<2>(c));
-        o += std::get<2>(c);
+        const uint32_t j = std::get<1>(c), k = std::get<2>(c);
+        std::memcpy(q.out.data() + j, s->h_pairs.data() + o, sizeof(bwfm_pair) * k);
+        if (s->sp.rescue_mapq) {
+            std::memcpy(q.resc.data() + j, s->h_resc.data() + o, sizeof(bwfm_rescue) * k);
+            std::memcpy(q.mapq.data() + 2 * (size_t)j, s->h_mapq.data() + 2 * (size_t)o, 2 * (size_t)k);
+        }
+        o += k;
     }
+}
+
+// The step's pair records (device, dp) to the host; with rescue_mapq, first
+// the mates' rescue and the MAPQ of both ends from the step's alignments
+// (r2 NULL: single-end); then scatter.
+int finish_step(bwfm_server *s, const Chunks &chunks, uint32_t P, const bwfm_pair *dp, const bwfm_aln_result &r1,
+                const bwfm_aln_result *r2) {
+    if (s->sp.rescue_mapq) {
+        const bool rule = s->sp.budget_rule != 0;
+        if (r2) {
+            bwfm_reads e1{s->arena_mem, s->d_off, nullptr, P, s->sp.max_len, s->d_len};
+            bwfm_reads e2{s->arena_mem, s->d_off + P, nullptr, P, s->sp.max_len, s->d_len + P};
+            if (int rc = bwfm_rescue_mates(s->ix, &e1, &e2, P, dp, &s->pp, nullptr, s->d_resc, s->stream)) return rc;
+        } else if (P && hipMemsetAsync(s->d_resc, 0, sizeof(bwfm_rescue) * P, s->stream) != hipSuccess) {
+            return fail(BWFM_E_DEVICE, "server: clearing rescue records failed");
+        }
+        if (int rc = bwfm_mapq(P, &r1, r2, rule ? s->d_md : nullptr, rule && r2 ? s->d_md + P : nullptr,
+                               (uint32_t)s->ap.max_diff, dp, r2 ? s->d_resc : nullptr, nullptr, s->d_mapq, s->stream))
+            return rc;
+        if (hipMemcpyAsync(s->h_resc.data(), s->d_resc, sizeof(bwfm_rescue) * P, hipMemcpyDeviceToHost, s->stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(s->h_mapq.data(), s->d_mapq, 2ull * P, hipMemcpyDeviceToHost, s->stream) != hipSuccess)
+            return fail(BWFM_E_DEVICE, "server: result download failed");
+    }
+    if (hipMemcpyAsync(s->h_pairs.data(), dp, sizeof(bwfm_pair) * P, hipMemcpyDeviceToHost, s->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return fail(BWFM_E_DEVICE, "server: result download failed");
+    scatter_pairs(s, chunks);
+    return BWFM_OK;
 }
 
 // One scheduling step over the chunks (request, first pair, pair count).
@@ -211,14 +252,11 @@ int run_step(bwfm_server *s, Chunks &chunks) {
         if (rc) return rc;
         if (!ps.error) {
             bwfm_pair *dp = nullptr;
-            rc = bwfm_pipeline_outputs(s->pipe, 0, nullptr, nullptr, nullptr, &dp);
+            bwfm_aln_result pr1{}, pr2{};
+            rc = bwfm_pipeline_outputs(s->pipe, 0, &pr1, nullptr, nullptr, &dp);
+            if (!rc && paired) rc = bwfm_pipeline_outputs(s->pipe, 1, &pr2, nullptr, nullptr, nullptr);
             if (rc) return rc;
-            if (hipMemcpyAsync(s->h_pairs.data(), dp, sizeof(bwfm_pair) * P, hipMemcpyDeviceToHost, s->stream) !=
-                    hipSuccess ||
-                hipStreamSynchronize(s->stream) != hipSuccess)
-                return fail(BWFM_E_DEVICE, "server: result download failed");
-            scatter_pairs(s, chunks);
-            return BWFM_OK;
+            return finish_step(s, chunks, P, dp, pr1, paired ? &pr2 : nullptr);
         }
         rc = make_pipeline(s, std::max(s->pipe_hits, ps.n_hits + ps.n_hits / 4 + 1024),
                            std::max(s->pipe_pos, ps.n_positions + ps.n_positions / 4 + 4096));
@@ -247,12 +285,7 @@ int run_step(bwfm_server *s, Chunks &chunks) {
     r2.status = s->d_status + P;
     rc = bwfm_pair_reads(s->ix, P, &r1, paired ? &r2 : nullptr, &s->pp, s->d_pairs, s->stream);
     if (rc) return rc;
-    if (hipMemcpyAsync(s->h_pairs.data(), s->d_pairs, sizeof(bwfm_pair) * P, hipMemcpyDeviceToHost, s->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess)
-        return fail(BWFM_E_DEVICE, "server: result download failed");
-    scatter_pairs(s, chunks);
-    return BWFM_OK;
+    return finish_step(s, chunks, P, s->d_pairs, r1, paired ? &r2 : nullptr);
 }
 
 void worker_main(bwfm_server *s) {
@@ -352,6 +385,8 @@ extern "C" int bwfm_server_create(const bwfm_index *ix, const bwfm_aln_params *a
         return fail(BWFM_E_INVAL, "server_create: bad server parameters");
     if (ap->form != BWFM_FORM_BATCHED && ap->form != BWFM_FORM_PLAIN)
         return fail(BWFM_E_INVAL, "server_create: bad form");
+    if (sp->rescue_mapq && sp->paired && (pp->hi > BWFM_RESCUE_MAX_WINDOW || pp->lo > pp->hi))
+        return fail(BWFM_E_INVAL, "server_create: insert window unfit for mate rescue");
     auto s = std::make_unique<bwfm_server>();
     s->ix = ix;
     s->ap = *ap;
@@ -368,7 +403,9 @@ extern "C" int bwfm_server_create(const bwfm_index *ix, const bwfm_aln_params *a
         hipMalloc(&s->d_hoff, 8 * (R + 1)) != hipSuccess ||
         hipMalloc(&s->d_hits, 16 * s->hit_cap) != hipSuccess || hipMalloc(&s->d_c1, 4 * R) != hipSuccess ||
         hipMalloc(&s->d_c2, 4 * R) != hipSuccess || hipMalloc(&s->d_status, R) != hipSuccess ||
-        hipMalloc(&s->d_pairs, sizeof(bwfm_pair) * sp->step_pairs) != hipSuccess) {
+        hipMalloc(&s->d_pairs, sizeof(bwfm_pair) * sp->step_pairs) != hipSuccess ||
+        (sp->rescue_mapq && (hipMalloc(&s->d_resc, sizeof(bwfm_rescue) * sp->step_pairs) != hipSuccess ||
+                             hipMalloc(&s->d_mapq, 2ull * sp->step_pairs) != hipSuccess))) {
         release_device(s.get());
         return fail(BWFM_E_NOMEM, "server_create: device allocation failed");
     }
@@ -378,6 +415,10 @@ extern "C" int bwfm_server_create(const bwfm_index *ix, const bwfm_aln_params *a
     for (uint32_t L = 0; L <= BWFM_MAX_READ; L++)
         s->rule[L] = (uint8_t)std::min(bwfm_max_diff_rule(L, 0.02, 0.04), BWFM_MAX_DIFF);
     s->h_pairs.resize(sp->step_pairs);
+    if (sp->rescue_mapq) {
+        s->h_resc.resize(sp->step_pairs);
+        s->h_mapq.resize(2ull * sp->step_pairs);
+    }
     if (int rc = make_pipeline(s.get(), s->hit_cap, 64 * R + 4096)) {
         release_device(s.get());
         return rc;
@@ -411,6 +452,10 @@ extern "C" int bwfm_server_submit(bwfm_server *s, const uint8_t *b1, const uint6
     if (q->bytes > s->sp.arena_bytes)
         return fail(BWFM_E_CAPACITY, "server_submit: request larger than the arena");
     q->out.resize(n_pairs);
+    if (s->sp.rescue_mapq) {
+        q->resc.resize(n_pairs);
+        q->mapq.resize(2 * (size_t)n_pairs);
+    }
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return fail(BWFM_E_STATE, "server_submit: server is stopping");
     q->id = s->next_id++;
@@ -422,7 +467,8 @@ extern "C" int bwfm_server_submit(bwfm_server *s, const uint8_t *b1, const uint6
     return BWFM_OK;
 }
 
-extern "C" int bwfm_server_wait(bwfm_server *s, uint64_t ticket, bwfm_pair *out, bwfm_request_times *times) {
+extern "C" int bwfm_server_wait(bwfm_server *s, uint64_t ticket, bwfm_pair *out, bwfm_rescue *rescue, uint8_t *mapq,
+                                bwfm_request_times *times) {
     if (!s) return fail(BWFM_E_INVAL, "server_wait: NULL server");
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->all.find(ticket);
@@ -432,6 +478,8 @@ extern "C" int bwfm_server_wait(bwfm_server *s, uint64_t ticket, bwfm_pair *out,
     s->all.erase(it);
     if (q->state == 3) return fail(q->err, "server: request failed: " + s->worker_msg);
     if (out) std::memcpy(out, q->out.data(), sizeof(bwfm_pair) * q->n_pairs);
+    if (rescue && s->sp.rescue_mapq) std::memcpy(rescue, q->resc.data(), sizeof(bwfm_rescue) * q->n_pairs);
+    if (mapq && s->sp.rescue_mapq) std::memcpy(mapq, q->mapq.data(), 2 * (size_t)q->n_pairs);
     if (times) {
         times->queued_ms = q->t_admit - q->t_submit;
         times->latency_ms = q->t_done - q->t_submit;

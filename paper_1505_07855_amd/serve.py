@@ -42,7 +42,7 @@ def replay(server, reqs, rate_per_s: float, seed: int):
         for i in range(len(reqs)):
             while tickets[i] is None:
                 time.sleep(0.0002)
-            _, t = server.wait(tickets[i], reqs[i][4])
+            t = server.wait(tickets[i], reqs[i][4], extras=server.rescue_mapq)[-1]
             lat[i] = t
         done.set()
 
@@ -80,6 +80,7 @@ def main():
     ap.add_argument("--step-pairs", type=int, default=131072)
     ap.add_argument("--arena-mib", type=int, default=2048)
     ap.add_argument("--device-index", action="store_true", help="build the index on the GPU (for 3.1 Gbp)")
+    ap.add_argument("--rescue-mapq", action="store_true", help="also rescue mates and assign MAPQ in every step")
     args = ap.parse_args()
 
     import paper_1505_07855_amd as bw
@@ -92,14 +93,14 @@ def main():
     w = configs.PAIR_WINDOW
     params = bw.Params(**configs.PARAMS["C3"])
     srv = bw.Server(ix, params, w["lo"], w["hi"], w["mu"], configs.MAX_OCC, arena_bytes=args.arena_mib << 20,
-                    step_pairs=args.step_pairs, max_len=150, budget_rule=True)
+                    step_pairs=args.step_pairs, max_len=150, budget_rule=True, rescue_mapq=args.rescue_mapq)
     print("[serve] server up", file=sys.stderr, flush=True)
     # capacity: a saturating burst
     burst = make_requests(g, 20, 4001, 50_000, 50_000)
     lat, wall = replay(srv, burst, 0.0, 1)
     cap_pairs = sum(r[4] for r in burst) / wall
     mean_size = (args.max_pairs - args.min_pairs) / np.log(args.max_pairs / args.min_pairs)
-    out = {"genome": args.genome, "capacity_pairs_per_s": cap_pairs, "mean_request_pairs": mean_size, "rates": []}
+    out = {"genome": args.genome, "rescue_mapq": args.rescue_mapq, "capacity_pairs_per_s": cap_pairs, "mean_request_pairs": mean_size, "rates": []}
     print(f"[serve] capacity {cap_pairs:.0f} pairs/s", file=sys.stderr, flush=True)
     for k, rho in enumerate(args.rates):
         reqs = make_requests(g, args.requests, 5000 + k, args.min_pairs, args.max_pairs)

@@ -120,3 +120,52 @@ def test_request_larger_than_arena_is_rejected(setup):
     out, _ = srv.wait(t, small[4])
     srv.close()
     assert len(out) == small[4]
+
+
+def test_served_rescue_and_mapq(setup):
+    """A rescue_mapq server: every request's pair, rescue and MAPQ records
+    equal those of its pairs run alone through the direct calls, with steps
+    smaller than the requests; one request also against the oracle."""
+    g, ix, reqs = setup
+    w = configs.PAIR_WINDOW
+    p = bw.Params(**configs.PARAMS["C3"])
+    srv = bw.Server(ix, p, w["lo"], w["hi"], w["mu"], configs.MAX_OCC, arena_bytes=16 << 20, step_pairs=1500,
+                    max_len=150, budget_rule=True, rescue_mapq=True)
+    tickets = [srv.submit(r[0], r[1], r[2], r[3]) for r in reqs]
+    outs = [srv.wait(t, r[4], extras=True) for t, r in zip(tickets, reqs)]
+    srv.close()
+    for i, r in enumerate(reqs):
+        b1, o1, b2, o2, n = r
+        both = np.concatenate([b1, b2])
+        offs = np.concatenate([o1[:-1], o1[-1] + o2]).astype(np.uint64)
+        md = np.array([bw.max_diff_rule(int(x)) for x in np.diff(offs)], np.uint8)
+        res = bw.align_batch(ix, torch.from_numpy(both).cuda(), torch.from_numpy(offs.view(np.int64)).cuda(), p,
+                             max_diff=torch.from_numpy(md).cuda(), max_len=150)
+        r1, r2 = res.window(0, n), res.window(n, 2 * n)
+        prs = bw.pair_reads(ix, r1, r2, w["lo"], w["hi"], w["mu"], configs.MAX_OCC)
+        e1 = (torch.from_numpy(b1).cuda(), torch.from_numpy((o1 - o1[0]).view(np.int64)).cuda())
+        e2 = (torch.from_numpy(b2).cuda(), torch.from_numpy((o2 - o2[0]).view(np.int64)).cuda())
+        resc = bw.rescue_mates(ix, e1, e2, prs, w["lo"], w["hi"], max_len=150)
+        mdd = torch.from_numpy(md).cuda()
+        mq = bw.mapq(r1, r2, prs, rescue=resc, budgets1=mdd[:n], budgets2=mdd[n:]).cpu().numpy()[:n]
+        got_p, got_r, got_q, _ = outs[i]
+        assert np.array_equal(got_p.view(np.uint8), bw.pairs_numpy(prs)[:n].view(np.uint8)), f"pairs {i}"
+        assert np.array_equal(got_r.view(np.uint8), bw.rescue_numpy(resc)[:n].view(np.uint8)), f"rescue {i}"
+        assert np.array_equal(got_q, mq), f"mapq {i}"
+    # request 5 against the oracle's chain
+    b1, o1, b2, o2, n = reqs[5]
+    ox = oracle.Index(g.seq)
+    op = oracle.Params(**configs.PARAMS["C3"])
+    ores, mds = [], []
+    for b, o in ((b1, o1), (b2, o2)):
+        md = np.array([oracle.max_diff_rule(int(x)) for x in np.diff(o)], np.uint8)
+        mds.append(md)
+        ores.append(oracle.align(ox, b, o, op, max_diff=md, threads=8))
+    locs = [oracle.locate(ox, x.hits, configs.MAX_OCC) for x in ores]
+    exp = oracle.pair(ores[0], locs[0][0], locs[0][1], ores[1], locs[1][0], locs[1][1], w["lo"], w["hi"], w["mu"])
+    eres = oracle.rescue(g.seq, (b1, o1 - o1[0]), (b2, o2 - o2[0]), exp, w["lo"], w["hi"])
+    emq = oracle.mapq(ores[0], ores[1], exp, rescue=eres, budgets1=mds[0], budgets2=mds[1])
+    got_p, got_r, got_q, _ = outs[5]
+    assert np.array_equal(got_p.view(np.uint8), exp.view(np.uint8))
+    assert np.array_equal(got_r.view(np.uint8), eres.view(np.uint8))
+    assert np.array_equal(got_q, emq)
