@@ -16,6 +16,13 @@ checked against properties that hold at any size:
 * the tier rule: every reported hit scores at most S* + s_mm; tier-2 hits
   only when c1 <= max_best; c1 and c2 are the summed widths of the tiers;
 * report order (score, strand, k, len) without repeated (strand, k, len).
+
+Then the whole batch is paired, its mates rescued and MAPQ assigned, and
+checked by properties: rescue only where no proper pair exists, inserts
+within the window, scores within bounds, the reported span of a sample of
+rescued mates holding a local alignment of exactly the reported score, most
+rescued mates at their generated origin; MAPQ equal on both ends of a proper
+pair, 0 for ends left unplaced, a rescued mate's equal to its anchor's.
 """
 from __future__ import annotations
 
@@ -130,3 +137,58 @@ def test_c3_full_size_properties():
                 assert (int(t.strand[j]), int(t.pos[j]), int(t.ref_len[j])) in located, r
     _log(f"checked {n_checked} hits, {n_truth} reads with valid scripts")
     assert n_checked > SAMPLE // 2 and n_truth > SAMPLE // 2
+
+    # pairing, mate rescue and MAPQ over the whole batch
+    w = configs.PAIR_WINDOW
+    t0 = time.time()
+    r1, r2 = res.window(0, n), res.window(n, 2 * n)
+    prs = bw.pair_reads(ix, r1, r2, w["lo"], w["hi"], w["mu"], configs.MAX_OCC)
+    ends = [(torch.from_numpy(e.bases).cuda(), torch.from_numpy(e.offsets.view(np.int64)).cuda()) for e in (e1, e2)]
+    resc = bw.rescue_mates(ix, ends[0], ends[1], prs, w["lo"], w["hi"], max_len=150)
+    again = bw.rescue_mates(ix, ends[0], ends[1], prs, w["lo"], w["hi"], max_len=150)
+    mdd = torch.from_numpy(md).cuda()
+    mq = bw.mapq(r1, r2, prs, rescue=resc, budgets1=mdd[:n], budgets2=mdd[n:]).cpu().numpy()[:n]
+    torch.cuda.synchronize()
+    _log(f"paired, rescued and MAPQ in {time.time() - t0:.1f}s")
+    pr = bw.pairs_numpy(prs)[:n]
+    rs = bw.rescue_numpy(resc)[:n]
+    assert np.array_equal(rs.view(np.uint8), bw.rescue_numpy(again)[:n].view(np.uint8))
+    f = pr["flags"]
+    m1, m2 = (f & bw.PF_MAPPED1) != 0, (f & bw.PF_MAPPED2) != 0
+    cand = ((f & bw.PF_PAIRED) == 0) & (m1 | m2)
+    got = rs["end"] != 0
+    assert not (got & ~cand).any()
+    a1 = m1 & (~m2 | (pr["score1"] <= pr["score2"]))
+    assert (rs["end"][got] == np.where(a1, 2, 1)[got]).all()
+    assert (rs["insert"][got] >= w["lo"]).all() and (rs["insert"][got] <= w["hi"]).all()
+    mlen = np.where(rs["end"] == 1, np.diff(e1.offsets), np.diff(e2.offsets)).astype(np.int64)
+    assert (rs["score"][got] >= 20).all() and (rs["score"][got] <= mlen[got]).all()
+    anchor_strand = np.where(a1, pr["strand1"], pr["strand2"])
+    assert (rs["strand"][got] == 1 - anchor_strand[got]).all()
+    _log(f"{int(cand.sum())} pairs without a proper pair, {int(got.sum())} mates rescued")
+    assert got.sum() > 0.5 * cand.sum()
+    # rescued mates at their generated origin (local ends may clip a few bases)
+    idx = np.flatnonzero(got)
+    tpos = np.where(rs["end"][idx] == 1, e1.truth.pos[idx], e2.truth.pos[idx]).astype(np.int64)
+    near = np.abs(rs["pos"][idx].astype(np.int64) - tpos) <= 8
+    _log(f"rescued mates within 8 bases of their origin: {near.mean():.3f}")
+    assert near.mean() > 0.8
+    # a sample's reported span holds a local alignment of exactly that score
+    for i in rng.choice(idx, min(200, len(idx)), replace=False):
+        rec = rs[i]
+        e = e1 if rec["end"] == 1 else e2
+        mate = e.read(int(i))
+        q = revcomp(mate) if rec["strand"] == 1 else mate
+        span = gs[int(rec["pos"]):int(rec["pos"]) + int(rec["len"])]
+        sc, _, _ = oracle.local_best(q, span, -1)
+        assert sc == int(rec["score"]), i
+    # MAPQ
+    paired = (f & bw.PF_PAIRED) != 0
+    assert (mq <= 60).all() and (mq[paired, 0] == mq[paired, 1]).all()
+    un1 = (pr["pos1"] == 0xFFFFFFFF) & (rs["end"] != 1)
+    un2 = (pr["pos2"] == 0xFFFFFFFF) & (rs["end"] != 2)
+    assert (mq[un1, 0] == 0).all() and (mq[un2, 1] == 0).all()
+    r_2, r_1 = rs["end"] == 2, rs["end"] == 1
+    assert (mq[r_2, 1] == mq[r_2, 0]).all() and (mq[r_1, 0] == mq[r_1, 1]).all()
+    assert (mq[~paired] <= 37).all()
+    _log(f"MAPQ 60 on {np.mean(mq == 60):.3f} of ends")
