@@ -61,12 +61,12 @@ def kernel_source_hash(kernel: str = "k_align_persistent") -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str):
+def traffic_from_profiles(kernel: str, workload: str = "c2"):
     """HBM-side bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same
     counter reads for a device copy of known size), or None when the summary
     was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_bytes.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_bytes.md")
     if not os.path.exists(path):
         return None
     rec = None
@@ -140,6 +140,97 @@ def rescue_leg(bw, torch, ix, ends, results, prs, n, w, stream, launches, n_ref,
                                   "bytes_per_launch": mq_bytes}}}
 
 
+def main_c3(args):
+    """The uneven-length workload at full size (3.1 Gbp reference indexed on
+    the device, 10M pairs of 36-150 bp with per-read budgets): the batched
+    step (both ends in one persistent launch, locate, pair), timed as the
+    default workload is.  Its index lives in HBM, so its roofline compares
+    line fills with the gather probe on an index-sized buffer; the oracle
+    cannot index 3.1 Gbp within a bench run, so there is no CPU baseline and
+    no algorithmic byte count: the fills come from the committed FETCH_SIZE
+    summary of this workload."""
+    import torch
+
+    import paper_1505_07855_amd as bw
+    from gen import configs
+
+    torch.cuda.set_device(0)
+    genome = args.genome if args.genome != 100_000_000 else 3_100_000_000
+    n = args.pairs if args.pairs != 1_000_000 else 10_000_000
+    t0 = time.time()
+    g = configs.c2_genome(genome, seed=1003)
+    ix = bw.Index.build_device(g.seq, **configs.LAYOUT["C3"])
+    pairs = configs.c3_pairs(g, n)
+    log(f"C3 inputs and device index in {time.time() - t0:.1f}s ({ix.info()['device_bytes'] / 1e9:.2f} GB)")
+    e1, e2 = pairs.end1, pairs.end2
+    L = np.concatenate([np.diff(e1.offsets), np.diff(e2.offsets)]).astype(np.int64)
+    rule = np.array([bw.max_diff_rule(x) for x in range(513)], np.uint8)
+    md = torch.from_numpy(rule[L]).cuda()
+    bases = torch.from_numpy(np.concatenate([e1.bases, e2.bases])).cuda()
+    offs = torch.from_numpy(np.concatenate([e1.offsets[:-1], e1.offsets[-1] + e2.offsets]).view(np.int64)).cuda()
+    del g, pairs
+    p = bw.Params(**configs.PARAMS["C3"], waves_per_simd=args.waves_per_simd)
+    w = configs.PAIR_WINDOW
+    state = [None, None]
+
+    def step():
+        state[0] = bw.align_batch(ix, bases, offs, p, max_diff=md, max_len=150, out=state[0], hit_capacity=16 * n)
+        r1, r2 = state[0].window(0, n), state[0].window(n, 2 * n)
+        state[1] = bw.pair_reads(ix, r1, r2, w["lo"], w["hi"], w["mu"], configs.MAX_OCC, out=state[1])
+        return r1, r2
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"C3 warmup step {i + 1}/{args.warmup} done")
+    bw.timing_enable(True)
+    bw.timing_reset()
+    times = []
+    for i in range(args.steps):
+        t = time.perf_counter()
+        r1, r2 = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        log(f"C3 step {i + 1}/{args.steps}: {times[-1] * 1e3:.1f} ms")
+    bw.timing_enable(False)
+    kms, kl = bw.timing_get("align_persistent")
+    k_ms = kms / kl if kl else None
+    st = state[0].status.cpu().numpy()
+    aligned = int(((st & bw.ST_HIT) != 0).sum())
+    ms_step = sum(times) / len(times) * 1e3
+    value = aligned / (ms_step / 1e3)
+    roofline = None
+    traffic = traffic_from_profiles("k_align_persistent", "c3")
+    buf = torch.zeros(2048 << 20, dtype=torch.uint8, device="cuda")
+    bw.probe_gather(buf, 64, iters=16)
+    probe_lps = bw.probe_gather(buf, 64)
+    del buf
+    if k_ms:
+        fills_ps = traffic / 128 / (k_ms / 1e3) if traffic else None
+        roofline = {"bound": "hbm", "achieved": traffic / (k_ms / 1e3) / 1e9 if traffic else None,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": traffic / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS if traffic else None, "traffic": traffic,
+                    "kernel": "k_align_persistent", "avg_launch_ms": k_ms, "reads_per_launch": 2 * n,
+                    "basis": "counter-measured HBM-side bytes per launch (no oracle count at 3.1 Gbp)",
+                    "random_line_ceiling": {"probe_lines_per_s": probe_lps, "probe_buffer_mib": 2048,
+                                            "kernel_fills_per_s": fills_ps,
+                                            "frac": fills_ps / probe_lps if fills_ps else None}}
+    out = {
+        "metric": METRIC, "value": value, "unit": "aligned reads/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"C3 batched: {genome / 1e9:.1f} Gbp synthetic genome (GC 41%, 40% repeats), {n} pairs "
+                               "of 36-150 bp, per-read budgets 2-6, 1 gap open, seed 32/<=2",
+                   "pairs": n, "reads": 2 * n, "form": "batched: both ends in one persistent launch, locate, pair",
+                   "parallelism": "1 GPU"},
+        "p50_ms": float(np.percentile(np.array(times) * 1e3, 50)),
+        "p99_ms": float(np.percentile(np.array(times) * 1e3, 99)),
+        "aligned_fraction": aligned / (2 * n), "roofline": roofline, "cpu_baseline": None,
+        "cpu_baseline_note": "the oracle cannot index a 3.1 Gbp reference within a bench run",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,11 +248,16 @@ def main():
     ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue measurement")
     ap.add_argument("--rescue-launches", type=int, default=10)
     ap.add_argument("--steps-plain", type=int, default=0, help="steps for the plain form (default: --steps)")
+    ap.add_argument("--config", choices=("c2", "c3"), default="c2",
+                    help="c2: the benchmark workload (default); c3: the 3.1 Gbp uneven-length workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path would shard "
               "read pairs across GPUs with a replicated index, which is not built here)", file=sys.stderr)
         sys.exit(2)
+    if args.config == "c3":
+        main_c3(args)
+        return
 
     import torch
 
@@ -282,10 +378,34 @@ def main():
     plain = run("plain", step_plain, args.steps_plain or args.steps)
     eager = run("batched-eager", step_eager, args.steps_plain or args.steps)
     batched = run("batched", step_graph, args.steps)
+
+    # end to end: the same step with the reads coming from pinned host memory
+    # and the results (pair records, per-read status, c1, c2) going back to it
+    h_b = torch.from_numpy(np.concatenate([e1.bases, e2.bases])).pin_memory()
+    h_o = torch.from_numpy(np.concatenate([e1.offsets[:-1], e1.offsets[-1] + e2.offsets]).view(np.int64)).pin_memory()
+    h_out = {"pairs": torch.empty((n, 24), dtype=torch.uint8).pin_memory(),
+             "status": torch.empty(2 * n, dtype=torch.uint8).pin_memory(),
+             "c1": torch.empty(2 * n, dtype=torch.int32).pin_memory(),
+             "c2": torch.empty(2 * n, dtype=torch.int32).pin_memory()}
+
+    def step_e2e():
+        both_b.copy_(h_b, non_blocking=True)
+        both_o.copy_(h_o, non_blocking=True)
+        pipe.set_reads(both_b, both_o, n, max_len=100, stream=stream)
+        r1, r2, prs = step_graph()
+        h_out["pairs"].copy_(prs[:n], non_blocking=True)
+        for k in ("status", "c1", "c2"):
+            h_out[k][:n].copy_(getattr(r1, k), non_blocking=True)
+            h_out[k][n:].copy_(getattr(r2, k), non_blocking=True)
+        return r1, r2, prs
+
+    e2e = run("end-to-end", step_e2e, args.steps)
     # every form must agree exactly
-    a_out, e_out, b_out = plain.pop("out"), eager.pop("out"), batched.pop("out")
-    if not same(a_out, b_out) or not same(e_out, b_out):
+    a_out, e_out, b_out, x_out = plain.pop("out"), eager.pop("out"), batched.pop("out"), e2e.pop("out")
+    if not same(a_out, b_out) or not same(e_out, b_out) or not same(x_out, b_out):
         raise SystemExit("plain, eager batched and captured batched forms disagree")
+    if not np.array_equal(h_out["pairs"].numpy(), bw.pairs_numpy(b_out[2])[:n].view(np.uint8).reshape(n, 24)):
+        raise SystemExit("pair records copied to the host differ")
     n_reads = 2 * n
     aligned = batched["aligned"]
     ms_step = batched["ms_per_step"]
@@ -367,6 +487,9 @@ def main():
         "aligned_fraction": aligned / n_reads, "paired_fraction": batched["paired_fraction"],
         "plain": {k: v for k, v in plain.items()}, "batched": {k: v for k, v in batched.items()},
         "batched_eager": {k: v for k, v in eager.items()}, "autotune": tune,
+        "end_to_end": {"ms_per_step": e2e["ms_per_step"], "aligned_reads_per_s": e2e["aligned_reads_per_s"],
+                       "p99_ms": e2e["p99_ms"],
+                       "note": "reads from pinned host memory, pair records, status, c1, c2 back to it"},
         "roofline": roofline, "cpu_baseline": cpu, "rescue": rescue,
     }
     print(json.dumps(out), flush=True)
