@@ -45,14 +45,25 @@ namespace {
 
 // ------------------------------------------------------------------ constants
 
-constexpr int GAP_NONE = 0, GAP_INS = 1, GAP_DEL = 2;
+constexpr int GAP_INS = 1, GAP_DEL = 2;  // gap state of a search state (0: not in a gap)
 constexpr uint32_t ST_RESEARCH = 8;  // status bit: needed the second pass
 constexpr int PH_FAST = 0, PH_BEST = 1, PH_COLLECT = 2;
 constexpr int INF_SCORE = 0x7fffffff;
 constexpr uint32_t PLAIN_STACK = 320;  // stack entries per lane, plain form first pass
-constexpr uint32_t FAST_CAND = 64;     // hit slots per lane, first pass
+// Tuning constants a variant build may override with -D (results do not
+// depend on them; paper_1505_07855_amd/variants.py searches over them).
+#ifndef BWFM_FAST_CAND
+#define BWFM_FAST_CAND 64
+#endif
+#ifndef BWFM_POPS_PER_STEP
+#define BWFM_POPS_PER_STEP 1
+#endif
+#ifndef BWFM_SLOW_LANES
+#define BWFM_SLOW_LANES 16384
+#endif
+constexpr uint32_t FAST_CAND = BWFM_FAST_CAND;  // hit slots per lane, first pass
 constexpr int BLOCK = 256;
-constexpr int POPS_PER_STEP = 1;  // stack pops per lane per persistent iteration (more costs the
+constexpr int POPS_PER_STEP = BWFM_POPS_PER_STEP;  // stack pops per lane per persistent iteration (more costs the
                                   // whole wave a pass of the pop code; measured best at 1)
 
 struct Params {
@@ -1813,7 +1824,7 @@ inline uint32_t block_for(uint32_t stride) {
     return bs;
 }
 
-constexpr uint32_t SLOW_LANES = 16384;  // most lanes of the second pass
+constexpr uint32_t SLOW_LANES = BWFM_SLOW_LANES;  // most lanes of the second pass
 
 template <int LW>
 int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, bwfm_aln_result *res,

@@ -64,9 +64,12 @@ def _check_run(pl, n, exp):
     assert st["n_hits"] == int(po_h.shape[0] - 1) and st["n_positions"] == len(want_pos)
 
 
-@pytest.mark.parametrize("form", [bw.FORM_BATCHED, bw.FORM_PLAIN])
-def test_pipeline_eager_and_graph_replays_equal_oracle(setup, form):
+@pytest.mark.parametrize("form,fmt", [(bw.FORM_BATCHED, bw.RANK_PLANES), (bw.FORM_PLAIN, bw.RANK_PLANES),
+                                      (bw.FORM_BATCHED, bw.RANK_SUBCOUNTS)])
+def test_pipeline_eager_and_graph_replays_equal_oracle(setup, form, fmt):
     g, pairs, ox, ix = setup
+    if fmt == bw.RANK_SUBCOUNTS:
+        ix = bw.Index(g.seq, line_bytes=64, sa_sample=32, rank_format=fmt).upload()
     w = configs.PAIR_WINDOW
     p = bw.Params(**configs.PARAMS["C2"], form=form)
     op = oracle.Params(**configs.PARAMS["C2"])

@@ -141,3 +141,18 @@ def test_index_save_load_roundtrip_and_corruption(rng, tmp_path, fmt):
         bw.Index.load(str(tmp_path / "missing.bwfm"))
     assert e.value.code == bw.E_IO
     ix.close()
+
+
+def test_variant_knobs_match_the_source_defaults():
+    """The variant search's reference values are the kernel source's own
+    defaults, so its reference build is the shipped library."""
+    import re
+
+    from paper_1505_07855_amd import variants
+    src = open(os.path.join(os.path.dirname(bw.__file__), "csrc", "bwfm.hip")).read()
+    for knob, (ref, alts) in variants.KNOBS.items():
+        m = re.search(r"#ifndef %s\n#define %s (\d+)\n#endif" % (knob, knob), src)
+        assert m and int(m.group(1)) == ref, knob
+        assert ref not in alts
+    names = [n for n, _ in variants.variants()]
+    assert names[0] == "reference" and len(names) == len(set(names)) == 1 + sum(len(a) for _, a in variants.KNOBS.values())
