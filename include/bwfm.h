@@ -583,7 +583,7 @@ void bwfm_server_destroy(bwfm_server *srv);
 
 /*
  * Insert window from n inserts (host) of uniquely placed proper pairs
- * (section 2: the fragment length "can be inferred"): quartiles at index
+ * (section 2: the fragment length is known or estimated from the data): quartiles at index
  * floor(q (n - 1)) of the sorted inserts; inserts outside [p25 - 2 IQR,
  * p75 + 2 IQR] dropped; mu = mean, sigma = population sd of the rest;
  * lo = max(0, floor(mu - 4 sigma)), hi = ceil(mu + 4 sigma), mu rounded

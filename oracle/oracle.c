@@ -13,7 +13,7 @@
  *  - FM-index of T$ (symbols $ < A < C < G < T): suffix array SA, BWT,
  *    C[a] = 1 + #symbols of T smaller than a, Occ(a, i) = #a in BWT[0, i).
  *    A string X has the SA interval [k, l] of the rows whose suffix starts
- *    with X; it is empty iff k > l ("the pointers cross") and its width
+ *    with X; it is empty iff k > l (the two pointers have passed each other) and its width
  *    l - k + 1 is the number of occurrences of X (section 2, the upper and
  *    lower pointer description).  Backward step for aX:
  *        k' = C[a] + Occ(a, k),  l' = C[a] + Occ(a, l + 1) - 1,
