@@ -69,13 +69,11 @@ __device__ __forceinline__ int row_above(int v) {
 
 // Rescue one pair with the whole wave (all arguments wave-uniform).
 template <int R>
-__device__ void rescue_one(const uint32_t *pac, uint64_t n, const EndView &ev, uint32_t pair, int mate, uint32_t pa,
-                           int la, int sa, int lo, int hi, int max_len, const Scores &S, uint8_t *win,
+__device__ void rescue_one(const uint32_t *pac, uint64_t n, const EndView &ev, uint32_t pair, uint64_t o0, int m,
+                           int mate, uint32_t pa, int la, int sa, int lo, int hi, int max_len, const Scores &S,
+                           uint8_t *win,
                            bwfm_rescue *out) {
     const int lane = threadIdx.x & 63;
-    uint64_t o0;
-    int m;
-    end_span(ev, pair, o0, m);
     int64_t w0, w1;
     if (sa == 0) {
         w0 = pa;
@@ -207,7 +205,10 @@ __device__ void rescue_one(const uint32_t *pac, uint64_t n, const EndView &ev, u
     if (lane == 0) out[pair] = res;
 }
 
-template <int R>
+// RMAX: rows per lane that hold the batch's longest mate; each mate is
+// rescued by the build of the fewest rows per lane that hold it, so short
+// mates of a mixed batch keep more lanes busy and the sweep shorter.
+template <int RMAX>
 __global__ __launch_bounds__(RB) void k_rescue(const uint32_t *pac, uint64_t n, EndView e1, EndView e2,
                                                const bwfm_pair *pairs, uint32_t n_pairs, int lo, int hi, int max_len,
                                                Scores S, int win_stride, bwfm_rescue *out) {
@@ -244,8 +245,23 @@ __global__ __launch_bounds__(RB) void k_rescue(const uint32_t *pac, uint64_t n, 
         const int c_mate = __builtin_amdgcn_readlane(mate, src), c_la = __builtin_amdgcn_readlane(la, src),
                   c_sa = __builtin_amdgcn_readlane(sa, src);
         const uint32_t c_pa = (uint32_t)__builtin_amdgcn_readlane((int)pa, src);
-        rescue_one<R>(pac, n, c_mate == 1 ? e1 : e2, base + (uint32_t)src, c_mate, c_pa, c_la, c_sa, lo, hi, max_len,
-                      S, win, out);
+        const EndView &ev = c_mate == 1 ? e1 : e2;
+        const uint32_t pair = base + (uint32_t)src;
+        uint64_t o0;
+        int m;
+        end_span(ev, pair, o0, m);
+        const int need = m <= 64 ? 1 : m <= 128 ? 2 : m <= 256 ? 4 : 8;
+        if (RMAX >= 8 && need == 8)
+            rescue_one<(RMAX >= 8 ? 8 : 1)>(pac, n, ev, pair, o0, m, c_mate, c_pa, c_la, c_sa, lo, hi, max_len, S, win,
+                                           out);
+        else if (RMAX >= 4 && need == 4)
+            rescue_one<(RMAX >= 4 ? 4 : 1)>(pac, n, ev, pair, o0, m, c_mate, c_pa, c_la, c_sa, lo, hi, max_len, S, win,
+                                           out);
+        else if (RMAX >= 2 && need == 2)
+            rescue_one<(RMAX >= 2 ? 2 : 1)>(pac, n, ev, pair, o0, m, c_mate, c_pa, c_la, c_sa, lo, hi, max_len, S, win,
+                                           out);
+        else  // one row per lane; a mate longer than the batch's bound is reported unrescued there
+            rescue_one<1>(pac, n, ev, pair, o0, m, c_mate, c_pa, c_la, c_sa, lo, hi, max_len, S, win, out);
         wave_sync();  // the window is rewritten for the next pair
     }
 }
