@@ -461,10 +461,17 @@ def main():
         if kf:
             per_launch = bytes_per_read * n_reads
             achieved = per_launch / (kf["avg_ms"] / 1e3) / 1e9
+            traffic = traffic_from_profiles("k_align_persistent")
             roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles("k_align_persistent"),
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                         "kernel": "k_align_persistent", "bytes_per_read": bytes_per_read,
                         "reads_per_launch": n_reads, "avg_launch_ms": kf["avg_ms"], "timed_in": timed_in}
+            if traffic:
+                # each 64-byte line access fills a 128-byte L2 line: the measured
+                # traffic rate, against the same peak
+                rate = traffic / (kf["avg_ms"] / 1e3) / 1e9
+                roofline["traffic_rate"] = rate
+                roofline["traffic_frac"] = rate / HBM_PEAK_GBS
             if probe:
                 lines_ps = per_launch / ix.info()["line_bytes"] / (kf["avg_ms"] / 1e3)
                 roofline["random_line_ceiling"] = {
