@@ -159,7 +159,7 @@ def main_c3(args):
     n = args.pairs if args.pairs != 1_000_000 else 10_000_000
     t0 = time.time()
     g = configs.c2_genome(genome, seed=1003)
-    ix = bw.Index.build_device(g.seq, **configs.LAYOUT["C3"])
+    ix = bw.Index.build_device(g.seq, **configs.LAYOUT["C3"], kmer_levels=args.kmer_levels)
     pairs = configs.c3_pairs(g, n)
     log(f"C3 inputs and device index in {time.time() - t0:.1f}s ({ix.info()['device_bytes'] / 1e9:.2f} GB)")
     e1, e2 = pairs.end1, pairs.end2
@@ -243,6 +243,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--line-bytes", type=int, default=64)
     ap.add_argument("--rank-format", type=int, default=0, help="0: counts + bit planes; 1: sub-counted 160-row lines")
+    ap.add_argument("--kmer-levels", type=int, default=0,
+                    help="short-string interval table levels (0: none, -1: automatic)")
     ap.add_argument("--waves-per-simd", type=int, default=0, help="batched-form residency (0 = autotuned)")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the autotuner (most waves that fit)")
     ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue measurement")
@@ -282,7 +284,8 @@ def main():
     if want_cpu:
         th.start()
     t0 = time.time()
-    ix = bw.Index(g.seq, line_bytes=args.line_bytes, sa_sample=32, rank_format=args.rank_format).upload()
+    ix = bw.Index(g.seq, line_bytes=args.line_bytes, sa_sample=32, rank_format=args.rank_format).upload(
+        kmer_levels=args.kmer_levels)
     log(f"library index built and uploaded in {time.time() - t0:.1f}s ({ix.info()['device_bytes'] / 1e6:.1f} MB)")
 
     w = configs.PAIR_WINDOW

@@ -115,6 +115,35 @@ int bwfm_build_index_device(const uint8_t *ref, uint64_t n, const bwfm_index_par
  * no-ops).  Synchronises hip_stream.  Errors: E_INVAL, E_NOMEM, E_DEVICE. */
 int bwfm_index_upload(bwfm_index *idx, void *hip_stream);
 
+/* Short-string interval table (a device-side accelerator of the search in
+ * section 2; it changes no result).  For each direction and each string S
+ * of d <= levels bases (2 bits per base, the base prepended last in the
+ * low bits: code(aS) = 4 code(S) + a), the table holds the SA interval
+ * (k, l) of S on that direction's index, exactly as backward search steps
+ * reach it (k > l when S does not occur).  Level d starts at entry
+ * 4 + (4^d - 4) / 3 (level 0, entry 0, is the empty string's (0, n)), so the
+ * four one-base extensions of a string are 32 contiguous, 32-byte-aligned
+ * bytes.  The plain form's search and D-array scan, and the batched
+ * form's second pass, take the children of a state whose matched string is
+ * shorter than `levels` bases from there: one access in place of two
+ * rank-line fetches.  The batched form's persistent first pass does not:
+ * there it measured slower.  Built on the device from the
+ * uploaded rank lines; replaces an existing table (no call that uses the
+ * index may run meanwhile; captured pipeline steps are captured again on
+ * their next run).  levels: 0 releases the
+ * table, -1 picks the smallest d with 4^d >= n (at most 14: 2.9 GB per
+ * direction), 1..15 as given (15: 11.5 GB per direction).  Synchronises
+ * hip_stream.  Errors: E_INVAL (NULL, not uploaded, levels out of range),
+ * E_NOMEM, E_DEVICE. */
+int bwfm_index_kmer_table(bwfm_index *idx, int levels, void *hip_stream);
+
+/* Host copy of count entries of level `level` of direction `which`'s
+ * table, from string code `first` on, as (k, l) pairs: out (host,
+ * 2 * count uint32).  For tests.  Errors: E_INVAL (no table, level above
+ * its levels, range beyond 4^level codes), E_DEVICE. */
+int bwfm_index_kmer_get(const bwfm_index *idx, int which, int level, uint64_t first, uint64_t count,
+                        uint32_t *out);
+
 /* Release host and device memory of the index and its workspace. */
 void bwfm_index_free(bwfm_index *idx);
 
@@ -139,6 +168,8 @@ typedef struct {
     uint64_t sa_samples;    /* SA samples per direction */
     uint64_t device_bytes;  /* device memory the uploaded index occupies */
     uint32_t line_bytes, bases_per_line, sa_sample, uploaded, rank_format;
+    uint32_t kmer_levels;   /* levels of the device k-mer interval table (0: none) */
+    uint64_t kmer_bytes;    /* device memory of that table, both directions (each padded to 256 bytes) */
 } bwfm_index_info;
 
 int bwfm_index_get_info(const bwfm_index *idx, bwfm_index_info *out);

@@ -54,7 +54,8 @@ class _IndexInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("primary", ctypes.c_uint64 * 2), ("C", (ctypes.c_uint64 * 4) * 2),
                 ("lines", ctypes.c_uint64), ("sa_samples", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
                 ("line_bytes", ctypes.c_uint32), ("bases_per_line", ctypes.c_uint32),
-                ("sa_sample", ctypes.c_uint32), ("uploaded", ctypes.c_uint32), ("rank_format", ctypes.c_uint32)]
+                ("sa_sample", ctypes.c_uint32), ("uploaded", ctypes.c_uint32), ("rank_format", ctypes.c_uint32),
+                ("kmer_levels", ctypes.c_uint32), ("kmer_bytes", ctypes.c_uint64)]
 
 
 class _Reads(ctypes.Structure):
@@ -118,7 +119,8 @@ SYMBOLS = ("bwfm_build_index", "bwfm_index_upload", "bwfm_index_free", "bwfm_ind
            "bwfm_server_destroy", "bwfm_index_save", "bwfm_index_load", "bwfm_pipeline_create",
            "bwfm_pipeline_set_reads", "bwfm_pipeline_run", "bwfm_pipeline_finish", "bwfm_pipeline_outputs",
            "bwfm_pipeline_destroy", "bwfm_pipeline_bind_reads", "bwfm_pipeline_set_count",
-           "bwfm_build_index_device", "bwfm_index_get_ref", "bwfm_rescue_mates", "bwfm_mapq")
+           "bwfm_build_index_device", "bwfm_index_get_ref", "bwfm_rescue_mates", "bwfm_mapq",
+           "bwfm_index_kmer_table", "bwfm_index_kmer_get")
 
 
 def lib():
@@ -141,6 +143,8 @@ def lib():
         sig = {
             "bwfm_build_index": ([P, u64, P, ctypes.POINTER(P)], c_int),
             "bwfm_index_upload": ([P, P], c_int),
+            "bwfm_index_kmer_table": ([P, c_int, P], c_int),
+            "bwfm_index_kmer_get": ([P, c_int, c_int, u64, u64, P], c_int),
             "bwfm_build_index_device": ([P, u64, P, P, ctypes.POINTER(P)], c_int),
             "bwfm_index_save": ([P, ctypes.c_char_p], c_int),
             "bwfm_index_load": ([ctypes.c_char_p, ctypes.POINTER(P)], c_int),
@@ -249,9 +253,10 @@ class Index:
 
     @classmethod
     def build_device(cls, ref: np.ndarray, line_bytes: int = 128, bases_per_line: int = 0, sa_sample: int = 32,
-                     stream=None, rank_format: int = RANK_PLANES) -> "Index":
+                     stream=None, rank_format: int = RANK_PLANES, kmer_levels: int = 0) -> "Index":
         """The same index built on the current GPU (bwfm_build_index_device);
-        it comes back uploaded."""
+        it comes back uploaded, with a short-string table of kmer_levels
+        levels (as in upload)."""
         ref = np.ascontiguousarray(ref, np.uint8)
         h = ctypes.c_void_p()
         p = _IndexParams(line_bytes, bases_per_line, sa_sample, 0, rank_format)
@@ -260,6 +265,8 @@ class Index:
         self = cls.__new__(cls)
         self._h = h
         self.n = len(ref)
+        if kmer_levels:
+            self.kmer_table(kmer_levels, stream)
         return self
 
     @classmethod
@@ -291,16 +298,36 @@ class Index:
     def handle(self):
         return self._h
 
-    def upload(self, stream=None) -> "Index":
+    def upload(self, stream=None, kmer_levels: int = 0) -> "Index":
+        """Copy the index to the current GPU; with kmer_levels != 0 also
+        build its short-string interval table (bwfm_index_kmer_table: -1
+        picks the levels)."""
         _check(lib().bwfm_index_upload(self._h, _stream_ptr(stream)))
+        if kmer_levels:
+            self.kmer_table(kmer_levels, stream)
         return self
+
+    def kmer_table(self, levels: int = -1, stream=None) -> "Index":
+        """(Re)build the device short-string interval table with `levels`
+        levels (0 releases it)."""
+        _check(lib().bwfm_index_kmer_table(self._h, levels, _stream_ptr(stream)))
+        return self
+
+    def kmer_entries(self, which: int, level: int, first: int = 0, count: int | None = None) -> np.ndarray:
+        """Entries of one table level as an (count, 2) array of (k, l)."""
+        if count is None:
+            count = 4 ** level - first
+        out = np.empty((count, 2), np.uint32)
+        _check(lib().bwfm_index_kmer_get(self._h, which, level, first, count, _np_ptr(out)))
+        return out
 
     def info(self) -> dict:
         i = _IndexInfo()
         _check(lib().bwfm_index_get_info(self._h, ctypes.byref(i)))
         return dict(n=i.n, primary=list(i.primary), C=[list(c) for c in i.C], lines=i.lines, sa_samples=i.sa_samples,
                     device_bytes=i.device_bytes, line_bytes=i.line_bytes, bases_per_line=i.bases_per_line,
-                    sa_sample=i.sa_sample, uploaded=bool(i.uploaded), rank_format=i.rank_format)
+                    sa_sample=i.sa_sample, uploaded=bool(i.uploaded), rank_format=i.rank_format,
+                    kmer_levels=i.kmer_levels, kmer_bytes=i.kmer_bytes)
 
     def bwt(self, which: int = 0) -> np.ndarray:
         out = np.empty(self.n + 1, np.uint8)

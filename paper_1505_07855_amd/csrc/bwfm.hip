@@ -133,6 +133,7 @@ __device__ __forceinline__ DevDir pick_dir(const DevIndex &ix, int which) {
     for (int a = 0; a < 4; a++) d.C[a] = which ? ix.dir[1].C[a] : ix.dir[0].C[a];
     d.primary = which ? ix.dir[1].primary : ix.dir[0].primary;
     d.pad = 0;
+    d.kt = which ? ix.dir[1].kt : ix.dir[0].kt;
     return d;
 }
 
@@ -146,6 +147,27 @@ __device__ __forceinline__ uint32_t line_of(const DevIndex &ix, uint32_t i) {
 // first four 32-row boundaries as bytes, then the bit planes).
 constexpr int LW_SUB = 17;
 template <int LW> constexpr int line_words() { return LW == LW_SUB ? 16 : LW; }
+
+// The four (k, l) pairs of a string's one-base extensions, read from the
+// short-string table as two 16-byte words (p: A and C, q: G and T), in the
+// rank-query form the search consumes: o1[a] = k_a - C[a],
+// o2[a] = l_a + 1 - C[a].
+__device__ __forceinline__ void kt_pick(const DevDir &d, uint4 p, uint4 q, uint32_t o1[4], uint32_t o2[4]) {
+    o1[0] = p.x - d.C[0];
+    o2[0] = p.y + 1 - d.C[0];
+    o1[1] = p.z - d.C[1];
+    o2[1] = p.w + 1 - d.C[1];
+    o1[2] = q.x - d.C[2];
+    o2[2] = q.y + 1 - d.C[2];
+    o1[3] = q.z - d.C[3];
+    o2[3] = q.w + 1 - d.C[3];
+}
+// entry of the first child of the string of d < 15 bases with code c:
+// level d + 1 starts at (4^(d+1) + 8) / 3, and every entry below level 16
+// has an index under 2^32
+__device__ __forceinline__ uint32_t kt_children(int d, uint32_t c) {
+    return ((1u << (2 * d + 2)) + 8u) / 3u + 4u * c;
+}
 
 // Occ of all four bases at row i of a sub-counted line: the counts before
 // the line, the count at the boundary of row i's 32-row group, and a count
@@ -332,7 +354,8 @@ __device__ __forceinline__ uint32_t lf_step(const DevIndex &ix, const DevDir &d,
 
 // ------------------------------------------------------------------ search state
 
-// Search states are packed in 16 bytes: x = k, y = l,
+// Search states are packed in 16 bytes: x = k (or, while |X| is below the
+// index's short-string levels, the code of X: see state_k), y = l,
 // z = (i + 1) | gap state << 10 | n_mm << 12 | n_gapo << 16 | n_gape << 20 | seed diffs << 24,
 // w = score | |X| << 10 | lb << 20, where lb = score + minc * D[i] is the
 // state's lower bound on its final score, fixed once the D-array is built.
@@ -478,6 +501,16 @@ __device__ __forceinline__ int s_sd(uint4 s) { return (s.z >> 24) & 15; }
 __device__ __forceinline__ int s_score(uint4 s) { return s.w & 1023; }
 __device__ __forceinline__ int s_len(uint4 s) { return (s.w >> 10) & 1023; }
 
+// k of a state: x itself, or, for a state whose X is shorter than the
+// short-string levels (x holds the code of X), k from X's table entry on
+// the strand's search index.  Only completed hits need it.
+__device__ __forceinline__ uint32_t state_k(const DevIndex &ix, int strand, uint4 s) {
+    const int len = s_len(s);
+    if (len >= (int)ix.kt_levels) return s.x;
+    const uint32_t *kt = strand == 0 ? ix.dir[1].kt : ix.dir[0].kt;
+    return kt[2 * (kt_level_start(len) + s.x)];
+}
+
 // the empty string's interval, nothing consumed, lower bound minc * D[m - 1]
 __device__ __forceinline__ uint4 root_state(const DevIndex &ix, int m, int lb) {
     return make_uint4(0u, ix.n, (uint32_t)m, (uint32_t)lb << 20);
@@ -490,8 +523,9 @@ __device__ __forceinline__ uint4 root_state(const DevIndex &ix, int m, int lb) {
 // the pop limit was reached first, 3 when cur is a completed hit left for
 // the caller to record (only with defer), or -R_CAND when the hit buffer
 // overflowed.
+template <bool KT = true>
 __device__ int resolve(uint4 &cur, bool &valid, int strand, const Params &P, LaneCtx &c, int phase, int max_pops,
-                       bool defer = false) {
+                       const DevIndex &ix, bool defer = false) {
     for (int pops = 0;;) {
         const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
         if (!valid) {
@@ -511,7 +545,8 @@ __device__ int resolve(uint4 &cur, bool &valid, int strand, const Params &P, Lan
             const int score = s_score(cur);
             if (score < c.best) c.best = score;
             int rc = record(c, P,
-                            make_hit(strand, cur.x, cur.y, s_len(cur), score, s_nmm(cur), s_ngo(cur), s_nge(cur)),
+                            make_hit(strand, KT ? state_k(ix, strand, cur) : cur.x, cur.y, s_len(cur), score,
+                                     s_nmm(cur), s_ngo(cur), s_nge(cur)),
                             phase);
             if (rc) return -rc;
             valid = false;
@@ -529,9 +564,15 @@ __device__ int resolve(uint4 &cur, bool &valid, int strand, const Params &P, Lan
 // lower bounds.  Returns R_OK or R_STACK.
 __device__ int expand_children(uint4 &cur, bool &valid, const uint32_t (&ok)[4], const uint32_t (&ol)[4],
                                const DevDir &sd_, int b, int m, int maxd, int Di, int Dn, const Seed &S,
-                               const Params &P, LaneCtx &c) {
+                               const Params &P, LaneCtx &c, uint32_t K) {
     const int i = s_i(cur), gs = s_gs(cur), ngo = s_ngo(cur), nge = s_nge(cur), sd = s_sd(cur);
     const int score = s_score(cur), len = s_len(cur);
+    // x of the children that consume a base: k, or their code while
+    // shorter than the short-string levels
+    const bool coded = (uint32_t)(len + 1) < K;
+    uint32_t kx[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) kx[a] = coded ? (cur.x << 2) | (uint32_t)a : sd_.C[a] + ok[a];
     const int diffs = s_nmm(cur) + ngo + nge;
     const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
     const uint32_t z0 = cur.z & ~(3u << 10);  // gap state cleared
@@ -573,7 +614,7 @@ __device__ int expand_children(uint4 &cur, bool &valid, const uint32_t (&ok)[4],
             const uint32_t w = (uint32_t)nsc | ((uint32_t)(len + 1) << 10) | ((uint32_t)lb << 20);
 #pragma unroll
             for (int a = 3; a >= 0; a--)
-                if (ok[a] < ol[a]) offer(sd_.C[a] + ok[a], sd_.C[a] + ol[a] - 1, z, w);
+                if (ok[a] < ol[a]) offer(kx[a], sd_.C[a] + ol[a] - 1, z, w);
         }
     }
     const int in_i = (i >= S.lo && i < S.hi) ? 1 : 0;
@@ -599,11 +640,11 @@ __device__ int expand_children(uint4 &cur, bool &valid, const uint32_t (&ok)[4],
             const uint32_t w = (uint32_t)nsc | ((uint32_t)(len + 1) << 10) | ((uint32_t)lb << 20);
 #pragma unroll
             for (int a = 3; a >= 0; a--)
-                if (a != b && ok[a] < ol[a]) offer(sd_.C[a] + ok[a], sd_.C[a] + ol[a] - 1, z, w);
+                if (a != b && ok[a] < ol[a]) offer(kx[a], sd_.C[a] + ol[a] - 1, z, w);
         }
         const int lbm = score + P.minc * Dn;
         if (b < 4 && sel4(ok, b) < sel4(ol, b) && diffs + Dn <= maxd && lbm <= bound)
-            offer(sel4(sd_.C, b) + sel4(ok, b), sel4(sd_.C, b) + sel4(ol, b) - 1, z0 - 1u,
+            offer(sel4(kx, b), sel4(sd_.C, b) + sel4(ol, b) - 1, z0 - 1u,
                   (uint32_t)score | ((uint32_t)(len + 1) << 10) | ((uint32_t)lbm << 20));
     }
     if (have) cur = pend;
@@ -617,11 +658,19 @@ template <int LW>
 __device__ bool build_d(const DevIndex &ix, const DevDir &od, const uint8_t *W, int m, int strand, int maxd,
                         LaneCtx &c) {
     uint32_t k = 0, l = ix.n;
+    uint32_t code = 0, len = 0;  // the current segment, while shorter than the short-string levels
     int z = 0;
     for (int i = 0; i < m; i++) {
         int a = pat(W, m, strand, i);
         bool empty = true;
-        if (a < 4) {
+        if (a < 4 && len < ix.kt_levels) {
+            const uint2 e = reinterpret_cast<const uint2 *>(od.kt)[kt_children((int)len, code) + a];
+            empty = e.x > e.y;
+            k = e.x;
+            l = e.y;
+            code = (code << 2) | (uint32_t)a;
+            len++;
+        } else if (a < 4) {
             uint32_t ok = occ1<LW>(ix, od, a, k), ol = occ1<LW>(ix, od, a, l + 1);
             empty = ok >= ol;
             k = sel4(od.C, a) + ok;
@@ -631,6 +680,7 @@ __device__ bool build_d(const DevIndex &ix, const DevDir &od, const uint8_t *W, 
             z++;
             k = 0;
             l = ix.n;
+            code = len = 0;
             if (z > maxd) return false;
         }
         c.pd[i] = (uint8_t)(a | (z << 3));
@@ -647,17 +697,22 @@ __device__ int search_strand(const DevIndex &ix, const DevDir &sd_, const uint8_
     bool valid = true;
     c.sp = 0;
     for (;;) {
-        int rr = resolve(cur, valid, strand, P, c, phase, 0x7fffffff);
+        int rr = resolve(cur, valid, strand, P, c, phase, 0x7fffffff, ix);
         if (rr == 0) return R_OK;
         if (rr < 0) return -rr;
         c.expand++;
         uint32_t ok[4], ol[4];
-        occ4<LW>(ix, sd_, cur.x, ok);
-        occ4<LW>(ix, sd_, cur.y + 1, ol);
+        if ((uint32_t)s_len(cur) < ix.kt_levels) {
+            const uint4 *e = reinterpret_cast<const uint4 *>(sd_.kt + 2 * kt_children(s_len(cur), cur.x));
+            kt_pick(sd_, e[0], e[1], ok, ol);
+        } else {
+            occ4<LW>(ix, sd_, cur.x, ok);
+            occ4<LW>(ix, sd_, cur.y + 1, ol);
+        }
         const int i = s_i(cur);
         const int b = pd_base(c, i);
         const int Di = pd_d(c, i), Dn = pd_d(c, i - 1);
-        int rc = expand_children(cur, valid, ok, ol, sd_, b, m, maxd, Di, Dn, S, P, c);
+        int rc = expand_children(cur, valid, ok, ol, sd_, b, m, maxd, Di, Dn, S, P, c, ix.kt_levels);
         if (rc) return rc;
     }
 }
@@ -1029,7 +1084,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 q2 = dl + 1;
             }
         } else if (phase == PZ_SEARCH || phase == PZ_HELP) {
-            int rr = resolve(cur, valid, strand, P, c, PH_FAST, POPS_PER_STEP, endgame);
+            int rr = resolve<false>(cur, valid, strand, P, c, PH_FAST, POPS_PER_STEP, ix, endgame);
             if (rr == 2) {
                 // pop limit reached: keep popping next iteration
             } else if (rr == 3) {
@@ -1178,7 +1233,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
             const int i = s_i(cur);
             const int b = pd_base(c, i);
             const int Di = pd_d(c, i), Dn = pd_d(c, i - 1);
-            int rc = expand_children(cur, valid, ok, ol, qd, b, m, maxd, Di, Dn, S, P, c);
+            int rc = expand_children(cur, valid, ok, ol, qd, b, m, maxd, Di, Dn, S, P, c, 0);
             if (rc) {
                 // cannot happen with worst-case stacks; kept as a guard
                 if (endgame) {
@@ -1607,6 +1662,35 @@ __global__ void k_pair(uint32_t n_pairs, EndView e1, EndView e2, int paired, int
 }
 
 
+// ------------------------------------------------------------------ short-string table
+
+// Level d of direction `which`'s table from level d - 1: one thread per
+// string S of d - 1 bases writes the intervals of aS, a = 0..3, from the
+// rank counts at S's k and l + 1 (the same step the search takes).
+template <int LW>
+__global__ __launch_bounds__(256) void k_kt_level(DevIndex ix, int which, int d) {
+    const uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (p >= ((uint64_t)1 << (2 * (d - 1)))) return;
+    const DevDir dd = pick_dir(ix, which);
+    uint32_t *kt = const_cast<uint32_t *>(dd.kt);
+    const uint64_t pe = kt_level_start(d - 1) + p;
+    const uint32_t k = kt[2 * pe], l = kt[2 * pe + 1];
+    uint32_t ok[4], ol[4];
+    occ4<LW>(ix, dd, k, ok);
+    occ4<LW>(ix, dd, l + 1, ol);
+    uint4 *dst = reinterpret_cast<uint4 *>(kt + 2 * kt_children(d - 1, (uint32_t)p));
+    dst[0] = make_uint4(dd.C[0] + ok[0], dd.C[0] + ol[0] - 1, dd.C[1] + ok[1], dd.C[1] + ol[1] - 1);
+    dst[1] = make_uint4(dd.C[2] + ok[2], dd.C[2] + ol[2] - 1, dd.C[3] + ok[3], dd.C[3] + ol[3] - 1);
+}
+
+// level 0: the empty string's interval (0, n)
+__global__ void k_kt_root(uint32_t *kt, uint32_t n) {
+    if (threadIdx.x == 0) {
+        kt[0] = 0;
+        kt[1] = n;
+    }
+}
+
 // ------------------------------------------------------------------ random-line probe
 
 // Each lane performs `iters` dependent fetches of whole lines at
@@ -1708,7 +1792,9 @@ DevIndex dev_index(const bwfm_index *ix) {
         d.dir[k].sa = (const uint32_t *)ix->d_sa[k];
         for (int a = 0; a < 4; a++) d.dir[k].C[a] = (uint32_t)ix->dir[k].C[a];
         d.dir[k].primary = (uint32_t)ix->dir[k].primary;
+        d.dir[k].kt = (const uint32_t *)ix->d_kt[k];
     }
+    d.kt_levels = ix->kt_levels;
     d.magic = (uint64_t)(((unsigned __int128)1 << 64) / ix->bpl) + 1;
     d.n = (uint32_t)ix->n;
     d.bpl = ix->bpl;
@@ -1996,11 +2082,78 @@ extern "C" int bwfm_index_upload(bwfm_index *ix, void *stream) {
     return BWFM_OK;
 }
 
+// table bytes per direction, padded to a multiple of 256 so that a lane's
+// line-sized, line-aligned read around its 32 entry bytes stays inside
+static uint64_t kt_bytes(uint32_t levels) {
+    return levels ? (kt_level_start((int)levels + 1) * 8 + 255) / 256 * 256 : 0;
+}
+
+extern "C" int bwfm_index_kmer_table(bwfm_index *ix, int levels, void *stream) {
+    if (!ix) return fail(BWFM_E_INVAL, "kmer_table: NULL index");
+    std::lock_guard<std::mutex> g(ix->mu);
+    if (ix->device < 0) return fail(BWFM_E_INVAL, "kmer_table: the index is not uploaded");
+    if (levels < -1 || levels > 15) return fail(BWFM_E_INVAL, "kmer_table: levels must be -1, 0 or 1..15");
+    if (levels == -1) {
+        levels = 1;
+        while (levels < 14 && ((uint64_t)1 << (2 * levels)) < ix->n) levels++;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipStreamSynchronize(st));
+    ix->device_bytes -= 2 * kt_bytes(ix->kt_levels);
+    ix->kt_levels = 0;
+    ix->kt_gen++;
+    for (int d = 0; d < 2; d++) {
+        if (ix->d_kt[d]) (void)hipFree(ix->d_kt[d]);
+        ix->d_kt[d] = nullptr;
+    }
+    if (levels == 0) return BWFM_OK;
+    const uint64_t bytes = kt_bytes((uint32_t)levels);
+    for (int d = 0; d < 2; d++)
+        if (hipMalloc(&ix->d_kt[d], bytes) != hipSuccess) {
+            for (int e = 0; e < 2; e++) {
+                if (ix->d_kt[e]) (void)hipFree(ix->d_kt[e]);
+                ix->d_kt[e] = nullptr;
+            }
+            (void)hipGetLastError();
+            return fail(BWFM_E_NOMEM, "kmer_table: device allocation failed");
+        }
+    const DevIndex D = dev_index(ix);  // kt_levels 0: the builder reads rank lines only
+    for (int d = 0; d < 2; d++) {
+        k_kt_root<<<1, 64, 0, st>>>((uint32_t *)ix->d_kt[d], (uint32_t)ix->n);
+        for (int lv = 1; lv <= levels; lv++) {
+            const uint64_t np = (uint64_t)1 << (2 * (lv - 1));
+            by_layout(ix, [&](auto t) {
+                k_kt_level<decltype(t)::value><<<blocks(np, 256), 256, 0, st>>>(D, d, lv);
+                return 0;
+            });
+        }
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    ix->kt_levels = (uint32_t)levels;
+    ix->device_bytes += 2 * bytes;
+    return BWFM_OK;
+}
+
+extern "C" int bwfm_index_kmer_get(const bwfm_index *ix, int which, int level, uint64_t first, uint64_t count,
+                                   uint32_t *out) {
+    if (!ix || !out || (which != 0 && which != 1)) return fail(BWFM_E_INVAL, "kmer_get: bad argument");
+    if (level < 0 || (uint32_t)level > ix->kt_levels || !ix->d_kt[which])
+        return fail(BWFM_E_INVAL, "kmer_get: no such table level");
+    const uint64_t codes = (uint64_t)1 << (2 * level);
+    if (first > codes || count > codes - first) return fail(BWFM_E_INVAL, "kmer_get: codes out of range");
+    if (!count) return BWFM_OK;
+    const char *src = (const char *)ix->d_kt[which] + (kt_level_start(level) + first) * 8;
+    HIPCHK(hipMemcpy(out, src, count * 8, hipMemcpyDeviceToHost));
+    return BWFM_OK;
+}
+
 extern "C" void bwfm_index_free(bwfm_index *ix) {
     if (!ix) return;
     for (int d = 0; d < 2; d++) {
         if (ix->d_lines[d]) (void)hipFree(ix->d_lines[d]);
         if (ix->d_sa[d]) (void)hipFree(ix->d_sa[d]);
+        if (ix->d_kt[d]) (void)hipFree(ix->d_kt[d]);
     }
     if (ix->d_pac) (void)hipFree(ix->d_pac);
     if (ix->ws.ptr) (void)hipFree(ix->ws.ptr);
@@ -2329,6 +2482,7 @@ struct bwfm_pipeline {
     hipStream_t cap = nullptr;  // capture only: nothing runs on it
     bool timed_graph = false, timed_last = false;
     bool timing_uncapturable = false;  // a capture with event nodes failed once
+    uint64_t kt_gen = 0;               // the index's table generation the graph was captured with
 };
 
 namespace {
@@ -2562,7 +2716,7 @@ extern "C" int bwfm_pipeline_run(bwfm_pipeline *pl, int graph, void *stream) {
         return pipe_enqueue_any(pl, st, timed, false);
     }
     if (pl->timing_uncapturable) timed = false;
-    if (pl->exec && pl->timed_graph != timed) drop_graph(pl);
+    if (pl->exec && (pl->timed_graph != timed || pl->kt_gen != pl->ix->kt_gen)) drop_graph(pl);
     if (!pl->exec) {
         // recorded on the pipeline's own stream (the caller's may be the
         // null stream, which cannot be captured); launched on the caller's
@@ -2593,6 +2747,7 @@ extern "C" int bwfm_pipeline_run(bwfm_pipeline *pl, int graph, void *stream) {
         pl->graph = gph;
         pl->exec = ex;
         pl->timed_graph = timed;
+        pl->kt_gen = pl->ix->kt_gen;
     }
     pl->timed_last = pl->timed_graph;
     HIPCHK(hipGraphLaunch(pl->exec, st));

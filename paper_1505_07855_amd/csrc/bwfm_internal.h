@@ -26,6 +26,7 @@ struct DevDir {
     uint32_t C[4];
     uint32_t primary;
     uint32_t pad;
+    const uint32_t *kt;  // short-string interval table, (k, l) word pairs (kt_level_start), or null
 };
 
 struct DevIndex {
@@ -35,7 +36,14 @@ struct DevIndex {
     uint32_t bpl;         // rows per rank line
     uint32_t sa_shift;    // log2(sa_sample)
     uint32_t line_words;  // uint32 words per line
+    uint32_t kt_levels;   // levels of the short-string table (0: none)
 };
+
+// First entry of level d of the short-string table: level 0 is entry 0,
+// level d >= 1 starts at 4 + (4^d - 4) / 3, a multiple of 4.
+constexpr uint64_t kt_level_start(int d) {
+    return d == 0 ? 0 : 4 + (((uint64_t)1 << (2 * d)) - 4) / 3;
+}
 
 struct Workspace {
     void *ptr = nullptr;
@@ -74,6 +82,9 @@ struct bwfm_index {
     void *d_lines[2] = {nullptr, nullptr};
     void *d_sa[2] = {nullptr, nullptr};
     void *d_pac = nullptr;
+    void *d_kt[2] = {nullptr, nullptr};  // short-string interval tables
+    uint32_t kt_levels = 0;
+    uint64_t kt_gen = 0;  // bumped whenever the table changes (captured graphs hold its address)
     uint64_t device_bytes = 0;
     std::mutex mu;
     bwfm::Workspace ws;

@@ -339,6 +339,8 @@ extern "C" int bwfm_index_get_info(const bwfm_index *ix, bwfm_index_info *o) {
     o->sa_sample = ix->sa_sample;
     o->uploaded = ix->device >= 0;
     o->rank_format = ix->rank_format;
+    o->kmer_levels = ix->kt_levels;
+    o->kmer_bytes = ix->kt_levels ? 2 * ((8 * bwfm::kt_level_start((int)ix->kt_levels + 1) + 255) / 256 * 256) : 0;
     return BWFM_OK;
 }
 

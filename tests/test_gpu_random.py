@@ -1,7 +1,7 @@
 """Randomised parity sweep: many small configurations drawn from a seed --
 genome size and composition, read lengths from 1 to 300 bases, budgets,
 gaps, seeds, search mode, index layout and rank-line format, execution
-form -- each aligned, located and paired on the GPU and by the oracle, and
+form, short-string table depth -- each aligned, located and paired on the GPU and by the oracle, and
 compared bit for bit, with mate rescue and MAPQ on the same records.
 Complements the workload-shaped tests with
 combinations none of them reaches (tiny references with few rank lines,
@@ -45,14 +45,17 @@ def _config(seed: int):
     # every layout meets both forms as the seed runs through 2 x len(LAYOUTS) values
     layout = LAYOUTS[seed % len(LAYOUTS)]
     form = (bw.FORM_BATCHED, bw.FORM_PLAIN)[(seed // len(LAYOUTS)) % 2]
-    return g, reads, kw, layout, form
+    # and every short-string table depth (automatic, none, shallow, deeper
+    # than many reads) meets both
+    kmer = (-1, 0, 2, 9)[(seed // (2 * len(LAYOUTS))) % 4]
+    return g, reads, kw, layout, form, kmer
 
 
 @pytest.mark.parametrize("seed", range(120))
 def test_random_configuration(seed):
-    g, reads, kw, layout, form = _config(5000 + seed)
+    g, reads, kw, layout, form, kmer = _config(5000 + seed)
     lb, bpl, sas, fmt = layout
-    ix = bw.Index(g.seq, line_bytes=lb, bases_per_line=bpl, sa_sample=sas, rank_format=fmt).upload()
+    ix = bw.Index(g.seq, line_bytes=lb, bases_per_line=bpl, sa_sample=sas, rank_format=fmt).upload(kmer_levels=kmer)
     ox = oracle.Index(g.seq)
     p = bw.Params(**kw, form=form)
     op = oracle.Params(**kw)
@@ -62,7 +65,7 @@ def test_random_configuration(seed):
     torch.cuda.synchronize()
     ores = oracle.align(ox, reads.bases, reads.offsets, op, threads=8)
     ho, hits, c1, c2, st = res.to_numpy()
-    ctx = (seed, kw, layout, form)
+    ctx = (seed, kw, layout, form, kmer)
     assert np.array_equal(ho, ores.hit_off), ctx
     assert np.array_equal(hits.view(np.uint8), ores.hits.view(np.uint8)), ctx
     assert np.array_equal(c1, ores.c1) and np.array_equal(c2, ores.c2), ctx
