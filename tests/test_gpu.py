@@ -292,7 +292,8 @@ def test_hit_capacity_error_reports_need():
 
 @pytest.fixture(scope="module")
 def c2_full():
-    """The benchmark's workload at full size: 100 Mbp genome, 1M pairs."""
+    """The benchmark's workload at full size: 100 Mbp genome, 1M pairs, and
+    the benchmark's index layout (64-byte lines of 192 rows, SA/32)."""
     g = configs.c2_genome()
     box = {}
 
@@ -301,7 +302,7 @@ def c2_full():
 
     t = threading.Thread(target=build_oracle)
     t.start()
-    ix = bw.Index(g.seq).upload()
+    ix = bw.Index(g.seq, **configs.LAYOUT["C2"]).upload()
     t.join()
     pairs = configs.c2_pairs(g)
     return g, pairs, ix, box["ox"]
@@ -314,7 +315,7 @@ def test_c2_full_size_sampled_parity(c2_full):
     g, pairs, ix, ox = c2_full
     p, op = _params_pair(**configs.PARAMS["C2"])
     rng = np.random.default_rng(11)
-    sample = np.sort(rng.choice(pairs.end1.n, 1500, replace=False))
+    sample = np.sort(rng.choice(pairs.end1.n, 20_000, replace=False))
     n = pairs.end1.n
     both = gen.Reads(np.concatenate([pairs.end1.bases, pairs.end2.bases]),
                      np.concatenate([pairs.end1.offsets[:-1], pairs.end1.offsets[-1] + pairs.end2.offsets]))
