@@ -315,7 +315,7 @@ def test_c2_full_size_sampled_parity(c2_full):
     g, pairs, ix, ox = c2_full
     p, op = _params_pair(**configs.PARAMS["C2"])
     rng = np.random.default_rng(11)
-    sample = np.sort(rng.choice(pairs.end1.n, 20_000, replace=False))
+    sample = np.sort(rng.choice(pairs.end1.n, 200_000, replace=False))
     n = pairs.end1.n
     both = gen.Reads(np.concatenate([pairs.end1.bases, pairs.end2.bases]),
                      np.concatenate([pairs.end1.offsets[:-1], pairs.end1.offsets[-1] + pairs.end2.offsets]))
