@@ -121,20 +121,20 @@ int bwfm_index_upload(bwfm_index *idx, void *hip_stream);
  * low bits: code(aS) = 4 code(S) + a), the table holds the SA interval
  * (k, l) of S on that direction's index, exactly as backward search steps
  * reach it (k > l when S does not occur).  Level d starts at entry
- * 4 + (4^d - 4) / 3 (level 0, entry 0, is the empty string's (0, n)), so the
- * four one-base extensions of a string are 32 contiguous, 32-byte-aligned
- * bytes.  The plain form's search and D-array scan, and the batched
- * form's second pass, take the children of a state whose matched string is
- * shorter than `levels` bases from there: one access in place of two
- * rank-line fetches.  The batched form's persistent first pass does not:
- * there it measured slower.  Built on the device from the
+ * 4 + (4^d - 4) / 3 (level 0, entry 0, is the empty string's (0, n)), so
+ * the four one-base extensions of a string are 32 contiguous,
+ * 32-byte-aligned bytes.  The plain form's search and D-array scan, and
+ * the batched form's second pass, take the children of a state whose
+ * matched string is shorter than `levels` bases from there: one access in
+ * place of two rank-line fetches.  The batched form's persistent first
+ * pass does not: there it measured slower.  Built on the device from the
  * uploaded rank lines; replaces an existing table (no call that uses the
  * index may run meanwhile; captured pipeline steps are captured again on
- * their next run).  levels: 0 releases the
- * table, -1 picks the smallest d with 4^d >= n (at most 14: 2.9 GB per
- * direction), 1..15 as given (15: 11.5 GB per direction).  Synchronises
- * hip_stream.  Errors: E_INVAL (NULL, not uploaded, levels out of range),
- * E_NOMEM, E_DEVICE. */
+ * their next run).  levels: 0 releases the table, -1 picks the smallest d
+ * with 4^d >= n (at most 14: 2.9 GB per direction), 1..15 as given (15:
+ * 11.5 GB per direction).  Synchronises hip_stream.  Errors: E_INVAL
+ * (NULL, not uploaded, levels out of range; the index is left as it was),
+ * E_NOMEM (the index is left without a table), E_DEVICE (it may be). */
 int bwfm_index_kmer_table(bwfm_index *idx, int levels, void *hip_stream);
 
 /* Host copy of count entries of level `level` of direction `which`'s
