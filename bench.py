@@ -48,7 +48,8 @@ def log(msg):
 
 # sources each profiled kernel is built from; a counter summary is valid only for them
 KERNEL_SOURCES = {"k_align_persistent": ("bwfm.hip", "bwfm_internal.h"),
-                  "k_rescue": ("rescue.hip", "bwfm_internal.h")}
+                  "k_rescue": ("rescue.hip", "bwfm_internal.h"),
+                  "k_mapq": ("mapq.hip", "bwfm_internal.h")}
 
 
 def kernel_source_hash(kernel: str = "k_align_persistent") -> str:
@@ -136,7 +137,7 @@ def rescue_leg(bw, torch, ix, ends, results, prs, n, w, stream, launches, n_ref,
             "mapq": {"kernel": "k_mapq", "avg_launch_ms": mq_ms, "launches": launches,
                      "q60_fraction": float((q == 60).mean()), "q0_fraction": float((q == 0).mean()),
                      "roofline": {"bound": "hbm", "achieved": mq_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": mq_gbs / HBM_PEAK_GBS, "traffic": None,
+                                  "frac": mq_gbs / HBM_PEAK_GBS, "traffic": traffic_from_profiles("k_mapq"),
                                   "bytes_per_launch": mq_bytes}}}
 
 
