@@ -105,6 +105,25 @@ def test_align_without_upload_is_a_state_error():
     ix.close()
 
 
+def test_kmer_table_state_errors_on_a_host_index():
+    """The short-string table lives on the device: on an index that was
+    never uploaded it reports no levels, refuses to build and has no entries
+    to read.  Both checks come before any device call, so the C entry points
+    are called directly with a null stream."""
+    g = np.random.default_rng(5).integers(0, 4, 2000).astype(np.uint8)
+    ix = bw.Index(g, line_bytes=64)
+    info = ix.info()
+    assert info["kmer_levels"] == 0 and info["kmer_bytes"] == 0
+    L = bw.lib()
+    for levels in (-1, 0, 3):
+        assert L.bwfm_index_kmer_table(ix._h, levels, None) == -1  # BWFM_E_INVAL
+        assert b"not uploaded" in L.bwfm_last_error()
+    out = np.zeros(2, np.uint32)
+    assert L.bwfm_index_kmer_get(ix._h, 0, 0, 0, 1, out.ctypes.data) == -1
+    assert L.bwfm_index_kmer_table(None, 3, None) == -1
+    ix.close()
+
+
 @pytest.mark.parametrize("fmt", [bw.RANK_PLANES, bw.RANK_SUBCOUNTS])
 def test_index_save_load_roundtrip_and_corruption(rng, tmp_path, fmt):
     t = rng.integers(0, 4, 7000).astype(np.uint8)
