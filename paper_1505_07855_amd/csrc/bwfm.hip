@@ -950,7 +950,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
     bool valid = false;
     Seed S{0, 0, 0};
     // work statistics (measurement only)
-    unsigned long long w_iters = 0, w_busy = 0, w_query = 0;
+    uint32_t w_iters = 0, w_busy = 0, w_query = 0;  // per lane: far below 2^32 per launch
 
     for (;;) {
         // an opaque step on the pointer keeps the argument loads inside the
@@ -1247,9 +1247,9 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
         }
     }
     if (A->O.work) {
-        if (lane == 0) atomicAdd(&A->O.work[0], w_iters);
-        atomicAdd(&A->O.work[1], w_busy);
-        atomicAdd(&A->O.work[2], w_query);
+        if (lane == 0) atomicAdd(&A->O.work[0], (unsigned long long)w_iters);
+        atomicAdd(&A->O.work[1], (unsigned long long)w_busy);
+        atomicAdd(&A->O.work[2], (unsigned long long)w_query);
     }
 }
 
