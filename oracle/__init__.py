@@ -87,6 +87,12 @@ def _lib(name: str):
             L.brute_align.restype = i64
             L.brute_hamming.argtypes = [P, i64, P, ctypes.c_int, P, ctypes.POINTER(P)]
             L.brute_hamming.restype = i64
+            L.brute_hamming_many.argtypes = [P, i64, P, P, i64, P, ctypes.c_int, P, ctypes.POINTER(P)]
+            L.brute_hamming_many.restype = i64
+            L.brute_exact_many.argtypes = [P, i64, P, P, i64, ctypes.c_int, P, ctypes.POINTER(P)]
+            L.brute_exact_many.restype = i64
+            L.brute_edit_many.argtypes = [P, i64, P, P, i64, P, ctypes.c_int, P, P, ctypes.POINTER(P)]
+            L.brute_edit_many.restype = i64
             L.brute_free.argtypes = [P]
         _loaded[name] = L
     return _loaded[name]
@@ -345,3 +351,64 @@ def brute_align(text, read, params: Params) -> np.ndarray:
 
 def brute_hamming(text, read, params: Params) -> np.ndarray:
     return _brute_call("brute_hamming", text, read, params)
+
+
+def _recs(out, tot):
+    r = np.frombuffer((ctypes.c_char * (REC_DTYPE.itemsize * tot)).from_address(out.value), REC_DTYPE).copy() \
+        if tot else np.zeros(0, REC_DTYPE)
+    _lib("brute").brute_free(out)
+    return r
+
+
+def brute_hamming_many(text, bases, offsets, params: Params, threads: int = 8):
+    """brute_hamming for every read of a batch: (rec_off, records), the
+    records of read r at records[rec_off[r]:rec_off[r + 1]]."""
+    t = np.ascontiguousarray(text, np.uint8)
+    b = np.ascontiguousarray(bases, np.uint8)
+    o = np.ascontiguousarray(offsets, np.uint64)
+    n = len(o) - 1
+    off = np.zeros(n + 1, np.uint64)
+    out = ctypes.c_void_p()
+    bp = params._brute()
+    tot = _lib("brute").brute_hamming_many(_p(t), len(t), _p(b), _p(o), n, ctypes.byref(bp), threads, _p(off),
+                                           ctypes.byref(out))
+    if tot < 0:
+        raise RuntimeError("brute_hamming_many failed")
+    return off, _recs(out, tot)
+
+
+def brute_edit_many(text, bases, offsets, params: Params, threads: int = 8):
+    """The gapped ALL set of every read of a batch by an edit-distance filter
+    and transcript enumeration: (rec_off, records, candidate ends per read)."""
+    t = np.ascontiguousarray(text, np.uint8)
+    b = np.ascontiguousarray(bases, np.uint8)
+    o = np.ascontiguousarray(offsets, np.uint64)
+    n = len(o) - 1
+    off = np.zeros(n + 1, np.uint64)
+    ends = np.zeros(n, np.int64)
+    out = ctypes.c_void_p()
+    bp = params._brute()
+    tot = _lib("brute").brute_edit_many(_p(t), len(t), _p(b), _p(o), n, ctypes.byref(bp), threads, _p(off),
+                                        _p(ends), ctypes.byref(out))
+    if tot < 0:
+        raise RuntimeError("brute_edit_many failed")
+    return off, _recs(out, tot), ends
+
+
+def brute_exact_many(text, pats, offsets, threads: int = 8):
+    """Every occurrence of every pattern (codes 0..3, at least 16 bases):
+    (occ_off, positions), pattern k's ascending positions at
+    positions[occ_off[k]:occ_off[k + 1]]."""
+    t = np.ascontiguousarray(text, np.uint8)
+    b = np.ascontiguousarray(pats, np.uint8)
+    o = np.ascontiguousarray(offsets, np.uint64)
+    n = len(o) - 1
+    off = np.zeros(n + 1, np.uint64)
+    out = ctypes.c_void_p()
+    tot = _lib("brute").brute_exact_many(_p(t), len(t), _p(b), _p(o), n, threads, _p(off), ctypes.byref(out))
+    if tot < 0:
+        raise RuntimeError("brute_exact_many failed")
+    pos = np.frombuffer((ctypes.c_char * (4 * tot)).from_address(out.value), np.uint32).copy() if tot else \
+        np.zeros(0, np.uint32)
+    _lib("brute").brute_free(out)
+    return off, pos

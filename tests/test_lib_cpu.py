@@ -175,3 +175,18 @@ def test_variant_knobs_match_the_source_defaults():
         assert ref not in alts
     names = [n for n, _ in variants.variants()]
     assert names[0] == "reference" and len(names) == len(set(names)) == 1 + sum(len(a) for _, a in variants.KNOBS.values())
+
+
+@pytest.mark.parametrize("shape", ["C1", "C2"])
+def test_host_index_equals_oracle_index_at_workload_size(shape):
+    """The host builder against the oracle on the C1 genome in full (1 Mbp)
+    and on a 4 Mbp genome built like the 100 Mbp one, in the workload's
+    layout and in sub-counted lines."""
+    from gen import configs
+    from tests.util import assert_index_equals_oracle
+    g = configs.c1_genome() if shape == "C1" else configs.c2_genome(4_000_000, seed=64)
+    ox = oracle.Index(g.seq)
+    for lay in (dict(configs.LAYOUT[shape]), dict(line_bytes=64, sa_sample=32, rank_format=bw.RANK_SUBCOUNTS)):
+        ix = bw.Index(g.seq, **lay)
+        assert_index_equals_oracle(ix, ox, name=f"{shape} {lay}")
+        ix.close()

@@ -187,17 +187,27 @@ def test_d_array_is_a_lower_bound_and_pruning_is_exact():
     b = oracle.align(ix, reads.bases, reads.offsets, p0)
     assert np.array_equal(a.hit_off, b.hit_off) and np.array_equal(a.hits, b.hits)
     assert a.counts["expand"].sum() <= b.counts["expand"].sum()
-    # D[i] never exceeds the fewest mismatches placing w[0..i] anywhere in T
-    pm = oracle.Params(max_diff=8, max_gapo=0, seed_len=0, mode=oracle.MODE_ALL, max_hits=1 << 30)
-    for r in range(5):
+    # D[i] never exceeds the smallest unit edit distance of w[0..i] against
+    # any substring of T (mismatches and gap bases, the differences a
+    # transcript counts), and the fewest mismatches bound that from above
+    t = g.seq.astype(np.int16)
+    col = np.arange(len(t) + 1)
+    for r in range(8):
         w = reads.read(r)
         D = ix.darray(w, which=0)  # pattern w searched on the index of T
-        for i in [3, 10, 20, 31]:
-            pre = w[:i + 1]
-            best = min(int((g.seq[q:q + i + 1] != pre).sum()) for q in range(len(g.seq) - i))
-            assert D[i] <= best
+        row = np.zeros(len(t) + 1, np.int64)  # no read base consumed: free start in T
+        for i in range(len(w)):
+            cur = np.empty_like(row)
+            cur[0] = i + 1
+            cur[1:] = np.minimum(row[:-1] + ((t != w[i]) | (w[i] > 3)), row[1:] + 1)
+            cur = np.minimum.accumulate(cur - col) + col  # skipped reference bases
+            row = cur
+            ed = int(row.min())
+            if i in (3, 10, 20, 31):
+                mm = min(int((g.seq[q:q + i + 1] != w[:i + 1]).sum()) for q in range(len(g.seq) - i))
+                assert ed <= mm
+            assert D[i] <= ed, (r, i)
         assert np.all(np.diff(D.astype(int)) >= 0)
-    del pm
 
 
 def test_best_is_the_tier_filter_of_all():

@@ -104,3 +104,24 @@ def tier_filter(all_hits: np.ndarray, p: oracle.Params):
     rep = all_hits[keep]
     order = np.lexsort((rep["len"], rep["k"], rep["strand"], rep["score"]))
     return rep[order], min(c1, 0xFFFFFFFF), min(c2, 0xFFFFFFFF), False
+
+
+def assert_index_equals_oracle(ix, ox: oracle.Index, rows_per_dir: int = 200, seed: int = 0, name: str = ""):
+    """A library index (host- or device-built) against the oracle's index of
+    the same text: per direction the whole BWT, the $ row, C, every SA sample
+    (SA[r] for r a multiple of the sample interval) and Occ of all four bases
+    at random rows plus both ends; and the packed reference."""
+    info = ix.info()
+    sas = info["sa_sample"]
+    n = ox.n
+    rng = np.random.default_rng(seed)
+    for which in (0, 1):
+        sa, bwt, C, prim = ox.get(which)
+        assert np.array_equal(ix.bwt(which), bwt), (name, which, "bwt")
+        assert info["primary"][which] == prim, (name, which, "primary")
+        assert info["C"][which] == C.tolist(), (name, which, "C")
+        assert np.array_equal(ix.sa_samples(which), sa[::sas]), (name, which, "sa samples")
+        rows = np.unique(np.concatenate([rng.integers(0, n + 2, rows_per_dir), [0, 1, n, n + 1]]))
+        for i in rows:
+            assert ix.occ(int(i), which).tolist() == ox.occ4(int(i), which).tolist(), (name, which, int(i))
+    assert np.array_equal(ix.ref(), ox.text), (name, "reference")
