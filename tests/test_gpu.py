@@ -88,6 +88,33 @@ def test_c1_shape_parity(c1_small, layout, mode, form):
 
 
 @pytest.fixture(scope="module")
+def c1_full():
+    g = configs.c1_genome()
+    reads = configs.c1_reads(g)
+    assert len(g.seq) == 1_000_000 and reads.n == 10_000
+    return g, reads, oracle.Index(g.seq)
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("mode", [bw.MODE_BEST, bw.MODE_ALL])
+def test_c1_full_size_parity(c1_full, mode, form):
+    """C1 at its stated size: 1 Mbp, 10,000 reads of 36 bp, at most 2
+    mismatches, no gaps, in its own layout (checkpoints every 128 rows, SA
+    samples every 32); hits, counts, status and located positions."""
+    g, reads, ox = c1_full
+    ix = bw.Index(g.seq, **configs.LAYOUT["C1"]).upload()
+    p, op = _params_pair(form=form, **configs.PARAMS["C1"], mode=mode)
+    res = _gpu_align(ix, reads, p)
+    ores = oracle.align(ox, reads.bases, reads.offsets, op, threads=8)
+    _compare_align(res, ores)
+    assert (ores.status & oracle.ST_HIT).mean() > 0.9
+    po, pos = bw.locate(ix, res, configs.MAX_OCC)
+    opo, opos = oracle.locate(ox, ores.hits, configs.MAX_OCC)
+    assert np.array_equal(po.cpu().numpy().view(np.uint64), opo)
+    assert np.array_equal(pos.cpu().numpy().view(np.uint32), opos)
+
+
+@pytest.fixture(scope="module")
 def c2_small():
     g = configs.c2_genome(2_000_000, seed=77)
     pairs = configs.c2_pairs(g, 3000, seed=78)
@@ -348,3 +375,50 @@ def test_c2_full_size_sampled_parity(c2_full):
     assert np.array_equal(gr[sample].view(np.uint8), orr.view(np.uint8))
     unpaired = (gp["flags"] & bw.PF_PAIRED) == 0
     assert (gr["end"][~unpaired] == 0).all() and (gr["end"][unpaired] != 0).sum() > 0
+
+
+def _sample_reads(reads, rows):
+    offs = reads.offsets
+    sb = np.concatenate([reads.bases[offs[r]:offs[r + 1]] for r in rows])
+    so = np.zeros(len(rows) + 1, np.uint64)
+    so[1:] = np.cumsum(np.diff(offs)[rows])
+    return sb, so
+
+
+@pytest.mark.timeout(900)
+def test_c5_full_size_sampled_parity(c2_full):
+    """C5 at its stated size: the 100 Mbp genome, 2M single-end reads of
+    250 bp (3% substitutions, 0.3% indel events, a tenth from repeat
+    copies), at most 6 differences with a gap, no seed, all in one batched
+    launch; 40,000 sampled reads against the oracle (hits, counts, status,
+    located positions), and whole-batch properties."""
+    g, _, ix, ox = c2_full
+    reads = configs.c5_reads(g)
+    assert reads.n == 2_000_000 and (np.diff(reads.offsets) == 250).all()
+    p, op = _params_pair(**configs.PARAMS["C5"])
+    print(f"[c5-full] aligning {reads.n} reads", flush=True)
+    res = _gpu_align(ix, reads, p)
+    rng = np.random.default_rng(1005)
+    rows = np.sort(rng.choice(reads.n, 40_000, replace=False))
+    sb, so = _sample_reads(reads, rows)
+    ores = oracle.align(ox, sb, so, op, threads=16)
+    _compare_align(res, ores, rows=rows)
+    # positions of the sampled reads' hits
+    ho = res.hit_offsets.cpu().numpy().view(np.uint64)
+    po, pos = bw.locate(ix, res, configs.MAX_OCC)
+    po, pos = po.cpu().numpy().view(np.uint64), pos.cpu().numpy().view(np.uint32)
+    opo, opos = oracle.locate(ox, ores.hits, configs.MAX_OCC)
+    for j, r in enumerate(rows[:5000]):
+        a, b = int(ho[r]), int(ho[r + 1])
+        oa, ob = int(ores.hit_off[j]), int(ores.hit_off[j + 1])
+        assert b - a == ob - oa
+        got = [pos[po[h]:po[h + 1]].tolist() for h in range(a, b)]
+        exp = [opos[opo[h]:opo[h + 1]].tolist() for h in range(oa, ob)]
+        assert got == exp, r
+    st = res.status.cpu().numpy()
+    ost = ores.status
+    print(f"[c5-full] sample: {np.mean(ost & oracle.ST_HIT != 0):.3f} aligned, "
+          f"{int((ost & oracle.ST_OVERFLOW).astype(bool).sum())} over max_hits; whole batch: "
+          f"{np.mean(st & bw.ST_HIT != 0):.3f} aligned, {int((st & bw.ST_SHARED).astype(bool).sum())} shared trees",
+          flush=True)
+    assert not (st & bw.ST_INVALID).any()

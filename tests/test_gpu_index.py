@@ -1,14 +1,18 @@
-"""The device index builder against the host builder, byte for byte (rank
-lines, SA samples, C, the $ row), on texts that stress a suffix sort: random,
-one symbol repeated, short periods, long exact repeats, and a C2-shaped
-genome; and its index aligns like the host one."""
+"""The device index builder against the oracle's index (BWT, $ row, C, every
+SA sample, Occ at random rows, the packed reference) and against the host
+builder byte for byte, on texts that stress a suffix sort: random, one
+symbol repeated, short periods, long exact repeats, a 3 Mbp and a 16 Mbp
+genome built like the 100 Mbp one; and its index aligns like the host
+one."""
 from __future__ import annotations
 
 import numpy as np
 import pytest
 
+import oracle
 import paper_1505_07855_amd as bw
 from gen import configs
+from util import assert_index_equals_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -26,6 +30,15 @@ def _texts():
     t[100_000:150_000] = t[10_000:60_000]  # a 50 kbp exact repeat: many doubling rounds
     yield "repeat", t
     yield "c2", configs.c2_genome(3_000_000, seed=61).seq
+
+
+_ORACLE = {}
+
+
+def _oracle_index(name, t):
+    if name not in _ORACLE:
+        _ORACLE[name] = oracle.Index(t)
+    return _ORACLE[name]
 
 
 def _host_bytes(ix):
@@ -48,6 +61,7 @@ def test_device_index_equals_host_index(layout):
         a = bw.Index(t, line_bytes=lb, bases_per_line=bpl, sa_sample=sas, rank_format=fmt)
         b = bw.Index.build_device(t, line_bytes=lb, bases_per_line=bpl, sa_sample=sas, rank_format=fmt)
         assert b.info()["uploaded"]
+        assert_index_equals_oracle(b, _oracle_index(name, t), rows_per_dir=60, name=f"{name} {layout}")
         assert _host_bytes(a) == _host_bytes(b), name
         for which in (0, 1):
             for i in np.unique(np.concatenate([rng.integers(0, len(t) + 2, 40), [0, len(t), len(t) + 1]])):
@@ -69,3 +83,15 @@ def test_device_index_aligns_like_host_index(fmt):
                              max_len=100)
         out.append([x.tobytes() for x in res.to_numpy()])
     assert out[0] == out[1]
+
+
+@pytest.mark.parametrize("fmt", [bw.RANK_PLANES, bw.RANK_SUBCOUNTS])
+def test_device_index_equals_oracle_at_16_mbp(fmt):
+    """A 16 Mbp genome built like the 100 Mbp one: many prefix-doubling
+    rounds over repeat copies, rank lines across many device blocks."""
+    g = configs.c2_genome(16_000_000, seed=65)
+    ox = _oracle_index("c2_16m", g.seq)
+    lay = dict(configs.LAYOUT["C2"]) if fmt == bw.RANK_PLANES else dict(line_bytes=64, sa_sample=32)
+    b = bw.Index.build_device(g.seq, **lay, rank_format=fmt)
+    assert_index_equals_oracle(b, ox, rows_per_dir=400, name=f"16 Mbp fmt {fmt}")
+    b.close()

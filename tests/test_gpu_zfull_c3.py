@@ -15,7 +15,16 @@ checked against properties that hold at any size:
   among the reported hits' positions (unless the read overflowed max_hits);
 * the tier rule: every reported hit scores at most S* + s_mm; tier-2 hits
   only when c1 <= max_best; c1 and c2 are the summed widths of the tiers;
-* report order (score, strand, k, len) without repeated (strand, k, len).
+* report order (score, strand, k, len) without repeated (strand, k, len);
+* completeness of exact placements: for every sampled read whose best score
+  is 0, the positions of its score-0 hits are exactly the occurrences of the
+  read and of its reverse complement found by a plain scan of the whole
+  text, and c1 is their number.
+
+The device-built index itself is checked where the oracle cannot go: Occ at
+row n + 1 equals the base counts of the text in both directions, and LF
+walks from random sampled rows retrace the text backwards and meet the SA
+samples they pass.
 
 Then the whole batch is paired, its mates rescued and MAPQ assigned, and
 checked by properties: rescue only where no proper pair exists, inserts
@@ -59,6 +68,29 @@ def test_c3_full_size_properties():
     ix = bw.Index.build_device(g.seq, **configs.LAYOUT["C3"])
     _log(f"device index in {time.time() - t0:.0f}s, {ix.info()['device_bytes'] / 1e9:.2f} GB")
     t0 = time.time()
+    info = ix.info()
+    sas = info["sa_sample"]
+    cnt = sum(np.bincount(g.seq[i:i + (1 << 27)], minlength=4) for i in range(0, GENOME, 1 << 27))
+    irng = np.random.default_rng(31)
+    for which in (0, 1):
+        assert ix.occ(GENOME + 1, which).tolist() == cnt.tolist()
+        C, prim = info["C"][which], info["primary"][which]
+        samp = ix.sa_samples(which)
+        for j in irng.choice(len(samp), 100, replace=False):
+            row, pos = int(j) * sas, int(samp[j])
+            for _ in range(3 * sas):
+                if row % sas == 0:
+                    assert int(samp[row // sas]) == pos, (which, row)
+                if pos == 0:
+                    assert row == prim
+                    break
+                o0, o1 = ix.occ(row, which), ix.occ(row + 1, which)
+                a = int(np.flatnonzero(o1 - o0)[0])  # BWT[row]
+                assert a == int(g.seq[pos - 1] if which == 0 else g.seq[GENOME - pos]), (which, row)
+                row, pos = C[a] + int(o0[a]), pos - 1
+    del samp
+    _log(f"index: Occ totals and 200 LF walks checked in {time.time() - t0:.0f}s")
+    t0 = time.time()
     pairs = configs.c3_pairs(g, PAIRS)
     _log(f"{PAIRS} pairs in {time.time() - t0:.0f}s")
     e1, e2 = pairs.end1, pairs.end2
@@ -85,6 +117,7 @@ def test_c3_full_size_properties():
     op = oracle.Params(**configs.PARAMS["C3"])
     gs = g.seq
     n_checked = n_truth = 0
+    exact = []  # (row, read, positions of its score-0 hits by strand, c1)
     for r in rows:
         e, j = (e1, r) if r < n else (e2, r - n)
         w = e.read(j)
@@ -126,6 +159,10 @@ def test_c3_full_size_properties():
             assert (int(y["score"]), int(y["n_mm"]), int(y["n_gapo"]), int(y["n_gape"])) == \
                 (int(x["score"]), int(x["n_mm"]), int(x["n_gapo"]), int(x["n_gape"])), (r, i)
             n_checked += 1
+        if len(h) and int(h["score"].min()) == 0:
+            zero = {(int(x["strand"]), int(q)) for i, x in enumerate(h) if int(x["score"]) == 0
+                    for q in pos[po[i] - po[0]:po[i + 1] - po[0]]}
+            exact.append((int(r), w, zero, int(c1[r])))
         # the best score against the generated edit script
         t = e.truth
         ops, opos = truth_transcript(t.e_type[j], t.e_idx[j], int(t.n_edits[j]), m)
@@ -137,6 +174,20 @@ def test_c3_full_size_properties():
                 assert (int(t.strand[j]), int(t.pos[j]), int(t.ref_len[j])) in located, r
     _log(f"checked {n_checked} hits, {n_truth} reads with valid scripts")
     assert n_checked > SAMPLE // 2 and n_truth > SAMPLE // 2
+    # exact placements against a scan of the whole text
+    t0 = time.time()
+    pats = [x for _, w, _, _ in exact for x in (w, revcomp(w))]
+    poff = np.zeros(len(pats) + 1, np.uint64)
+    poff[1:] = np.cumsum([len(x) for x in pats])
+    occ_off, occ = oracle.brute_exact_many(gs, np.concatenate(pats), poff, threads=16)
+    for j, (r, w, zero, c1r) in enumerate(exact):
+        fw = occ[occ_off[2 * j]:occ_off[2 * j + 1]]
+        rc = occ[occ_off[2 * j + 1]:occ_off[2 * j + 2]]
+        assert zero == {(0, int(q)) for q in fw} | {(1, int(q)) for q in rc}, r
+        assert c1r == len(fw) + len(rc), r
+    _log(f"{len(exact)} sampled reads with exact placements complete against a text scan "
+         f"({time.time() - t0:.0f}s)")
+    assert len(exact) > SAMPLE // 10
 
     # pairing, mate rescue and MAPQ over the whole batch
     w = configs.PAIR_WINDOW
