@@ -25,9 +25,21 @@
  *    memory.  Work is issued on the hip_stream argument (a hipStream_t
  *    passed as void *, NULL = the default stream).
  *  - The caller owns every buffer it passes in.  The library owns the
- *    index (host and device copies) and a per-index workspace, both
- *    released by bwfm_index_free.  Calls on one index are serialised by
- *    the library (a mutex guards its workspace).
+ *    index (host and device copies) and, per index, one grow-only device
+ *    workspace for each stream it has been called on, all released by
+ *    bwfm_index_free.
+ *  - Concurrency.  The index is read-only after upload: bwfm_align_batch,
+ *    bwfm_locate and bwfm_pair_reads calls on different streams may run at
+ *    the same time from different host threads, and their kernels overlap
+ *    on the device; each uses its own stream's workspace.  Calls on one
+ *    stream from several threads take turns.  bwfm_index_upload and
+ *    bwfm_index_kmer_table change the index and wait for the calls in
+ *    flight; bwfm_index_free must not overlap any other call on the index.
+ *  - The three calls above block the calling thread until their own stream
+ *    has finished the call's work (the number of hits decides the output
+ *    size, which they check); the captured step (bwfm_pipeline_*) is the
+ *    fully asynchronous form, with every count and capacity checked on the
+ *    device.
  */
 #ifndef BWFM_H
 #define BWFM_H
@@ -170,6 +182,9 @@ typedef struct {
     uint32_t line_bytes, bases_per_line, sa_sample, uploaded, rank_format;
     uint32_t kmer_levels;   /* levels of the device k-mer interval table (0: none) */
     uint64_t kmer_bytes;    /* device memory of that table, both directions (each padded to 256 bytes) */
+    uint64_t ws_bytes;      /* device memory of the per-stream workspaces, summed */
+    uint32_t ws_streams;    /* streams that have a workspace */
+    uint32_t pad;
 } bwfm_index_info;
 
 int bwfm_index_get_info(const bwfm_index *idx, bwfm_index_info *out);
@@ -344,8 +359,10 @@ typedef struct {
  * the chosen pair minimises (score1 + score2, |insert - mu|, pf, strand1,
  * pos1, len1, pos2, len2).  Without one, each end takes its primary: the
  * smallest (score, diffs, strand, pos, len) over its located hits.
- * out: device, n_pairs records.  Synchronous.  Errors: E_INVAL, E_STATE,
- * E_NOMEM, E_DEVICE.
+ * out: device, n_pairs records.  Synchronous.  The located positions live
+ * in the stream's workspace, which grows only when a call needs more than
+ * any earlier one on that stream.  Errors: E_INVAL, E_STATE, E_NOMEM,
+ * E_DEVICE.
  */
 int bwfm_pair_reads(const bwfm_index *idx, uint32_t n_pairs, const bwfm_aln_result *r1,
                     const bwfm_aln_result *r2, const bwfm_pair_params *p, bwfm_pair *out, void *hip_stream);

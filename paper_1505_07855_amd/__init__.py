@@ -55,7 +55,8 @@ class _IndexInfo(ctypes.Structure):
                 ("lines", ctypes.c_uint64), ("sa_samples", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
                 ("line_bytes", ctypes.c_uint32), ("bases_per_line", ctypes.c_uint32),
                 ("sa_sample", ctypes.c_uint32), ("uploaded", ctypes.c_uint32), ("rank_format", ctypes.c_uint32),
-                ("kmer_levels", ctypes.c_uint32), ("kmer_bytes", ctypes.c_uint64)]
+                ("kmer_levels", ctypes.c_uint32), ("kmer_bytes", ctypes.c_uint64), ("ws_bytes", ctypes.c_uint64),
+                ("ws_streams", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 
 class _Reads(ctypes.Structure):
@@ -327,7 +328,7 @@ class Index:
         return dict(n=i.n, primary=list(i.primary), C=[list(c) for c in i.C], lines=i.lines, sa_samples=i.sa_samples,
                     device_bytes=i.device_bytes, line_bytes=i.line_bytes, bases_per_line=i.bases_per_line,
                     sa_sample=i.sa_sample, uploaded=bool(i.uploaded), rank_format=i.rank_format,
-                    kmer_levels=i.kmer_levels, kmer_bytes=i.kmer_bytes)
+                    kmer_levels=i.kmer_levels, kmer_bytes=i.kmer_bytes, ws_bytes=i.ws_bytes, ws_streams=i.ws_streams)
 
     def bwt(self, which: int = 0) -> np.ndarray:
         out = np.empty(self.n + 1, np.uint8)

@@ -1825,23 +1825,37 @@ Params make_params(const bwfm_aln_params &p) {
     return P;
 }
 
-// carve a workspace of at least `bytes` (grow-only, per index)
-int ws_reserve(bwfm_index *ix, size_t bytes, void **out) {
-    if (ix->ws.bytes < bytes) {
-        if (ix->ws.ptr) {
-            hipError_t e = hipFree(ix->ws.ptr);
-            (void)e;
-        }
-        ix->ws.ptr = nullptr;
-        ix->ws.bytes = 0;
-        size_t want = bytes + bytes / 8;
-        if (hipMalloc(&ix->ws.ptr, want) != hipSuccess) {
-            ix->ws.ptr = nullptr;
-            return fail(BWFM_E_NOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
-        }
-        ix->ws.bytes = want;
+// The workspace of a stream on this index, created on first use.
+bwfm::Workspace &stream_ws(bwfm_index *ix, hipStream_t st) {
+    std::lock_guard<std::mutex> g(ix->ws_mu);
+    auto &w = ix->ws[(void *)st];
+    if (!w) w.reset(new bwfm::Workspace());
+    return *w;
+}
+
+// Grow a workspace buffer to at least `bytes` (grow-only).  The stream's
+// earlier work may still read the old buffer, so it is drained first.
+int ws_grow(void *&ptr, size_t &have, size_t bytes, hipStream_t st) {
+    if (have >= bytes && ptr) return BWFM_OK;
+    if (ptr) {
+        HIPCHK(hipStreamSynchronize(st));
+        (void)hipFree(ptr);
     }
-    *out = ix->ws.ptr;
+    ptr = nullptr;
+    have = 0;
+    const size_t want = std::max<size_t>(bytes + bytes / 8, 4096);
+    if (hipMalloc(&ptr, want) != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(BWFM_E_NOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    have = want;
+    return BWFM_OK;
+}
+
+int ws_reserve(bwfm::Workspace &w, size_t bytes, hipStream_t st, void **out) {
+    if (int rc = ws_grow(w.ptr, w.bytes, bytes, st)) return rc;
+    *out = w.ptr;
     return BWFM_OK;
 }
 
@@ -1913,8 +1927,8 @@ inline uint32_t block_for(uint32_t stride) {
 constexpr uint32_t SLOW_LANES = BWFM_SLOW_LANES;  // most lanes of the second pass
 
 template <int LW>
-int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, bwfm_aln_result *res,
-               hipStream_t st, uint32_t *expand, uint64_t *work = nullptr) {
+int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const bwfm_aln_params *p,
+               bwfm_aln_result *res, hipStream_t st, uint32_t *expand, uint64_t *work = nullptr) {
     const uint32_t n = rd->n_reads;
     const DevIndex D = dev_index(ix);
     const Params P = make_params(*p);
@@ -1938,7 +1952,7 @@ int align_impl(bwfm_index *ix, const bwfm_reads *rd, const bwfm_aln_params *p, b
     need += (size_t)n * 4 * 2 + (size_t)n * 8 + stage_cap * 16 + scan_part_elems(n) * 8 + 16 * 256;
     need += sizeof(PersistentArgs) + 256;
     void *w;
-    int rc = ws_reserve(ix, need, &w);
+    int rc = ws_reserve(ws, need, st, &w);
     if (rc) return rc;
     Carver cv{(char *)w};
     uint4 *lstack = cv.take<uint4>((size_t)lanes * stack_cap);
@@ -2057,7 +2071,7 @@ template <class F> auto by_layout(const bwfm_index *ix, F &&f) {
 
 extern "C" int bwfm_index_upload(bwfm_index *ix, void *stream) {
     if (!ix) return fail(BWFM_E_INVAL, "upload: NULL index");
-    std::lock_guard<std::mutex> g(ix->mu);
+    std::unique_lock<std::shared_mutex> g(ix->mu);
     if (ix->device >= 0) return BWFM_OK;
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
@@ -2090,7 +2104,7 @@ static uint64_t kt_bytes(uint32_t levels) {
 
 extern "C" int bwfm_index_kmer_table(bwfm_index *ix, int levels, void *stream) {
     if (!ix) return fail(BWFM_E_INVAL, "kmer_table: NULL index");
-    std::lock_guard<std::mutex> g(ix->mu);
+    std::unique_lock<std::shared_mutex> g(ix->mu);
     if (ix->device < 0) return fail(BWFM_E_INVAL, "kmer_table: the index is not uploaded");
     if (levels < -1 || levels > 15) return fail(BWFM_E_INVAL, "kmer_table: levels must be -1, 0 or 1..15");
     if (levels == -1) {
@@ -2156,7 +2170,10 @@ extern "C" void bwfm_index_free(bwfm_index *ix) {
         if (ix->d_kt[d]) (void)hipFree(ix->d_kt[d]);
     }
     if (ix->d_pac) (void)hipFree(ix->d_pac);
-    if (ix->ws.ptr) (void)hipFree(ix->ws.ptr);
+    for (auto &kv : ix->ws) {
+        if (kv.second->ptr) (void)hipFree(kv.second->ptr);
+        if (kv.second->pos) (void)hipFree(kv.second->pos);
+    }
     delete ix;
 }
 
@@ -2184,9 +2201,11 @@ extern "C" int bwfm_align_batch(const bwfm_index *cix, const bwfm_reads *rd, con
                                 bwfm_aln_result *res, void *stream) {
     bwfm_index *ix = const_cast<bwfm_index *>(cix);
     if (int rc = check_align_args(ix, rd, p, res)) return rc;
-    std::lock_guard<std::mutex> g(ix->mu);
+    std::shared_lock<std::shared_mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
-    return by_layout(ix, [&](auto lw) { return align_impl<decltype(lw)::value>(ix, rd, p, res, st, nullptr); });
+    bwfm::Workspace &ws = stream_ws(ix, st);
+    std::lock_guard<std::mutex> wg(ws.mu);
+    return by_layout(ix, [&](auto lw) { return align_impl<decltype(lw)::value>(ix, ws, rd, p, res, st, nullptr); });
 }
 
 // Same as bwfm_align_batch, also writing per-read search work (states
@@ -2196,9 +2215,13 @@ extern "C" int bwfm_align_batch_counted(const bwfm_index *cix, const bwfm_reads 
     bwfm_index *ix = const_cast<bwfm_index *>(cix);
     if (!expand) return fail(BWFM_E_INVAL, "align_batch_counted: NULL counter array");
     if (int rc = check_align_args(ix, rd, p, res)) return rc;
-    std::lock_guard<std::mutex> g(ix->mu);
+    std::shared_lock<std::shared_mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
-    return by_layout(ix, [&](auto lw) { return align_impl<decltype(lw)::value>(ix, rd, p, res, st, expand, work); });
+    bwfm::Workspace &ws = stream_ws(ix, st);
+    std::lock_guard<std::mutex> wg(ws.mu);
+    return by_layout(ix, [&](auto lw) {
+        return align_impl<decltype(lw)::value>(ix, ws, rd, p, res, st, expand, work);
+    });
 }
 
 extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_aln_result *res, uint32_t max_occ,
@@ -2206,8 +2229,10 @@ extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_a
     bwfm_index *ix = const_cast<bwfm_index *>(cix);
     if (!ix || !check_result(res, n_reads) || !pos_off || (!pos && cap)) return fail(BWFM_E_INVAL, "locate: NULL argument");
     if (!check_index(ix)) return fail(BWFM_E_STATE, "locate: index not uploaded");
-    std::lock_guard<std::mutex> g(ix->mu);
+    std::shared_lock<std::shared_mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
+    bwfm::Workspace &ws = stream_ws(ix, st);
+    std::lock_guard<std::mutex> wg(ws.mu);
     uint64_t h0 = 0, h1 = 0;
     HIPCHK(hipMemcpyAsync(&h0, res->hit_offsets, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&h1, res->hit_offsets + n_reads, 8, hipMemcpyDeviceToHost, st));
@@ -2216,7 +2241,7 @@ extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_a
     const uint64_t n_hits = h1 - h0;
     size_t need = n_hits * 4 + scan_part_elems(n_hits) * 8 + n_hits * 4 + 4096;
     void *w;
-    int rc = ws_reserve(ix, need, &w);
+    int rc = ws_reserve(ws, need, st, &w);
     if (rc) return rc;
     Carver cv{(char *)w};
     uint32_t *cnt = cv.take<uint32_t>(n_hits);
@@ -2241,8 +2266,10 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
         return fail(BWFM_E_INVAL, "pair_reads: NULL argument");
     if (!check_index(ix)) return fail(BWFM_E_STATE, "pair_reads: index not uploaded");
     if (pp->lo > pp->hi) return fail(BWFM_E_INVAL, "pair_reads: lo > hi");
-    std::lock_guard<std::mutex> g(ix->mu);
+    std::shared_lock<std::shared_mutex> g(ix->mu);
     hipStream_t st = (hipStream_t)stream;
+    bwfm::Workspace &ws = stream_ws(ix, st);
+    std::lock_guard<std::mutex> wg(ws.mu);
     const bwfm_aln_result *rr[2] = {r1, r2};
     uint64_t hb[2] = {0, 0}, he[2] = {0, 0}, nh[2] = {0, 0};
     for (int e = 0; e < 2; e++)
@@ -2255,46 +2282,43 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
         if (he[e] < hb[e]) return fail(BWFM_E_INVAL, "pair_reads: hit offsets decrease");
         nh[e] = he[e] - hb[e];
     }
-    // control buffers, then the positions of each end's hits
-    void *pairmem = nullptr;
-    uint64_t *poff[2] = {nullptr, nullptr};
-    uint32_t *pos[2] = {nullptr, nullptr};
+    // control buffers and each end's position offsets in the stream's
+    // workspace; the positions of both ends in its second buffer, sized by
+    // a counting pass
     const uint64_t nmax = std::max(nh[0], nh[1]);
-    size_t ctl = nmax * 4 * 2 + scan_part_elems(nmax) * 8 + 4096 + (nh[0] + nh[1] + 2) * 8;
-    if (hipMalloc(&pairmem, ctl) != hipSuccess) return fail(BWFM_E_NOMEM, "pair_reads: control buffers");
-    Carver cv{(char *)pairmem};
+    const size_t ctl = nmax * 4 * 2 + scan_part_elems(nmax) * 8 + 4096 + (nh[0] + nh[1] + 2) * 8 + 6 * 256;
+    void *wmem;
+    if (int rc = ws_reserve(ws, ctl, st, &wmem)) return rc;
+    Carver cv{(char *)wmem};
     uint32_t *cnt = cv.take<uint32_t>(nmax);
     uint32_t *big = cv.take<uint32_t>(nmax);
     uint64_t *part = cv.take<uint64_t>(scan_part_elems(nmax));
     uint32_t *n_big = cv.take<uint32_t>(1);
-    poff[0] = cv.take<uint64_t>(nh[0] + 1);
-    poff[1] = cv.take<uint64_t>(nh[1] + 1);
-    void *posmem[2] = {nullptr, nullptr};
-    int rc = BWFM_OK;
-    for (int e = 0; e < 2 && rc == BWFM_OK; e++) {
+    uint64_t *poff[2] = {cv.take<uint64_t>(nh[0] + 1), cv.take<uint64_t>(nh[1] + 1)};
+    uint64_t total[2] = {0, 0};
+    for (int e = 0; e < 2; e++) {
         if (!rr[e]) continue;
         const uint4 *hits = (const uint4 *)rr[e]->hits + hb[e];
-        // count pass (capacity 0 reports the total)
-        uint64_t total = 0;
-        rc = by_layout(ix, [&](auto lw) {
+        // counting pass: capacity 0 reports the total
+        int rc = by_layout(ix, [&](auto lw) {
             return locate_impl<decltype(lw)::value>(ix, nh[e], hits, pp->max_occ, poff[e], nullptr, 0, cnt, part, big,
-                                                    n_big, st, &total);
+                                                    n_big, st, &total[e]);
         });
-        if (rc == BWFM_E_CAPACITY || (rc == BWFM_OK && total == 0)) {
-            rc = BWFM_OK;
-            if (hipMalloc(&posmem[e], std::max<uint64_t>(total, 1) * 4) != hipSuccess) {
-                rc = fail(BWFM_E_NOMEM, "pair_reads: position buffer");
-                break;
-            }
-            pos[e] = (uint32_t *)posmem[e];
-            if (total)
-                rc = by_layout(ix, [&](auto lw) {
-                    return locate_impl<decltype(lw)::value>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total, cnt,
-                                                            part, big, n_big, st, &total);
-                });
-        }
+        if (rc != BWFM_OK && rc != BWFM_E_CAPACITY) return rc;
     }
-    if (rc == BWFM_OK && n_pairs) {
+    if (int rc = ws_grow(ws.pos, ws.pos_bytes, (total[0] + total[1] + 1) * 4, st)) return rc;
+    uint32_t *pos[2] = {(uint32_t *)ws.pos, (uint32_t *)ws.pos + total[0]};
+    for (int e = 0; e < 2; e++) {
+        if (!rr[e] || !total[e]) continue;
+        const uint4 *hits = (const uint4 *)rr[e]->hits + hb[e];
+        uint64_t t2 = 0;
+        int rc = by_layout(ix, [&](auto lw) {
+            return locate_impl<decltype(lw)::value>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total[e], cnt,
+                                                    part, big, n_big, st, &t2);
+        });
+        if (rc) return rc;
+    }
+    if (n_pairs) {
         EndView e1{r1->hit_offsets, (const uint4 *)r1->hits, poff[0], pos[0], hb[0]};
         EndView e2 = e1;
         if (r2) e2 = EndView{r2->hit_offsets, (const uint4 *)r2->hits, poff[1], pos[1], hb[1]};
@@ -2303,15 +2327,10 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
         k_pair<<<blocks(n_pairs, 256), 256, 0, st>>>(n_pairs, e1, e2, r2 ? 1 : 0, pp->lo, pp->hi, pp->mu, out, nullptr,
                                                      nullptr);
         tm.end(t);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) rc = fail(BWFM_E_DEVICE, std::string("k_pair: ") + hipGetErrorString(e));
+        HIPCHK(hipGetLastError());
     }
-    hipError_t es = hipStreamSynchronize(st);
-    if (rc == BWFM_OK && es != hipSuccess) rc = fail(BWFM_E_DEVICE, "pair_reads: synchronise failed");
-    for (int e = 0; e < 2; e++)
-        if (posmem[e]) (void)hipFree(posmem[e]);
-    (void)hipFree(pairmem);
-    return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    return BWFM_OK;
 }
 
 extern "C" int bwfm_max_diff_rule(uint32_t len, double err, double thres) {

@@ -3,7 +3,10 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
+#include <memory>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -45,9 +48,16 @@ constexpr uint64_t kt_level_start(int d) {
     return d == 0 ? 0 : 4 + (((uint64_t)1 << (2 * d)) - 4) / 3;
 }
 
+// Grow-only device scratch of one stream: calls on that stream carve their
+// temporaries from it; its mutex is held for the whole of a call, so calls
+// on one stream from several threads take turns while calls on different
+// streams proceed together.
 struct Workspace {
-    void *ptr = nullptr;
+    void *ptr = nullptr;  // control buffers and per-read temporaries
     size_t bytes = 0;
+    void *pos = nullptr;  // located positions (bwfm_pair_reads)
+    size_t pos_bytes = 0;
+    std::mutex mu;
 };
 
 std::string &last_error();
@@ -86,6 +96,10 @@ struct bwfm_index {
     uint32_t kt_levels = 0;
     uint64_t kt_gen = 0;  // bumped whenever the table changes (captured graphs hold its address)
     uint64_t device_bytes = 0;
-    std::mutex mu;
-    bwfm::Workspace ws;
+    // held shared by calls that only read the index's device state (align,
+    // locate, pair), exclusively by calls that change it (upload, the
+    // short-string table)
+    std::shared_mutex mu;
+    std::mutex ws_mu;                                           // guards ws
+    std::map<void *, std::unique_ptr<bwfm::Workspace>> ws;      // one per stream used
 };

@@ -341,6 +341,10 @@ extern "C" int bwfm_index_get_info(const bwfm_index *ix, bwfm_index_info *o) {
     o->rank_format = ix->rank_format;
     o->kmer_levels = ix->kt_levels;
     o->kmer_bytes = ix->kt_levels ? 2 * ((8 * bwfm::kt_level_start((int)ix->kt_levels + 1) + 255) / 256 * 256) : 0;
+    bwfm_index *mix = const_cast<bwfm_index *>(ix);
+    std::lock_guard<std::mutex> g(mix->ws_mu);
+    for (auto &kv : mix->ws) o->ws_bytes += kv.second->bytes + kv.second->pos_bytes;
+    o->ws_streams = (uint32_t)mix->ws.size();
     return BWFM_OK;
 }
 
