@@ -42,6 +42,17 @@ INT_ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 RESCUE_OPS_PER_CELL = 12
 
 
+def host_threads() -> int:
+    """Threads for the oracle's timed sample: every CPU this process may run
+    on, capped by the job's thread allowance when the environment sets one
+    (OMP_NUM_THREADS: a shared host's share for this job)."""
+    n = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(n, 1)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -226,7 +237,8 @@ def main_c3(args):
                    "parallelism": "1 GPU"},
         "p50_ms": float(np.percentile(np.array(times) * 1e3, 50)),
         "p99_ms": float(np.percentile(np.array(times) * 1e3, 99)),
-        "aligned_fraction": aligned / (2 * n), "roofline": roofline, "cpu_baseline": None,
+        "aligned_fraction": aligned / (2 * n), "overflow_reads": int(((st & bw.ST_OVERFLOW) != 0).sum()),
+        "roofline": roofline, "cpu_baseline": None,
         "cpu_baseline_note": "the oracle cannot index a 3.1 Gbp reference within a bench run",
     }
     print(json.dumps(out), flush=True)
@@ -363,12 +375,13 @@ def main():
         st = [r.status.cpu().numpy() for r in (r1, r2)]
         aligned = int(sum(((x & bw.ST_HIT) != 0).sum() for x in st))
         research = int(sum(((x & bw.ST_RESEARCH) != 0).sum() for x in st))
+        overflow = int(sum(((x & bw.ST_OVERFLOW) != 0).sum() for x in st))
         flags = bw.pairs_numpy(po)["flags"][:n]
         ms_step = total / steps * 1e3
         return {"steps": steps, "ms_per_step": ms_step, "aligned_reads_per_s": aligned / (ms_step / 1e3), "aligned": aligned,
                 "p50_ms": float(np.percentile(np.array(times) * 1e3, 50)),
                 "p99_ms": float(np.percentile(np.array(times) * 1e3, 99)),
-                "research_reads": research, "paired_fraction": float((flags & bw.PF_PAIRED).astype(bool).mean()),
+                "research_reads": research, "overflow_reads": overflow, "paired_fraction": float((flags & bw.PF_PAIRED).astype(bool).mean()),
                 "kernel_ms": kms, "out": out}
 
     def same(a, b):
@@ -430,7 +443,7 @@ def main():
         import oracle
         ox = ox_box["ox"]
         op = oracle.Params(**configs.PARAMS["C2"], bases_per_line=ix.info()["bases_per_line"])
-        nthreads = args.cpu_threads or min(os.cpu_count() or 1, 16)
+        nthreads = args.cpu_threads or host_threads()
         ns = min(args.cpu_pairs, args.pairs)
         sb = [(e.bases[:int(e.offsets[ns])], e.offsets[:ns + 1]) for e in (pairs.end1, pairs.end2)]
         t0 = time.perf_counter()
@@ -440,6 +453,7 @@ def main():
         cpu_s = time.perf_counter() - t0
         cpu_aligned = int(sum(((r.status & oracle.ST_HIT) != 0).sum() for r in ores))
         cpu = {"value": cpu_aligned / cpu_s, "unit": "aligned reads/s", "cores": nthreads, "kind": "oracle",
+               "host_cpus_visible": len(os.sched_getaffinity(0)),
                "sample": f"first {ns} pairs of the same batch ({2 * ns} reads): align both ends, locate, pair; "
                          f"{cpu_s:.1f} s"}
         # algorithmic bytes of the first-pass search kernel: rank lines the
@@ -496,6 +510,9 @@ def main():
         "p50_ms": batched["p50_ms"], "p99_ms": batched["p99_ms"],
         "reads_per_s": n_reads / (ms_step / 1e3), "pairs_per_s": n / (ms_step / 1e3),
         "aligned_fraction": aligned / n_reads, "paired_fraction": batched["paired_fraction"],
+        "overflow_reads": batched["overflow_reads"],
+        "overflow_note": "reads with more than max_hits (256) distinct candidate hits report none (status "
+                         "OVERFLOW, c1 = c2 = 0xFFFFFFFF), on the GPU and in the oracle alike",
         "plain": {k: v for k, v in plain.items()}, "batched": {k: v for k, v in batched.items()},
         "batched_eager": {k: v for k, v in eager.items()}, "autotune": tune,
         "end_to_end": {"ms_per_step": e2e["ms_per_step"], "aligned_reads_per_s": e2e["aligned_reads_per_s"],
