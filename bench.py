@@ -152,6 +152,111 @@ def rescue_leg(bw, torch, ix, ends, results, prs, n, w, stream, launches, n_ref,
                                   "bytes_per_launch": mq_bytes}}}
 
 
+def served_leg(bw, torch, ix, g, args, stream):
+    """The served form on the resident index, with serving-shaped requests
+    (76-150 bp pairs, 1% substitutions, 0.1% indel events, per-read budgets
+    from the length rule, sizes log-uniform in [1k, 200k] pairs).
+
+    First the same inputs through all three forms: a fixed set of requests
+    aligned as one batch by the plain form (a launch per end) and by the
+    batched form (both ends in one persistent launch), each followed by
+    pairing, and submitted at once to the server; the pair records must be
+    identical, and each form's rate is reads over the wall time to the last
+    record.  Then Poisson streams at fractions rho of the server's capacity
+    from that burst: request latency (submit to records on the host) p50
+    and p99, and reads/s over the replay."""
+    from gen import configs
+    from paper_1505_07855_amd import serve
+
+    w = configs.PAIR_WINDOW
+    params = dict(configs.PARAMS["C3"])
+    # same inputs, three forms
+    reqs = serve.make_requests(g, args.serve_same_requests, 7001, 1000, 200_000)
+    n = sum(r[4] for r in reqs)
+    b1 = np.concatenate([r[0] for r in reqs])
+    b2 = np.concatenate([r[2] for r in reqs])
+
+    def cat_offsets(k):
+        parts, base = [np.zeros(1, np.uint64)], np.uint64(0)
+        for r in reqs:
+            o = r[k].astype(np.uint64)
+            parts.append(o[1:] - o[0] + base)
+            base = parts[-1][-1]
+        return np.concatenate(parts)
+
+    o1, o2 = cat_offsets(1), cat_offsets(3)
+    L = np.concatenate([np.diff(o1), np.diff(o2)]).astype(np.int64)
+    rule = np.array([min(bw.max_diff_rule(x), 15) for x in range(513)], np.uint8)
+    md = torch.from_numpy(rule[L]).cuda()
+    ends = [(torch.from_numpy(b).cuda(), torch.from_numpy(o.view(np.int64)).cuda()) for b, o in ((b1, o1), (b2, o2))]
+    both_b = torch.cat([ends[0][0], ends[1][0]])
+    both_o = torch.from_numpy(np.concatenate([o1[:-1], o1[-1] + o2]).view(np.int64)).cuda()
+    forms = {}
+    recs = {}
+    for name, form in (("plain", bw.FORM_PLAIN), ("batched", bw.FORM_BATCHED)):
+        p = bw.Params(**params, form=form)
+        best = None
+        for rep in range(3):  # the first call grows workspaces
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if form == bw.FORM_PLAIN:
+                r1 = bw.align_batch(ix, ends[0][0], ends[0][1], p, max_diff=md[:n], max_len=150, stream=stream)
+                r2 = bw.align_batch(ix, ends[1][0], ends[1][1], p, max_diff=md[n:], max_len=150, stream=stream)
+            else:
+                r = bw.align_batch(ix, both_b, both_o, p, max_diff=md, max_len=150, stream=stream)
+                r1, r2 = r.window(0, n), r.window(n, 2 * n)
+            prs = bw.pair_reads(ix, r1, r2, w["lo"], w["hi"], w["mu"], configs.MAX_OCC, stream=stream)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        recs[name] = bw.pairs_numpy(prs)[:n].copy()
+        forms[name] = {"reads_per_s": 2 * n / best, "ms": best * 1e3}
+        log(f"served leg, same inputs: {name} {best * 1e3:.1f} ms")
+    srv = bw.Server(ix, bw.Params(**params), w["lo"], w["hi"], w["mu"], configs.MAX_OCC,
+                    arena_bytes=args.serve_arena_mib << 20, step_pairs=args.serve_step_pairs, max_len=150,
+                    budget_rule=True)
+    try:
+        serve.replay(srv, reqs[:2], 0.0, 1)  # warm-up: the server's first steps
+        best, lat = None, None
+        for rep in range(2):
+            lt, wall = serve.replay(srv, reqs, 0.0, 1)
+            if best is None or wall < best:
+                best, lat = wall, lt
+        # the records of the same burst, collected request by request
+        outs = []
+        tk = [srv.submit(r[0], r[1], r[2], r[3]) for r in reqs]
+        for t, r in zip(tk, reqs):
+            outs.append(srv.wait(t, r[4])[0])
+        got = np.concatenate(outs)
+        forms["served"] = {"reads_per_s": 2 * n / best, "ms": best * 1e3, "note": "burst of every request at once"}
+        log(f"served leg, same inputs: served {best * 1e3:.1f} ms")
+        same = (np.array_equal(recs["plain"].view(np.uint8), recs["batched"].view(np.uint8))
+                and np.array_equal(got.view(np.uint8), recs["batched"].view(np.uint8)))
+        if not same:
+            raise SystemExit("served, batched and plain forms disagree on the same requests")
+        cap_pairs = n / best
+        mean_size = (200_000 - 1000) / np.log(200_000 / 1000)
+        rates = []
+        for k, rho in enumerate(args.serve_rates):
+            rq = serve.make_requests(g, args.serve_requests, 5000 + k, 1000, 200_000)
+            lam = rho * cap_pairs / mean_size
+            lt, wall = serve.replay(srv, rq, lam, 77 + k)
+            sm = serve.summarize(lt, wall, rq)
+            sm.update({"rho": rho, "arrivals_per_s": lam})
+            rates.append(sm)
+            log(f"served leg: rho {rho}: p50 {sm['p50_ms']:.1f} ms, p99 {sm['p99_ms']:.1f} ms, "
+                f"{sm['reads_per_s'] / 1e6:.2f} M reads/s")
+            del rq
+        stats = srv.stats()
+    finally:
+        srv.close()
+    return {"workload": f"requests of 1k-200k pairs, 76-150 bp, 1% substitutions, 0.1% indel events, budgets by "
+                        f"the length rule, on the resident {len(g.seq) / 1e6:.0f} Mbp index",
+            "same_inputs": {"requests": len(reqs), "pairs": n, "identical_records": True, **forms},
+            "capacity_pairs_per_s": cap_pairs, "step_pairs": args.serve_step_pairs, "rates": rates,
+            "server": stats}
+
+
 def main_c3(args):
     """The uneven-length workload at full size (3.1 Gbp reference indexed on
     the device, 10M pairs of 36-150 bp with per-read budgets): the batched
@@ -262,6 +367,13 @@ def main():
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the autotuner (most waves that fit)")
     ap.add_argument("--no-rescue", action="store_true", help="skip the mate-rescue measurement")
     ap.add_argument("--rescue-launches", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served leg")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[0.3, 0.6, 0.9])
+    ap.add_argument("--serve-requests", type=int, default=300, help="requests per arrival rate")
+    ap.add_argument("--serve-same-requests", type=int, default=12,
+                    help="requests in the same-inputs comparison of the three forms")
+    ap.add_argument("--serve-step-pairs", type=int, default=131072)
+    ap.add_argument("--serve-arena-mib", type=int, default=2048)
     ap.add_argument("--steps-plain", type=int, default=0, help="steps for the plain form (default: --steps)")
     ap.add_argument("--config", choices=("c2", "c3"), default="c2",
                     help="c2: the benchmark workload (default); c3: the 3.1 Gbp uneven-length workload")
@@ -436,6 +548,10 @@ def main():
         log(f"rescue: {rescue['candidates']} candidates, {rescue['rescued']} rescued, "
             f"{rescue['avg_launch_ms']:.3f} ms per launch")
 
+    served = None
+    if not args.no_serve:
+        served = served_leg(bw, torch, ix, g, args, stream)
+
     roofline = None
     cpu = None
     if want_cpu:
@@ -518,7 +634,7 @@ def main():
         "end_to_end": {"ms_per_step": e2e["ms_per_step"], "aligned_reads_per_s": e2e["aligned_reads_per_s"],
                        "p99_ms": e2e["p99_ms"],
                        "note": "reads from pinned host memory, pair records, status, c1, c2 back to it"},
-        "roofline": roofline, "cpu_baseline": cpu, "rescue": rescue,
+        "roofline": roofline, "cpu_baseline": cpu, "rescue": rescue, "served": served,
     }
     print(json.dumps(out), flush=True)
 
