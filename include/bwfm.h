@@ -367,6 +367,28 @@ typedef struct {
 int bwfm_pair_reads(const bwfm_index *idx, uint32_t n_pairs, const bwfm_aln_result *r1,
                     const bwfm_aln_result *r2, const bwfm_pair_params *p, bwfm_pair *out, void *hip_stream);
 
+/* bytes of device scratch bwfm_pair_reads_noalloc works in (per device) */
+#define BWFM_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * bwfm_pair_reads for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, hosts that forbid hipMalloc):
+ * the same arguments, checks and results, but its control buffers and
+ * located positions live in a fixed device array of
+ * BWFM_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs
+ * on until the process ends; it calls no hipMalloc or hipFree.  The index's
+ * device must be current.  Limit: the control area (about 16 bytes per hit
+ * of the larger end plus 8 per hit of each end) and the positions (4 bytes
+ * each, both ends) must fit the scratch together; otherwise E_CAPACITY with
+ * the bytes needed in bwfm_last_error() and `out` unwritten.  Every call on
+ * a device shares that device's scratch: calls that overlap on one device,
+ * on any streams or threads, race and must be serialised by the caller.
+ * Synchronous.  Errors: E_INVAL, E_STATE, E_CAPACITY, E_DEVICE.
+ */
+int bwfm_pair_reads_noalloc(const bwfm_index *idx, uint32_t n_pairs, const bwfm_aln_result *r1,
+                            const bwfm_aln_result *r2, const bwfm_pair_params *p, bwfm_pair *out,
+                            void *hip_stream);
+
 /* ------------------------------------------------------------------ */
 /* Mate rescue (section 3.7: the pipeline ends with BWA's pairing step,  */
 /* which gives an end without a partner a local alignment near its mate) */

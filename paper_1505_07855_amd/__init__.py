@@ -36,6 +36,7 @@ FORM_BATCHED, FORM_PLAIN = 0, 1
 E_CAPACITY = -5
 E_IO = -8
 PIPE_E_HITS, PIPE_E_POSITIONS = 1, 2
+NOALLOC_SCRATCH_BYTES = 64 << 20  # BWFM_NOALLOC_SCRATCH_BYTES: the fixed scratch of bwfm_pair_reads_noalloc
 RANK_PLANES, RANK_SUBCOUNTS = 0, 1  # rank-line formats (bwfm_index_params.rank_format)
 
 
@@ -113,7 +114,7 @@ class _PipeStatus(ctypes.Structure):
 
 # every function include/bwfm.h declares, plus the counted variant
 SYMBOLS = ("bwfm_build_index", "bwfm_index_upload", "bwfm_index_free", "bwfm_index_get_info", "bwfm_index_get_bwt",
-           "bwfm_index_get_sa_samples", "bwfm_index_occ", "bwfm_align_batch", "bwfm_locate", "bwfm_pair_reads",
+           "bwfm_index_get_sa_samples", "bwfm_index_occ", "bwfm_align_batch", "bwfm_locate", "bwfm_pair_reads", "bwfm_pair_reads_noalloc",
            "bwfm_estimate_insert", "bwfm_max_diff_rule", "bwfm_last_error", "bwfm_align_batch_counted",
            "bwfm_timing_enable", "bwfm_timing_reset", "bwfm_timing_get", "bwfm_probe_gather",
            "bwfm_server_create", "bwfm_server_submit", "bwfm_server_wait", "bwfm_server_get_stats",
@@ -161,6 +162,7 @@ def lib():
             "bwfm_align_batch_counted": ([P, P, P, P, P, P, P], c_int),
             "bwfm_locate": ([P, u32, P, u32, P, P, u64, P], c_int),
             "bwfm_pair_reads": ([P, u32, P, P, P, P, P], c_int),
+            "bwfm_pair_reads_noalloc": ([P, u32, P, P, P, P, P], c_int),
             "bwfm_estimate_insert": ([P, u64, P], c_int),
             "bwfm_max_diff_rule": ([u32, ctypes.c_double, ctypes.c_double], c_int),
             "bwfm_last_error": ([], ctypes.c_char_p),
@@ -463,9 +465,11 @@ def locate(index: Index, res: AlignResult, max_occ: int, stream=None):
 
 
 def pair_reads(index: Index, r1: AlignResult, r2: AlignResult | None, lo: int, hi: int, mu: int, max_occ: int,
-               stream=None, out=None):
+               stream=None, out=None, noalloc: bool = False):
     """Pair end-1 and end-2 alignments (r2 None: single-end primaries).
-    Returns a device uint8 tensor [n, 24] of bwfm_pair records."""
+    Returns a device uint8 tensor [n, 24] of bwfm_pair records.  noalloc:
+    call bwfm_pair_reads_noalloc, which works in the library's fixed device
+    scratch (pass `out` too for a call that allocates nothing at all)."""
     torch = _torch()
     n = r1.n_reads
     if out is None:
@@ -473,8 +477,9 @@ def pair_reads(index: Index, r1: AlignResult, r2: AlignResult | None, lo: int, h
     pp = _PairParams(lo, hi, mu, max_occ)
     a = r1._c()
     b = r2._c() if r2 is not None else None
-    _check(lib().bwfm_pair_reads(index.handle, n, ctypes.byref(a), ctypes.byref(b) if b is not None else None,
-                                 ctypes.byref(pp), _dptr(out), _stream_ptr(stream)))
+    fn = lib().bwfm_pair_reads_noalloc if noalloc else lib().bwfm_pair_reads
+    _check(fn(index.handle, n, ctypes.byref(a), ctypes.byref(b) if b is not None else None,
+              ctypes.byref(pp), _dptr(out), _stream_ptr(stream)))
     return out
 
 

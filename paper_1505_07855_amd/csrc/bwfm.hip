@@ -32,6 +32,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -1752,7 +1753,8 @@ struct CallTimer {
     std::vector<Rec> recs;
     bool on;
     hipStream_t st;
-    explicit CallTimer(hipStream_t s) : st(s) {
+    explicit CallTimer(hipStream_t s, bool allowed = true) : on(false), st(s) {
+        if (!allowed) return;  // callers that must not create events
         std::lock_guard<std::mutex> g(timing().mu);
         on = timing().on;
     }
@@ -2020,7 +2022,7 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
 template <int LW>
 int locate_impl(bwfm_index *ix, uint64_t n_hits, const uint4 *hits, uint32_t max_occ, uint64_t *pos_off,
                 uint32_t *pos, uint64_t cap, uint32_t *cnt, uint64_t *part, uint32_t *big, uint32_t *n_big,
-                hipStream_t st, uint64_t *total_out) {
+                hipStream_t st, uint64_t *total_out, bool timed = true) {
     const DevIndex D = dev_index(ix);
     if (n_hits) {
         k_loc_count<<<blocks(n_hits, 256), 256, 0, st>>>(n_hits, hits, max_occ, cnt, nullptr);
@@ -2034,7 +2036,7 @@ int locate_impl(bwfm_index *ix, uint64_t n_hits, const uint4 *hits, uint32_t max
     *total_out = total;
     if (total > cap) return fail(BWFM_E_CAPACITY, "position capacity too small");
     if (total) {
-        CallTimer tm(st);
+        CallTimer tm(st, timed);
         int t = tm.begin("locate_rows");
         k_loc_rows<LW><<<(uint32_t)std::min<uint64_t>(blocks(total, 256), 65536), 256, 0, st>>>(D, n_hits, hits, pos_off, total,
                                                                                             pos, nullptr, nullptr);
@@ -2259,17 +2261,20 @@ extern "C" int bwfm_locate(const bwfm_index *cix, uint32_t n_reads, const bwfm_a
     return BWFM_OK;
 }
 
-extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bwfm_aln_result *r1,
-                               const bwfm_aln_result *r2, const bwfm_pair_params *pp, bwfm_pair *out, void *stream) {
-    bwfm_index *ix = const_cast<bwfm_index *>(cix);
-    if (!ix || !check_result(r1, n_pairs) || (r2 && !check_result(r2, n_pairs)) || !pp || (!out && n_pairs))
-        return fail(BWFM_E_INVAL, "pair_reads: NULL argument");
-    if (!check_index(ix)) return fail(BWFM_E_STATE, "pair_reads: index not uploaded");
-    if (pp->lo > pp->hi) return fail(BWFM_E_INVAL, "pair_reads: lo > hi");
-    std::shared_lock<std::shared_mutex> g(ix->mu);
-    hipStream_t st = (hipStream_t)stream;
-    bwfm::Workspace &ws = stream_ws(ix, st);
-    std::lock_guard<std::mutex> wg(ws.mu);
+namespace {
+
+// Buffers of one pair_reads call: `ctl` returns the control area (counts,
+// scan partials, per-hit position offsets of both ends), `pos` the located
+// positions of both ends; either may fail with an error code.
+struct PairMem {
+    std::function<int(size_t, void **)> ctl, pos;
+};
+
+// Locate every hit of both ends, then pair: the body shared by the
+// allocating and the non-allocating entry points.  The stream must be held
+// by the caller (workspace mutex or the scratch contract).
+int pair_impl(bwfm_index *ix, uint32_t n_pairs, const bwfm_aln_result *r1, const bwfm_aln_result *r2,
+              const bwfm_pair_params *pp, bwfm_pair *out, hipStream_t st, const PairMem &mem, bool timed) {
     const bwfm_aln_result *rr[2] = {r1, r2};
     uint64_t hb[2] = {0, 0}, he[2] = {0, 0}, nh[2] = {0, 0};
     for (int e = 0; e < 2; e++)
@@ -2282,13 +2287,12 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
         if (he[e] < hb[e]) return fail(BWFM_E_INVAL, "pair_reads: hit offsets decrease");
         nh[e] = he[e] - hb[e];
     }
-    // control buffers and each end's position offsets in the stream's
-    // workspace; the positions of both ends in its second buffer, sized by
-    // a counting pass
+    // control buffers and each end's position offsets first; the positions
+    // of both ends in the second buffer, sized by a counting pass
     const uint64_t nmax = std::max(nh[0], nh[1]);
     const size_t ctl = nmax * 4 * 2 + scan_part_elems(nmax) * 8 + 4096 + (nh[0] + nh[1] + 2) * 8 + 6 * 256;
     void *wmem;
-    if (int rc = ws_reserve(ws, ctl, st, &wmem)) return rc;
+    if (int rc = mem.ctl(ctl, &wmem)) return rc;
     Carver cv{(char *)wmem};
     uint32_t *cnt = cv.take<uint32_t>(nmax);
     uint32_t *big = cv.take<uint32_t>(nmax);
@@ -2302,19 +2306,20 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
         // counting pass: capacity 0 reports the total
         int rc = by_layout(ix, [&](auto lw) {
             return locate_impl<decltype(lw)::value>(ix, nh[e], hits, pp->max_occ, poff[e], nullptr, 0, cnt, part, big,
-                                                    n_big, st, &total[e]);
+                                                    n_big, st, &total[e], timed);
         });
         if (rc != BWFM_OK && rc != BWFM_E_CAPACITY) return rc;
     }
-    if (int rc = ws_grow(ws.pos, ws.pos_bytes, (total[0] + total[1] + 1) * 4, st)) return rc;
-    uint32_t *pos[2] = {(uint32_t *)ws.pos, (uint32_t *)ws.pos + total[0]};
+    void *pmem;
+    if (int rc = mem.pos((total[0] + total[1] + 1) * 4, &pmem)) return rc;
+    uint32_t *pos[2] = {(uint32_t *)pmem, (uint32_t *)pmem + total[0]};
     for (int e = 0; e < 2; e++) {
         if (!rr[e] || !total[e]) continue;
         const uint4 *hits = (const uint4 *)rr[e]->hits + hb[e];
         uint64_t t2 = 0;
         int rc = by_layout(ix, [&](auto lw) {
             return locate_impl<decltype(lw)::value>(ix, nh[e], hits, pp->max_occ, poff[e], pos[e], total[e], cnt,
-                                                    part, big, n_big, st, &t2);
+                                                    part, big, n_big, st, &t2, timed);
         });
         if (rc) return rc;
     }
@@ -2322,7 +2327,7 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
         EndView e1{r1->hit_offsets, (const uint4 *)r1->hits, poff[0], pos[0], hb[0]};
         EndView e2 = e1;
         if (r2) e2 = EndView{r2->hit_offsets, (const uint4 *)r2->hits, poff[1], pos[1], hb[1]};
-        CallTimer tm(st);
+        CallTimer tm(st, timed);
         int t = tm.begin("pair");
         k_pair<<<blocks(n_pairs, 256), 256, 0, st>>>(n_pairs, e1, e2, r2 ? 1 : 0, pp->lo, pp->hi, pp->mu, out, nullptr,
                                                      nullptr);
@@ -2331,6 +2336,99 @@ extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bw
     }
     HIPCHK(hipStreamSynchronize(st));
     return BWFM_OK;
+}
+
+int check_pair_args(const bwfm_index *ix, uint32_t n_pairs, const bwfm_aln_result *r1, const bwfm_aln_result *r2,
+                    const bwfm_pair_params *pp, const bwfm_pair *out) {
+    if (!ix || !check_result(r1, n_pairs) || (r2 && !check_result(r2, n_pairs)) || !pp || (!out && n_pairs))
+        return fail(BWFM_E_INVAL, "pair_reads: NULL argument");
+    if (!check_index(ix)) return fail(BWFM_E_STATE, "pair_reads: index not uploaded");
+    if (pp->lo > pp->hi) return fail(BWFM_E_INVAL, "pair_reads: lo > hi");
+    return BWFM_OK;
+}
+
+}  // namespace
+
+extern "C" int bwfm_pair_reads(const bwfm_index *cix, uint32_t n_pairs, const bwfm_aln_result *r1,
+                               const bwfm_aln_result *r2, const bwfm_pair_params *pp, bwfm_pair *out, void *stream) {
+    bwfm_index *ix = const_cast<bwfm_index *>(cix);
+    if (int rc = check_pair_args(ix, n_pairs, r1, r2, pp, out)) return rc;
+    std::shared_lock<std::shared_mutex> g(ix->mu);
+    hipStream_t st = (hipStream_t)stream;
+    bwfm::Workspace &ws = stream_ws(ix, st);
+    std::lock_guard<std::mutex> wg(ws.mu);
+    PairMem mem{[&](size_t b, void **p) { return ws_reserve(ws, b, st, p); },
+                [&](size_t b, void **p) {
+                    if (int rc = ws_grow(ws.pos, ws.pos_bytes, b, st)) return rc;
+                    *p = ws.pos;
+                    return (int)BWFM_OK;
+                }};
+    return pair_impl(ix, n_pairs, r1, r2, pp, out, st, mem, true);
+}
+
+// ------------------------------------------------------------------ fixed scratch
+
+// Device scratch of bwfm_pair_reads_noalloc: the control area at its start,
+// the located positions after it.  Each device holds its own copy; in host
+// code `scratch` names a host-side stand-in, so only the address returned
+// by hipGetSymbolAddress (kept per device below) reaches kernels.
+static __device__ __align__(256) uint8_t scratch[BWFM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// the device address of `scratch` on device dev, looked up on the first
+// call made with that device current
+int scratch_of(int dev, uint8_t **out) {
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(BWFM_E_DEVICE, "noalloc: device ordinal out of range");
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(BWFM_E_DEVICE, std::string("noalloc: scratch address lookup failed: ") + hipGetErrorString(e));
+        scratch_ptr[dev] = p;
+    }
+    *out = (uint8_t *)scratch_ptr[dev];
+    return BWFM_OK;
+}
+}  // namespace
+
+extern "C" int bwfm_pair_reads_noalloc(const bwfm_index *cix, uint32_t n_pairs, const bwfm_aln_result *r1,
+                                       const bwfm_aln_result *r2, const bwfm_pair_params *pp, bwfm_pair *out,
+                                       void *stream) {
+    bwfm_index *ix = const_cast<bwfm_index *>(cix);
+    if (int rc = check_pair_args(ix, n_pairs, r1, r2, pp, out)) return rc;
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != ix->device) return fail(BWFM_E_INVAL, "pair_reads_noalloc: the index's device must be current");
+    uint8_t *base;
+    if (int rc = scratch_of(dev, &base)) return rc;
+    std::shared_lock<std::shared_mutex> g(ix->mu);
+    hipStream_t st = (hipStream_t)stream;
+    size_t ctl_end = 0;
+    PairMem mem{[&](size_t b, void **p) {
+                    if (b > BWFM_NOALLOC_SCRATCH_BYTES)
+                        return fail(BWFM_E_CAPACITY, "pair_reads_noalloc: the hits need " + std::to_string(b) +
+                                                         " bytes of control buffers, more than the " +
+                                                         std::to_string((size_t)BWFM_NOALLOC_SCRATCH_BYTES) +
+                                                         "-byte scratch");
+                    ctl_end = (b + 255) & ~(size_t)255;
+                    *p = base;
+                    return (int)BWFM_OK;
+                },
+                [&](size_t b, void **p) {
+                    if (ctl_end + b > BWFM_NOALLOC_SCRATCH_BYTES)
+                        return fail(BWFM_E_CAPACITY, "pair_reads_noalloc: control buffers and positions need " +
+                                                         std::to_string(ctl_end + b) + " bytes, more than the " +
+                                                         std::to_string((size_t)BWFM_NOALLOC_SCRATCH_BYTES) +
+                                                         "-byte scratch");
+                    *p = base + ctl_end;
+                    return (int)BWFM_OK;
+                }};
+    return pair_impl(ix, n_pairs, r1, r2, pp, out, st, mem, false);
 }
 
 extern "C" int bwfm_max_diff_rule(uint32_t len, double err, double thres) {
