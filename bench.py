@@ -359,8 +359,10 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=250000, help="pairs in the oracle's timed sample (~15 s of host work)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--line-bytes", type=int, default=64)
-    ap.add_argument("--rank-format", type=int, default=0, help="0: counts + bit planes; 1: sub-counted 160-row lines")
+    ap.add_argument("--line-bytes", type=int, default=128)
+    ap.add_argument("--rank-format", type=int, default=2,
+                    help="0: counts + bit planes; 1: sub-counted 64-byte lines of 160 rows; "
+                         "2: sub-counted 128-byte lines of 384 rows")
     ap.add_argument("--kmer-levels", type=int, default=0,
                     help="short-string interval table levels (0: none, -1: automatic)")
     ap.add_argument("--waves-per-simd", type=int, default=0, help="batched-form residency (0 = autotuned)")
@@ -426,9 +428,22 @@ def main():
     tune = None
     if args.tune and args.waves_per_simd == 0:
         from paper_1505_07855_amd.tune import tune_batched
-        best, table = tune_batched(ix, both_b, both_o, p_batched, max_len=100, hit_capacity=8 * n, log=log)
+        # the same reference in every rank-line layout (the others built on
+        # the device, which gives the host builder's bytes)
+        cands = [ix]
+        have = (ix.info()["line_bytes"], ix.info()["rank_format"])
+        for lb, fmt in ((64, bw.RANK_PLANES), (64, bw.RANK_SUBCOUNTS), (128, bw.RANK_SUB128)):
+            if (lb, fmt) != have and args.kmer_levels == 0:
+                cands.append(bw.Index.build_device(g.seq, line_bytes=lb, sa_sample=32, rank_format=fmt))
+        best, table = tune_batched(cands, both_b, both_o, p_batched, max_len=100, hit_capacity=8 * n, log=log)
         p_batched.waves_per_simd = best["waves_per_simd"]
-        tune = {"best": best, "table": table}
+        ix = cands[best["key"]]
+        for c in cands:
+            if c is not ix:
+                c.close()
+        tune = {"best": best, "table": table,
+                "note": "median of 3 timed batched calls per candidate; every candidate's output identical"}
+        log(f"tune: picked {best['index']}, waves_per_simd {best['waves_per_simd']}")
     state = {"plain": [None, None, None], "eager": [None, None]}
 
     def step_plain():
@@ -622,7 +637,8 @@ def main():
                                f"{args.pairs} pairs 2x100 bp, <=4 diffs, 1 gap open, seed 32/<=2",
                    "pairs": args.pairs, "reads": n_reads, "form": "batched: align both ends in one persistent launch, locate, pair; replayed as one captured hipGraph",
                    "waves_per_simd": p_batched.waves_per_simd,
-                   "line_bytes": args.line_bytes, "rank_format": args.rank_format, "parallelism": "1 GPU"},
+                   "line_bytes": ix.info()["line_bytes"], "rank_format": ix.info()["rank_format"],
+                   "bases_per_line": ix.info()["bases_per_line"], "parallelism": "1 GPU"},
         "p50_ms": batched["p50_ms"], "p99_ms": batched["p99_ms"],
         "reads_per_s": n_reads / (ms_step / 1e3), "pairs_per_s": n / (ms_step / 1e3),
         "aligned_fraction": aligned / n_reads, "paired_fraction": batched["paired_fraction"],

@@ -82,7 +82,7 @@ typedef struct {
     uint32_t sa_sample;      /* rows r with r % sa_sample == 0 keep SA[r];
                                 a power of two in [1, 1024] */
     uint32_t n_threads;      /* host threads for the build; 0 = all cores */
-    uint32_t rank_format;    /* BWFM_RANK_PLANES or BWFM_RANK_SUBCOUNTS */
+    uint32_t rank_format;    /* BWFM_RANK_PLANES, BWFM_RANK_SUBCOUNTS or BWFM_RANK_SUB128 */
 } bwfm_index_params;
 
 /* Rank-line formats.  PLANES: 16 bytes of counts (A, C, G, T before the
@@ -90,11 +90,17 @@ typedef struct {
  * bytes of counts (C, G, T before the line; A follows from the row number),
  * then for each of C, G and T a uint32 of four bytes, byte g - 1 counting
  * that base in the line's first 32 g rows (g = 1..4), then the rows; a rank
- * query then counts bits in one 32-row group only.  Rows in both: for each
- * 32 rows a uint32 of the 2-bit codes' high bits, then one of their low
- * bits. */
+ * query then counts bits in one 32-row group only.  SUB128 (128-byte lines
+ * of 384 rows only): C, G, T before the line (12 bytes), then five uint32
+ * boundary words, word g - 1 holding the counts of C, G and T in the
+ * line's first 64 g rows (g = 1..5) as C | G << 9 | T << 18, then the rows;
+ * a rank query reads the line's first 32 bytes at most and the 16 bytes of
+ * its row's 64-row group, all inside the one 128-byte line.  Rows in every
+ * format: for each 32 rows a uint32 of the 2-bit codes' high bits, then one
+ * of their low bits. */
 #define BWFM_RANK_PLANES 0
 #define BWFM_RANK_SUBCOUNTS 1
+#define BWFM_RANK_SUB128 2
 
 /*
  * Build the FM-index of T = ref[0, n) and of reverse(T) on the host.

@@ -37,7 +37,7 @@ E_CAPACITY = -5
 E_IO = -8
 PIPE_E_HITS, PIPE_E_POSITIONS = 1, 2
 NOALLOC_SCRATCH_BYTES = 64 << 20  # BWFM_NOALLOC_SCRATCH_BYTES: the fixed scratch of bwfm_pair_reads_noalloc
-RANK_PLANES, RANK_SUBCOUNTS = 0, 1  # rank-line formats (bwfm_index_params.rank_format)
+RANK_PLANES, RANK_SUBCOUNTS, RANK_SUB128 = 0, 1, 2  # rank-line formats (bwfm_index_params.rank_format)
 
 
 class BwfmError(RuntimeError):

@@ -62,6 +62,30 @@ constexpr uint32_t PLAIN_STACK = 320;  // stack entries per lane, plain form fir
 #ifndef BWFM_SLOW_LANES
 #define BWFM_SLOW_LANES 16384
 #endif
+// Alternative implementations of single code sites ("genes"), chosen at
+// compile time; every alternative computes the same results, only its cost
+// differs.  0 is the shipped one.  paper_1505_07855_amd/variants.py
+// searches over them.
+//   ROWMASK:  row masks of a 32-row group by compare and select (0) or by
+//             one 64-bit shift (1).
+//   PAIRLINE: the paired rank query of planar lines shares a line that
+//             holds both rows (0) or always fetches two (1).
+//   REFILL:   idle lanes take new reads every iteration (0) or only once a
+//             quarter of the wave is idle or no lane is busy (1).
+//   SUBHDR:   a 128-byte sub-counted query reads the boundary words only
+//             for rows past 128 (0) or always (1).
+#ifndef BWFM_GENE_ROWMASK
+#define BWFM_GENE_ROWMASK 0
+#endif
+#ifndef BWFM_GENE_PAIRLINE
+#define BWFM_GENE_PAIRLINE 0
+#endif
+#ifndef BWFM_GENE_REFILL
+#define BWFM_GENE_REFILL 0
+#endif
+#ifndef BWFM_GENE_SUBHDR
+#define BWFM_GENE_SUBHDR 0
+#endif
 constexpr uint32_t FAST_CAND = BWFM_FAST_CAND;  // hit slots per lane, first pass
 constexpr int BLOCK = 256;
 constexpr int POPS_PER_STEP = BWFM_POPS_PER_STEP;  // stack pops per lane per persistent iteration (more costs the
@@ -147,7 +171,16 @@ __device__ __forceinline__ uint32_t line_of(const DevIndex &ix, uint32_t i) {
 // lines of 160 rows (counts of C, G, T, then per base the counts at the
 // first four 32-row boundaries as bytes, then the bit planes).
 constexpr int LW_SUB = 17;
-template <int LW> constexpr int line_words() { return LW == LW_SUB ? 16 : LW; }
+// LW_SUB128 = 128-byte sub-counted lines of 384 rows: counts of C, G, T
+// before the line (words 0-2); the counts within the line before rows 64,
+// 128, 192, 256 and 320, each as C | G << 9 | T << 18 (words 3-7); the bit
+// planes (words 8-31), per 32 rows a word of high bits then one of low bits,
+// so the four plane words of a 64-row group are one aligned 16-byte load.
+// A rank query reads the line's first 16 bytes, its boundary word and one
+// group: an L2 fill brings 128 bytes the query can use.
+constexpr int LW_SUB128 = 33;
+template <int LW> constexpr int line_words() { return LW == LW_SUB ? 16 : (LW == LW_SUB128 ? 32 : LW); }
+constexpr uint32_t SUB128_ROWS = 384;
 
 // The four (k, l) pairs of a string's one-base extensions, read from the
 // short-string table as two 16-byte words (p: A and C, q: G and T), in the
@@ -235,9 +268,73 @@ __device__ __forceinline__ void occ4_sub_pair(const DevIndex &ix, const DevDir &
     count(b, i2, l2, o2);
 }
 
+// Occ of all four bases at row i from the pieces of its 128-byte
+// sub-counted line: h = words 0-3 (C, G, T before the line, boundary word
+// of row 64), b = words 4-7 (boundary words of rows 128 .. 320; read only
+// when the row's group needs one of them), p = the four plane words of the
+// row's 64-row group; r = i's row within the line.
+__device__ __forceinline__ void sub128_count(uint4 h, uint4 b, uint4 p, uint32_t r, uint32_t i, uint32_t primary,
+                                             uint32_t o[4]) {
+    const uint32_t g = r >> 6, t = r & 63;
+    const uint32_t m0 = t >= 32 ? 0xffffffffu : (1u << t) - 1u;
+    const uint32_t m1 = t > 32 ? (1u << (t - 32)) - 1u : 0u;
+    // high plane set: G or T; low plane set: C or T; both: T
+    const uint32_t cT = __popc(p.x & p.y & m0) + __popc(p.z & p.w & m1);
+    const uint32_t cH = __popc(p.x & m0) + __popc(p.z & m1);
+    const uint32_t cL = __popc(p.y & m0) + __popc(p.w & m1);
+    const uint32_t bw = g == 0 ? 0u : (g == 1 ? h.w : (g == 2 ? b.x : (g == 3 ? b.y : (g == 4 ? b.z : b.w))));
+    o[1] = h.x + (bw & 511u) + cL - cT;
+    o[2] = h.y + ((bw >> 9) & 511u) + cH - cT;
+    o[3] = h.z + (bw >> 18) + cT;
+    o[0] = i - o[1] - o[2] - o[3] - (i > primary ? 1u : 0u);
+}
+
+__device__ __forceinline__ void occ4_sub128(const DevIndex &ix, const DevDir &d, uint32_t i, uint32_t o[4]) {
+    const uint32_t line = line_of(ix, i);
+    const uint32_t r = i - line * SUB128_ROWS;
+    const uint4 *L = reinterpret_cast<const uint4 *>(d.lines) + (size_t)line * 8;
+    const uint4 h = L[0];
+    uint4 b = make_uint4(0, 0, 0, 0);
+    if (BWFM_GENE_SUBHDR == 1 || r >= 128) b = L[1];
+    const uint4 p = L[2 + (r >> 6)];
+    sub128_count(h, b, p, r, i, d.primary, o);
+}
+
+// Occ at rows i1 and i2 (k and l + 1 of an interval) on 128-byte
+// sub-counted lines: the shared parts of one line are read once.
+__device__ __forceinline__ void occ4_sub128_pair(const DevIndex &ix, const DevDir &d, uint32_t i1, uint32_t i2,
+                                                 uint32_t o1[4], uint32_t o2[4]) {
+    const uint32_t l1 = line_of(ix, i1), l2 = line_of(ix, i2);
+    const uint32_t r1 = i1 - l1 * SUB128_ROWS, r2 = i2 - l2 * SUB128_ROWS;
+    const uint4 *L1 = reinterpret_cast<const uint4 *>(d.lines) + (size_t)l1 * 8;
+    const uint4 *L2 = reinterpret_cast<const uint4 *>(d.lines) + (size_t)l2 * 8;
+    const bool same = l1 == l2;
+    const uint4 h1 = L1[0];
+    uint4 b1 = make_uint4(0, 0, 0, 0), h2 = h1, b2 = b1;
+    if (BWFM_GENE_SUBHDR == 1 || r1 >= 128 || (same && r2 >= 128)) b1 = L1[1];
+    const uint4 p1 = L1[2 + (r1 >> 6)];
+    if (!same) {
+        h2 = L2[0];
+        if (BWFM_GENE_SUBHDR == 1 || r2 >= 128) b2 = L2[1];
+    } else {
+        b2 = b1;
+    }
+    uint4 p2 = p1;
+    if (!same || (r1 >> 6) != (r2 >> 6)) p2 = L2[2 + (r2 >> 6)];
+    sub128_count(h1, b1, p1, r1, i1, d.primary, o1);
+    sub128_count(h2, b2, p2, r2, i2, d.primary, o2);
+}
+
 // mask of the first t rows of a 32-row group (t may be <= 0 or >= 32)
 __device__ __forceinline__ uint32_t rows_mask(int t) {
+#if BWFM_GENE_ROWMASK == 1
+    // the low t bits of a 64-bit all-ones word shifted right by 64 - t,
+    // clamped to [0, 32] rows
+    const int c = t < 0 ? 0 : (t > 32 ? 32 : t);
+    return (uint32_t)(c == 0 ? 0ull : (~0ull >> (64 - c)));
+#else
     return t >= 32 ? 0xffffffffu : (t <= 0 ? 0u : ((1u << t) - 1u));
+#endif
 }
 
 // Occ(a, i) for all four bases (i <= n + 1).  Per 32-row group: one word of
@@ -246,6 +343,10 @@ template <int LW>
 __device__ __forceinline__ void occ4(const DevIndex &ix, const DevDir &d, uint32_t i, uint32_t o[4]) {
     if constexpr (LW == LW_SUB) {
         occ4_sub(ix, d, i, o);
+        return;
+    }
+    if constexpr (LW == LW_SUB128) {
+        occ4_sub128(ix, d, i, o);
         return;
     }
     uint32_t line = line_of(ix, i);
@@ -280,10 +381,14 @@ __device__ __forceinline__ void occ4_pair(const DevIndex &ix, const DevDir &d, u
         occ4_sub_pair(ix, d, i1, i2, o1, o2);
         return;
     }
+    if constexpr (LW == LW_SUB128) {
+        occ4_sub128_pair(ix, d, i1, i2, o1, o2);
+        return;
+    }
     const uint32_t l1 = line_of(ix, i1), l2 = line_of(ix, i2);
     const uint4 *L1 = reinterpret_cast<const uint4 *>(d.lines) + (size_t)l1 * (LW / 4);
     const uint4 *L2 = reinterpret_cast<const uint4 *>(d.lines) + (size_t)l2 * (LW / 4);
-    const bool same = l1 == l2;
+    const bool same = BWFM_GENE_PAIRLINE == 0 && l1 == l2;
     uint4 a[LW / 4], b[LW / 4];
 #pragma unroll
     for (int q = 0; q < LW / 4; q++) a[q] = L1[q];
@@ -320,9 +425,9 @@ __device__ __forceinline__ void occ4_pair(const DevIndex &ix, const DevDir &d, u
 // Occ(a, i) for one base a.
 template <int LW>
 __device__ __forceinline__ uint32_t occ1(const DevIndex &ix, const DevDir &d, int a, uint32_t i) {
-    if constexpr (LW == LW_SUB) {
+    if constexpr (LW == LW_SUB || LW == LW_SUB128) {
         uint32_t o[4];
-        occ4_sub(ix, d, i, o);
+        occ4<LW>(ix, d, i, o);
         return sel4(o, a);
     }
     uint32_t line = line_of(ix, i);
@@ -345,6 +450,20 @@ __device__ __forceinline__ uint32_t occ1(const DevIndex &ix, const DevDir &d, in
 // BWT symbol at row j (j != primary) and Occ(that symbol, j): one line.
 template <int LW>
 __device__ __forceinline__ uint32_t lf_step(const DevIndex &ix, const DevDir &d, uint32_t j) {
+    if constexpr (LW == LW_SUB128) {
+        const uint32_t line = line_of(ix, j);
+        const uint32_t r = j - line * SUB128_ROWS;
+        const uint4 *L = reinterpret_cast<const uint4 *>(d.lines) + (size_t)line * 8;
+        const uint4 h = L[0];
+        uint4 b = make_uint4(0, 0, 0, 0);
+        if (r >= 128) b = L[1];
+        const uint4 p = L[2 + (r >> 6)];
+        const uint32_t hi = (r & 32) ? p.z : p.x, lo = (r & 32) ? p.w : p.y, s = r & 31;
+        const int a = (int)((((hi >> s) & 1u) << 1) | ((lo >> s) & 1u));
+        uint32_t o[4];
+        sub128_count(h, b, p, r, j, d.primary, o);
+        return sel4(d.C, a) + sel4(o, a);
+    }
     uint32_t line = line_of(ix, j);
     uint32_t r = j - line * ix.bpl;
     const uint32_t *L = d.lines + (size_t)line * line_words<LW>();
@@ -963,7 +1082,12 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
         // refill idle lanes, one atomic per wave
         const bool want = phase == PZ_IDLE && !exhausted;
         const unsigned long long wm = __ballot(want);
+#if BWFM_GENE_REFILL == 1
+        // refill in bulk: a quarter of the wave idle, or nothing left running
+        if (wm && (__popcll(wm) >= 16 || __ballot(phase != PZ_IDLE) == 0)) {
+#else
         if (wm) {
+#endif
             const int leader = __ffsll(wm) - 1;
             uint32_t base = 0;
             if (lane == leader) base = atomicAdd(next_read, (uint32_t)__popcll(wm));
@@ -2064,6 +2188,7 @@ int check_result(const bwfm_aln_result *r, uint32_t n) {
 // Call f with the index's rank-line format as a compile-time tag.
 template <class F> auto by_layout(const bwfm_index *ix, F &&f) {
     if (ix->rank_format == BWFM_RANK_SUBCOUNTS) return f(std::integral_constant<int, LW_SUB>());
+    if (ix->rank_format == BWFM_RANK_SUB128) return f(std::integral_constant<int, LW_SUB128>());
     if (ix->line_bytes == 128) return f(std::integral_constant<int, 32>());
     if (ix->line_bytes == 32) return f(std::integral_constant<int, 8>());
     return f(std::integral_constant<int, 16>());

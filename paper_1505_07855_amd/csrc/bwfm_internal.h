@@ -72,6 +72,7 @@ int build_dir(const uint8_t *text, uint64_t n, uint32_t line_bytes, uint32_t bpl
               uint32_t rank_format, HostDir &out);
 // rewrite planar 64-byte lines of 160 rows as sub-counted ones, in place
 void subcount_lines(uint32_t *lines, uint64_t n_lines);
+void sub128_lines(uint32_t *lines, uint64_t n_lines);
 void occ_host(const HostDir &d, uint32_t line_words, uint32_t bpl, uint32_t rank_format, uint64_t i,
               uint64_t out[4]);
 uint8_t bwt_host(const HostDir &d, uint32_t line_words, uint32_t bpl, uint32_t rank_format, uint64_t row);

@@ -85,6 +85,32 @@ __global__ void k_ix_subcount(uint32_t *lines, uint64_t n_lines) {
     }
 }
 
+// planar 128-byte lines of 384 rows rewritten in place as 128-byte
+// sub-counted ones: counts of C, G, T before the line, the boundary words
+// of rows 64, 128, 192, 256 and 320 (C | G << 9 | T << 18), then the 24 row
+// words
+__global__ void k_ix_sub128(uint32_t *lines, uint64_t n_lines) {
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n_lines; x += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t *L = lines + x * 32;
+        uint32_t P[32];
+        for (int w = 0; w < 32; w++) P[w] = L[w];
+        uint32_t cC = 0, cG = 0, cT = 0;
+        for (int g = 0; g < 6; g++) {
+            if (g > 0) L[2 + g] = cC | (cG << 9) | (cT << 18);
+            for (int w = 0; w < 2; w++) {
+                const uint32_t h = P[4 + 4 * g + 2 * w], l = P[5 + 4 * g + 2 * w];
+                cC += __popc(~h & l);
+                cG += __popc(h & ~l);
+                cT += __popc(h & l);
+            }
+        }
+        L[0] = P[1];
+        L[1] = P[2];
+        L[2] = P[3];
+        for (int w = 0; w < 24; w++) L[8 + w] = P[4 + w];
+    }
+}
+
 // first-round keys: the 21 symbols from i, each code + 1, 0 from $ on
 __global__ void k_sa_init(const uint8_t *t, uint64_t n, uint64_t N, uint64_t *key, uint32_t *val) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -262,6 +288,7 @@ int build_dir_device(const uint8_t *t, uint64_t n, uint32_t line_bytes, uint32_t
     }
     k_ix_heads<<<grid_for(n_lines, B), B, 0, st>>>(off, n_lines, lw, lines);
     if (rank_format == BWFM_RANK_SUBCOUNTS) k_ix_subcount<<<grid_for(n_lines, B), B, 0, st>>>(lines, n_lines);
+    if (rank_format == BWFM_RANK_SUB128) k_ix_sub128<<<grid_for(n_lines, B), B, 0, st>>>(lines, n_lines);
     DCHK(hipGetLastError());
     // totals per base ($ counted as A) and the $ row
     uint64_t last_off[4];

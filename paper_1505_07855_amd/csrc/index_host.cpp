@@ -173,7 +173,31 @@ int build_dir(const uint8_t *text, uint64_t n, uint32_t line_bytes, uint32_t bpl
     out.C[0] = 1;
     for (int a = 1; a < 4; a++) out.C[a] = out.C[a - 1] + cnt[a - 1];
     if (rank_format == BWFM_RANK_SUBCOUNTS) subcount_lines(out.lines.data(), n_lines);
+    if (rank_format == BWFM_RANK_SUB128) sub128_lines(out.lines.data(), n_lines);
     return BWFM_OK;
+}
+
+// Plane lines of 128 bytes and 384 rows (counts of A, C, G, T, then 24
+// plane words) rewritten in place as 128-byte sub-counted lines.
+void sub128_lines(uint32_t *lines, uint64_t n_lines) {
+    for (uint64_t x = 0; x < n_lines; x++) {
+        uint32_t *L = lines + x * 32, P[32];
+        std::memcpy(P, L, sizeof P);
+        uint32_t cum[3] = {0, 0, 0};  // C, G, T in the rows before the group
+        for (int g = 0; g < 6; g++) {
+            if (g > 0) L[2 + g] = cum[0] | (cum[1] << 9) | (cum[2] << 18);
+            for (int w = 0; w < 2; w++) {
+                const uint32_t h = P[4 + 4 * g + 2 * w], l = P[5 + 4 * g + 2 * w];
+                cum[0] += (uint32_t)__builtin_popcount(~h & l);
+                cum[1] += (uint32_t)__builtin_popcount(h & ~l);
+                cum[2] += (uint32_t)__builtin_popcount(h & l);
+            }
+        }
+        L[0] = P[1];
+        L[1] = P[2];
+        L[2] = P[3];
+        for (int w = 0; w < 24; w++) L[8 + w] = P[4 + w];
+    }
 }
 
 void subcount_lines(uint32_t *lines, uint64_t n_lines) {
@@ -197,7 +221,9 @@ void subcount_lines(uint32_t *lines, uint64_t n_lines) {
     }
 }
 
-static inline uint32_t planes_at(uint32_t rank_format) { return rank_format == BWFM_RANK_SUBCOUNTS ? 6 : 4; }
+static inline uint32_t planes_at(uint32_t rank_format) {
+    return rank_format == BWFM_RANK_SUBCOUNTS ? 6 : (rank_format == BWFM_RANK_SUB128 ? 8 : 4);
+}
 
 static inline uint32_t code_at(const uint32_t *L, uint32_t po, uint64_t r) {
     return (((L[po + 2 * (r >> 5)] >> (r & 31)) & 1) << 1) | ((L[po + 1 + 2 * (r >> 5)] >> (r & 31)) & 1);
@@ -218,6 +244,19 @@ void occ_host(const HostDir &d, uint32_t lw, uint32_t bpl, uint32_t rank_format,
         const uint64_t g = r >> 5;
         for (int b = 0; b < 3; b++) out[1 + b] = L[b] + (g ? (L[3 + b] >> (8 * (g - 1))) & 255u : 0u);
         for (uint64_t x = 32 * g; x < r; x++) {
+            const uint32_t c = code_at(L, planes_at(rank_format), x);
+            if (c) out[c]++;
+        }
+        out[0] = i - out[1] - out[2] - out[3] - (i > d.primary ? 1 : 0);
+        return;
+    }
+    if (rank_format == BWFM_RANK_SUB128) {
+        // counts before the line, at the start of row r's 64-row group (the
+        // boundary word), then the group's rows before r
+        const uint64_t g = r >> 6;
+        const uint32_t bw = g ? L[2 + g] : 0u;
+        for (int b = 0; b < 3; b++) out[1 + b] = L[b] + ((bw >> (9 * b)) & 511u);
+        for (uint64_t x = 64 * g; x < r; x++) {
             const uint32_t c = code_at(L, planes_at(rank_format), x);
             if (c) out[c]++;
         }
@@ -248,12 +287,18 @@ namespace bwfm {
 int check_index_params(bwfm_index_params &q, uint64_t n) {
     if (q.line_bytes != 32 && q.line_bytes != 64 && q.line_bytes != 128)
         return fail(BWFM_E_INVAL, "line_bytes must be 32, 64 or 128");
-    if (q.rank_format != BWFM_RANK_PLANES && q.rank_format != BWFM_RANK_SUBCOUNTS)
+    if (q.rank_format != BWFM_RANK_PLANES && q.rank_format != BWFM_RANK_SUBCOUNTS &&
+        q.rank_format != BWFM_RANK_SUB128)
         return fail(BWFM_E_INVAL, "unknown rank_format");
     if (q.rank_format == BWFM_RANK_SUBCOUNTS) {
         if (q.bases_per_line == 0) q.bases_per_line = 160;
         if (q.line_bytes != 64 || q.bases_per_line != 160)
             return fail(BWFM_E_INVAL, "sub-counted rank lines are 64 bytes of 160 rows");
+    }
+    if (q.rank_format == BWFM_RANK_SUB128) {
+        if (q.bases_per_line == 0) q.bases_per_line = 384;
+        if (q.line_bytes != 128 || q.bases_per_line != 384)
+            return fail(BWFM_E_INVAL, "128-byte sub-counted rank lines are 128 bytes of 384 rows");
     }
     uint32_t maxb = (q.line_bytes - 16) * 4;
     if (q.bases_per_line == 0) q.bases_per_line = maxb;
@@ -486,7 +531,8 @@ extern "C" int bwfm_index_load(const char *path, bwfm_index **out) {
                            ix->bpl <= (ix->line_bytes - 16) * 4 && ix->sa_sample >= 1 && ix->sa_sample <= 1024 &&
                            (ix->sa_sample & (ix->sa_sample - 1)) == 0 && ix->n >= 1 && ix->n + 1 < (1ULL << 32) &&
                            (ix->rank_format == BWFM_RANK_PLANES ||
-                            (ix->rank_format == BWFM_RANK_SUBCOUNTS && ix->line_bytes == 64 && ix->bpl == 160)) &&
+                            (ix->rank_format == BWFM_RANK_SUBCOUNTS && ix->line_bytes == 64 && ix->bpl == 160) ||
+                            (ix->rank_format == BWFM_RANK_SUB128 && ix->line_bytes == 128 && ix->bpl == 384)) &&
                            ix->n_lines == (ix->n + 1) / ix->bpl + 1 && ix->n_samples == ix->n / ix->sa_sample + 1;
     if (!r.ok || !layout_ok) return fail(BWFM_E_IO, "index_load: corrupt header");
     const uint64_t words = ix->n_lines * (ix->line_bytes / 4);

@@ -1,14 +1,16 @@
 """Autotuner for the batched form.
 
-The batched form's speed depends on launch knobs that do not change its
-results: the kernel build and how many waves stay resident per SIMD (a
-build held to 128 registers keeps 4 waves per SIMD for latency hiding; the
-compiler's own budget keeps 3 with fewer instructions; fewer resident lanes
-also means more reads per lane) and the rank-line size of the index (64- or
-128-byte lines: bytes per rank query against popcount work per query).
-`tune_batched` times one batched call per candidate on the caller's own
-batch, checks that every candidate returns the same bytes, and returns the
-fastest.
+The batched form's speed depends on knobs that do not change its results:
+the rank-line format of the index (64-byte planar lines of 192 rows,
+64-byte sub-counted lines of 160 rows, 128-byte sub-counted lines of 384
+rows: bytes per rank query against bit counting per query), the kernel
+build and how many waves stay resident per SIMD (a build held to 128
+registers keeps 4 waves per SIMD; the compiler's own budget keeps 3; fewer
+resident waves mean fewer lanes in the grid and more reads per lane).
+`tune_batched` times every candidate on the caller's own batch (the median
+of `repeats` timed calls after one untimed call), checks that every
+candidate returns the same bytes, and returns the fastest with the whole
+table.
 """
 from __future__ import annotations
 
@@ -18,26 +20,37 @@ import numpy as np
 
 from . import FORM_BATCHED, Index, Params, align_batch, lib
 
+FORMAT_NAMES = {0: "planes", 1: "sub-counted", 2: "sub-counted"}
+
 
 def _digest(res):
     ho, hits, c1, c2, st = res.to_numpy()
     return (ho.tobytes(), hits.tobytes(), c1.tobytes(), c2.tobytes(), (st & 7).tobytes())
 
 
-def tune_batched(indexes: dict[int, Index] | Index, bases, offsets, params: Params, max_len: int, max_diff=None,
-                 waves=(0, 3), repeats: int = 1, hit_capacity: int | None = None, log=None):
-    """Time the batched form for every (rank-line size, waves per SIMD)
-    candidate.  `indexes` maps line bytes to an uploaded index of the same
-    reference (or is a single index).  Returns (best, table): best is a dict
-    with line_bytes, waves_per_simd and ms; table lists every candidate."""
+def index_label(ix: Index) -> str:
+    i = ix.info()
+    return f"{i['line_bytes']}B {FORMAT_NAMES.get(i['rank_format'], '?')} x{i['bases_per_line']}"
+
+
+def tune_batched(indexes, bases, offsets, params: Params, max_len: int, max_diff=None, waves=(0, 3, 2),
+                 repeats: int = 3, hit_capacity: int | None = None, log=None):
+    """Time the batched form for every (index layout, waves per SIMD)
+    candidate.  `indexes`: one uploaded index, or several of the same
+    reference in different layouts (a list or a dict of any keys).  Returns
+    (best, table): best is the fastest table row (index label, line bytes,
+    rank format, rows per line, waves per SIMD, median ms, every timing) plus
+    `key`, the position (list) or key (dict) of its index."""
     import torch
 
     lib()
     if isinstance(indexes, Index):
-        indexes = {indexes.info()["line_bytes"]: indexes}
+        indexes = [indexes]
+    items = list(indexes.items()) if isinstance(indexes, dict) else list(enumerate(indexes))
     table = []
     ref = None
-    for lb, ix in sorted(indexes.items()):
+    for key, ix in items:
+        info = ix.info()
         for w in waves:
             p = Params(**{**params.__dict__, "form": FORM_BATCHED, "waves_per_simd": w})
             res = align_batch(ix, bases, offsets, p, max_diff=max_diff, max_len=max_len, hit_capacity=hit_capacity)
@@ -46,16 +59,18 @@ def tune_batched(indexes: dict[int, Index] | Index, bases, offsets, params: Para
             if ref is None:
                 ref = d
             elif d != ref:
-                raise RuntimeError(f"batched form differs at line_bytes={lb}, waves_per_simd={w}")
+                raise RuntimeError(f"batched form differs for {index_label(ix)}, waves_per_simd={w}")
             ts = []
             for _ in range(repeats):
                 t0 = time.perf_counter()
                 res = align_batch(ix, bases, offsets, p, max_diff=max_diff, max_len=max_len, out=res)
                 torch.cuda.synchronize()
                 ts.append((time.perf_counter() - t0) * 1e3)
-            row = {"line_bytes": lb, "waves_per_simd": w, "ms": float(np.median(ts))}
+            row = {"index": index_label(ix), "key": key, "line_bytes": info["line_bytes"],
+                   "rank_format": info["rank_format"], "bases_per_line": info["bases_per_line"],
+                   "waves_per_simd": w, "ms": float(np.median(ts)), "ms_all": [float(t) for t in ts]}
             table.append(row)
             if log:
-                log(f"tune: line_bytes {lb} waves_per_simd {w}: {row['ms']:.1f} ms")
+                log(f"tune: {row['index']} waves_per_simd {w}: {row['ms']:.1f} ms (median of {repeats})")
     best = min(table, key=lambda r: r["ms"])
     return dict(best), table

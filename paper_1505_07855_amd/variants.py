@@ -1,19 +1,34 @@
-"""Search over compile-time variants of the search kernel.
+"""Genetic-improvement style search over compile-time variants of the
+search kernel.
 
-The paper improves BarraCUDA by evolving its kernel source and keeping a
+The paper improves BarraCUDA by changing its kernel source and keeping a
 change only when the output stays the same and the kernel gets faster
-(sections 1, 3 and 5).  Here the changes are restricted to the tuning
-constants the kernel source exposes as macros: stack pops per persistent
-iteration, first-pass hit slots per lane, second-pass lanes.  Each variant
-is its own library build; a variant counts only if its results on the batch
-are byte-identical to the reference build's, and the fastest such one wins.
+(sections 1, 3 and 5).  Here the kernel source (csrc/bwfm.hip) carries
+alternative implementations of single code sites ("genes", macros
+BWFM_GENE_*: row masks, the paired rank query, the refill of idle lanes,
+the sub-counted line's header loads) next to the tuning constants it
+exposes (stack pops per iteration, first-pass hit slots, second-pass
+lanes).  A variant is one value per gene; each variant is its own library
+build.  The search is a (1+1) evolution strategy in generations:
 
-    python -m paper_1505_07855_amd.variants build     # CPU: compile every variant library
-    python -m paper_1505_07855_amd.variants search    # GPU: time them on the benchmark batch
+* generation 1 mutates the reference in every single gene (each
+  alternative value once);
+* every later generation starts from the best variant so far (the parent)
+  and combines it with the genes of the other variants that beat the
+  reference, one gene at a time;
+* a variant is accepted only if its results on the benchmark batch are
+  byte-identical to the reference build's (the fitness test of the paper's
+  GI); among those the fastest wins, and a child replaces its parent only
+  when it is faster.
 
-`build` needs the objects of a normal build (paper_1505_07855_amd.build)
-next to it; `search` runs each variant in a process of its own and prints
-one JSON line: the table and the winner.
+Builds run on the CPU and timings on the GPU, so a generation is two steps:
+
+    python -m paper_1505_07855_amd.variants build [state.json]    # CPU: build the generation's variants
+    python -m paper_1505_07855_amd.variants search [state.json]   # GPU: time them, update the state
+
+The state file (default _variants/state.json) holds every evaluated
+variant, the parent and the next generation to build.  `search` runs each
+variant in a process of its own and prints one JSON line per generation.
 """
 from __future__ import annotations
 
@@ -27,26 +42,58 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 OUT = os.path.join(HERE, "_variants")
 
-# knob -> (reference value, alternatives)
-KNOBS = {
-    "BWFM_POPS_PER_STEP": (1, (2, 4)),
+# gene -> (reference value, alternatives)
+GENES = {
+    "BWFM_GENE_ROWMASK": (0, (1,)),
+    "BWFM_GENE_PAIRLINE": (0, (1,)),
+    "BWFM_GENE_REFILL": (0, (1,)),
+    "BWFM_GENE_SUBHDR": (0, (1,)),
+    "BWFM_POPS_PER_STEP": (1, (2,)),
     "BWFM_FAST_CAND": (64, (32, 128)),
-    "BWFM_SLOW_LANES": (16384, (8192, 32768)),
+    "BWFM_SLOW_LANES": (16384, (8192,)),
 }
 
 
-def variants():
-    """(name, {macro: value}): the reference build, then one knob changed at a time."""
-    out = [("reference", {})]
-    for knob, (_, alts) in KNOBS.items():
+# two variants the package build compiles for the GPU tests: every gene
+# away from the shipped value in one of them
+TEST_VARIANTS = [{"BWFM_GENE_ROWMASK": 1, "BWFM_GENE_PAIRLINE": 1},
+                 {"BWFM_GENE_REFILL": 1, "BWFM_GENE_SUBHDR": 1, "BWFM_POPS_PER_STEP": 2}]
+
+
+def name_of(defs: dict) -> str:
+    """A variant's name: its genes that differ from the reference."""
+    parts = [f"{k[5:].lower().replace('gene_', '')}{v}" for k, v in sorted(defs.items()) if GENES[k][0] != v]
+    return "_".join(parts) or "reference"
+
+
+def first_generation():
+    out = [{}]
+    for gene, (_, alts) in GENES.items():
         for v in alts:
-            out.append((f"{knob[5:].lower()}_{v}", {knob: v}))
+            out.append({gene: v})
     return out
 
 
-def build_one(name: str, defs: dict) -> str:
+def next_generation(state: dict):
+    """Children of the parent: the parent plus one gene of each variant that
+    beat the reference, not evaluated before."""
+    parent = state["parent"]["defines"]
+    seen = {name_of(r["defines"]) for r in state["table"]}
+    ref_ms = state["reference_ms"]
+    good = [r for r in state["table"] if r["accepted"] and r["ms"] < ref_ms]
+    kids = []
+    for r in good:
+        for gene, v in r["defines"].items():
+            child = {**parent, gene: v}
+            child = {k: x for k, x in child.items() if GENES[k][0] != x}
+            if name_of(child) not in seen and child not in kids:
+                kids.append(child)
+    return kids
+
+
+def build_one(defs: dict) -> str:
     from paper_1505_07855_amd import build as B
-    d = os.path.join(OUT, name)
+    d = os.path.join(OUT, name_of(defs))
     os.makedirs(d, exist_ok=True)
     obj = os.path.join(d, "bwfm.o")
     flags = [f"-D{k}={v}" for k, v in sorted(defs.items())]
@@ -61,9 +108,30 @@ def build_one(name: str, defs: dict) -> str:
     return lib
 
 
-def build() -> None:
-    for name, defs in variants():
-        build_one(name, defs)
+def lib_path(defs: dict) -> str:
+    return os.path.join(OUT, name_of(defs), "libbwfm.so")
+
+
+def _load_state(path: str) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {"generation": 0, "table": [], "parent": None, "reference_ms": None, "pending": first_generation()}
+
+
+def _save_state(path: str, state: dict) -> None:
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path + ".tmp", "w") as f:
+        json.dump(state, f, indent=1)
+    os.replace(path + ".tmp", path)
+
+
+def build(state_path: str) -> list:
+    """Build the pending generation's variants (CPU)."""
+    state = _load_state(state_path)
+    libs = [build_one(d) for d in state["pending"]]
+    _save_state(state_path, state)
+    return libs
 
 
 def _digest(res) -> str:
@@ -74,9 +142,9 @@ def _digest(res) -> str:
     return h.hexdigest()[:16]
 
 
-def time_one(lib: str, repeats: int = 3) -> dict:
+def time_one(lib: str, line_bytes: int, rank_format: int, repeats: int = 3) -> dict:
     """Time the batched search of the benchmark batch (both ends in one
-    launch) with the library at lib."""
+    launch) with the library at lib; median of `repeats` calls."""
     import numpy as np
     import torch
 
@@ -85,11 +153,11 @@ def time_one(lib: str, repeats: int = 3) -> dict:
     bw.LIB_PATH = lib
     g = configs.c2_genome()
     pairs = configs.c2_pairs(g)
-    ix = bw.Index.build_device(g.seq, line_bytes=64)
+    ix = bw.Index.build_device(g.seq, line_bytes=line_bytes, rank_format=rank_format)
     e1, e2 = pairs.end1, pairs.end2
     b = torch.from_numpy(np.concatenate([e1.bases, e2.bases])).cuda()
     o = torch.from_numpy(np.concatenate([e1.offsets[:-1], e1.offsets[-1] + e2.offsets]).view(np.int64)).cuda()
-    p = bw.Params(**configs.PARAMS["C2"], waves_per_simd=4)
+    p = bw.Params(**configs.PARAMS["C2"], waves_per_simd=0)
     res = bw.align_batch(ix, b, o, p, max_len=100, hit_capacity=8_000_000)
     torch.cuda.synchronize()
     ms = []
@@ -98,36 +166,53 @@ def time_one(lib: str, repeats: int = 3) -> dict:
         res = bw.align_batch(ix, b, o, p, max_len=100, out=res)
         torch.cuda.synchronize()
         ms.append((time.perf_counter() - t) * 1e3)
-    return {"lib": lib, "ms": min(ms), "digest": _digest(res)}
+    return {"lib": lib, "ms": float(np.median(ms)), "ms_all": ms, "digest": _digest(res)}
 
 
-def search() -> dict:
-    table = []
-    for name, defs in variants():
-        lib = os.path.join(OUT, name, "libbwfm.so")
+def search(state_path: str, line_bytes: int = 128, rank_format: int = 2) -> dict:
+    """Time the pending generation (GPU), each variant in its own process,
+    and advance the state: accept byte-identical variants, move the parent
+    to the fastest, and list the next generation."""
+    state = _load_state(state_path)
+    todo = state["pending"]
+    if state["reference_ms"] is None and {} not in todo:
+        todo = [{}] + todo
+    for defs in todo:
+        lib = lib_path(defs)
         if not os.path.exists(lib):
             raise RuntimeError(f"{lib} is missing: run the build step first")
-        r = subprocess.run([sys.executable, "-m", "paper_1505_07855_amd.variants", "time", lib],
-                           capture_output=True, text=True, cwd=os.path.dirname(HERE))
+        r = subprocess.run([sys.executable, "-m", "paper_1505_07855_amd.variants", "time", lib, str(line_bytes),
+                            str(rank_format)], capture_output=True, text=True, cwd=os.path.dirname(HERE))
         if r.returncode != 0:
-            raise RuntimeError(f"variant {name} failed: {r.stderr[-2000:]}")
+            raise RuntimeError(f"variant {name_of(defs)} failed: {r.stderr[-2000:]}")
         rec = json.loads(r.stdout.strip().splitlines()[-1])
-        rec.update(name=name, defines=defs)
-        table.append(rec)
-        print(f"[variants] {name}: {rec['ms']:.1f} ms digest {rec['digest']}", file=sys.stderr, flush=True)
-    ref = table[0]["digest"]
-    valid = [r for r in table if r["digest"] == ref]
-    best = min(valid, key=lambda r: r["ms"])
-    return {"table": table, "rejected": [r["name"] for r in table if r["digest"] != ref], "best": best["name"],
-            "best_ms": best["ms"], "reference_ms": table[0]["ms"]}
+        rec.update(name=name_of(defs), defines=defs, generation=state["generation"] + 1)
+        if not defs:
+            state["reference_ms"], state["reference_digest"] = rec["ms"], rec["digest"]
+        rec["accepted"] = rec["digest"] == state["reference_digest"]
+        state["table"].append(rec)
+        print(f"[variants] gen {rec['generation']} {rec['name']}: {rec['ms']:.1f} ms digest {rec['digest']}"
+              f"{'' if rec['accepted'] else ' REJECTED (output differs)'}", file=sys.stderr, flush=True)
+    ok = [r for r in state["table"] if r["accepted"]]
+    best = min(ok, key=lambda r: r["ms"])
+    if state["parent"] is None or best["ms"] < state["parent"]["ms"]:
+        state["parent"] = best
+    state["generation"] += 1
+    state["pending"] = next_generation(state)
+    _save_state(state_path, state)
+    return {"generation": state["generation"], "parent": state["parent"]["name"], "parent_ms": state["parent"]["ms"],
+            "reference_ms": state["reference_ms"], "evaluated": len(state["table"]),
+            "rejected": [r["name"] for r in state["table"] if not r["accepted"]],
+            "next": [name_of(d) for d in state["pending"]]}
 
 
 if __name__ == "__main__":
     sys.path.insert(0, os.path.dirname(HERE))
     what = sys.argv[1] if len(sys.argv) > 1 else "search"
+    default_state = os.path.join(OUT, "state.json")
     if what == "build":
-        build()
+        build(sys.argv[2] if len(sys.argv) > 2 else default_state)
     elif what == "time":
-        print(json.dumps(time_one(sys.argv[2])), flush=True)
+        print(json.dumps(time_one(sys.argv[2], int(sys.argv[3]), int(sys.argv[4]))), flush=True)
     else:
-        print(json.dumps(search()), flush=True)
+        print(json.dumps(search(sys.argv[2] if len(sys.argv) > 2 else default_state)), flush=True)

@@ -68,7 +68,7 @@ FORMS = [bw.FORM_BATCHED, bw.FORM_PLAIN]
 
 
 @pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("layout", [(64, 128), (128, 448), (64, 160, bw.RANK_SUBCOUNTS)])
+@pytest.mark.parametrize("layout", [(64, 128), (128, 448), (64, 160, bw.RANK_SUBCOUNTS), (128, 384, bw.RANK_SUB128)])
 @pytest.mark.parametrize("mode", [bw.MODE_BEST, bw.MODE_ALL])
 def test_c1_shape_parity(c1_small, layout, mode, form):
     g, reads, ox = c1_small
@@ -122,7 +122,8 @@ def c2_small():
 
 
 @pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("layout", [(128, 448, 32), (64, 192, 16), (32, 64, 32), (64, 160, 32, bw.RANK_SUBCOUNTS)])
+@pytest.mark.parametrize("layout", [(128, 448, 32), (64, 192, 16), (32, 64, 32), (64, 160, 32, bw.RANK_SUBCOUNTS),
+                                    (128, 384, 32, bw.RANK_SUB128)])
 def test_c2_shape_parity_align_locate_pair(c2_small, layout, form):
     g, pairs, ox = c2_small
     ix = bw.Index(g.seq, line_bytes=layout[0], bases_per_line=layout[1], sa_sample=layout[2],
@@ -266,7 +267,8 @@ def test_c3_shape_per_read_budgets_parity(form):
 
 
 @pytest.mark.parametrize("form,wps,fmt", [(bw.FORM_BATCHED, 0, bw.RANK_PLANES), (bw.FORM_BATCHED, 3, bw.RANK_PLANES),
-                                          (bw.FORM_PLAIN, 0, bw.RANK_PLANES), (bw.FORM_BATCHED, 0, bw.RANK_SUBCOUNTS)])
+                                          (bw.FORM_PLAIN, 0, bw.RANK_PLANES), (bw.FORM_BATCHED, 0, bw.RANK_SUBCOUNTS),
+                                          (bw.FORM_BATCHED, 0, bw.RANK_SUB128), (bw.FORM_PLAIN, 0, bw.RANK_SUB128)])
 def test_c5_shape_stress_parity(form, wps, fmt):
     """250 bp reads, 6 differences with gaps, a tenth from repeat copies: a few
     reads expand hundreds of thousands of states.  In the batched form their
@@ -274,7 +276,8 @@ def test_c5_shape_stress_parity(form, wps, fmt):
     g = configs.c2_genome(2_000_000, seed=55)
     reads = configs.c5_reads(g, 2000, seed=56)
     ox = oracle.Index(g.seq)
-    lay = dict(configs.LAYOUT["C5"]) if fmt == bw.RANK_PLANES else dict(line_bytes=64, sa_sample=32)
+    lay = dict(configs.LAYOUT["C5"]) if fmt == bw.RANK_PLANES else \
+        dict(line_bytes=128 if fmt == bw.RANK_SUB128 else 64, sa_sample=32)
     ix = bw.Index(g.seq, **lay, rank_format=fmt).upload()
     p, op = _params_pair(form=form, **configs.PARAMS["C5"])
     p.waves_per_simd = wps  # every build of the batched kernel

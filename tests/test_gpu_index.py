@@ -52,7 +52,7 @@ def _host_bytes(ix):
 
 
 @pytest.mark.parametrize("layout", [(64, 0, 32), (128, 0, 32), (64, 128, 8), (32, 0, 32),
-                                    (64, 0, 32, bw.RANK_SUBCOUNTS)])
+                                    (64, 0, 32, bw.RANK_SUBCOUNTS), (128, 0, 32, bw.RANK_SUB128)])
 def test_device_index_equals_host_index(layout):
     lb, bpl, sas = layout[:3]
     fmt = layout[3] if len(layout) > 3 else bw.RANK_PLANES
@@ -70,13 +70,20 @@ def test_device_index_equals_host_index(layout):
         b.close()
 
 
-@pytest.mark.parametrize("fmt", [bw.RANK_PLANES, bw.RANK_SUBCOUNTS])
+def _layout(fmt):
+    """The benchmark's line layout for planar lines, else the format's own."""
+    if fmt == bw.RANK_PLANES:
+        return dict(configs.LAYOUT["C2"])
+    return dict(line_bytes=128 if fmt == bw.RANK_SUB128 else 64, sa_sample=32)
+
+
+@pytest.mark.parametrize("fmt", [bw.RANK_PLANES, bw.RANK_SUBCOUNTS, bw.RANK_SUB128])
 def test_device_index_aligns_like_host_index(fmt):
     g = configs.c2_genome(2_000_000, seed=62)
     pairs = configs.c2_pairs(g, 1000, seed=63)
     p = bw.Params(**configs.PARAMS["C2"])
     out = []
-    lay = dict(configs.LAYOUT["C2"]) if fmt == bw.RANK_PLANES else dict(line_bytes=64, sa_sample=32)
+    lay = _layout(fmt)
     for ix in (bw.Index(g.seq, **lay, rank_format=fmt).upload(), bw.Index.build_device(g.seq, **lay, rank_format=fmt)):
         e = pairs.end1
         res = bw.align_batch(ix, torch.from_numpy(e.bases).cuda(), torch.from_numpy(e.offsets.view(np.int64)).cuda(), p,
@@ -85,13 +92,13 @@ def test_device_index_aligns_like_host_index(fmt):
     assert out[0] == out[1]
 
 
-@pytest.mark.parametrize("fmt", [bw.RANK_PLANES, bw.RANK_SUBCOUNTS])
+@pytest.mark.parametrize("fmt", [bw.RANK_PLANES, bw.RANK_SUBCOUNTS, bw.RANK_SUB128])
 def test_device_index_equals_oracle_at_16_mbp(fmt):
     """A 16 Mbp genome built like the 100 Mbp one: many prefix-doubling
     rounds over repeat copies, rank lines across many device blocks."""
     g = configs.c2_genome(16_000_000, seed=65)
     ox = _oracle_index("c2_16m", g.seq)
-    lay = dict(configs.LAYOUT["C2"]) if fmt == bw.RANK_PLANES else dict(line_bytes=64, sa_sample=32)
+    lay = _layout(fmt)
     b = bw.Index.build_device(g.seq, **lay, rank_format=fmt)
     assert_index_equals_oracle(b, ox, rows_per_dir=400, name=f"16 Mbp fmt {fmt}")
     b.close()

@@ -28,7 +28,7 @@ def _codes_to_strings(level: int) -> np.ndarray:
 
 
 @pytest.mark.parametrize("layout", [(64, 192, bw.RANK_PLANES), (128, 0, bw.RANK_PLANES), (32, 0, bw.RANK_PLANES),
-                                    (64, 0, bw.RANK_SUBCOUNTS)])
+                                    (64, 0, bw.RANK_SUBCOUNTS), (128, 0, bw.RANK_SUB128)])
 def test_table_entries_match_exact_search(layout):
     lb, bpl, fmt = layout
     g = gen.genome_repeats(71, 30_000, repeat_frac=0.4, n_fam=10, min_len=50, max_len=800, div_lo=0.0,

@@ -20,7 +20,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 LAYOUTS = [(32, 0, 1, bw.RANK_PLANES), (64, 0, 32, bw.RANK_PLANES), (64, 96, 8, bw.RANK_PLANES),
-           (128, 0, 32, bw.RANK_PLANES), (128, 224, 64, bw.RANK_PLANES), (64, 0, 16, bw.RANK_SUBCOUNTS)]
+           (128, 0, 32, bw.RANK_PLANES), (128, 224, 64, bw.RANK_PLANES), (64, 0, 16, bw.RANK_SUBCOUNTS),
+           (128, 0, 32, bw.RANK_SUB128), (128, 384, 8, bw.RANK_SUB128)]
 
 
 def _config(seed: int):

@@ -40,7 +40,8 @@ def _texts(rng):
 
 @pytest.mark.parametrize("layout", [(128, 0, 32), (64, 0, 32), (64, 128, 32), (128, 64, 1), (64, 32, 8),
                                     (128, 448, 1024), (32, 0, 32), (32, 32, 4), (64, 0, 32, bw.RANK_SUBCOUNTS),
-                                    (64, 160, 1, bw.RANK_SUBCOUNTS)])
+                                    (64, 160, 1, bw.RANK_SUBCOUNTS), (128, 0, 32, bw.RANK_SUB128),
+                                    (128, 384, 1, bw.RANK_SUB128)])
 def test_host_index_equals_oracle_index(layout, rng):
     lb, bpl, sas = layout[:3]
     fmt = layout[3] if len(layout) > 3 else bw.RANK_PLANES
@@ -162,19 +163,39 @@ def test_index_save_load_roundtrip_and_corruption(rng, tmp_path, fmt):
     ix.close()
 
 
-def test_variant_knobs_match_the_source_defaults():
+def test_variant_genes_match_the_source_defaults():
     """The variant search's reference values are the kernel source's own
-    defaults, so its reference build is the shipped library."""
+    defaults, so its reference build is the shipped library; its first
+    generation changes one gene at a time; the next generation combines the
+    parent with the genes of variants that beat the reference; the test
+    variants use only declared genes and alternatives."""
     import re
 
     from paper_1505_07855_amd import variants
     src = open(os.path.join(os.path.dirname(bw.__file__), "csrc", "bwfm.hip")).read()
-    for knob, (ref, alts) in variants.KNOBS.items():
-        m = re.search(r"#ifndef %s\n#define %s (\d+)\n#endif" % (knob, knob), src)
-        assert m and int(m.group(1)) == ref, knob
+    for gene, (ref, alts) in variants.GENES.items():
+        m = re.search(r"#ifndef %s\n#define %s (\d+)\n#endif" % (gene, gene), src)
+        assert m and int(m.group(1)) == ref, gene
         assert ref not in alts
-    names = [n for n, _ in variants.variants()]
-    assert names[0] == "reference" and len(names) == len(set(names)) == 1 + sum(len(a) for _, a in variants.KNOBS.values())
+        if gene.startswith("BWFM_GENE_"):
+            # the source branches on the gene
+            assert re.search(r"%s == \d" % gene, src), gene
+    first = variants.first_generation()
+    names = [variants.name_of(d) for d in first]
+    assert names[0] == "reference" and len(names) == len(set(names)) == 1 + sum(len(a) for _, a in
+                                                                               variants.GENES.values())
+    for d in variants.TEST_VARIANTS:
+        assert all(k in variants.GENES and v in variants.GENES[k][1] for k, v in d.items())
+    # a generation after singles: the parent (the fastest single) combined
+    # with each other single that beat the reference, never re-evaluating one
+    table = [{"defines": d, "accepted": True, "ms": 100.0 - i} for i, d in enumerate(first)]
+    table[2]["accepted"] = False
+    state = {"table": table, "reference_ms": 100.0, "parent": table[-1]}
+    kids = variants.next_generation(state)
+    parent = table[-1]["defines"]
+    assert kids and all(len(k) == 2 and all(parent.items() <= k.items() for _ in [0]) for k in kids)
+    assert not any(first[2].items() <= k.items() for k in kids)
+    assert len({variants.name_of(k) for k in kids}) == len(kids)
 
 
 @pytest.mark.parametrize("shape", ["C1", "C2"])
