@@ -19,19 +19,27 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gen.c")
-_LIB = os.path.join(_HERE, "libgen.so")
+# BWFM_SANITIZE=1 selects the AddressSanitizer + UndefinedBehaviorSanitizer
+# build (libgen.san.so; the process must preload the sanitizer runtimes)
+SANITIZE = os.environ.get("BWFM_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "libgen.san.so" if SANITIZE else "libgen.so")
 _lib = None
 
 MAX_EDITS = 64
 
 
-def build(force: bool = True) -> str:
-    """Compile gen.c into libgen.so next to it (gcc, OpenMP)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = True, sanitize: bool | None = None) -> str:
+    """Compile gen.c into libgen.so next to it (gcc, OpenMP); sanitize: the
+    sanitizer build libgen.san.so instead (default: as BWFM_SANITIZE selects)."""
+    sanitize = SANITIZE if sanitize is None else sanitize
+    so = os.path.join(_HERE, "libgen.san.so" if sanitize else "libgen.so")
+    if force or not os.path.exists(so):
+        tmp = so + ".tmp"
+        extra = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"] \
+            if sanitize else []
+        subprocess.check_call(["gcc", "-O2", *extra, "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, so)
+    return so
 
 
 def lib():

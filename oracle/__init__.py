@@ -20,9 +20,19 @@ from dataclasses import dataclass, fields
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
+# BWFM_SANITIZE=1 selects the AddressSanitizer + UndefinedBehaviorSanitizer
+# builds (lib*.san.so; the process must preload the sanitizer runtimes)
+SANITIZE = os.environ.get("BWFM_SANITIZE") == "1"
+SAN_FLAGS = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+def _so(name: str, sanitize: bool) -> str:
+    return os.path.join(_HERE, f"lib{name}.san.so" if sanitize else f"lib{name}.so")
+
+
 _LIBS = {
-    "oracle": (os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "liboracle.so")),
-    "brute": (os.path.join(_HERE, "brute.c"), os.path.join(_HERE, "libbrute.so")),
+    "oracle": (os.path.join(_HERE, "oracle.c"), _so("oracle", SANITIZE)),
+    "brute": (os.path.join(_HERE, "brute.c"), _so("brute", SANITIZE)),
 }
 _loaded: dict = {}
 
@@ -40,12 +50,16 @@ PF_PAIRED, PF_MAPPED1, PF_MAPPED2, PF_REP1, PF_REP2 = 1, 2, 4, 8, 16
 MODE_ALL, MODE_BEST = 0, 1
 
 
-def build(force: bool = True) -> None:
-    """Compile the oracle and the brute-force checkers with gcc."""
-    for src, so in _LIBS.values():
+def build(force: bool = True, sanitize: bool | None = None) -> None:
+    """Compile the oracle and the brute-force checkers with gcc (sanitize:
+    the sanitizer builds instead; default: as BWFM_SANITIZE selects)."""
+    sanitize = SANITIZE if sanitize is None else sanitize
+    for name, (src, _) in _LIBS.items():
+        so = _so(name, sanitize)
         if force or not os.path.exists(so):
             tmp = so + ".tmp"
-            subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-pthread", "-o", tmp, src, "-lm"])
+            extra = SAN_FLAGS if sanitize else []
+            subprocess.check_call(["gcc", "-O2", *extra, "-fPIC", "-shared", "-pthread", "-o", tmp, src, "-lm"])
             os.replace(tmp, so)
 
 
