@@ -86,6 +86,13 @@ constexpr uint32_t PLAIN_STACK = 320;  // stack entries per lane, plain form fir
 #ifndef BWFM_GENE_SUBHDR
 #define BWFM_GENE_SUBHDR 0
 #endif
+//   DPREPASS: the batched form scans each read's D-arrays inside the
+//             persistent loop, one rank query per iteration (0), or in a
+//             pre-pass kernel of its own, one lane per read, so the loop
+//             only searches (1).
+#ifndef BWFM_GENE_DPREPASS
+#define BWFM_GENE_DPREPASS 0
+#endif
 constexpr uint32_t FAST_CAND = BWFM_FAST_CAND;  // hit slots per lane, first pass
 constexpr int BLOCK = 256;
 constexpr int POPS_PER_STEP = BWFM_POPS_PER_STEP;  // stack pops per lane per persistent iteration (more costs the
@@ -1035,7 +1042,57 @@ struct PersistentArgs {
     LaneBufs B;
     ReadOut O;
     uint32_t *next_read;
+    // the D-array pre-pass's output: per read, one row per strand of
+    // dstride bytes (base | D << 3 per pattern position) and a byte whose
+    // bit s is set when strand s is pruned at the root
+    const uint8_t *drows;
+    const uint8_t *dflag;
+    uint32_t dstride;
 };
+
+// Row of read r, strand s, in the pre-pass's output.
+__device__ __forceinline__ const uint8_t *drow_of(const uint8_t *drows, uint32_t dstride, uint32_t r, int s) {
+    return drows + ((size_t)r * 2 + (size_t)s) * dstride;
+}
+
+// D-array pre-pass of the batched form: one lane per read, both strands in
+// turn on the other index (the same scan as the plain form's, with the
+// short-string table when the index has one), each strand's row staged in
+// LDS and then copied out whole.
+template <int LW>
+__global__ __launch_bounds__(BLOCK) void k_dscan(DevIndex ix, ReadsView rd, Params P, uint8_t *drows, uint8_t *dflag,
+                                                 uint32_t dstride, uint32_t lstride) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= reads_n(rd)) return;
+    uint64_t o0, len;
+    bool bad;
+    read_span(rd, r, o0, len, bad);
+    const int maxd = rd.maxd ? rd.maxd[r] : P.max_diff;
+    // reads the search will not take (invalid or empty) get no rows
+    if (bad || len == 0 || len > rd.max_len || len > BWFM_MAX_READ || maxd > BWFM_MAX_DIFF) return;
+    const int m = (int)len;
+    LaneCtx c;
+    c.pd = lds_bytes + (size_t)threadIdx.x * lstride;
+    uint8_t fl = 0;
+    for (int strand = 0; strand < 2; strand++) {
+        const DevDir odir = pick_dir(ix, strand == 0 ? 0 : 1);
+        if (!build_d<LW>(ix, odir, rd.bases + o0, m, strand, maxd, c)) {
+            fl |= (uint8_t)(1 << strand);
+            continue;
+        }
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(c.pd);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(drows + ((size_t)r * 2 + (size_t)strand) * dstride);
+        for (int k = 0; k < (m + 3) / 4; k++) dst[k] = src[k];
+    }
+    dflag[r] = fl;
+}
+
+// Copy a pre-pass row (m bytes) into the lane's LDS row.
+__device__ __forceinline__ void load_drow(uint8_t *pd, const uint8_t *row, int m) {
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(row);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(pd);
+    for (int k = 0; k < (m + 3) / 4; k++) dst[k] = src[k];
+}
 
 __global__ void k_set_args(PersistentArgs *dst, PersistentArgs a) {
     if (threadIdx.x == 0) *dst = a;
@@ -1100,19 +1157,36 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                     r = rr;
                     uint64_t o0;
                     if (!check_read(rd, P, O, r, m, maxd, o0)) {
-                        stage_read(own_pd, rd.bases + o0, m);
                         ow = lane;
                         c.pd = own_pd;
                         c.cand = own_cand;
                         c.ncand = 0;
                         c.best = INF_SCORE;
                         c.expand = 0;
+#if BWFM_GENE_DPREPASS == 1
+                        // the first strand the pre-pass left searchable, or
+                        // nothing to search
+                        const int dfl = A->dflag[r];
+                        strand = (dfl & 1) ? 1 : 0;
+                        if ((dfl & 3) == 3) {
+                            publish(c, P, O, r);
+                            phase = PZ_IDLE;
+                        } else {
+                            load_drow(own_pd, drow_of(A->drows, A->dstride, r, strand), m);
+                            phase = PZ_SEARCH;
+                            cur = root_state(ix, m, P.minc * pd_d(c, m - 1));
+                            valid = true;
+                            c.sp = c.sbase = 0;
+                        }
+#else
+                        stage_read(own_pd, rd.bases + o0, m);
                         strand = 0;
                         phase = PZ_DSCAN;
                         di = 0;
                         dz = 0;
                         dk = 0;
                         dl = ix.n;
+#endif
                         S = seed_of(P, m);
                         sh_st(&ws.best[lane], INF_SCORE);
                         sh_st(&ws.ncand[lane], 0);
@@ -1196,7 +1270,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
         uint32_t q1 = 0, q2 = 0;
         int da = 4;
         bool part_done = false;  // this lane's part of the strand's search is over
-        if (phase == PZ_DSCAN) {
+        if (BWFM_GENE_DPREPASS == 0 && phase == PZ_DSCAN) {
             act = ACT_DSTEP;
             {
                 const int b = own_pd[di] & 7;  // the staged base (strand +)
@@ -1285,13 +1359,21 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 send_to_second_pass(O, r);
                 if (O.expand) O.expand[r] = c.expand + (uint32_t)sh_ld(&ws.hexp[lane]);
                 phase = PZ_IDLE;
-            } else if (strand == 0) {
+            } else if (strand == 0 && (BWFM_GENE_DPREPASS == 0 || !(A->dflag[r] & 2))) {
                 strand = 1;
+#if BWFM_GENE_DPREPASS == 1
+                load_drow(own_pd, drow_of(A->drows, A->dstride, r, 1), m);
+                phase = PZ_SEARCH;
+                cur = root_state(ix, m, P.minc * pd_d(c, m - 1));
+                valid = true;
+                c.sp = c.sbase = 0;
+#else
                 phase = PZ_DSCAN;
                 di = 0;
                 dz = 0;
                 dk = 0;
                 dl = ix.n;
+#endif
             } else {
                 c.ncand = (uint32_t)sh_ld(&ws.ncand[lane]);
                 const int sb = sh_ld(&ws.best[lane]);
@@ -1310,7 +1392,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
         if (query) occ4_pair<LW>(ix, qd, q1, q2, ok, ol);
 
         // consume
-        if (act == ACT_DSTEP) {
+        if (BWFM_GENE_DPREPASS == 0 && act == ACT_DSTEP) {
             bool empty = true;
             if (da < 4) {
                 const uint32_t a1 = sel4(ok, da), a2 = sel4(ol, da);
@@ -2077,6 +2159,10 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
     need += (size_t)slow_lanes * worst_stack * 16 + (size_t)slow_lanes * scap * 16;
     need += (size_t)n * 4 * 2 + (size_t)n * 8 + stage_cap * 16 + scan_part_elems(n) * 8 + 16 * 256;
     need += sizeof(PersistentArgs) + 256;
+    // the D-array pre-pass's rows (batched form, when that gene is on)
+    const bool dpre = BWFM_GENE_DPREPASS == 1 && !plain;
+    const uint32_t dstride = ((mlen + 15) / 16) * 16;
+    if (dpre) need += (size_t)n * 2 * dstride + n + 2 * 256;
     void *w;
     int rc = ws_reserve(ws, need, st, &w);
     if (rc) return rc;
@@ -2091,6 +2177,8 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
     uint4 *stage = cv.take<uint4>(stage_cap);
     uint64_t *part = cv.take<uint64_t>(scan_part_elems(n));
     PersistentArgs *pargs = cv.take<PersistentArgs>(1);
+    uint8_t *drows = dpre ? cv.take<uint8_t>((size_t)n * 2 * dstride) : nullptr;
+    uint8_t *dflag = dpre ? cv.take<uint8_t>(n) : nullptr;
     uint32_t *ctl = cv.take<uint32_t>(16);  // n_slow, next_read, stage_used (64-bit), slow_next
     uint32_t *n_slow = ctl, *next_read = ctl + 1, *slow_next = ctl + 4;
     unsigned long long *stage_used = reinterpret_cast<unsigned long long *>(ctl + 2);
@@ -2110,7 +2198,12 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
             k_align_plain<LW><<<nr_up / bs, bs, lds, st>>>(D, rv, P, lb, O);
             tm.end(t);
         } else {
-            k_set_args<<<1, 64, 0, st>>>(pargs, PersistentArgs{rv, lb, O, next_read});
+            if (dpre) {
+                int td = tm.begin("dscan");
+                k_dscan<LW><<<nr_up / bs, bs, (size_t)bs * lstride, st>>>(D, rv, P, drows, dflag, dstride, lstride);
+                tm.end(td);
+            }
+            k_set_args<<<1, 64, 0, st>>>(pargs, PersistentArgs{rv, lb, O, next_read, drows, dflag, dstride});
             int t = tm.begin("align_persistent");
             hipLaunchKernelGGL(persistent_kernel<LW>(p->waves_per_simd), dim3(lanes / bs), dim3(bs), lds, st, D, P,
                                (const PersistentArgs *)pargs);
@@ -2711,6 +2804,8 @@ struct bwfm_pipeline {
     bwfm_pair *pairs = nullptr;
     uint64_t *ctl = nullptr;
     PersistentArgs *pargs = nullptr;
+    uint8_t *drows = nullptr, *dflag = nullptr;  // D-array pre-pass output (gene DPREPASS)
+    uint32_t dstride = 0;
     // launch shape
     uint32_t lanes = 0, slow_lanes = 0, bs = 0, lstride = 0, stack_cap = 0, worst_stack = 0, scap = 0;
     size_t lds = 0;
@@ -2751,7 +2846,13 @@ int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed, bool capture) {
     auto mark = [&](hipEvent_t e) {
         return capture ? hipEventRecordWithFlags(e, st, hipEventRecordExternal) : hipEventRecord(e, st);
     };
-    if (!plain) k_set_args<<<1, 64, 0, st>>>(pl->pargs, PersistentArgs{rv, lb, O, actl + 1});
+    if (!plain && pl->drows) {
+        const uint32_t nr_up = ((nmax + pl->bs - 1) / pl->bs) * pl->bs;
+        k_dscan<LW><<<nr_up / pl->bs, pl->bs, (size_t)pl->bs * pl->lstride, st>>>(D, rv, P, pl->drows, pl->dflag,
+                                                                               pl->dstride, pl->lstride);
+    }
+    if (!plain)
+        k_set_args<<<1, 64, 0, st>>>(pl->pargs, PersistentArgs{rv, lb, O, actl + 1, pl->drows, pl->dflag, pl->dstride});
     if (timed) HIPCHK(mark(pl->ev[0]));
     if (plain)
         k_align_plain<LW><<<pl->lanes / pl->bs, pl->bs, pl->lds, st>>>(D, rv, P, lb, O);
@@ -2855,6 +2956,12 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
     add(hcap * 4); add(hcap * 4); add((hcap + 1) * 8); add(pcap * 4); add((size_t)q->max_pairs * sizeof(bwfm_pair));
     add(PC_WORDS * 8);
     add(sizeof(PersistentArgs));
+    const bool dpre = BWFM_GENE_DPREPASS == 1 && !plain;
+    pl->dstride = ((mlen + 15) / 16) * 16;
+    if (dpre) {
+        add((size_t)nmax * 2 * pl->dstride);
+        add(nmax);
+    }
     need += 4096;
     if (hipMalloc(&pl->mem, need) != hipSuccess) return fail(BWFM_E_NOMEM, "pipeline: device allocation failed");
     Carver cv{(char *)pl->mem};
@@ -2882,6 +2989,10 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
     pl->pairs = cv.take<bwfm_pair>(q->max_pairs);
     pl->ctl = cv.take<uint64_t>(PC_WORDS);
     pl->pargs = cv.take<PersistentArgs>(1);
+    if (dpre) {
+        pl->drows = cv.take<uint8_t>((size_t)nmax * 2 * pl->dstride);
+        pl->dflag = cv.take<uint8_t>(nmax);
+    }
     if (hipEventCreate(&pl->ev[0]) != hipSuccess || hipEventCreate(&pl->ev[1]) != hipSuccess ||
         hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess) {
         bwfm_pipeline_destroy(pl.release());

@@ -6,7 +6,8 @@ change only when the output stays the same and the kernel gets faster
 (sections 1, 3 and 5).  Here the kernel source (csrc/bwfm.hip) carries
 alternative implementations of single code sites ("genes", macros
 BWFM_GENE_*: row masks, the paired rank query, the refill of idle lanes,
-the sub-counted line's header loads) next to the tuning constants it
+the sub-counted line's header loads, the D-array scan in the loop or in a
+pre-pass) next to the tuning constants it
 exposes (stack pops per iteration, first-pass hit slots, second-pass
 lanes).  A variant is one value per gene; each variant is its own library
 build.  The search is a (1+1) evolution strategy in generations:
@@ -48,6 +49,7 @@ GENES = {
     "BWFM_GENE_PAIRLINE": (0, (1,)),
     "BWFM_GENE_REFILL": (0, (1,)),
     "BWFM_GENE_SUBHDR": (0, (1,)),
+    "BWFM_GENE_DPREPASS": (0, (1,)),
     "BWFM_POPS_PER_STEP": (1, (2,)),
     "BWFM_FAST_CAND": (64, (32, 128)),
     "BWFM_SLOW_LANES": (16384, (8192,)),
@@ -57,7 +59,7 @@ GENES = {
 # two variants the package build compiles for the GPU tests: every gene
 # away from the shipped value in one of them
 TEST_VARIANTS = [{"BWFM_GENE_ROWMASK": 1, "BWFM_GENE_PAIRLINE": 1},
-                 {"BWFM_GENE_REFILL": 1, "BWFM_GENE_SUBHDR": 1, "BWFM_POPS_PER_STEP": 2}]
+                 {"BWFM_GENE_REFILL": 1, "BWFM_GENE_SUBHDR": 1, "BWFM_GENE_DPREPASS": 1, "BWFM_POPS_PER_STEP": 2}]
 
 
 def name_of(defs: dict) -> str:
