@@ -591,11 +591,13 @@ void bwfm_pipeline_destroy(bwfm_pipeline *pl);
 
 /*
  * A request server for the paired-end path.  Requests (host buffers) are
- * copied at submit and queued; a worker thread with its own stream admits
- * them in arrival order while their reads fit in a device arena of
- * arena_bytes, then runs scheduling steps of at most step_pairs pairs taken
- * from every admitted request, oldest first -- so requests that arrive while
- * others are on the GPU join the next step and share its launch.  Each step
+ * copied at submit and queued; a worker thread admits them in arrival order
+ * while their reads fit in a device arena of arena_bytes, then runs
+ * scheduling steps of at most step_pairs pairs taken from every admitted
+ * request, oldest first -- so requests that arrive while others are on the
+ * GPU join the next step and share its launch.  Two steps are in flight at
+ * once, on two streams of the worker's own, so staging, the tail of one
+ * step and the collection of its records overlap the next step.  Each step
  * aligns both ends in one call (form and search parameters from ap), pairs
  * them (pp) and copies the pair records back.  A request's results are the
  * same whatever it was mixed with.  The index must stay alive and uploaded
@@ -625,7 +627,8 @@ typedef struct {
 
 typedef struct {
     uint64_t steps, pairs, requests_done;
-    double busy_ms;     /* wall time the worker spent in steps */
+    double busy_ms;     /* summed step durations, launch to collection
+                           (two steps overlap, so it can exceed wall time) */
 } bwfm_server_stats;
 
 /* Errors: E_INVAL, E_STATE (index not uploaded), E_NOMEM, E_DEVICE. */
