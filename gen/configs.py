@@ -24,12 +24,22 @@ PARAMS = {
     "C3": dict(max_diff=4, max_gapo=1, seed_len=32, seed_diff=2),   # per-read budgets override max_diff
     "C5": dict(max_diff=6, max_gapo=1, seed_len=0),
 }
-# index layout per workload: rows per rank line, SA sample interval
+# index layout per workload: line size, rows per rank line, SA sample
+# interval, rank-line format (0: counts + bit planes; 1: 64-byte sub-counted
+# lines of 160 rows; 2: 128-byte sub-counted lines of 384 rows).  C1 keeps
+# its stated checkpoint every 128 rows; the others use the layout the
+# benchmark's autotuner picks.
 LAYOUT = {
-    "C1": dict(line_bytes=64, bases_per_line=128, sa_sample=32),
-    "C2": dict(line_bytes=64, bases_per_line=192, sa_sample=32),
-    "C3": dict(line_bytes=64, bases_per_line=192, sa_sample=32),
-    "C5": dict(line_bytes=64, bases_per_line=192, sa_sample=32),
+    "C1": dict(line_bytes=64, bases_per_line=128, sa_sample=32, rank_format=0),
+    "C2": dict(line_bytes=128, bases_per_line=384, sa_sample=32, rank_format=2),
+    "C3": dict(line_bytes=128, bases_per_line=384, sa_sample=32, rank_format=2),
+    "C5": dict(line_bytes=128, bases_per_line=384, sa_sample=32, rank_format=2),
+}
+# one layout per rank-line format, for tests that sweep them
+FORMAT_LAYOUT = {
+    0: dict(line_bytes=64, bases_per_line=192, sa_sample=32, rank_format=0),
+    1: dict(line_bytes=64, bases_per_line=160, sa_sample=32, rank_format=1),
+    2: dict(line_bytes=128, bases_per_line=384, sa_sample=32, rank_format=2),
 }
 # fixed insert window for the N(300, 30) fragment model: mu +- 4 sd
 PAIR_WINDOW = dict(lo=180, hi=420, mu=300)

@@ -72,8 +72,8 @@ constexpr uint32_t PLAIN_STACK = 320;  // stack entries per lane, plain form fir
 //             holds both rows (0) or always fetches two (1).
 //   REFILL:   idle lanes take new reads every iteration (0) or only once a
 //             quarter of the wave is idle or no lane is busy (1).
-//   SUBHDR:   a 128-byte sub-counted query reads the boundary words only
-//             for rows past 128 (0) or always (1).
+//   SUBHDR:   with SUBLOAD 0, a 128-byte sub-counted query reads the
+//             boundary words only for rows past 128 (0) or always (1).
 #ifndef BWFM_GENE_ROWMASK
 #define BWFM_GENE_ROWMASK 0
 #endif
@@ -93,6 +93,31 @@ constexpr uint32_t PLAIN_STACK = 320;  // stack entries per lane, plain form fir
 #ifndef BWFM_GENE_DPREPASS
 #define BWFM_GENE_DPREPASS 0
 #endif
+//   TWOSTATE: a searching lane expands one state per iteration (0), or two
+//             (1): besides its current state it keeps a second one, taken
+//             from the top of its stack, whose rank query is issued with
+//             the first, so two expansions share one round trip (before the
+//             batch runs dry; in the endgame the second state goes back on
+//             the stack for the sharing).
+#ifndef BWFM_GENE_TWOSTATE
+#define BWFM_GENE_TWOSTATE 0
+#endif
+//   SUBLOAD:  a 128-byte sub-counted query loads the line's first 16 bytes
+//             and, past row 128, its next 16 (0), or 12 bytes of counts and
+//             the one boundary word its row needs (1, shipped: fewer
+//             registers hold line data, 1.5% faster on the benchmark batch).
+#ifndef BWFM_GENE_SUBLOAD
+#define BWFM_GENE_SUBLOAD 1
+#endif
+//   KTLOOP:   the batched form's persistent loop ignores the short-string
+//             table (0), or reads it, like the plain form, for states and
+//             D-array steps whose string is shorter than its levels (1):
+//             with a few levels the table sits in L2, where those rank
+//             queries' line fills from the Infinity Cache do not.
+#ifndef BWFM_GENE_KTLOOP
+#define BWFM_GENE_KTLOOP 0
+#endif
+constexpr bool KT_LOOP = BWFM_GENE_KTLOOP == 1;
 constexpr uint32_t FAST_CAND = BWFM_FAST_CAND;  // hit slots per lane, first pass
 constexpr int BLOCK = 256;
 constexpr int POPS_PER_STEP = BWFM_POPS_PER_STEP;  // stack pops per lane per persistent iteration (more costs the
@@ -296,7 +321,44 @@ __device__ __forceinline__ void sub128_count(uint4 h, uint4 b, uint4 p, uint32_t
     o[0] = i - o[1] - o[2] - o[3] - (i > primary ? 1u : 0u);
 }
 
+// The same count from the counts before the line (C, G, T), the row's
+// boundary word (0 for the first 64 rows) and its group's plane words.
+__device__ __forceinline__ void sub128_count3(uint3 h, uint32_t bw, uint4 p, uint32_t r, uint32_t i,
+                                              uint32_t primary, uint32_t o[4]) {
+    const uint32_t t = r & 63;
+    const uint32_t m0 = t >= 32 ? 0xffffffffu : (1u << t) - 1u;
+    const uint32_t m1 = t > 32 ? (1u << (t - 32)) - 1u : 0u;
+    const uint32_t cT = __popc(p.x & p.y & m0) + __popc(p.z & p.w & m1);
+    const uint32_t cH = __popc(p.x & m0) + __popc(p.z & m1);
+    const uint32_t cL = __popc(p.y & m0) + __popc(p.w & m1);
+    o[1] = h.x + (bw & 511u) + cL - cT;
+    o[2] = h.y + ((bw >> 9) & 511u) + cH - cT;
+    o[3] = h.z + (bw >> 18) + cT;
+    o[0] = i - o[1] - o[2] - o[3] - (i > primary ? 1u : 0u);
+}
+
+// One row's pieces of its line: counts, boundary word, group planes.
+__device__ __forceinline__ void sub128_load(const uint32_t *L, uint32_t r, uint3 &h, uint32_t &bw, uint4 &p) {
+    h = *reinterpret_cast<const uint3 *>(L);
+    const uint32_t g = r >> 6;
+    bw = 0;
+    if (g) bw = L[2 + g];
+    p = reinterpret_cast<const uint4 *>(L)[2 + g];
+}
+
 __device__ __forceinline__ void occ4_sub128(const DevIndex &ix, const DevDir &d, uint32_t i, uint32_t o[4]) {
+#if BWFM_GENE_SUBLOAD == 1
+    {
+        const uint32_t line = line_of(ix, i);
+        const uint32_t r = i - line * SUB128_ROWS;
+        uint3 h;
+        uint32_t bw;
+        uint4 p;
+        sub128_load(d.lines + (size_t)line * 32, r, h, bw, p);
+        sub128_count3(h, bw, p, r, i, d.primary, o);
+        return;
+    }
+#endif
     const uint32_t line = line_of(ix, i);
     const uint32_t r = i - line * SUB128_ROWS;
     const uint4 *L = reinterpret_cast<const uint4 *>(d.lines) + (size_t)line * 8;
@@ -311,6 +373,26 @@ __device__ __forceinline__ void occ4_sub128(const DevIndex &ix, const DevDir &d,
 // sub-counted lines: the shared parts of one line are read once.
 __device__ __forceinline__ void occ4_sub128_pair(const DevIndex &ix, const DevDir &d, uint32_t i1, uint32_t i2,
                                                  uint32_t o1[4], uint32_t o2[4]) {
+#if BWFM_GENE_SUBLOAD == 1
+    {
+        const uint32_t l1 = line_of(ix, i1), l2 = line_of(ix, i2);
+        const uint32_t r1 = i1 - l1 * SUB128_ROWS, r2 = i2 - l2 * SUB128_ROWS;
+        uint3 h1, h2;
+        uint32_t b1, b2;
+        uint4 p1, p2;
+        sub128_load(d.lines + (size_t)l1 * 32, r1, h1, b1, p1);
+        if (l1 != l2 || (r1 >> 6) != (r2 >> 6)) {
+            sub128_load(d.lines + (size_t)l2 * 32, r2, h2, b2, p2);
+        } else {
+            h2 = h1;
+            b2 = b1;
+            p2 = p1;
+        }
+        sub128_count3(h1, b1, p1, r1, i1, d.primary, o1);
+        sub128_count3(h2, b2, p2, r2, i2, d.primary, o2);
+        return;
+    }
+#endif
     const uint32_t l1 = line_of(ix, i1), l2 = line_of(ix, i2);
     const uint32_t r1 = i1 - l1 * SUB128_ROWS, r2 = i2 - l2 * SUB128_ROWS;
     const uint4 *L1 = reinterpret_cast<const uint4 *>(d.lines) + (size_t)l1 * 8;
@@ -1122,9 +1204,14 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
     // D scan state
     int di = 0, dz = 0;
     uint32_t dk = 0, dl = 0;
+    uint32_t dcode = 0, dlen = 0;  // the current segment while the table covers it (KTLOOP)
     // search state
     uint4 cur = make_uint4(0, 0, 0, 0);
     bool valid = false;
+#if BWFM_GENE_TWOSTATE == 1
+    uint4 cur2 = make_uint4(0, 0, 0, 0);  // the second state (valid2), same read and strand
+    bool valid2 = false;
+#endif
     Seed S{0, 0, 0};
     // work statistics (measurement only)
     uint32_t w_iters = 0, w_busy = 0, w_query = 0;  // per lane: far below 2^32 per launch
@@ -1186,6 +1273,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                         dz = 0;
                         dk = 0;
                         dl = ix.n;
+                        dcode = dlen = 0;
 #endif
                         S = seed_of(P, m);
                         sh_st(&ws.best[lane], INF_SCORE);
@@ -1202,6 +1290,25 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
             continue;
         }
         endgame = endgame || __ballot(exhausted) != 0;
+#if BWFM_GENE_TWOSTATE == 1
+        if (endgame && valid2) {
+            // the sharing below works on single states: the second one goes
+            // back on the stack; with the stack full the read (still this
+            // lane's alone: nothing is shared before the endgame) goes to
+            // the second pass
+            if (c.sp < c.stack_cap) {
+                c.stack[(size_t)c.sp * c.sstride] = cur2;
+                c.sp++;
+            } else {
+                send_to_second_pass(A->O, r);
+                if (A->O.expand) A->O.expand[r] = c.expand;
+                phase = PZ_IDLE;
+                valid = false;
+                c.sp = c.sbase = 0;
+            }
+            valid2 = false;
+        }
+#endif
         if (O.work) {
             w_iters++;
             w_busy += phase != PZ_IDLE && phase != PZ_WAIT;
@@ -1283,7 +1390,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 q2 = dl + 1;
             }
         } else if (phase == PZ_SEARCH || phase == PZ_HELP) {
-            int rr = resolve<false>(cur, valid, strand, P, c, PH_FAST, POPS_PER_STEP, ix, endgame);
+            int rr = resolve<KT_LOOP>(cur, valid, strand, P, c, PH_FAST, POPS_PER_STEP, ix, endgame);
             if (rr == 2) {
                 // pop limit reached: keep popping next iteration
             } else if (rr == 3) {
@@ -1295,13 +1402,64 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 phase = PZ_IDLE;
             } else if (rr == 0) {
                 part_done = true;
-            } else {
+            }
+            if (rr == 1) {
                 act = ACT_EXPAND;
                 query = true;
                 qdir = strand == 0 ? 1 : 0;
                 q1 = cur.x;
                 q2 = cur.y + 1;
             }
+#if BWFM_GENE_TWOSTATE == 1
+            if (!endgame && phase == PZ_SEARCH) {
+                const int bound = (P.mode == BWFM_MODE_BEST && c.best != INF_SCORE) ? c.best + P.s_mm : INF_SCORE;
+                // the second state: dropped once the bound passes it,
+                // recorded when it is a completed hit
+                if (valid2 && entry_lb(cur2) > bound) valid2 = false;
+                if (valid2 && s_i(cur2) < 0) {
+                    valid2 = false;
+                    const int score = s_score(cur2);
+                    if (score < c.best) c.best = score;
+                    if (record(c, P, make_hit(strand, KT_LOOP ? state_k(ix, strand, cur2) : cur2.x, cur2.y,
+                                              s_len(cur2), score, s_nmm(cur2), s_ngo(cur2), s_nge(cur2)),
+                               PH_FAST)) {
+                        send_to_second_pass(O, r);
+                        if (O.expand) O.expand[r] = c.expand;
+                        phase = PZ_IDLE;
+                        act = ACT_NONE;
+                        query = false;
+                        part_done = false;
+                    }
+                }
+                // else the next state on the stack, unless it is a completed
+                // hit (left for resolve) or already beaten by the bound
+                if (phase == PZ_SEARCH && !valid2 && c.sp > c.sbase) {
+                    const uint4 t = c.stack[(size_t)(c.sp - 1) * c.sstride];
+                    if (entry_lb(t) > bound) {
+                        c.sp--;
+                    } else if (s_i(t) >= 0) {
+                        c.sp--;
+                        cur2 = t;
+                        valid2 = true;
+                    }
+                }
+                // the lane's part is not over while the second state is left:
+                // it becomes the current one (already resolved above)
+                if (part_done && valid2) {
+                    part_done = false;
+                    cur = cur2;
+                    valid = true;
+                    valid2 = false;
+                    act = ACT_EXPAND;
+                    query = true;
+                    q1 = cur.x;
+                    q2 = cur.y + 1;
+                }
+                // a searching lane queries the strand's search index, for
+                // either state
+                qdir = strand == 0 ? 1 : 0;
+            }
+#endif
             if (!endgame && phase == PZ_SEARCH) {
                 sh_st(&ws.best[lane], c.best);
                 sh_st(&ws.ncand[lane], (int)c.ncand);
@@ -1321,8 +1479,8 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                     const int score = s_score(cur);
                     if (score < c.best) c.best = score;
                     const int rc = record(c, P,
-                                          make_hit(strand, cur.x, cur.y, s_len(cur), score, s_nmm(cur), s_ngo(cur),
-                                                   s_nge(cur)),
+                                          make_hit(strand, KT_LOOP ? state_k(ix, strand, cur) : cur.x, cur.y,
+                                                   s_len(cur), score, s_nmm(cur), s_ngo(cur), s_nge(cur)),
                                           PH_FAST);
                     sh_st(&ws.best[ow], c.best);
                     sh_st(&ws.ncand[ow], (int)c.ncand);
@@ -1373,6 +1531,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 dz = 0;
                 dk = 0;
                 dl = ix.n;
+                dcode = dlen = 0;
 #endif
             } else {
                 c.ncand = (uint32_t)sh_ld(&ws.ncand[lane]);
@@ -1389,7 +1548,31 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
         uint32_t ok[4] = {0, 0, 0, 0}, ol[4] = {0, 0, 0, 0};
         const DevDir qd = pick_dir(ix, qdir);
         if (O.work) w_query += query;
-        if (query) occ4_pair<LW>(ix, qd, q1, q2, ok, ol);
+        if (query) {
+            // a D-array step or an expansion whose string the table covers
+            // reads the children's intervals there
+            const uint32_t qlen = act == ACT_DSTEP ? dlen : (uint32_t)s_len(cur);
+            if (KT_LOOP && qlen < ix.kt_levels) {
+                const uint32_t code = act == ACT_DSTEP ? dcode : cur.x;
+                const uint4 *e = reinterpret_cast<const uint4 *>(qd.kt + 2 * kt_children((int)qlen, code));
+                kt_pick(qd, e[0], e[1], ok, ol);
+            } else {
+                occ4_pair<LW>(ix, qd, q1, q2, ok, ol);
+            }
+        }
+#if BWFM_GENE_TWOSTATE == 1
+        const bool act2 = valid2 && phase == PZ_SEARCH && !endgame;
+        uint32_t ok2[4] = {0, 0, 0, 0}, ol2[4] = {0, 0, 0, 0};
+        if (act2) {
+            if (KT_LOOP && (uint32_t)s_len(cur2) < ix.kt_levels) {
+                const uint4 *e = reinterpret_cast<const uint4 *>(qd.kt + 2 * kt_children(s_len(cur2), cur2.x));
+                kt_pick(qd, e[0], e[1], ok2, ol2);
+            } else {
+                occ4_pair<LW>(ix, qd, cur2.x, cur2.y + 1, ok2, ol2);
+            }
+        }
+        if (O.work) w_query += act2;
+#endif
 
         // consume
         if (BWFM_GENE_DPREPASS == 0 && act == ACT_DSTEP) {
@@ -1399,12 +1582,17 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 empty = a1 >= a2;
                 dk = sel4(qd.C, da) + a1;
                 dl = sel4(qd.C, da) + a2 - 1;
+                if (KT_LOOP) {
+                    dcode = (dcode << 2) | (uint32_t)da;
+                    dlen++;
+                }
             }
             bool skip = false;
             if (empty) {
                 dz++;
                 dk = 0;
                 dl = ix.n;
+                dcode = dlen = 0;
                 skip = dz > maxd;
             }
             if (!skip) {
@@ -1423,6 +1611,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                     dz = 0;
                     dk = 0;
                     dl = ix.n;
+                    dcode = dlen = 0;
                 } else {
                     // strand - cannot match; the read's helpers, if any,
                     // were all done before this D scan began
@@ -1440,7 +1629,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
             const int i = s_i(cur);
             const int b = pd_base(c, i);
             const int Di = pd_d(c, i), Dn = pd_d(c, i - 1);
-            int rc = expand_children(cur, valid, ok, ol, qd, b, m, maxd, Di, Dn, S, P, c, 0);
+            int rc = expand_children(cur, valid, ok, ol, qd, b, m, maxd, Di, Dn, S, P, c, KT_LOOP ? ix.kt_levels : 0);
             if (rc) {
                 // cannot happen with worst-case stacks; kept as a guard
                 if (endgame) {
@@ -1452,6 +1641,23 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 }
             }
         }
+#if BWFM_GENE_TWOSTATE == 1
+        if (act2 && phase == PZ_SEARCH) {
+            c.expand++;
+            const int i2 = s_i(cur2);
+            const int b2 = pd_base(c, i2);
+            const int Di2 = pd_d(c, i2), Dn2 = pd_d(c, i2 - 1);
+            // with two states in flight the stack can outgrow its one-path
+            // worst case; the read then goes to the second pass
+            if (expand_children(cur2, valid2, ok2, ol2, qd, b2, m, maxd, Di2, Dn2, S, P, c,
+                                KT_LOOP ? ix.kt_levels : 0)) {
+                send_to_second_pass(O, r);
+                if (O.expand) O.expand[r] = c.expand;
+                phase = PZ_IDLE;
+            }
+        }
+        if (phase == PZ_IDLE) valid2 = false;
+#endif
     }
     if (A->O.work) {
         if (lane == 0) atomicAdd(&A->O.work[0], (unsigned long long)w_iters);

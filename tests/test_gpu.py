@@ -276,9 +276,7 @@ def test_c5_shape_stress_parity(form, wps, fmt):
     g = configs.c2_genome(2_000_000, seed=55)
     reads = configs.c5_reads(g, 2000, seed=56)
     ox = oracle.Index(g.seq)
-    lay = dict(configs.LAYOUT["C5"]) if fmt == bw.RANK_PLANES else \
-        dict(line_bytes=128 if fmt == bw.RANK_SUB128 else 64, sa_sample=32)
-    ix = bw.Index(g.seq, **lay, rank_format=fmt).upload()
+    ix = bw.Index(g.seq, **configs.FORMAT_LAYOUT[fmt]).upload()
     p, op = _params_pair(form=form, **configs.PARAMS["C5"])
     p.waves_per_simd = wps  # every build of the batched kernel
     op.bases_per_line = ix.info()["bases_per_line"]

@@ -71,10 +71,10 @@ def test_device_index_equals_host_index(layout):
 
 
 def _layout(fmt):
-    """The benchmark's line layout for planar lines, else the format's own."""
-    if fmt == bw.RANK_PLANES:
-        return dict(configs.LAYOUT["C2"])
-    return dict(line_bytes=128 if fmt == bw.RANK_SUB128 else 64, sa_sample=32)
+    """The format's own layout, without its rank_format key."""
+    lay = dict(configs.FORMAT_LAYOUT[fmt])
+    del lay["rank_format"]
+    return lay
 
 
 @pytest.mark.parametrize("fmt", [bw.RANK_PLANES, bw.RANK_SUBCOUNTS, bw.RANK_SUB128])

@@ -68,8 +68,8 @@ def _check_run(pl, n, exp):
                                       (bw.FORM_BATCHED, bw.RANK_SUBCOUNTS), (bw.FORM_BATCHED, bw.RANK_SUB128)])
 def test_pipeline_eager_and_graph_replays_equal_oracle(setup, form, fmt):
     g, pairs, ox, ix = setup
-    if fmt != bw.RANK_PLANES:
-        ix = bw.Index(g.seq, line_bytes=128 if fmt == bw.RANK_SUB128 else 64, sa_sample=32, rank_format=fmt).upload()
+    if fmt != ix.info()["rank_format"]:
+        ix = bw.Index(g.seq, **configs.FORMAT_LAYOUT[fmt]).upload()
     w = configs.PAIR_WINDOW
     p = bw.Params(**configs.PARAMS["C2"], form=form)
     op = oracle.Params(**configs.PARAMS["C2"])

@@ -207,7 +207,8 @@ def test_host_index_equals_oracle_index_at_workload_size(shape):
     from tests.util import assert_index_equals_oracle
     g = configs.c1_genome() if shape == "C1" else configs.c2_genome(4_000_000, seed=64)
     ox = oracle.Index(g.seq)
-    for lay in (dict(configs.LAYOUT[shape]), dict(line_bytes=64, sa_sample=32, rank_format=bw.RANK_SUBCOUNTS)):
+    for lay in (dict(configs.LAYOUT[shape]), dict(configs.FORMAT_LAYOUT[bw.RANK_SUBCOUNTS]),
+                dict(configs.FORMAT_LAYOUT[bw.RANK_PLANES])):
         ix = bw.Index(g.seq, **lay)
         assert_index_equals_oracle(ix, ox, name=f"{shape} {lay}")
         ix.close()

@@ -1,8 +1,9 @@
 """Child process of tests/test_gpu_variants.py: load the variant library
 named on the command line in place of the shipped one and check it against
 the oracle on a small paired-end batch -- both rank-line layouts the
-variants touch (64-byte planar, 128-byte sub-counted), the batched and the
-plain form, then locate and pairing.  Prints "variant ok" on success."""
+variants touch (64-byte planar, 128-byte sub-counted), without and with a
+short-string table, the batched and the plain form, then locate and
+pairing.  Prints "variant ok" on success."""
 from __future__ import annotations
 
 import os
@@ -34,8 +35,9 @@ def main(lib: str) -> None:
     opr = oracle.pair(ores[0], locs[0][0], locs[0][1], ores[1], locs[1][0], locs[1][1], w["lo"], w["hi"], w["mu"])
     ends = [(torch.from_numpy(e.bases).cuda(), torch.from_numpy(e.offsets.view(np.int64)).cuda())
             for e in (pairs.end1, pairs.end2)]
-    for lb, fmt in ((64, bw.RANK_PLANES), (128, bw.RANK_SUB128)):
-        ix = bw.Index(g.seq, line_bytes=lb, sa_sample=32, rank_format=fmt).upload()
+    for lb, fmt, levels in ((64, bw.RANK_PLANES, 0), (128, bw.RANK_SUB128, 0), (128, bw.RANK_SUB128, 6),
+                            (64, bw.RANK_PLANES, 9)):
+        ix = bw.Index(g.seq, line_bytes=lb, sa_sample=32, rank_format=fmt).upload(kmer_levels=levels)
         for form in (bw.FORM_BATCHED, bw.FORM_PLAIN):
             p = bw.Params(**configs.PARAMS["C2"], form=form)
             res = [bw.align_batch(ix, b, o, p, max_len=100) for b, o in ends]
