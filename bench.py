@@ -318,9 +318,10 @@ def main_c3(args):
     value = aligned / (ms_step / 1e3)
     roofline = None
     traffic = traffic_from_profiles("k_align_persistent", "c3")
+    lb = ix.info()["line_bytes"]
     buf = torch.zeros(2048 << 20, dtype=torch.uint8, device="cuda")
-    bw.probe_gather(buf, 64, iters=16)
-    probe_lps = bw.probe_gather(buf, 64)
+    bw.probe_gather(buf, lb, iters=16)
+    probe_lps = bw.probe_gather(buf, lb)
     del buf
     if k_ms:
         fills_ps = traffic / 128 / (k_ms / 1e3) if traffic else None
@@ -330,6 +331,7 @@ def main_c3(args):
                     "kernel": "k_align_persistent", "avg_launch_ms": k_ms, "reads_per_launch": 2 * n,
                     "basis": "counter-measured HBM-side bytes per launch (no oracle count at 3.1 Gbp)",
                     "random_line_ceiling": {"probe_lines_per_s": probe_lps, "probe_buffer_mib": 2048,
+                                            "probe_line_bytes": lb,
                                             "kernel_fills_per_s": fills_ps,
                                             "frac": fills_ps / probe_lps if fills_ps else None}}
     out = {
