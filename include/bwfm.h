@@ -250,6 +250,15 @@ typedef struct {
                                (3 waves); 1, 2: that build capped at 1 or 2
                                waves per SIMD.  A tuning knob: results do not
                                depend on it. */
+    int32_t split_budget;   /* batched form: once the batch's reads are all
+                               taken, a lane whose part of a read's search
+                               has expanded this many states hands the rest of
+                               it to tasks that every lane of the device may
+                               take (rounds of one launch each); the lanes
+                               of a wave share the rest of their reads in
+                               flight either way.  0 = the library's default
+                               (16384), -1 = no splitting, else 16 .. 2^24.
+                               A tuning knob: results do not depend on it. */
 } bwfm_aln_params;
 
 /*
@@ -275,6 +284,10 @@ typedef struct {
                               tree were handed to other lanes once the batch ran dry;
                               results are unaffected, its work counter then covers a
                               different traversal than one lane's depth-first order */
+#define BWFM_ST_SPLIT 32   /* informational (batched form): the read's search outgrew
+                              split_budget and was finished by tasks spread over the
+                              device; results are unaffected, its work counter covers
+                              every part */
 
 typedef struct {
     uint64_t *hit_offsets;  /* device, n_reads + 1: hits of read r are [hit_offsets[r], hit_offsets[r+1]) */
@@ -312,9 +325,13 @@ int bwfm_align_batch(const bwfm_index *idx, const bwfm_reads *reads, const bwfm_
 /* As bwfm_align_batch, also writing each read's search work -- the number
  * of search states expanded (each expansion issues the two rank queries at
  * k and l + 1), summed over both passes -- to expand (device, n_reads).
- * work (device, 3 uint64, or NULL; batched form only) receives the first
+ * work (device, 22 uint64, or NULL; batched form only) receives the first
  * pass's loop iterations summed over waves, lane iterations spent on a read,
- * and lane iterations that issued a rank query. */
+ * and lane iterations that issued a rank query, then the reads whose search
+ * was split, the tasks handed out over all rounds, the split reads that went
+ * on to the second pass, and for each of the sixteen task generations (the
+ * first pass's, then each round's but the last) the task entries asked for
+ * (more than the room when some split found none). */
 int bwfm_align_batch_counted(const bwfm_index *idx, const bwfm_reads *reads, const bwfm_aln_params *p,
                              bwfm_aln_result *res, uint32_t *expand, uint64_t *work, void *hip_stream);
 
@@ -562,9 +579,11 @@ typedef struct {
     uint32_t error;         /* 0, or BWFM_PIPE_E_* bits: a capacity was too small */
     uint64_t n_hits;        /* reported hits, both ends (needed size when too small) */
     uint64_t n_positions;   /* located positions, both ends */
-    double kernel_ms;       /* the batched search kernel's duration in this
-                               run, from HIP events captured around it; 0
-                               when timing is off */
+    double kernel_ms;       /* the search's duration in this run (the first
+                               pass, then for the batched form the split
+                               searches' rounds and publication), from HIP
+                               events captured around it; 0 when timing is
+                               off */
 } bwfm_pipeline_status;
 #define BWFM_PIPE_E_HITS 1
 #define BWFM_PIPE_E_POSITIONS 2

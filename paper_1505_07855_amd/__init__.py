@@ -29,11 +29,11 @@ PAIR_DTYPE = np.dtype([("pos1", "<u4"), ("pos2", "<u4"), ("insert", "<i4"), ("le
 RESCUE_DTYPE = np.dtype([("pos", "<u4"), ("len", "<u2"), ("score", "<i2"), ("insert", "<i4"), ("end", "u1"),
                          ("strand", "u1"), ("pad", "u1", 2)])
 
-ST_HIT, ST_OVERFLOW, ST_INVALID, ST_RESEARCH, ST_SHARED = 1, 2, 4, 8, 16
+ST_HIT, ST_OVERFLOW, ST_INVALID, ST_RESEARCH, ST_SHARED, ST_SPLIT = 1, 2, 4, 8, 16, 32
 PF_PAIRED, PF_MAPPED1, PF_MAPPED2, PF_REP1, PF_REP2 = 1, 2, 4, 8, 16
 MODE_ALL, MODE_BEST = 0, 1
 FORM_BATCHED, FORM_PLAIN = 0, 1
-E_CAPACITY = -5
+E_INVAL, E_CAPACITY = -1, -5
 E_IO = -8
 PIPE_E_HITS, PIPE_E_POSITIONS = 1, 2
 NOALLOC_SCRATCH_BYTES = 64 << 20  # BWFM_NOALLOC_SCRATCH_BYTES: the fixed scratch of bwfm_pair_reads_noalloc
@@ -68,7 +68,8 @@ class _Reads(ctypes.Structure):
 class _AlnParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("max_diff", "max_gapo", "max_gape", "seed_len", "seed_diff",
                                               "indel_end_skip", "s_mm", "s_gapo", "s_gape", "mode", "max_best")] + [
-        ("max_hits", ctypes.c_uint32), ("form", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
+        ("max_hits", ctypes.c_uint32), ("form", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+        ("split_budget", ctypes.c_int32)]
 
 
 class _AlnResult(ctypes.Structure):
@@ -237,6 +238,8 @@ class Params:
     max_hits: int = 256
     form: int = FORM_BATCHED
     waves_per_simd: int = 0  # batched form residency (tuning only; 0 = the most that fit)
+    split_budget: int = 0    # batched form: expansions between splits of a read's search into
+                             # device-wide tasks (tuning only; 0 = the library's default, -1 = off)
 
     def _c(self) -> _AlnParams:
         return _AlnParams(*[getattr(self, f.name) for f in fields(self)])
@@ -424,7 +427,7 @@ def align_batch(index: Index, bases, offsets, params: Params, max_diff=None, max
     if counted and out.expand is None:
         out.expand = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     if counted and getattr(out, "work", None) is None:
-        out.work = torch.zeros(3, dtype=torch.int64, device=dev)
+        out.work = torch.zeros(22, dtype=torch.int64, device=dev)
     pc = params._c()
     for attempt in range(2):
         res = out._c()

@@ -1047,11 +1047,214 @@ __device__ __forceinline__ int check_read(const ReadsView &rd, const Params &P, 
         O.status[r] = BWFM_ST_INVALID;
         return 1;
     }
-    if (m == 0) {
-        O.status[r] = 0;
-        return 1;
+    O.status[r] = 0;
+    return m == 0 ? 1 : 0;
+}
+
+// ------------------------------------------------------------------ split searches
+
+// Batched form: a read whose search outgrows a budget of expansions is
+// split.  Its pending states become tasks that any lane of the grid may
+// take, in rounds of one launch each, so that the largest trees of a batch
+// are searched by the whole device rather than by one lane or one wave.
+// The read's slot holds what a task needs (the strand's pattern and D-array
+// row, the read's length and budget, the best score found so far) and
+// collects the hits of every part; after the rounds each slot's read is
+// canonicalised like any other, duplicates merged first.  The reported hits
+// do not depend on how the tree was cut: each part prunes with a bound that
+// is never below the final one, so every hit within the final bound is
+// found by the part that holds it.
+constexpr int SPLIT_ROUNDS = 16;              // task rounds; the last one runs every task to its end
+constexpr uint32_t TASK_EMPTY = 0xffffffffu;  // a reserved task entry left unused
+constexpr uint8_t ST_SPLIT_PEND = 0x80;       // status of a split read until its slot is published
+constexpr uint32_t SLOT_HITS = FAST_CAND;     // hits a slot collects, as many as a first-pass lane
+// control words: [0] slots taken; [1 + g] task entries reserved in
+// generation g (0: by the first pass, k: by round k); [2 + SPLIT_ROUNDS + g]
+// entries of generation g taken by round g + 1
+constexpr uint32_t SPLIT_CTL = 2 * (SPLIT_ROUNDS + 1) + 2;
+
+struct SplitBufs {
+    uint32_t *slot_read;    // the slot's read
+    uint32_t *slot_meta;    // m | budget << 10
+    int *slot_best;         // best score found by any part
+    uint32_t *slot_nhit;    // hits delivered (above SLOT_HITS: the slot failed)
+    uint32_t *slot_fail;    // nonzero: the read goes to the second pass
+    uint32_t *slot_exp;     // states expanded by the read's parts
+    uint8_t *slot_rows;     // per slot and strand: the pattern and D-array row, dstride bytes
+    uint4 *slot_hits;       // per slot: SLOT_HITS hits
+    uint4 *tasks[2];        // task states, by generation parity
+    uint32_t *task_ref[2];  // slot | strand << 31, or TASK_EMPTY
+    uint32_t *ctl;          // SPLIT_CTL control words
+    uint32_t slot_cap, task_cap, dstride;
+    uint32_t budget;  // expansions of a lane's part of a read before it is split (endgame); 0: off
+    uint32_t count;   // nonzero: the parts' expansions are summed (per-read work counters)
+};
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Reserve cnt task entries of generation g at off.  False when they do not
+// all fit; reserved entries inside the array are then marked unused.
+__device__ bool take_tasks(const SplitBufs &X, uint32_t g, uint32_t cnt, uint32_t &off) {
+    // a full generation is not reserved from again, which also keeps the
+    // counter far from wrapping
+    if (ld_agent(&X.ctl[1 + g]) >= X.task_cap) return false;
+    off = atomicAdd(&X.ctl[1 + g], cnt);
+    if (off + cnt <= X.task_cap) return true;
+    for (uint32_t j = off; j < X.task_cap; j++) X.task_ref[g & 1][j] = TASK_EMPTY;
+    return false;
+}
+
+// Write cur when has_cur, then the lane's pending stack entries, to the
+// entries reserved at off in generation g; the lane's stack is left empty.
+__device__ void put_tasks(const SplitBufs &X, uint32_t g, uint32_t off, uint32_t ref, LaneCtx &c, uint4 cur,
+                          bool has_cur) {
+    uint4 *T = X.tasks[g & 1];
+    uint32_t *R = X.task_ref[g & 1];
+    if (has_cur) {
+        T[off] = cur;
+        R[off] = ref;
+        off++;
     }
-    return 0;
+    for (uint32_t j = c.sbase; j < c.sp; j++, off++) {
+        T[off] = c.stack[(size_t)j * c.sstride];
+        R[off] = ref;
+    }
+    c.sp = c.sbase = 0;
+}
+
+// Copy an m-byte pattern and D-array row from the lane's LDS row to the
+// slot: whole dwords, within both rows.
+__device__ __forceinline__ void save_row(const SplitBufs &X, uint32_t s, int strand, const uint8_t *pd, int m) {
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(pd);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(X.slot_rows + ((size_t)s * 2 + (size_t)strand) * X.dstride);
+    for (int k = 0; k < (m + 3) / 4; k++) dst[k] = src[k];
+}
+// Deliver the lane's hits to slot s -- those within the bound of the best
+// score known -- with its expansions; the lane's hit buffer is emptied.
+__device__ void flush_slot(const SplitBufs &X, const Params &P, uint32_t s, LaneCtx &c) {
+    if (X.count && c.expand) atomicAdd(&X.slot_exp[s], c.expand);
+    c.expand = 0;
+    // a lane's best score changes only with a hit it holds: without hits
+    // there is nothing to deliver
+    if (c.ncand == 0) return;
+    const int old = atomicMin(&X.slot_best[s], c.best);
+    const int best = old < c.best ? old : c.best;
+    const int bound = (P.mode == BWFM_MODE_BEST && best != INF_SCORE) ? best + P.s_mm : INF_SCORE;
+    uint32_t keep = 0;
+    for (uint32_t j = 0; j < c.ncand; j++) keep += h_score(c.cand[(size_t)j * c.cstride]) <= bound ? 1u : 0u;
+    if (keep) {
+        uint32_t off = atomicAdd(&X.slot_nhit[s], keep);
+        if (off + keep > SLOT_HITS) {
+            atomicOr(&X.slot_fail[s], 1u);
+        } else {
+            uint4 *dst = X.slot_hits + (size_t)s * SLOT_HITS;
+            for (uint32_t j = 0; j < c.ncand; j++) {
+                const uint4 h = c.cand[(size_t)j * c.cstride];
+                if (h_score(h) <= bound) dst[off++] = h;
+            }
+        }
+    }
+    c.ncand = 0;
+}
+
+// Flag word of a read in its wave's sharing block: SH_FAIL, SH_HELPED, the
+// strands whose rows the read's slot holds, and the slot plus one above
+// SH_SLOT_SHIFT (0: none yet).
+enum { SH_FAIL = 1, SH_HELPED = 2, SH_ROW0 = 4 };
+constexpr int SH_SLOT_SHIFT = 4;
+
+// Endgame of the first pass: hand this lane's part of read r on `strand`
+// -- cur when valid, then the pending stack entries -- to the tasks of
+// generation 0, taking the read's slot at its first split (fl is the
+// read's flag word; best its best score so far).  The caller runs one lane
+// of a wave at a time.  False, with the lane's search unchanged, when no
+// slot or task room is left.
+__device__ bool split_part(const SplitBufs &X, const ReadOut &O, uint32_t r, int strand, int m, int maxd, int best,
+                           LaneCtx &c, uint4 cur, bool valid, int &fl) {
+    const uint32_t cnt = (valid ? 1u : 0u) + (c.sp - c.sbase);
+    const bool had = (fl >> SH_SLOT_SHIFT) != 0;
+    if (!had && ld_agent(&X.ctl[0]) >= X.slot_cap) return false;
+    uint32_t off = 0;
+    if (!take_tasks(X, 0, cnt, off)) return false;
+    uint32_t s;
+    if (had) {
+        s = (uint32_t)(fl >> SH_SLOT_SHIFT) - 1;
+    } else {
+        s = atomicAdd(&X.ctl[0], 1u);
+        if (s >= X.slot_cap) {
+            for (uint32_t j = 0; j < cnt; j++) X.task_ref[0][off + j] = TASK_EMPTY;
+            return false;
+        }
+        X.slot_read[s] = r;
+        X.slot_meta[s] = (uint32_t)m | ((uint32_t)maxd << 10);
+        X.slot_best[s] = best;
+        X.slot_nhit[s] = 0;
+        X.slot_fail[s] = 0;
+        X.slot_exp[s] = 0;
+        O.status[r] = ST_SPLIT_PEND;
+        O.n_rep[r] = s;
+        fl |= (int)((s + 1) << SH_SLOT_SHIFT);
+    }
+    if (!(fl & (SH_ROW0 << strand))) {
+        save_row(X, s, strand, c.pd, m);
+        fl |= SH_ROW0 << strand;
+    }
+    put_tasks(X, 0, off, s | ((uint32_t)strand << 31), c, cur, valid);
+    return true;
+}
+
+// A read that cannot finish in the first pass goes to the second pass;
+// once split, through its slot, whose publication sends it there.
+__device__ __forceinline__ void give_up(const ReadOut &O, const SplitBufs &X, uint32_t r) {
+    if (X.budget && O.status[r] == ST_SPLIT_PEND)
+        atomicOr(&X.slot_fail[O.n_rep[r]], 1u);
+    else
+        send_to_second_pass(O, r);
+}
+
+// The end of a read's first-pass search: published, or, once split, its
+// hits delivered to the slot.
+__device__ __forceinline__ void finish_read(LaneCtx &c, const Params &P, const ReadOut &O, const SplitBufs &X,
+                                            uint32_t r, uint8_t extra) {
+    if (X.budget && O.status[r] == ST_SPLIT_PEND)
+        flush_slot(X, P, O.n_rep[r], c);
+    else
+        publish(c, P, O, r, extra);
+}
+
+// After the rounds: each split read's hits, duplicates merged as a lane's
+// buffer merges them, are canonicalised and published; a failed slot's
+// read goes to the second pass.
+__global__ void k_split_publish(Params P, SplitBufs X, ReadOut O) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ns = min(X.ctl[0], X.slot_cap);
+    if (s >= ns) return;
+    const uint32_t r = X.slot_read[s];
+    const uint32_t nh = X.slot_nhit[s];
+    if (X.slot_fail[s] || nh > SLOT_HITS) {
+        if (O.expand) O.expand[r] = X.slot_exp[s];
+        send_to_second_pass(O, r);
+        return;
+    }
+    LaneCtx c;
+    c.cand = X.slot_hits + (size_t)s * SLOT_HITS;
+    c.cstride = 1;
+    uint32_t w = 0;
+    for (uint32_t j = 0; j < nh; j++) {
+        const uint4 h = c.cand[j];
+        uint32_t q = 0;
+        while (q < w && !(h_strand(c.cand[q]) == h_strand(h) && c.cand[q].x == h.x && h_len(c.cand[q]) == h_len(h))) q++;
+        if (q == w)
+            c.cand[w++] = h;
+        else if (better(h, c.cand[q]))
+            c.cand[q] = h;
+    }
+    c.ncand = w;
+    c.best = X.slot_best[s];
+    c.expand = X.slot_exp[s];
+    publish(c, P, O, r, (uint8_t)BWFM_ST_SPLIT);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -1077,7 +1280,6 @@ __global__ __launch_bounds__(BLOCK) void k_align_plain(DevIndex ix, ReadsView rd
 
 enum { PZ_IDLE = 0, PZ_DSCAN = 1, PZ_SEARCH = 2, PZ_HELP = 3, PZ_WAIT = 4 };
 enum { ACT_NONE = 0, ACT_DSTEP = 1, ACT_EXPAND = 2 };
-enum { SH_FAIL = 1, SH_HELPED = 2 };
 
 // Per-wave block in LDS through which the lanes of a wave share one read's
 // search once the batch's reads are all taken: an idle lane receives the
@@ -1089,7 +1291,7 @@ struct WaveShare {
     int best[64];       // best score found so far for the owner's read
     int ncand[64];      // hits in the owner's hit buffer
     int pending[64];    // helper lanes still searching donated subtrees
-    int flags[64];      // SH_FAIL: the hit buffer overflowed; SH_HELPED
+    int flags[64];      // SH_FAIL: the hit buffer overflowed; SH_HELPED; the read's slot
     int hexp[64];       // states expanded by helpers
     uint4 box[64];      // donated states
     uint32_t meta[64];  // owner lane | strand << 6 | budget << 7 | m << 11
@@ -1130,6 +1332,10 @@ struct PersistentArgs {
     const uint8_t *drows;
     const uint8_t *dflag;
     uint32_t dstride;
+    // split searches (X.budget 0: off), and per lane the read it owns
+    // (helpers of a read find its index there)
+    SplitBufs X;
+    uint32_t *lane_read;
 };
 
 // Row of read r, strand s, in the pre-pass's output.
@@ -1264,6 +1470,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                             cur = root_state(ix, m, P.minc * pd_d(c, m - 1));
                             valid = true;
                             c.sp = c.sbase = 0;
+                            di = 0;  // during a search: the expansions at its start
                         }
 #else
                         stage_read(own_pd, rd.bases + o0, m);
@@ -1281,6 +1488,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                         sh_st(&ws.pending[lane], 0);
                         sh_st(&ws.flags[lane], 0);
                         sh_st(&ws.hexp[lane], 0);
+                        if (A->X.budget) A->lane_read[gl] = r;
                     }
                 }
             }
@@ -1361,10 +1569,33 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                         c.cand = own_cand + ((int)ow - lane) * (ptrdiff_t)FAST_CAND;
                         c.best = sh_ld(&ws.best[ow]);
                         c.expand = 0;
+                        di = 0;
                         phase = PZ_HELP;
                     }
                 }
                 wave_fence();
+            }
+            // a part past the budget goes to the split searches, one lane
+            // of the wave at a time (a read's slot is taken once)
+            const uint32_t bud = A->X.budget;
+            if (bud) {
+                const bool want = (phase == PZ_SEARCH || phase == PZ_HELP) && c.sp > c.sbase &&
+                                  c.expand - (uint32_t)di >= bud && !(sh_ld(&ws.flags[ow]) & SH_FAIL);
+                unsigned long long sm = __ballot(want);
+                while (sm) {
+                    const int L = __ffsll(sm) - 1;
+                    if (lane == L) {
+                        int fl = sh_ld(&ws.flags[ow]);
+                        const uint32_t rr = ow == lane ? r : A->lane_read[gl - (uint32_t)lane + (uint32_t)ow];
+                        if (split_part(A->X, O, rr, strand, m, maxd, sh_ld(&ws.best[ow]), c, cur, valid, fl))
+                            valid = false;  // the lane's part is over
+                        else
+                            di = (int)c.expand;  // no room: try again after another budget
+                        sh_st(&ws.flags[ow], fl);
+                    }
+                    wave_fence();
+                    sm &= sm - 1;
+                }
             }
         }
 
@@ -1397,7 +1628,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 hit = true;
             } else if (rr < 0) {
                 // only without endgame, so the lane owns its read alone
-                send_to_second_pass(O, r);
+                give_up(O, A->X, r);
                 if (O.expand) O.expand[r] = c.expand;
                 phase = PZ_IDLE;
             } else if (rr == 0) {
@@ -1423,7 +1654,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                     if (record(c, P, make_hit(strand, KT_LOOP ? state_k(ix, strand, cur2) : cur2.x, cur2.y,
                                               s_len(cur2), score, s_nmm(cur2), s_ngo(cur2), s_nge(cur2)),
                                PH_FAST)) {
-                        send_to_second_pass(O, r);
+                        give_up(O, A->X, r);
                         if (O.expand) O.expand[r] = c.expand;
                         phase = PZ_IDLE;
                         act = ACT_NONE;
@@ -1514,7 +1745,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             const int fl = sh_ld(&ws.flags[lane]);
             if (fl & SH_FAIL) {
-                send_to_second_pass(O, r);
+                give_up(O, A->X, r);
                 if (O.expand) O.expand[r] = c.expand + (uint32_t)sh_ld(&ws.hexp[lane]);
                 phase = PZ_IDLE;
             } else if (strand == 0 && (BWFM_GENE_DPREPASS == 0 || !(A->dflag[r] & 2))) {
@@ -1525,6 +1756,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 cur = root_state(ix, m, P.minc * pd_d(c, m - 1));
                 valid = true;
                 c.sp = c.sbase = 0;
+                di = (int)c.expand;
 #else
                 phase = PZ_DSCAN;
                 di = 0;
@@ -1539,7 +1771,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 if (sb < c.best) c.best = sb;
                 c.cand = own_cand;
                 c.expand += (uint32_t)sh_ld(&ws.hexp[lane]);
-                publish(c, P, O, r, (fl & SH_HELPED) ? (uint8_t)BWFM_ST_SHARED : (uint8_t)0);
+                finish_read(c, P, O, A->X, r, (fl & SH_HELPED) ? (uint8_t)BWFM_ST_SHARED : (uint8_t)0);
                 phase = PZ_IDLE;
             }
         }
@@ -1605,6 +1837,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                     cur = root_state(ix, m, P.minc * dz);
                     valid = true;
                     c.sp = c.sbase = 0;
+                    di = (int)c.expand;  // during a search: the expansions at its start
                 } else if (strand == 0) {
                     strand = 1;
                     di = 0;
@@ -1620,7 +1853,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                     if (sb < c.best) c.best = sb;
                     c.expand += (uint32_t)sh_ld(&ws.hexp[lane]);
                     const int fl = sh_ld(&ws.flags[lane]);
-                    publish(c, P, O, r, (fl & SH_HELPED) ? (uint8_t)BWFM_ST_SHARED : (uint8_t)0);
+                    finish_read(c, P, O, A->X, r, (fl & SH_HELPED) ? (uint8_t)BWFM_ST_SHARED : (uint8_t)0);
                     phase = PZ_IDLE;
                 }
             }
@@ -1635,7 +1868,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 if (endgame) {
                     atomicOr(&ws.flags[ow], SH_FAIL);  // every lane of the read drops out
                 } else {
-                    send_to_second_pass(O, r);
+                    give_up(O, A->X, r);
                     if (O.expand) O.expand[r] = c.expand;
                     phase = PZ_IDLE;
                 }
@@ -1651,7 +1884,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
             // worst case; the read then goes to the second pass
             if (expand_children(cur2, valid2, ok2, ol2, qd, b2, m, maxd, Di2, Dn2, S, P, c,
                                 KT_LOOP ? ix.kt_levels : 0)) {
-                send_to_second_pass(O, r);
+                give_up(O, A->X, r);
                 if (O.expand) O.expand[r] = c.expand;
                 phase = PZ_IDLE;
             }
@@ -1687,6 +1920,179 @@ using PersistentKernel = void (*)(DevIndex, Params, const PersistentArgs *);
 template <int LW>
 PersistentKernel persistent_kernel(int waves_per_simd) {
     return (waves_per_simd == 0 || waves_per_simd >= 4) ? k_align_persistent4<LW> : k_align_persistent<LW>;
+}
+
+// Arguments of the task rounds, kept in device memory like PersistentArgs.
+struct TaskArgs {
+    LaneBufs B;
+    SplitBufs X;
+};
+
+__global__ void k_set_task_args(TaskArgs *dst, TaskArgs a) {
+    if (threadIdx.x == 0) *dst = a;
+}
+
+// One round of split searches: a persistent grid whose lanes take the
+// tasks of generation g from a counter, one atomic per wave as the batched
+// kernel takes reads.  A task is one state of a split read: its subtree is
+// searched depth-first on the lane's own stack with the slot's row (read in
+// place, so the kernel needs no LDS and as many lanes as its registers
+// allow), budget and best score, one rank-query pair per lane and
+// iteration.  Once the
+// round's tasks are all taken (drain set), a lane that has expanded at
+// least DRAIN_MIN states of its task hands its pending states to
+// generation g + 1, so that the round ends soon and the next one spreads
+// them over the grid; the last round has no drain.  At a task's end its
+// hits go to the slot.
+constexpr uint32_t DRAIN_MIN = 256;
+template <int LW>
+__global__ __launch_bounds__(BLOCK) void k_align_tasks(DevIndex ix, Params P, const TaskArgs *A, uint32_t g,
+                                                       uint32_t drain) {
+    const uint32_t ntask = min(ld_agent(&A->X.ctl[1 + g]), A->X.task_cap);
+    if (ntask == 0) return;  // the whole grid: nothing was split
+    const int lane = threadIdx.x & 63;
+    LaneCtx c;
+    init_ctx(c, A->B, blockIdx.x * blockDim.x + threadIdx.x);
+    c.sstride = 1;
+    c.cstride = 1;
+    bool busy = false, exhausted = false, valid = false;
+    bool drained = false;  // wave-uniform: the round's tasks are all taken
+    uint32_t s = 0, texp = 0, witer = 0;
+    int strand = 0, m = 0, maxd = 0;
+    uint4 cur = make_uint4(0, 0, 0, 0);
+    Seed S{0, 0, 0};
+    for (;;) {
+        asm volatile("" : "+s"(A));
+        const SplitBufs &X = A->X;
+        witer++;
+        // a wave learns that the round's tasks are all taken when one of
+        // its lanes finds none left, else from one load of the counter
+        // every 64 iterations (the same address for the whole wave)
+        if (drain && !drained && (witer & 63) == 0) drained = ld_agent(&X.ctl[2 + SPLIT_ROUNDS + g]) >= ntask;
+        // every 64 iterations, at once for the wave (lanes on one read share
+        // the load), the bound takes the best score any part has found
+        if ((witer & 63) == 32 && busy) {
+            const int sb = (int)ld_agent(reinterpret_cast<const uint32_t *>(&X.slot_best[s]));
+            if (sb < c.best) c.best = sb;
+        }
+        // idle lanes take the next tasks, one atomic per wave
+        const bool want = !busy && !exhausted;
+        const unsigned long long wm = __ballot(want);
+        uint32_t t = 0;
+        if (wm) {
+            const int leader = __ffsll(wm) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&X.ctl[2 + SPLIT_ROUNDS + g], (uint32_t)__popcll(wm));
+            base = __shfl(base, leader);
+            t = base + (uint32_t)__popcll(wm & ((1ULL << lane) - 1));
+            if (want && t >= ntask) exhausted = true;
+        }
+        if (want && !exhausted) {
+            const uint32_t ref = X.task_ref[g & 1][t];
+            // unused entries and the parts of failed reads are skipped (a
+            // stale flag only costs the work)
+            if (ref != TASK_EMPTY && !X.slot_fail[ref & 0x7fffffffu]) {
+                s = ref & 0x7fffffffu;
+                strand = (int)(ref >> 31);
+                const uint32_t meta = X.slot_meta[s];
+                m = (int)(meta & 1023);
+                maxd = (int)(meta >> 10);
+                // the slot's row, read in place: the tasks of one read share
+                // it in the caches
+                c.pd = X.slot_rows + ((size_t)s * 2 + (size_t)strand) * X.dstride;
+                cur = X.tasks[g & 1][t];
+                valid = true;
+                c.sp = c.sbase = 0;
+                c.ncand = 0;
+                c.best = X.slot_best[s];  // a stale value only prunes less
+                c.expand = 0;
+                texp = 0;
+                S = seed_of(P, m);
+                busy = true;
+            }
+        }
+        if (__ballot(busy) == 0) {
+            if (__ballot(!exhausted) == 0) break;
+            continue;
+        }
+        drained = drained || __ballot(exhausted) != 0;
+        bool query = false, done = false;
+        if (busy) {
+            const int rr = resolve<KT_LOOP>(cur, valid, strand, P, c, PH_FAST, POPS_PER_STEP, ix, true);
+            if (rr == 3) {
+                // a completed hit; a better score is shared with the read's
+                // other parts at once, a full buffer is first delivered
+                const int score = s_score(cur);
+                if (score < c.best) {
+                    c.best = score;
+                    atomicMin(&X.slot_best[s], score);
+                }
+                const uint4 h = make_hit(strand, KT_LOOP ? state_k(ix, strand, cur) : cur.x, cur.y, s_len(cur), score,
+                                         s_nmm(cur), s_ngo(cur), s_nge(cur));
+                if (record(c, P, h, PH_FAST)) {
+                    flush_slot(X, P, s, c);
+                    if (record(c, P, h, PH_FAST)) {
+                        atomicOr(&X.slot_fail[s], 1u);
+                        done = true;
+                    }
+                }
+                valid = false;
+            } else if (rr == 0) {
+                done = true;
+            } else if (rr == 1) {
+                if (drain && drained && texp >= DRAIN_MIN && c.sp > c.sbase) {
+                    uint32_t off = 0;
+                    if (take_tasks(X, g + 1, 1 + (c.sp - c.sbase), off)) {
+                        put_tasks(X, g + 1, off, s | ((uint32_t)strand << 31), c, cur, true);
+                        valid = false;
+                        done = true;
+                    }
+                }
+                query = !done;
+            }
+            // rr == 2: the pop limit; popping goes on next iteration
+        }
+        uint32_t ok[4] = {0, 0, 0, 0}, ol[4] = {0, 0, 0, 0};
+        const DevDir qd = pick_dir(ix, strand == 0 ? 1 : 0);
+        if (query) {
+            if (KT_LOOP && (uint32_t)s_len(cur) < ix.kt_levels) {
+                const uint4 *e = reinterpret_cast<const uint4 *>(qd.kt + 2 * kt_children(s_len(cur), cur.x));
+                kt_pick(qd, e[0], e[1], ok, ol);
+            } else {
+                occ4_pair<LW>(ix, qd, cur.x, cur.y + 1, ok, ol);
+            }
+            c.expand++;
+            texp++;
+            const int i = s_i(cur);
+            if (expand_children(cur, valid, ok, ol, qd, pd_base(c, i), m, maxd, pd_d(c, i), pd_d(c, i - 1), S, P, c,
+                                KT_LOOP ? ix.kt_levels : 0)) {
+                atomicOr(&X.slot_fail[s], 1u);  // cannot happen with worst-case stacks; kept as a guard
+                done = true;
+            }
+        }
+        if (done) {
+            flush_slot(X, P, s, c);
+            busy = false;
+            valid = false;
+        }
+    }
+}
+
+// Totals of the split searches for the work counters (work[3..5] start at
+// zero): reads split, task entries handed out over all generations, split
+// reads sent on to the second pass; then per generation the entries asked
+// for (above the room when some found none).  One thread per slot.
+__global__ void k_split_stats(SplitBufs X, unsigned long long *work) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ns = min(X.ctl[0], X.slot_cap);
+    if (s == 0) {
+        unsigned long long t = 0;
+        for (int g = 0; g <= SPLIT_ROUNDS; g++) t += min(X.ctl[1 + g], X.task_cap);
+        work[3] = ns;
+        work[4] = t;
+        for (int g = 0; g < SPLIT_ROUNDS; g++) work[6 + g] = X.ctl[1 + g];
+    }
+    if (s < ns && (X.slot_fail[s] || X.slot_nhit[s] > SLOT_HITS)) atomicAdd(&work[5], 1ull);
 }
 
 // Second pass for the reads listed in slow_list (*O.n_slow of them, set by
@@ -2339,6 +2745,90 @@ inline uint32_t block_for(uint32_t stride) {
 }
 
 constexpr uint32_t SLOW_LANES = BWFM_SLOW_LANES;  // most lanes of the second pass
+constexpr uint32_t SPLIT_DEFAULT = 16384;         // split budget unless the caller sets one
+
+// Expansions between splits for a parameter block; 0: no splitting (the
+// plain form never splits).
+inline uint32_t split_budget_of(const bwfm_aln_params &p) {
+    if (p.form == BWFM_FORM_PLAIN || p.split_budget < 0) return 0;
+    return p.split_budget == 0 ? SPLIT_DEFAULT : (uint32_t)p.split_budget;
+}
+
+// Room of the split searches for a batch of n reads of at most mlen bases:
+// a slot for one read in eight (at least 64, at most 2^26) and sixteen task entries a
+// read (at least 4096, at most 2^26) per generation.  A split hands out a
+// few hundred entries on long reads.  Running out is not an error: a read
+// or task that finds no room goes on alone.
+struct SplitShape {
+    uint32_t slot_cap, task_cap, dstride;
+};
+inline SplitShape split_shape(uint32_t n, uint32_t mlen) {
+    SplitShape z;
+    z.slot_cap = std::min<uint32_t>(std::min<uint32_t>(std::max<uint32_t>(n, 1), std::max<uint32_t>(64, n / 8)), 1u << 26);
+    z.task_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(16ull * n, 4096), 1ull << 26);
+    z.dstride = ((mlen + 15) / 16) * 16;
+    return z;
+}
+inline size_t split_bytes(const SplitShape &z) {
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return 6 * al((size_t)z.slot_cap * 4) + al((size_t)z.slot_cap * 2 * z.dstride) +
+           al((size_t)z.slot_cap * SLOT_HITS * 16) + 2 * al((size_t)z.task_cap * 16) + 2 * al((size_t)z.task_cap * 4) +
+           al(SPLIT_CTL * 4) + al(sizeof(TaskArgs)) + 256;
+}
+inline SplitBufs carve_split(Carver &cv, const SplitShape &z, uint32_t budget, TaskArgs **targs) {
+    SplitBufs X{};
+    X.slot_read = cv.take<uint32_t>(z.slot_cap);
+    X.slot_meta = cv.take<uint32_t>(z.slot_cap);
+    X.slot_best = cv.take<int>(z.slot_cap);
+    X.slot_nhit = cv.take<uint32_t>(z.slot_cap);
+    X.slot_fail = cv.take<uint32_t>(z.slot_cap);
+    X.slot_exp = cv.take<uint32_t>(z.slot_cap);
+    X.slot_rows = cv.take<uint8_t>((size_t)z.slot_cap * 2 * z.dstride);
+    X.slot_hits = cv.take<uint4>((size_t)z.slot_cap * SLOT_HITS);
+    for (int k = 0; k < 2; k++) {
+        X.tasks[k] = cv.take<uint4>(z.task_cap);
+        X.task_ref[k] = cv.take<uint32_t>(z.task_cap);
+    }
+    X.ctl = cv.take<uint32_t>(SPLIT_CTL);
+    *targs = cv.take<TaskArgs>(1);
+    X.slot_cap = z.slot_cap;
+    X.task_cap = z.task_cap;
+    X.dstride = z.dstride;
+    X.budget = budget;
+    return X;
+}
+
+// Lanes of the task rounds' grid (blocks of BLOCK lanes, no LDS): as many
+// as fit on the device at once, but at most sixteen per read of the batch
+// (n_up lanes) or the first pass's lanes, whichever is more, since they
+// all need lane buffers.
+template <int LW>
+uint32_t task_lanes(uint32_t n_up, uint32_t lanes) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_align_tasks<LW>, (int)BLOCK, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const uint64_t fit = (uint64_t)cus * (uint64_t)per_cu * BLOCK;
+    const uint64_t want = std::max<uint64_t>(lanes, ((16ull * n_up + BLOCK - 1) / BLOCK) * BLOCK);
+    return (uint32_t)std::max<uint64_t>(std::min(fit, want), BLOCK);
+}
+
+// After the first pass (split searches on): the task rounds on their own
+// grid of tlanes lanes, on the first pass's lane buffers (allocated for
+// both grids), the last round without a drain, then the publication of the
+// split reads.  Every launch reads its counts on the device, so the
+// sequence can be captured.
+template <int LW>
+void enqueue_split(const DevIndex &D, const Params &P, const SplitBufs &X, TaskArgs *targs, const LaneBufs &lb,
+                   const ReadOut &O, uint32_t tlanes, hipStream_t st) {
+    k_set_task_args<<<1, 64, 0, st>>>(targs, TaskArgs{lb, X});
+    for (uint32_t g = 0; g < (uint32_t)SPLIT_ROUNDS; g++)
+        k_align_tasks<LW><<<tlanes / BLOCK, BLOCK, 0, st>>>(D, P, targs, g, g + 1 < (uint32_t)SPLIT_ROUNDS ? 1u : 0u);
+    k_split_publish<<<blocks(X.slot_cap, 256), 256, 0, st>>>(P, X, O);
+}
 
 template <int LW>
 int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const bwfm_aln_params *p,
@@ -2350,18 +2840,22 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
     const uint32_t mlen = std::max<uint32_t>(rd->max_len, 1);
     const uint32_t worst_stack = 8 * (mlen + BWFM_MAX_DIFF) + 1;  // never overflows
     const uint32_t lstride = lds_stride_for(mlen);
-    const uint32_t bs = block_for(lstride);
     const bool plain = p->form == BWFM_FORM_PLAIN;
+    const uint32_t sbud = plain ? 0u : split_budget_of(*p);  // split searches (batched form)
+    const uint32_t bs = block_for(lstride);
     const size_t lds = (size_t)bs * lstride + (plain ? 0 : (bs / 64) * sizeof(WaveShare));
     const uint32_t nr_up = ((std::max<uint32_t>(n, 1) + bs - 1) / bs) * bs;
     const uint32_t lanes = plain ? nr_up : std::min<uint32_t>(persistent_lanes<LW>(bs, lds, p->waves_per_simd), nr_up);
     const uint32_t stack_cap = plain ? std::min<uint32_t>(worst_stack, PLAIN_STACK) : worst_stack;
+    // the task rounds' grid shares the lane buffers: room for the larger one
+    const uint32_t tlanes = sbud ? task_lanes<LW>(nr_up, lanes) : 0u;
+    const uint32_t blanes = std::max(lanes, tlanes);
     // the staging arena holds the reported hits of every read: as many as
     // the output can take
     const uint64_t stage_cap = res->hit_capacity;
     const uint32_t slow_lanes = std::min<uint32_t>(nr_up, SLOW_LANES);
     const uint32_t scap = P.max_hits + 1;
-    size_t need = (size_t)lanes * stack_cap * 16 + (size_t)lanes * FAST_CAND * 16;
+    size_t need = (size_t)blanes * stack_cap * 16 + (size_t)blanes * FAST_CAND * 16;
     need += (size_t)slow_lanes * worst_stack * 16 + (size_t)slow_lanes * scap * 16;
     need += (size_t)n * 4 * 2 + (size_t)n * 8 + stage_cap * 16 + scan_part_elems(n) * 8 + 16 * 256;
     need += sizeof(PersistentArgs) + 256;
@@ -2369,12 +2863,14 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
     const bool dpre = BWFM_GENE_DPREPASS == 1 && !plain;
     const uint32_t dstride = ((mlen + 15) / 16) * 16;
     if (dpre) need += (size_t)n * 2 * dstride + n + 2 * 256;
+    const SplitShape zs = split_shape(n, mlen);
+    if (sbud) need += split_bytes(zs) + (size_t)lanes * 4 + 256;
     void *w;
     int rc = ws_reserve(ws, need, st, &w);
     if (rc) return rc;
     Carver cv{(char *)w};
-    uint4 *lstack = cv.take<uint4>((size_t)lanes * stack_cap);
-    uint4 *lcand = cv.take<uint4>((size_t)lanes * FAST_CAND);
+    uint4 *lstack = cv.take<uint4>((size_t)blanes * stack_cap);
+    uint4 *lcand = cv.take<uint4>((size_t)blanes * FAST_CAND);
     uint4 *sstack = cv.take<uint4>((size_t)slow_lanes * worst_stack);
     uint4 *scand = cv.take<uint4>((size_t)slow_lanes * scap);
     uint32_t *n_rep = cv.take<uint32_t>(n);
@@ -2385,6 +2881,10 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
     PersistentArgs *pargs = cv.take<PersistentArgs>(1);
     uint8_t *drows = dpre ? cv.take<uint8_t>((size_t)n * 2 * dstride) : nullptr;
     uint8_t *dflag = dpre ? cv.take<uint8_t>(n) : nullptr;
+    TaskArgs *targs = nullptr;
+    SplitBufs X = sbud ? carve_split(cv, zs, sbud, &targs) : SplitBufs{};
+    X.count = expand != nullptr;
+    uint32_t *lane_read = sbud ? cv.take<uint32_t>(lanes) : nullptr;
     uint32_t *ctl = cv.take<uint32_t>(16);  // n_slow, next_read, stage_used (64-bit), slow_next
     uint32_t *n_slow = ctl, *next_read = ctl + 1, *slow_next = ctl + 4;
     unsigned long long *stage_used = reinterpret_cast<unsigned long long *>(ctl + 2);
@@ -2396,7 +2896,8 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
     ReadOut O{n_rep,     res->c1,   res->c2,   res->status, slow_list,
               n_slow,    stage,     stage_used, stage_cap,  stage_off,
               expand,    reinterpret_cast<unsigned long long *>(work)};
-    if (work) k_fill_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t *>(work), 6, 0u);
+    if (work) k_fill_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t *>(work), 2 * (6 + SPLIT_ROUNDS), 0u);
+    if (sbud) k_fill_u32<<<1, 64, 0, st>>>(X.ctl, SPLIT_CTL, 0u);
     CallTimer tm(st);
     if (n) {
         if (plain) {
@@ -2409,11 +2910,18 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
                 k_dscan<LW><<<nr_up / bs, bs, (size_t)bs * lstride, st>>>(D, rv, P, drows, dflag, dstride, lstride);
                 tm.end(td);
             }
-            k_set_args<<<1, 64, 0, st>>>(pargs, PersistentArgs{rv, lb, O, next_read, drows, dflag, dstride});
+            k_set_args<<<1, 64, 0, st>>>(pargs, PersistentArgs{rv, lb, O, next_read, drows, dflag, dstride, X, lane_read});
+            int ts = tm.begin("align_search");
             int t = tm.begin("align_persistent");
             hipLaunchKernelGGL(persistent_kernel<LW>(p->waves_per_simd), dim3(lanes / bs), dim3(bs), lds, st, D, P,
                                (const PersistentArgs *)pargs);
             tm.end(t);
+            if (sbud) {
+                int tt = tm.begin("align_tasks");
+                enqueue_split<LW>(D, P, X, targs, lb, O, tlanes, st);
+                tm.end(tt);
+            }
+            tm.end(ts);
         }
         // the second pass reads its count on the device: no host round trip
         const size_t slds = (size_t)bs * lstride;
@@ -2421,6 +2929,8 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
         int t = tm.begin("align_slow");
         k_align_slow<LW><<<slow_lanes / bs, bs, slds, st>>>(D, rv, P, sb, O, slow_next);
         tm.end(t);
+        if (work && sbud)
+            k_split_stats<<<blocks(X.slot_cap, 256), 256, 0, st>>>(X, reinterpret_cast<unsigned long long *>(work));
         HIPCHK(hipGetLastError());
     }
     rc = scan_counts(n_rep, n, res->hit_offsets, part, st);
@@ -2611,6 +3121,9 @@ static int check_aln_params(const bwfm_aln_params *p) {
         (p->form != BWFM_FORM_BATCHED && p->form != BWFM_FORM_PLAIN) || p->waves_per_simd < 0 ||
         p->waves_per_simd > 8 || p->max_hits > 65536 || p->s_mm > 63 || p->s_gapo > 63 || p->s_gape > 63)
         return fail(BWFM_E_INVAL, "align_batch: parameter out of range");
+    const int32_t b = p->split_budget;
+    if (b != 0 && b != -1 && (b < 16 || b > (1 << 24)))
+        return fail(BWFM_E_INVAL, "align_batch: split_budget must be 0, -1 or in [16, 2^24]");
     return BWFM_OK;
 }
 
@@ -3012,8 +3525,12 @@ struct bwfm_pipeline {
     PersistentArgs *pargs = nullptr;
     uint8_t *drows = nullptr, *dflag = nullptr;  // D-array pre-pass output (gene DPREPASS)
     uint32_t dstride = 0;
+    SplitBufs X{};               // split searches (X.budget 0: off)
+    TaskArgs *targs = nullptr;
+    uint32_t *lane_read = nullptr;
     // launch shape
     uint32_t lanes = 0, slow_lanes = 0, bs = 0, lstride = 0, stack_cap = 0, worst_stack = 0, scap = 0;
+    uint32_t tlanes = 0;  // the split searches' round grid (shares the lane buffers)
     size_t lds = 0;
     uint32_t n_pairs = 0;  // of the batch last set
     uint32_t ends = 2;     // reads per pair record
@@ -3021,7 +3538,7 @@ struct bwfm_pipeline {
     bwfm_reads in{};       // the bound input
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // first pass start, end; the search's end
     hipStream_t cap = nullptr;  // capture only: nothing runs on it
     bool timed_graph = false, timed_last = false;
     bool timing_uncapturable = false;  // a capture with event nodes failed once
@@ -3057,8 +3574,11 @@ int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed, bool capture) {
         k_dscan<LW><<<nr_up / pl->bs, pl->bs, (size_t)pl->bs * pl->lstride, st>>>(D, rv, P, pl->drows, pl->dflag,
                                                                                pl->dstride, pl->lstride);
     }
+    if (pl->X.budget) k_fill_u32<<<1, 64, 0, st>>>(pl->X.ctl, SPLIT_CTL, 0u);
     if (!plain)
-        k_set_args<<<1, 64, 0, st>>>(pl->pargs, PersistentArgs{rv, lb, O, actl + 1, pl->drows, pl->dflag, pl->dstride});
+        k_set_args<<<1, 64, 0, st>>>(pl->pargs,
+                                     PersistentArgs{rv, lb, O, actl + 1, pl->drows, pl->dflag, pl->dstride, pl->X,
+                                                    pl->lane_read});
     if (timed) HIPCHK(mark(pl->ev[0]));
     if (plain)
         k_align_plain<LW><<<pl->lanes / pl->bs, pl->bs, pl->lds, st>>>(D, rv, P, lb, O);
@@ -3066,6 +3586,8 @@ int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed, bool capture) {
         hipLaunchKernelGGL(persistent_kernel<LW>(pl->ap.waves_per_simd), dim3(pl->lanes / pl->bs), dim3(pl->bs),
                            pl->lds, st, D, P, (const PersistentArgs *)pl->pargs);
     if (timed) HIPCHK(mark(pl->ev[1]));
+    if (pl->X.budget) enqueue_split<LW>(D, P, pl->X, pl->targs, lb, O, pl->tlanes, st);
+    if (timed) HIPCHK(mark(pl->ev[2]));
     LaneBufs sb{pl->sstack, pl->scand, pl->worst_stack, 1, pl->worst_stack, pl->scap, 1, pl->scap, pl->lstride};
     k_align_slow<LW><<<pl->slow_lanes / pl->bs, pl->bs, (size_t)pl->bs * pl->lstride, st>>>(D, rv, P, sb, O, actl + 4);
     HIPCHK(hipGetLastError());
@@ -3135,8 +3657,9 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
     const uint32_t mlen = q->max_len;
     pl->worst_stack = 8 * (mlen + BWFM_MAX_DIFF) + 1;
     pl->lstride = lds_stride_for(mlen);
-    pl->bs = block_for(pl->lstride);
     const bool plain = ap->form == BWFM_FORM_PLAIN;
+    const uint32_t sbud = plain ? 0u : split_budget_of(*ap);
+    pl->bs = block_for(pl->lstride);
     pl->lds = (size_t)pl->bs * pl->lstride + (plain ? 0 : (pl->bs / 64) * sizeof(WaveShare));
     const uint32_t nr_up = ((nmax + pl->bs - 1) / pl->bs) * pl->bs;
     pl->lanes = plain ? nr_up
@@ -3147,6 +3670,8 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
                                                      }),
                                            nr_up);
     pl->stack_cap = plain ? std::min<uint32_t>(pl->worst_stack, PLAIN_STACK) : pl->worst_stack;
+    pl->tlanes = sbud ? by_layout(ix, [&](auto lw) { return task_lanes<decltype(lw)::value>(nr_up, pl->lanes); }) : 0u;
+    const uint32_t blanes = std::max(pl->lanes, pl->tlanes);
     pl->slow_lanes = std::min<uint32_t>(nr_up, SLOW_LANES);
     pl->scap = ap->max_hits + 1;
     const uint64_t hcap = std::max<uint64_t>(q->hit_capacity, 1);
@@ -3154,7 +3679,7 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
     size_t need = 0;
     auto add = [&](size_t b) { need += (b + 255) & ~size_t(255); };
     add(q->max_bases); add((size_t)(nmax + 1) * 8); add(nmax);
-    add((size_t)pl->lanes * pl->stack_cap * 16); add((size_t)pl->lanes * FAST_CAND * 16);
+    add((size_t)blanes * pl->stack_cap * 16); add((size_t)blanes * FAST_CAND * 16);
     add((size_t)pl->slow_lanes * pl->worst_stack * 16); add((size_t)pl->slow_lanes * pl->scap * 16);
     add((size_t)nmax * 4); add((size_t)nmax * 4); add((size_t)nmax * 8); add(hcap * 16);
     add(scan_part_elems(std::max<uint64_t>(nmax, hcap)) * 8);
@@ -3168,14 +3693,16 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
         add((size_t)nmax * 2 * pl->dstride);
         add(nmax);
     }
+    const SplitShape zs = split_shape(nmax, mlen);
+    if (sbud) need += split_bytes(zs) + (size_t)pl->lanes * 4 + 256;
     need += 4096;
     if (hipMalloc(&pl->mem, need) != hipSuccess) return fail(BWFM_E_NOMEM, "pipeline: device allocation failed");
     Carver cv{(char *)pl->mem};
     pl->bases = cv.take<uint8_t>(q->max_bases);
     pl->offsets = cv.take<uint64_t>(nmax + 1);
     pl->maxd = cv.take<uint8_t>(nmax);
-    pl->lstack = cv.take<uint4>((size_t)pl->lanes * pl->stack_cap);
-    pl->lcand = cv.take<uint4>((size_t)pl->lanes * FAST_CAND);
+    pl->lstack = cv.take<uint4>((size_t)blanes * pl->stack_cap);
+    pl->lcand = cv.take<uint4>((size_t)blanes * FAST_CAND);
     pl->sstack = cv.take<uint4>((size_t)pl->slow_lanes * pl->worst_stack);
     pl->scand = cv.take<uint4>((size_t)pl->slow_lanes * pl->scap);
     pl->n_rep = cv.take<uint32_t>(nmax);
@@ -3199,7 +3726,12 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
         pl->drows = cv.take<uint8_t>((size_t)nmax * 2 * pl->dstride);
         pl->dflag = cv.take<uint8_t>(nmax);
     }
+    if (sbud) {
+        pl->X = carve_split(cv, zs, sbud, &pl->targs);
+        pl->lane_read = cv.take<uint32_t>(pl->lanes);
+    }
     if (hipEventCreate(&pl->ev[0]) != hipSuccess || hipEventCreate(&pl->ev[1]) != hipSuccess ||
+        hipEventCreate(&pl->ev[2]) != hipSuccess ||
         hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess) {
         bwfm_pipeline_destroy(pl.release());
         return fail(BWFM_E_DEVICE, "pipeline: event or stream creation failed");
@@ -3326,12 +3858,19 @@ extern "C" int bwfm_pipeline_finish(bwfm_pipeline *pl, void *stream, bwfm_pipeli
     out->kernel_ms = 0;
     if (pl->timed_last) {
         float ms = 0;
-        if (hipEventElapsedTime(&ms, pl->ev[0], pl->ev[1]) == hipSuccess) {
-            out->kernel_ms = ms;
+        float ms_all = 0;
+        if (hipEventElapsedTime(&ms, pl->ev[0], pl->ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&ms_all, pl->ev[0], pl->ev[2]) == hipSuccess) {
+            out->kernel_ms = ms_all;
             std::lock_guard<std::mutex> g(timing().mu);
             auto &e = timing().acc[pl->ap.form == BWFM_FORM_PLAIN ? "align_plain" : "align_persistent"];
             e.first += ms;
             e.second += 1;
+            if (pl->ap.form != BWFM_FORM_PLAIN) {
+                auto &f = timing().acc["align_search"];
+                f.first += ms_all;
+                f.second += 1;
+            }
         }
     }
     return BWFM_OK;

@@ -82,8 +82,8 @@ def test_c1_shape_parity(c1_small, layout, mode, form):
     # same traversal order: the work counters agree for reads done in one pass
     st = res.status.cpu().numpy()
     exp = res.expand.cpu().numpy().view(np.uint32)
-    # (reads whose tree was split across lanes traverse in another order)
-    one = (st & (bw.ST_RESEARCH | bw.ST_SHARED)) == 0
+    # (reads whose tree was split across lanes or tasks traverse in another order)
+    one = (st & (bw.ST_RESEARCH | bw.ST_SHARED | bw.ST_SPLIT)) == 0
     assert np.array_equal(exp[one], ores.counts["expand"][one].astype(np.uint32))
 
 
@@ -135,7 +135,7 @@ def test_c2_shape_parity_align_locate_pair(c2_small, layout, form):
         ores = oracle.align(ox, end.bases, end.offsets, op, threads=8)
         _compare_align(res, ores)
         st = res.status.cpu().numpy()
-        one = (st & (bw.ST_RESEARCH | bw.ST_SHARED)) == 0
+        one = (st & (bw.ST_RESEARCH | bw.ST_SHARED | bw.ST_SPLIT)) == 0
         assert np.array_equal(res.expand.cpu().numpy().view(np.uint32)[one],
                               ores.counts["expand"][one].astype(np.uint32))
         r.append((res, ores))
@@ -266,31 +266,64 @@ def test_c3_shape_per_read_budgets_parity(form):
         _compare_align(res, ores)
 
 
-@pytest.mark.parametrize("form,wps,fmt", [(bw.FORM_BATCHED, 0, bw.RANK_PLANES), (bw.FORM_BATCHED, 3, bw.RANK_PLANES),
-                                          (bw.FORM_PLAIN, 0, bw.RANK_PLANES), (bw.FORM_BATCHED, 0, bw.RANK_SUBCOUNTS),
-                                          (bw.FORM_BATCHED, 0, bw.RANK_SUB128), (bw.FORM_PLAIN, 0, bw.RANK_SUB128)])
-def test_c5_shape_stress_parity(form, wps, fmt):
+@pytest.mark.parametrize("form,wps,fmt,split", [(bw.FORM_BATCHED, 0, bw.RANK_PLANES, 4096),
+                                                (bw.FORM_BATCHED, 3, bw.RANK_PLANES, 4096),
+                                                (bw.FORM_PLAIN, 0, bw.RANK_PLANES, 0),
+                                                (bw.FORM_BATCHED, 0, bw.RANK_SUBCOUNTS, 4096),
+                                                (bw.FORM_BATCHED, 0, bw.RANK_SUB128, 4096),
+                                                (bw.FORM_PLAIN, 0, bw.RANK_SUB128, 0),
+                                                (bw.FORM_BATCHED, 0, bw.RANK_SUB128, 0),
+                                                (bw.FORM_BATCHED, 0, bw.RANK_SUB128, -1),
+                                                (bw.FORM_BATCHED, 3, bw.RANK_PLANES, -1),
+                                                (bw.FORM_BATCHED, 0, bw.RANK_SUB128, 64),
+                                                (bw.FORM_BATCHED, 0, bw.RANK_SUB128, 1024)])
+def test_c5_shape_stress_parity(form, wps, fmt, split):
     """250 bp reads, 6 differences with gaps, a tenth from repeat copies: a few
-    reads expand hundreds of thousands of states.  In the batched form their
-    trees are split across the lanes of a wave once the batch runs dry."""
+    reads expand hundreds of thousands of states.  In the batched form the
+    lanes of a wave share the reads in flight once the batch runs dry, and a
+    lane's part past the split budget is handed to tasks for the whole grid
+    (0: the library's default, at which this small batch may split nothing;
+    64: so small that slots and task room run out at this batch size and
+    parts go on alone; -1: no splitting)."""
     g = configs.c2_genome(2_000_000, seed=55)
     reads = configs.c5_reads(g, 2000, seed=56)
     ox = oracle.Index(g.seq)
     ix = bw.Index(g.seq, **configs.FORMAT_LAYOUT[fmt]).upload()
     p, op = _params_pair(form=form, **configs.PARAMS["C5"])
     p.waves_per_simd = wps  # every build of the batched kernel
+    p.split_budget = split
     op.bases_per_line = ix.info()["bases_per_line"]
     res = _gpu_align(ix, reads, p, counted=True)
     ores = oracle.align(ox, reads.bases, reads.offsets, op, threads=8)
     _compare_align(res, ores)
     st = res.status.cpu().numpy()
-    if form == bw.FORM_BATCHED:
-        assert int((st & bw.ST_SHARED).astype(bool).sum()) > 0, "no search tree was split"
+    work = res.work.cpu().numpy()
+    if form == bw.FORM_BATCHED and split >= 0:
+        n_split = int((st & bw.ST_SPLIT).astype(bool).sum())
+        assert n_split > 0 or split == 0, "no search was split"
+        # reads split = slots taken (those sent on to the second pass carry
+        # the second pass's status instead)
+        assert int(work[3]) == n_split + int(work[5]) and int(work[4]) > 0
+        print(f"[c5-split {split}] {n_split} split reads, {int(work[4])} tasks, {int(work[5])} to the second pass, "
+              f"per generation {work[6:22].tolist()}", flush=True)
+    elif form == bw.FORM_BATCHED:
+        assert int((st & bw.ST_SHARED).astype(bool).sum()) > 0, "no search tree was shared"
+        assert not (st & bw.ST_SPLIT).any()
     else:
-        assert not (st & bw.ST_SHARED).any()
-    one = (st & (bw.ST_RESEARCH | bw.ST_SHARED)) == 0
+        assert not (st & (bw.ST_SHARED | bw.ST_SPLIT)).any()
+    one = (st & (bw.ST_RESEARCH | bw.ST_SHARED | bw.ST_SPLIT)) == 0
     exp = res.expand.cpu().numpy().view(np.uint32)
     assert np.array_equal(exp[one], ores.counts["expand"][one].astype(np.uint32))
+
+
+def test_split_budget_is_checked():
+    g = gen.genome_iid(7, 100_000)
+    reads = gen.reads_se(8, g, 50, 30, ps=0.0)
+    ix = bw.Index(g.seq).upload()
+    for b in (8, 15, (1 << 24) + 1, -2):
+        with pytest.raises(bw.BwfmError) as e:
+            _gpu_align(ix, reads, bw.Params(max_diff=1, split_budget=b))
+        assert e.value.code == bw.E_INVAL
 
 
 def test_hit_capacity_error_reports_need():

@@ -43,11 +43,13 @@ def _expected(ox, pairs, n, op, w):
     return res, locs, pr
 
 
-def _check_run(pl, n, exp):
+def _check_run(pl, n, exp, split=0):
     res, locs, pr = exp
     st = pl.finish()
     assert st["error"] == 0 and st["n_pairs"] == n
     r1, r2, prs, po, pos = pl.results()
+    if split > 0 and n:
+        assert any((r.status.cpu().numpy() & bw.ST_SPLIT).any() for r in (r1, r2)), "no search was split"
     for got, want in ((r1, res[0]), (r2, res[1])):
         ho, hits, c1, c2, s = got.to_numpy()
         assert np.array_equal(ho, want.hit_off)
@@ -64,14 +66,19 @@ def _check_run(pl, n, exp):
     assert st["n_hits"] == int(po_h.shape[0] - 1) and st["n_positions"] == len(want_pos)
 
 
-@pytest.mark.parametrize("form,fmt", [(bw.FORM_BATCHED, bw.RANK_PLANES), (bw.FORM_PLAIN, bw.RANK_PLANES),
-                                      (bw.FORM_BATCHED, bw.RANK_SUBCOUNTS), (bw.FORM_BATCHED, bw.RANK_SUB128)])
-def test_pipeline_eager_and_graph_replays_equal_oracle(setup, form, fmt):
+@pytest.mark.parametrize("form,fmt,split", [(bw.FORM_BATCHED, bw.RANK_PLANES, 0), (bw.FORM_PLAIN, bw.RANK_PLANES, 0),
+                                            (bw.FORM_BATCHED, bw.RANK_SUBCOUNTS, 0),
+                                            (bw.FORM_BATCHED, bw.RANK_SUB128, 0),
+                                            (bw.FORM_BATCHED, bw.RANK_SUB128, 16),
+                                            (bw.FORM_BATCHED, bw.RANK_PLANES, -1)])
+def test_pipeline_eager_and_graph_replays_equal_oracle(setup, form, fmt, split):
+    """split 16: nearly every read's search is split, so every replay runs
+    the task rounds and the slot publication; -1: splitting off."""
     g, pairs, ox, ix = setup
     if fmt != ix.info()["rank_format"]:
         ix = bw.Index(g.seq, **configs.FORMAT_LAYOUT[fmt]).upload()
     w = configs.PAIR_WINDOW
-    p = bw.Params(**configs.PARAMS["C2"], form=form)
+    p = bw.Params(**configs.PARAMS["C2"], form=form, split_budget=split)
     op = oracle.Params(**configs.PARAMS["C2"])
     N = 2500
     pl = bw.Pipeline(ix, p, w["lo"], w["hi"], w["mu"], configs.MAX_OCC, max_pairs=N, max_len=100)
@@ -79,10 +86,10 @@ def test_pipeline_eager_and_graph_replays_equal_oracle(setup, form, fmt):
     pl.set_reads(torch.from_numpy(b).cuda(), torch.from_numpy(o.view(np.int64)).cuda(), N, max_len=100)
     exp = _expected(ox, pairs, N, op, w)
     pl.run(graph=False)
-    _check_run(pl, N, exp)
+    _check_run(pl, N, exp, split)
     for k in range(3):
         pl.run(graph=True)
-        _check_run(pl, N, exp)
+        _check_run(pl, N, exp, split)
         # unrelated device work and a synchronisation between replays
         x = torch.arange(1 << 20, device="cuda", dtype=torch.int64)
         assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
