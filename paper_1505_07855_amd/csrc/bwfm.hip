@@ -1047,8 +1047,11 @@ __device__ __forceinline__ int check_read(const ReadsView &rd, const Params &P, 
         O.status[r] = BWFM_ST_INVALID;
         return 1;
     }
-    O.status[r] = 0;
-    return m == 0 ? 1 : 0;
+    if (m == 0) {
+        O.status[r] = 0;
+        return 1;
+    }
+    return 0;
 }
 
 // ------------------------------------------------------------------ split searches
@@ -1066,8 +1069,9 @@ __device__ __forceinline__ int check_read(const ReadsView &rd, const Params &P, 
 // found by the part that holds it.
 constexpr int SPLIT_ROUNDS = 16;              // task rounds; the last one runs every task to its end
 constexpr uint32_t TASK_EMPTY = 0xffffffffu;  // a reserved task entry left unused
-constexpr uint8_t ST_SPLIT_PEND = 0x80;       // status of a split read until its slot is published
-constexpr uint32_t SLOT_HITS = FAST_CAND;     // hits a slot collects, as many as a first-pass lane
+// hits a slot collects: those of the read's first-pass lane (at most
+// FAST_CAND), then at most as many again from its tasks
+constexpr uint32_t SLOT_HITS = 2 * FAST_CAND;
 // control words: [0] slots taken; [1 + g] task entries reserved in
 // generation g (0: by the first pass, k: by round k); [2 + SPLIT_ROUNDS + g]
 // entries of generation g taken by round g + 1
@@ -1080,11 +1084,15 @@ struct SplitBufs {
     uint32_t *slot_nhit;    // hits delivered (above SLOT_HITS: the slot failed)
     uint32_t *slot_fail;    // nonzero: the read goes to the second pass
     uint32_t *slot_exp;     // states expanded by the read's parts
+    uint32_t *slot_owner;   // the first-pass lane that owns the read (its hit buffer)
+    uint32_t *slot_own;     // hits in that buffer when the first pass finished the read
+    int *slot_obest;        // and its best score then
     uint8_t *slot_rows;     // per slot and strand: the pattern and D-array row, dstride bytes
     uint4 *slot_hits;       // per slot: SLOT_HITS hits
     uint4 *tasks[2];        // task states, by generation parity
     uint32_t *task_ref[2];  // slot | strand << 31, or TASK_EMPTY
     uint32_t *ctl;          // SPLIT_CTL control words
+    uint4 *lane_cand;       // the first pass's hit buffers, FAST_CAND per lane
     uint32_t slot_cap, task_cap, dstride;
     uint32_t budget;  // expansions of a lane's part of a read before it is split (endgame); 0: off
     uint32_t count;   // nonzero: the parts' expansions are summed (per-read work counters)
@@ -1146,7 +1154,7 @@ __device__ void flush_slot(const SplitBufs &X, const Params &P, uint32_t s, Lane
     for (uint32_t j = 0; j < c.ncand; j++) keep += h_score(c.cand[(size_t)j * c.cstride]) <= bound ? 1u : 0u;
     if (keep) {
         uint32_t off = atomicAdd(&X.slot_nhit[s], keep);
-        if (off + keep > SLOT_HITS) {
+        if (off + keep > SLOT_HITS) {  // the collection left room for FAST_CAND of them
             atomicOr(&X.slot_fail[s], 1u);
         } else {
             uint4 *dst = X.slot_hits + (size_t)s * SLOT_HITS;
@@ -1160,18 +1168,19 @@ __device__ void flush_slot(const SplitBufs &X, const Params &P, uint32_t s, Lane
 }
 
 // Flag word of a read in its wave's sharing block: SH_FAIL, SH_HELPED, the
-// strands whose rows the read's slot holds, and the slot plus one above
-// SH_SLOT_SHIFT (0: none yet).
-enum { SH_FAIL = 1, SH_HELPED = 2, SH_ROW0 = 4 };
-constexpr int SH_SLOT_SHIFT = 4;
+// strands whose rows the read's slot holds, SH_NOSPLIT once a split found
+// no room, and the slot plus one above SH_SLOT_SHIFT (0: none yet).
+enum { SH_FAIL = 1, SH_HELPED = 2, SH_ROW0 = 4, SH_NOSPLIT = 16 };
+constexpr int SH_SLOT_SHIFT = 5;
 
 // Endgame of the first pass: hand this lane's part of read r on `strand`
 // -- cur when valid, then the pending stack entries -- to the tasks of
 // generation 0, taking the read's slot at its first split (fl is the
-// read's flag word; best its best score so far).  The caller runs one lane
-// of a wave at a time.  False, with the lane's search unchanged, when no
-// slot or task room is left.
-__device__ bool split_part(const SplitBufs &X, const ReadOut &O, uint32_t r, int strand, int m, int maxd, int best,
+// read's flag word; best its best score so far; owner the global index of
+// the lane that owns the read).  The caller runs one lane of a wave at a
+// time.  False, with the lane's search unchanged, when no slot or task room
+// is left.
+__device__ bool split_part(const SplitBufs &X, uint32_t r, uint32_t owner, int strand, int m, int maxd, int best,
                            LaneCtx &c, uint4 cur, bool valid, int &fl) {
     const uint32_t cnt = (valid ? 1u : 0u) + (c.sp - c.sbase);
     const bool had = (fl >> SH_SLOT_SHIFT) != 0;
@@ -1193,8 +1202,9 @@ __device__ bool split_part(const SplitBufs &X, const ReadOut &O, uint32_t r, int
         X.slot_nhit[s] = 0;
         X.slot_fail[s] = 0;
         X.slot_exp[s] = 0;
-        O.status[r] = ST_SPLIT_PEND;
-        O.n_rep[r] = s;
+        X.slot_owner[s] = owner;
+        X.slot_own[s] = 0;
+        X.slot_obest[s] = INF_SCORE;
         fl |= (int)((s + 1) << SH_SLOT_SHIFT);
     }
     if (!(fl & (SH_ROW0 << strand))) {
@@ -1205,23 +1215,33 @@ __device__ bool split_part(const SplitBufs &X, const ReadOut &O, uint32_t r, int
     return true;
 }
 
-// A read that cannot finish in the first pass goes to the second pass;
-// once split, through its slot, whose publication sends it there.
-__device__ __forceinline__ void give_up(const ReadOut &O, const SplitBufs &X, uint32_t r) {
-    if (X.budget && O.status[r] == ST_SPLIT_PEND)
-        atomicOr(&X.slot_fail[O.n_rep[r]], 1u);
-    else
-        send_to_second_pass(O, r);
+// The first pass's end of a split read (fl: its flag word, with the slot):
+// the owner's hits stay in its hit buffer -- a lane whose wave has reached
+// the endgame takes no further read -- and the slot records their number
+// and the best score, for the collection before the rounds.  A failed read
+// goes to the second pass through its slot.
+__device__ __forceinline__ void end_split_read(const SplitBufs &X, const LaneCtx &c, int fl) {
+    const uint32_t s = (uint32_t)(fl >> SH_SLOT_SHIFT) - 1;
+    if (fl & SH_FAIL) {
+        X.slot_fail[s] = 1;
+        return;
+    }
+    X.slot_own[s] = c.ncand;
+    X.slot_obest[s] = c.best;
+    if (X.count) X.slot_exp[s] += c.expand;
 }
 
-// The end of a read's first-pass search: published, or, once split, its
-// hits delivered to the slot.
-__device__ __forceinline__ void finish_read(LaneCtx &c, const Params &P, const ReadOut &O, const SplitBufs &X,
-                                            uint32_t r, uint8_t extra) {
-    if (X.budget && O.status[r] == ST_SPLIT_PEND)
-        flush_slot(X, P, O.n_rep[r], c);
-    else
-        publish(c, P, O, r, extra);
+// Before the rounds: each split read's first-pass hits join its slot's
+// list, and the slot's best score takes theirs.  One thread per slot.
+__global__ void k_split_collect(SplitBufs X) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= min(X.ctl[0], X.slot_cap) || X.slot_fail[s]) return;
+    const uint32_t n = X.slot_own[s];
+    const uint4 *src = X.lane_cand + (size_t)X.slot_owner[s] * FAST_CAND;
+    uint4 *dst = X.slot_hits + (size_t)s * SLOT_HITS;
+    for (uint32_t j = 0; j < n; j++) dst[j] = src[j];
+    X.slot_nhit[s] = n;
+    if (X.slot_obest[s] < X.slot_best[s]) X.slot_best[s] = X.slot_obest[s];
 }
 
 // After the rounds: each split read's hits, duplicates merged as a lane's
@@ -1470,7 +1490,6 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                             cur = root_state(ix, m, P.minc * pd_d(c, m - 1));
                             valid = true;
                             c.sp = c.sbase = 0;
-                            di = 0;  // during a search: the expansions at its start
                         }
 #else
                         stage_read(own_pd, rd.bases + o0, m);
@@ -1569,28 +1588,30 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                         c.cand = own_cand + ((int)ow - lane) * (ptrdiff_t)FAST_CAND;
                         c.best = sh_ld(&ws.best[ow]);
                         c.expand = 0;
-                        di = 0;
                         phase = PZ_HELP;
                     }
                 }
                 wave_fence();
             }
             // a part past the budget goes to the split searches, one lane
-            // of the wave at a time (a read's slot is taken once)
+            // of the wave at a time (a read's slot is taken once); a part's
+            // expansions count from the read's start for its owner and from
+            // the hand-over for a helper
             const uint32_t bud = A->X.budget;
             if (bud) {
-                const bool want = (phase == PZ_SEARCH || phase == PZ_HELP) && c.sp > c.sbase &&
-                                  c.expand - (uint32_t)di >= bud && !(sh_ld(&ws.flags[ow]) & SH_FAIL);
+                const bool want = (phase == PZ_SEARCH || phase == PZ_HELP) && c.sp > c.sbase && c.expand >= bud &&
+                                  !(sh_ld(&ws.flags[ow]) & (SH_FAIL | SH_NOSPLIT));
                 unsigned long long sm = __ballot(want);
                 while (sm) {
                     const int L = __ffsll(sm) - 1;
                     if (lane == L) {
                         int fl = sh_ld(&ws.flags[ow]);
-                        const uint32_t rr = ow == lane ? r : A->lane_read[gl - (uint32_t)lane + (uint32_t)ow];
-                        if (split_part(A->X, O, rr, strand, m, maxd, sh_ld(&ws.best[ow]), c, cur, valid, fl))
+                        const uint32_t og = gl - (uint32_t)lane + (uint32_t)ow;  // the owner's global lane
+                        const uint32_t rr = ow == lane ? r : A->lane_read[og];
+                        if (split_part(A->X, rr, og, strand, m, maxd, sh_ld(&ws.best[ow]), c, cur, valid, fl))
                             valid = false;  // the lane's part is over
                         else
-                            di = (int)c.expand;  // no room: try again after another budget
+                            fl |= SH_NOSPLIT;  // no room: the read's parts go on in the wave
                         sh_st(&ws.flags[ow], fl);
                     }
                     wave_fence();
@@ -1628,7 +1649,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 hit = true;
             } else if (rr < 0) {
                 // only without endgame, so the lane owns its read alone
-                give_up(O, A->X, r);
+                send_to_second_pass(O, r);
                 if (O.expand) O.expand[r] = c.expand;
                 phase = PZ_IDLE;
             } else if (rr == 0) {
@@ -1654,7 +1675,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                     if (record(c, P, make_hit(strand, KT_LOOP ? state_k(ix, strand, cur2) : cur2.x, cur2.y,
                                               s_len(cur2), score, s_nmm(cur2), s_ngo(cur2), s_nge(cur2)),
                                PH_FAST)) {
-                        give_up(O, A->X, r);
+                        send_to_second_pass(O, r);
                         if (O.expand) O.expand[r] = c.expand;
                         phase = PZ_IDLE;
                         act = ACT_NONE;
@@ -1745,7 +1766,10 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             const int fl = sh_ld(&ws.flags[lane]);
             if (fl & SH_FAIL) {
-                give_up(O, A->X, r);
+                if (fl >> SH_SLOT_SHIFT)
+                    end_split_read(A->X, c, fl);
+                else
+                    send_to_second_pass(O, r);
                 if (O.expand) O.expand[r] = c.expand + (uint32_t)sh_ld(&ws.hexp[lane]);
                 phase = PZ_IDLE;
             } else if (strand == 0 && (BWFM_GENE_DPREPASS == 0 || !(A->dflag[r] & 2))) {
@@ -1756,7 +1780,6 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 cur = root_state(ix, m, P.minc * pd_d(c, m - 1));
                 valid = true;
                 c.sp = c.sbase = 0;
-                di = (int)c.expand;
 #else
                 phase = PZ_DSCAN;
                 di = 0;
@@ -1771,7 +1794,10 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 if (sb < c.best) c.best = sb;
                 c.cand = own_cand;
                 c.expand += (uint32_t)sh_ld(&ws.hexp[lane]);
-                finish_read(c, P, O, A->X, r, (fl & SH_HELPED) ? (uint8_t)BWFM_ST_SHARED : (uint8_t)0);
+                if (fl >> SH_SLOT_SHIFT)
+                    end_split_read(A->X, c, fl);
+                else
+                    publish(c, P, O, r, (fl & SH_HELPED) ? (uint8_t)BWFM_ST_SHARED : (uint8_t)0);
                 phase = PZ_IDLE;
             }
         }
@@ -1837,7 +1863,6 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                     cur = root_state(ix, m, P.minc * dz);
                     valid = true;
                     c.sp = c.sbase = 0;
-                    di = (int)c.expand;  // during a search: the expansions at its start
                 } else if (strand == 0) {
                     strand = 1;
                     di = 0;
@@ -1853,7 +1878,10 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                     if (sb < c.best) c.best = sb;
                     c.expand += (uint32_t)sh_ld(&ws.hexp[lane]);
                     const int fl = sh_ld(&ws.flags[lane]);
-                    finish_read(c, P, O, A->X, r, (fl & SH_HELPED) ? (uint8_t)BWFM_ST_SHARED : (uint8_t)0);
+                    if (fl >> SH_SLOT_SHIFT)
+                        end_split_read(A->X, c, fl);
+                    else
+                        publish(c, P, O, r, (fl & SH_HELPED) ? (uint8_t)BWFM_ST_SHARED : (uint8_t)0);
                     phase = PZ_IDLE;
                 }
             }
@@ -1868,7 +1896,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                 if (endgame) {
                     atomicOr(&ws.flags[ow], SH_FAIL);  // every lane of the read drops out
                 } else {
-                    give_up(O, A->X, r);
+                    send_to_second_pass(O, r);
                     if (O.expand) O.expand[r] = c.expand;
                     phase = PZ_IDLE;
                 }
@@ -1884,7 +1912,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
             // worst case; the read then goes to the second pass
             if (expand_children(cur2, valid2, ok2, ol2, qd, b2, m, maxd, Di2, Dn2, S, P, c,
                                 KT_LOOP ? ix.kt_levels : 0)) {
-                give_up(O, A->X, r);
+                send_to_second_pass(O, r);
                 if (O.expand) O.expand[r] = c.expand;
                 phase = PZ_IDLE;
             }
@@ -2771,7 +2799,7 @@ inline SplitShape split_shape(uint32_t n, uint32_t mlen) {
 }
 inline size_t split_bytes(const SplitShape &z) {
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return 6 * al((size_t)z.slot_cap * 4) + al((size_t)z.slot_cap * 2 * z.dstride) +
+    return 9 * al((size_t)z.slot_cap * 4) + al((size_t)z.slot_cap * 2 * z.dstride) +
            al((size_t)z.slot_cap * SLOT_HITS * 16) + 2 * al((size_t)z.task_cap * 16) + 2 * al((size_t)z.task_cap * 4) +
            al(SPLIT_CTL * 4) + al(sizeof(TaskArgs)) + 256;
 }
@@ -2783,6 +2811,9 @@ inline SplitBufs carve_split(Carver &cv, const SplitShape &z, uint32_t budget, T
     X.slot_nhit = cv.take<uint32_t>(z.slot_cap);
     X.slot_fail = cv.take<uint32_t>(z.slot_cap);
     X.slot_exp = cv.take<uint32_t>(z.slot_cap);
+    X.slot_owner = cv.take<uint32_t>(z.slot_cap);
+    X.slot_own = cv.take<uint32_t>(z.slot_cap);
+    X.slot_obest = cv.take<int>(z.slot_cap);
     X.slot_rows = cv.take<uint8_t>((size_t)z.slot_cap * 2 * z.dstride);
     X.slot_hits = cv.take<uint4>((size_t)z.slot_cap * SLOT_HITS);
     for (int k = 0; k < 2; k++) {
@@ -2816,14 +2847,17 @@ uint32_t task_lanes(uint32_t n_up, uint32_t lanes) {
     return (uint32_t)std::max<uint64_t>(std::min(fit, want), BLOCK);
 }
 
-// After the first pass (split searches on): the task rounds on their own
-// grid of tlanes lanes, on the first pass's lane buffers (allocated for
-// both grids), the last round without a drain, then the publication of the
-// split reads.  Every launch reads its counts on the device, so the
+// After the first pass (split searches on): the collection of the split
+// reads' first-pass hits, the task rounds on their own grid of tlanes
+// lanes, on the first pass's lane buffers (allocated for both grids), the
+// last round without a drain, then the publication of the split reads.  Every launch reads its counts on the device, so the
 // sequence can be captured.
 template <int LW>
 void enqueue_split(const DevIndex &D, const Params &P, const SplitBufs &X, TaskArgs *targs, const LaneBufs &lb,
                    const ReadOut &O, uint32_t tlanes, hipStream_t st) {
+    SplitBufs Xc = X;
+    Xc.lane_cand = lb.cand;
+    k_split_collect<<<blocks(X.slot_cap, 256), 256, 0, st>>>(Xc);
     k_set_task_args<<<1, 64, 0, st>>>(targs, TaskArgs{lb, X});
     for (uint32_t g = 0; g < (uint32_t)SPLIT_ROUNDS; g++)
         k_align_tasks<LW><<<tlanes / BLOCK, BLOCK, 0, st>>>(D, P, targs, g, g + 1 < (uint32_t)SPLIT_ROUNDS ? 1u : 0u);
