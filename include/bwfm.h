@@ -325,11 +325,11 @@ int bwfm_align_batch(const bwfm_index *idx, const bwfm_reads *reads, const bwfm_
 /* As bwfm_align_batch, also writing each read's search work -- the number
  * of search states expanded (each expansion issues the two rank queries at
  * k and l + 1), summed over both passes -- to expand (device, n_reads).
- * work (device, 22 uint64, or NULL; batched form only) receives the first
+ * work (device, 14 uint64, or NULL; batched form only) receives the first
  * pass's loop iterations summed over waves, lane iterations spent on a read,
  * and lane iterations that issued a rank query, then the reads whose search
  * was split, the tasks handed out over all rounds, the split reads that went
- * on to the second pass, and for each of the sixteen task generations (the
+ * on to the second pass, and for each of the eight task generations (the
  * first pass's, then each round's but the last) the task entries asked for
  * (more than the room when some split found none). */
 int bwfm_align_batch_counted(const bwfm_index *idx, const bwfm_reads *reads, const bwfm_aln_params *p,

@@ -427,7 +427,7 @@ def align_batch(index: Index, bases, offsets, params: Params, max_diff=None, max
     if counted and out.expand is None:
         out.expand = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     if counted and getattr(out, "work", None) is None:
-        out.work = torch.zeros(22, dtype=torch.int64, device=dev)
+        out.work = torch.zeros(14, dtype=torch.int64, device=dev)
     pc = params._c()
     for attempt in range(2):
         res = out._c()

@@ -1067,7 +1067,7 @@ __device__ __forceinline__ int check_read(const ReadsView &rd, const Params &P, 
 // do not depend on how the tree was cut: each part prunes with a bound that
 // is never below the final one, so every hit within the final bound is
 // found by the part that holds it.
-constexpr int SPLIT_ROUNDS = 16;              // task rounds; the last one runs every task to its end
+constexpr int SPLIT_ROUNDS = 8;               // task rounds; the last one runs every task to its end
 constexpr uint32_t TASK_EMPTY = 0xffffffffu;  // a reserved task entry left unused
 // hits a slot collects: those of the read's first-pass lane (at most
 // FAST_CAND), then at most as many again from its tasks

@@ -305,7 +305,7 @@ def test_c5_shape_stress_parity(form, wps, fmt, split):
         # the second pass's status instead)
         assert int(work[3]) == n_split + int(work[5]) and int(work[4]) > 0
         print(f"[c5-split {split}] {n_split} split reads, {int(work[4])} tasks, {int(work[5])} to the second pass, "
-              f"per generation {work[6:22].tolist()}", flush=True)
+              f"per generation {work[6:14].tolist()}", flush=True)
     elif form == bw.FORM_BATCHED:
         assert int((st & bw.ST_SHARED).astype(bool).sum()) > 0, "no search tree was shared"
         assert not (st & bw.ST_SPLIT).any()
