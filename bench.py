@@ -299,10 +299,35 @@ def main_se(args):
     # on the stress batch that makes a launch over all 2M reads run for
     # minutes, so it is timed on a leading part of the batch there
     n_plain = n if cfg == "C1" else min(args.plain_reads, n)
+    # the batched form's split budget: the one given, or on the stress batch
+    # the faster of the library's default and a smaller one, each candidate's
+    # output byte-identical to the first's (a tuning knob like the layout)
+    split_tune = None
+    split = args.split_budget
+    if split is None:
+        split = 0
+        if cfg == "C5":
+            split_tune, ref = [], None
+            for cand in (0, 4096):
+                p = bw.Params(**configs.PARAMS[cfg], split_budget=cand)
+                r = bw.align_batch(ix, b, o, p, max_len=max_len, hit_capacity=16 * n)
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                r = bw.align_batch(ix, b, o, p, max_len=max_len, out=r)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - ts) * 1e3
+                st = r.status.cpu().numpy()
+                d = [x.tobytes() for x in r.to_numpy()[:4]] + [(st & 7).tobytes()]
+                if ref is not None and d != ref:
+                    raise SystemExit(f"split budget {cand} changes the output")
+                ref = ref or d
+                split_tune.append({"split_budget": cand, "ms": ms})
+                log(f"{cfg}: split budget {cand or 'default'}: {ms:.1f} ms")
+            split = min(split_tune, key=lambda x: x["ms"])["split_budget"]
     out = {}
     res = {}
     for name, form in (("plain", bw.FORM_PLAIN), ("batched", bw.FORM_BATCHED)):
-        p = bw.Params(**configs.PARAMS[cfg], form=form)
+        p = bw.Params(**configs.PARAMS[cfg], form=form, split_budget=split if form == bw.FORM_BATCHED else 0)
         nn = n_plain if form == bw.FORM_PLAIN else n
         b_, o_ = (b, o) if nn == n else (b[:int(reads.offsets[nn])], o[:nn + 1])
         ts = time.perf_counter()
@@ -392,7 +417,8 @@ def main_se(args):
                                 f"C5 stress: 100 Mbp synthetic genome, {n} single-end 250 bp reads, 3% substitutions, "
                                 "0.3% indel events, 10% from repeats, <=6 diffs with a gap, no seed"),
                    "reads": n, "form": best, "line_bytes": lay["line_bytes"], "rank_format": lay["rank_format"],
-                   "parallelism": "1 GPU"},
+                   "split_budget": split or "default (16384)", "parallelism": "1 GPU"},
+        "split_tune": split_tune,
         "plain": out["plain"], "batched": out["batched"], "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -524,6 +550,8 @@ def main():
     ap.add_argument("--steps-plain", type=int, default=0, help="steps for the plain form (default: --steps)")
     ap.add_argument("--cpu-reads", type=int, default=20000, help="C5: reads in the oracle's timed sample")
     ap.add_argument("--plain-reads", type=int, default=4000, help="C5: reads the plain form is timed on")
+    ap.add_argument("--split-budget", type=int, default=None,
+                    help="C1/C5: the batched form's split budget (default: the library's; tuned on C5)")
     ap.add_argument("--config", choices=("c2", "c3", "c1", "c5"), default="c2",
                     help="c2: the benchmark workload (default); c3: the 3.1 Gbp uneven-length workload; "
                          "c1, c5: the single-end tiny and stress workloads at their stated sizes")

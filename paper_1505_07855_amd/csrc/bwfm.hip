@@ -1973,6 +1973,7 @@ __global__ void k_set_task_args(TaskArgs *dst, TaskArgs a) {
 // them over the grid; the last round has no drain.  At a task's end its
 // hits go to the slot.
 constexpr uint32_t DRAIN_MIN = 256;
+constexpr int TASK_REFILL = 32;  // idle lanes of a wave that make it take new tasks
 template <int LW>
 __global__ __launch_bounds__(BLOCK) void k_align_tasks(DevIndex ix, Params P, const TaskArgs *A, uint32_t g,
                                                        uint32_t drain) {
@@ -2003,9 +2004,15 @@ __global__ __launch_bounds__(BLOCK) void k_align_tasks(DevIndex ix, Params P, co
             const int sb = (int)ld_agent(reinterpret_cast<const uint32_t *>(&X.slot_best[s]));
             if (sb < c.best) c.best = sb;
         }
-        // idle lanes take the next tasks, one atomic per wave
-        const bool want = !busy && !exhausted;
-        const unsigned long long wm = __ballot(want);
+        // idle lanes take the next tasks, one atomic per wave, once
+        // TASK_REFILL lanes of the wave are idle (or none is busy): tasks
+        // end every few hundred expansions, and one counter taken by every
+        // wave at that rate held the rounds to half their speed
+        const bool idle = !busy && !exhausted;
+        const unsigned long long im = __ballot(idle);
+        const bool bulk = __popcll(im) >= TASK_REFILL || __ballot(busy) == 0;
+        const bool want = idle && bulk;
+        const unsigned long long wm = bulk ? im : 0ull;
         uint32_t t = 0;
         if (wm) {
             const int leader = __ffsll(wm) - 1;
