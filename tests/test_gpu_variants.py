@@ -3,7 +3,8 @@
 the package build with alternative implementations of the row masks, the
 paired rank query, the refill of idle lanes and the sub-counted header
 loads, each loaded in a process of its own and compared with the oracle on
-both rank-line layouts, both forms, locate and pairing."""
+both rank-line layouts, both forms (the batched one also with split
+searches), locate and pairing."""
 from __future__ import annotations
 
 import os

@@ -2,8 +2,9 @@
 named on the command line in place of the shipped one and check it against
 the oracle on a small paired-end batch -- both rank-line layouts the
 variants touch (64-byte planar, 128-byte sub-counted), without and with a
-short-string table, the batched and the plain form, then locate and
-pairing.  Prints "variant ok" on success."""
+short-string table, the batched form (also with nearly every read's search
+split into task rounds) and the plain form, then locate and pairing.
+Prints "variant ok" on success."""
 from __future__ import annotations
 
 import os
@@ -38,9 +39,13 @@ def main(lib: str) -> None:
     for lb, fmt, levels in ((64, bw.RANK_PLANES, 0), (128, bw.RANK_SUB128, 0), (128, bw.RANK_SUB128, 6),
                             (64, bw.RANK_PLANES, 9)):
         ix = bw.Index(g.seq, line_bytes=lb, sa_sample=32, rank_format=fmt).upload(kmer_levels=levels)
-        for form in (bw.FORM_BATCHED, bw.FORM_PLAIN):
-            p = bw.Params(**configs.PARAMS["C2"], form=form)
+        # the batched form at the default split budget and at one so small
+        # that nearly every read's search is split into task rounds
+        for form, split in ((bw.FORM_BATCHED, 0), (bw.FORM_BATCHED, 32), (bw.FORM_PLAIN, 0)):
+            p = bw.Params(**configs.PARAMS["C2"], form=form, split_budget=split)
             res = [bw.align_batch(ix, b, o, p, max_len=100) for b, o in ends]
+            if split:
+                assert any((r.status.cpu().numpy() & bw.ST_SPLIT).any() for r in res), "no search was split"
             for r, orr in zip(res, ores):
                 ho, hits, c1, c2, st = r.to_numpy()
                 assert np.array_equal(ho, orr.hit_off), (lb, form)
