@@ -65,6 +65,10 @@ def c1_small():
 
 
 FORMS = [bw.FORM_BATCHED, bw.FORM_PLAIN]
+# the forms, and the batched one with a split budget so small that nearly
+# every read's search is split into task rounds
+FORMS_SPLIT = [(bw.FORM_BATCHED, 0), (bw.FORM_BATCHED, 32), (bw.FORM_PLAIN, 0)]
+FORMS_SPLIT_IDS = ["batched", "batched-split32", "plain"]
 
 
 @pytest.mark.parametrize("form", FORMS)
@@ -185,8 +189,8 @@ def test_both_ends_in_one_batch(c2_small):
     assert np.array_equal(gp.view(np.uint8), opr.view(np.uint8))
 
 
-@pytest.mark.parametrize("form", FORMS)
-def test_second_pass_and_overflow_parity(form):
+@pytest.mark.parametrize("form,split", FORMS_SPLIT, ids=FORMS_SPLIT_IDS)
+def test_second_pass_and_overflow_parity(form, split):
     # a repeat-rich genome and ALL mode: many reads exceed the first pass's
     # hit slots (or, in the plain form, its stack) and are searched again
     g = gen.genome_repeats(91, 400_000, gc=0.41, repeat_frac=0.7, n_fam=5, min_len=300, max_len=800, div_lo=0.0,
@@ -199,18 +203,21 @@ def test_second_pass_and_overflow_parity(form):
                dict(max_diff=3, max_gapo=1, mode=bw.MODE_BEST, max_hits=5),
                dict(max_diff=2, max_gapo=0, mode=bw.MODE_ALL, max_hits=1000)):
         p, op = _params_pair(form=form, **kw)
+        p.split_budget = split
         res = _gpu_align(ix, reads, p)
         ores = oracle.align(ox, reads.bases, reads.offsets, op, threads=8)
         _compare_align(res, ores)
         st = res.status.cpu().numpy()
+        if split:
+            assert (st & bw.ST_SPLIT).any() or (st & bw.ST_RESEARCH).any()
         researched += int((st & bw.ST_RESEARCH).astype(bool).sum())
         overflowed += int((st & bw.ST_OVERFLOW).astype(bool).sum())
     assert researched > 0, "the second pass was not exercised"
     assert overflowed > 0, "the max_hits rule was not exercised"
 
 
-@pytest.mark.parametrize("form", FORMS)
-def test_edge_cases_parity(form):
+@pytest.mark.parametrize("form,split", FORMS_SPLIT, ids=FORMS_SPLIT_IDS)
+def test_edge_cases_parity(form, split):
     g = configs.c2_genome(300_000, seed=5)
     ox = oracle.Index(g.seq)
     ix = bw.Index(g.seq).upload()
@@ -232,6 +239,7 @@ def test_edge_cases_parity(form):
     reads = gen.Reads(bases, offs)
     md = np.array([4, 2, 6, 4, 0, 4, 5, 15], np.uint8)
     p, op = _params_pair(form=form, **configs.PARAMS["C2"])
+    p.split_budget = split
     res = _gpu_align(ix, reads, p, max_diff=md)
     ores = oracle.align(ox, reads.bases, reads.offsets, op, max_diff=md, threads=1)
     _compare_align(res, ores)
@@ -249,13 +257,14 @@ def test_edge_cases_parity(form):
     assert res3.n_hits == 0
 
 
-@pytest.mark.parametrize("form", FORMS)
-def test_c3_shape_per_read_budgets_parity(form):
+@pytest.mark.parametrize("form,split", FORMS_SPLIT, ids=FORMS_SPLIT_IDS)
+def test_c3_shape_per_read_budgets_parity(form, split):
     g = configs.c2_genome(1_000_000, seed=33)
     pairs = configs.c3_pairs(g, 1500, seed=34)
     ox = oracle.Index(g.seq)
     ix = bw.Index(g.seq).upload()
     p, op = _params_pair(form=form, **configs.PARAMS["C3"])
+    p.split_budget = split
     for end in (pairs.end1, pairs.end2):
         L = np.diff(end.offsets).astype(int)
         md_lib = np.array([bw.max_diff_rule(int(x)) for x in L], np.uint8)
@@ -264,6 +273,8 @@ def test_c3_shape_per_read_budgets_parity(form):
         res = _gpu_align(ix, end, p, max_diff=md_lib)
         ores = oracle.align(ox, end.bases, end.offsets, op, max_diff=md_orc, threads=8)
         _compare_align(res, ores)
+        if split:
+            assert (res.status.cpu().numpy() & bw.ST_SPLIT).any(), "no search was split"
 
 
 @pytest.mark.parametrize("form,wps,fmt,split", [(bw.FORM_BATCHED, 0, bw.RANK_PLANES, 4096),
