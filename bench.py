@@ -300,15 +300,16 @@ def main_se(args):
     # minutes, so it is timed on a leading part of the batch there
     n_plain = n if cfg == "C1" else min(args.plain_reads, n)
     # the batched form's split budget: the one given, or on the stress batch
-    # the faster of the library's default and a smaller one, each candidate's
-    # output byte-identical to the first's (a tuning knob like the layout)
+    # the fastest of the library's default and two smaller ones, each
+    # candidate's output byte-identical to the first's (a tuning knob like
+    # the layout)
     split_tune = None
     split = args.split_budget
     if split is None:
         split = 0
         if cfg == "C5":
             split_tune, ref = [], None
-            for cand in (0, 4096):
+            for cand in (0, 4096, 1024):
                 p = bw.Params(**configs.PARAMS[cfg], split_budget=cand)
                 r = bw.align_batch(ix, b, o, p, max_len=max_len, hit_capacity=16 * n)
                 torch.cuda.synchronize()
