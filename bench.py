@@ -355,10 +355,13 @@ def main_se(args):
             if cfg != "C1":
                 log(f"{cfg} {name}: step {i + 1}/{args.steps} {times[-1] * 1e3:.1f} ms")
         bw.timing_enable(False)
-        # the batched form's search: the first pass, the split searches'
-        # rounds and their publication
+        # the batched form's search: the D-array pre-pass (long reads), the
+        # first pass, the split searches' rounds and their publication
         key = "align_plain" if form == bw.FORM_PLAIN else "align_search"
         kms, kl = bw.timing_get(key)
+        if form == bw.FORM_BATCHED:
+            dms, dl = bw.timing_get("dscan")
+            kms += dms if dl == kl else 0.0
         st = r.status.cpu().numpy()
         aligned = int(((st & bw.ST_HIT) != 0).sum())
         ms = float(np.mean(times) * 1e3)
@@ -404,7 +407,9 @@ def main_se(args):
             achieved = bytes_per_read * n / (kms / 1e3) / 1e9
             roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "k_align_plain" if best == "plain" else "k_align_persistent + k_align_tasks",
+                        "kernel": ("k_align_plain" if best == "plain" else
+                                   "k_dscan + k_align_persistent + k_align_tasks" if max_len >= 200 else
+                                   "k_align_persistent + k_align_tasks"),
                         "bytes_per_read": bytes_per_read, "reads_per_launch": n, "avg_launch_ms": kms,
                         "note": "index resident in the Infinity Cache at this size; algorithmic bytes per step "
                                 "over the search's HIP-event time, against HBM's peak"}

@@ -87,12 +87,17 @@ constexpr uint32_t PLAIN_STACK = 320;  // stack entries per lane, plain form fir
 #define BWFM_GENE_SUBHDR 0
 #endif
 //   DPREPASS: the batched form scans each read's D-arrays inside the
-//             persistent loop, one rank query per iteration (0), or in a
-//             pre-pass kernel of its own, one lane per read, so the loop
-//             only searches (1).
+//             persistent loop, one rank query per iteration, unless its
+//             reads may be DPRE_MIN_LEN bases or longer (0), or always (1)
+//             in a pre-pass kernel of its own, one lane per read, so the
+//             loop only searches.
 #ifndef BWFM_GENE_DPREPASS
 #define BWFM_GENE_DPREPASS 0
 #endif
+// Batches whose max_len reaches this scan their D-arrays in the pre-pass:
+// on 250 bp reads the pre-pass and a loop that only searches take 5-6% less
+// time than the loop's own scans, on 100 bp reads 7% more.
+constexpr uint32_t DPRE_MIN_LEN = 200;
 //   TWOSTATE: a searching lane expands one state per iteration (0), or two
 //             (1): besides its current state it keeps a second one, taken
 //             from the top of its stack, whose rank query is issued with
@@ -1406,7 +1411,9 @@ __global__ void k_set_args(PersistentArgs *dst, PersistentArgs a) {
     if (threadIdx.x == 0) *dst = a;
 }
 
-template <int LW>
+// DP: the D-arrays come from the pre-pass (k_dscan); otherwise the loop
+// scans them itself.
+template <int LW, bool DP>
 __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params &P, const PersistentArgs *A) {
     const uint32_t gl = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -1476,31 +1483,31 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                         c.ncand = 0;
                         c.best = INF_SCORE;
                         c.expand = 0;
-#if BWFM_GENE_DPREPASS == 1
-                        // the first strand the pre-pass left searchable, or
-                        // nothing to search
-                        const int dfl = A->dflag[r];
-                        strand = (dfl & 1) ? 1 : 0;
-                        if ((dfl & 3) == 3) {
-                            publish(c, P, O, r);
-                            phase = PZ_IDLE;
+                        if (DP) {
+                            // the first strand the pre-pass left searchable,
+                            // or nothing to search
+                            const int dfl = A->dflag[r];
+                            strand = (dfl & 1) ? 1 : 0;
+                            if ((dfl & 3) == 3) {
+                                publish(c, P, O, r);
+                                phase = PZ_IDLE;
+                            } else {
+                                load_drow(own_pd, drow_of(A->drows, A->dstride, r, strand), m);
+                                phase = PZ_SEARCH;
+                                cur = root_state(ix, m, P.minc * pd_d(c, m - 1));
+                                valid = true;
+                                c.sp = c.sbase = 0;
+                            }
                         } else {
-                            load_drow(own_pd, drow_of(A->drows, A->dstride, r, strand), m);
-                            phase = PZ_SEARCH;
-                            cur = root_state(ix, m, P.minc * pd_d(c, m - 1));
-                            valid = true;
-                            c.sp = c.sbase = 0;
+                            stage_read(own_pd, rd.bases + o0, m);
+                            strand = 0;
+                            phase = PZ_DSCAN;
+                            di = 0;
+                            dz = 0;
+                            dk = 0;
+                            dl = ix.n;
+                            dcode = dlen = 0;
                         }
-#else
-                        stage_read(own_pd, rd.bases + o0, m);
-                        strand = 0;
-                        phase = PZ_DSCAN;
-                        di = 0;
-                        dz = 0;
-                        dk = 0;
-                        dl = ix.n;
-                        dcode = dlen = 0;
-#endif
                         S = seed_of(P, m);
                         sh_st(&ws.best[lane], INF_SCORE);
                         sh_st(&ws.ncand[lane], 0);
@@ -1629,7 +1636,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
         uint32_t q1 = 0, q2 = 0;
         int da = 4;
         bool part_done = false;  // this lane's part of the strand's search is over
-        if (BWFM_GENE_DPREPASS == 0 && phase == PZ_DSCAN) {
+        if (!DP && phase == PZ_DSCAN) {
             act = ACT_DSTEP;
             {
                 const int b = own_pd[di] & 7;  // the staged base (strand +)
@@ -1772,22 +1779,22 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
                     send_to_second_pass(O, r);
                 if (O.expand) O.expand[r] = c.expand + (uint32_t)sh_ld(&ws.hexp[lane]);
                 phase = PZ_IDLE;
-            } else if (strand == 0 && (BWFM_GENE_DPREPASS == 0 || !(A->dflag[r] & 2))) {
+            } else if (strand == 0 && (!DP || !(A->dflag[r] & 2))) {
                 strand = 1;
-#if BWFM_GENE_DPREPASS == 1
-                load_drow(own_pd, drow_of(A->drows, A->dstride, r, 1), m);
-                phase = PZ_SEARCH;
-                cur = root_state(ix, m, P.minc * pd_d(c, m - 1));
-                valid = true;
-                c.sp = c.sbase = 0;
-#else
-                phase = PZ_DSCAN;
-                di = 0;
-                dz = 0;
-                dk = 0;
-                dl = ix.n;
-                dcode = dlen = 0;
-#endif
+                if (DP) {
+                    load_drow(own_pd, drow_of(A->drows, A->dstride, r, 1), m);
+                    phase = PZ_SEARCH;
+                    cur = root_state(ix, m, P.minc * pd_d(c, m - 1));
+                    valid = true;
+                    c.sp = c.sbase = 0;
+                } else {
+                    phase = PZ_DSCAN;
+                    di = 0;
+                    dz = 0;
+                    dk = 0;
+                    dl = ix.n;
+                    dcode = dlen = 0;
+                }
             } else {
                 c.ncand = (uint32_t)sh_ld(&ws.ncand[lane]);
                 const int sb = sh_ld(&ws.best[lane]);
@@ -1833,7 +1840,7 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
 #endif
 
         // consume
-        if (BWFM_GENE_DPREPASS == 0 && act == ACT_DSTEP) {
+        if (!DP && act == ACT_DSTEP) {
             bool empty = true;
             if (da < 4) {
                 const uint32_t a1 = sel4(ok, da), a2 = sel4(ol, da);
@@ -1932,21 +1939,24 @@ __device__ __forceinline__ void persistent_body(const DevIndex &ix, const Params
 // waves stay resident per SIMD.  The search is latency-bound, so the second
 // is faster on the benchmark batch (122 ms against 134); a build held to 96
 // VGPRs spills to scratch and is slower still (205 ms).  The autotuner picks.
-template <int LW>
+template <int LW, bool DP = false>
 __global__ __launch_bounds__(BLOCK) void k_align_persistent(DevIndex ix, Params P, const PersistentArgs *A) {
-    persistent_body<LW>(ix, P, A);
+    persistent_body<LW, DP>(ix, P, A);
 }
-template <int LW>
+template <int LW, bool DP = false>
 __global__ __launch_bounds__(BLOCK, 4) void k_align_persistent4(DevIndex ix, Params P, const PersistentArgs *A) {
-    persistent_body<LW>(ix, P, A);
+    persistent_body<LW, DP>(ix, P, A);
 }
 
 using PersistentKernel = void (*)(DevIndex, Params, const PersistentArgs *);
 
 // the build serving a waves_per_simd setting: 0 and >= 4 take the 4-wave
-// build, 1-3 the compiler's own
+// build, 1-3 the compiler's own; dp: D-arrays from the pre-pass
 template <int LW>
-PersistentKernel persistent_kernel(int waves_per_simd) {
+PersistentKernel persistent_kernel(int waves_per_simd, bool dp = false) {
+    if (dp)
+        return (waves_per_simd == 0 || waves_per_simd >= 4) ? k_align_persistent4<LW, true>
+                                                              : k_align_persistent<LW, true>;
     return (waves_per_simd == 0 || waves_per_simd >= 4) ? k_align_persistent4<LW> : k_align_persistent<LW>;
 }
 
@@ -2749,12 +2759,12 @@ size_t scan_part_elems(uint64_t n) { return (n + SCAN_BLOCK - 1) / SCAN_BLOCK + 
 // size and its dynamic LDS, at most waves_per_simd waves per SIMD (0 = no
 // cap; a CU has 4 SIMDs).
 template <int LW>
-uint32_t persistent_lanes(uint32_t bs, size_t lds, int waves_per_simd) {
+uint32_t persistent_lanes(uint32_t bs, size_t lds, int waves_per_simd, bool dp = false) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<LW>(waves_per_simd), (int)bs, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<LW>(waves_per_simd, dp), (int)bs, lds) !=
             hipSuccess ||
         per_cu < 1)
         per_cu = 1;
@@ -2883,10 +2893,13 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
     const uint32_t lstride = lds_stride_for(mlen);
     const bool plain = p->form == BWFM_FORM_PLAIN;
     const uint32_t sbud = plain ? 0u : split_budget_of(*p);  // split searches (batched form)
+    // the D-array pre-pass (batched form, long reads or when that gene is on)
+    const bool dpre = !plain && (BWFM_GENE_DPREPASS == 1 || mlen >= DPRE_MIN_LEN);
     const uint32_t bs = block_for(lstride);
     const size_t lds = (size_t)bs * lstride + (plain ? 0 : (bs / 64) * sizeof(WaveShare));
     const uint32_t nr_up = ((std::max<uint32_t>(n, 1) + bs - 1) / bs) * bs;
-    const uint32_t lanes = plain ? nr_up : std::min<uint32_t>(persistent_lanes<LW>(bs, lds, p->waves_per_simd), nr_up);
+    const uint32_t lanes =
+        plain ? nr_up : std::min<uint32_t>(persistent_lanes<LW>(bs, lds, p->waves_per_simd, dpre), nr_up);
     const uint32_t stack_cap = plain ? std::min<uint32_t>(worst_stack, PLAIN_STACK) : worst_stack;
     // the task rounds' grid shares the lane buffers: room for the larger one
     const uint32_t tlanes = sbud ? task_lanes<LW>(nr_up, lanes) : 0u;
@@ -2900,8 +2913,7 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
     need += (size_t)slow_lanes * worst_stack * 16 + (size_t)slow_lanes * scap * 16;
     need += (size_t)n * 4 * 2 + (size_t)n * 8 + stage_cap * 16 + scan_part_elems(n) * 8 + 16 * 256;
     need += sizeof(PersistentArgs) + 256;
-    // the D-array pre-pass's rows (batched form, when that gene is on)
-    const bool dpre = BWFM_GENE_DPREPASS == 1 && !plain;
+    // the D-array pre-pass's rows
     const uint32_t dstride = ((mlen + 15) / 16) * 16;
     if (dpre) need += (size_t)n * 2 * dstride + n + 2 * 256;
     const SplitShape zs = split_shape(n, mlen);
@@ -2954,7 +2966,7 @@ int align_impl(bwfm_index *ix, bwfm::Workspace &ws, const bwfm_reads *rd, const 
             k_set_args<<<1, 64, 0, st>>>(pargs, PersistentArgs{rv, lb, O, next_read, drows, dflag, dstride, X, lane_read});
             int ts = tm.begin("align_search");
             int t = tm.begin("align_persistent");
-            hipLaunchKernelGGL(persistent_kernel<LW>(p->waves_per_simd), dim3(lanes / bs), dim3(bs), lds, st, D, P,
+            hipLaunchKernelGGL(persistent_kernel<LW>(p->waves_per_simd, dpre), dim3(lanes / bs), dim3(bs), lds, st, D, P,
                                (const PersistentArgs *)pargs);
             tm.end(t);
             if (sbud) {
@@ -3624,7 +3636,8 @@ int pipe_enqueue(bwfm_pipeline *pl, hipStream_t st, bool timed, bool capture) {
     if (plain)
         k_align_plain<LW><<<pl->lanes / pl->bs, pl->bs, pl->lds, st>>>(D, rv, P, lb, O);
     else
-        hipLaunchKernelGGL(persistent_kernel<LW>(pl->ap.waves_per_simd), dim3(pl->lanes / pl->bs), dim3(pl->bs),
+        hipLaunchKernelGGL(persistent_kernel<LW>(pl->ap.waves_per_simd, pl->drows != nullptr), dim3(pl->lanes / pl->bs),
+                           dim3(pl->bs),
                            pl->lds, st, D, P, (const PersistentArgs *)pl->pargs);
     if (timed) HIPCHK(mark(pl->ev[1]));
     if (pl->X.budget) enqueue_split<LW>(D, P, pl->X, pl->targs, lb, O, pl->tlanes, st);
@@ -3700,6 +3713,7 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
     pl->lstride = lds_stride_for(mlen);
     const bool plain = ap->form == BWFM_FORM_PLAIN;
     const uint32_t sbud = plain ? 0u : split_budget_of(*ap);
+    const bool dpre = !plain && (BWFM_GENE_DPREPASS == 1 || mlen >= DPRE_MIN_LEN);
     pl->bs = block_for(pl->lstride);
     pl->lds = (size_t)pl->bs * pl->lstride + (plain ? 0 : (pl->bs / 64) * sizeof(WaveShare));
     const uint32_t nr_up = ((nmax + pl->bs - 1) / pl->bs) * pl->bs;
@@ -3707,7 +3721,7 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
                       : std::min<uint32_t>(by_layout(ix,
                                                      [&](auto lw) {
                                                          return persistent_lanes<decltype(lw)::value>(
-                                                             pl->bs, pl->lds, ap->waves_per_simd);
+                                                             pl->bs, pl->lds, ap->waves_per_simd, dpre);
                                                      }),
                                            nr_up);
     pl->stack_cap = plain ? std::min<uint32_t>(pl->worst_stack, PLAIN_STACK) : pl->worst_stack;
@@ -3728,7 +3742,6 @@ extern "C" int bwfm_pipeline_create(const bwfm_index *cix, const bwfm_aln_params
     add(hcap * 4); add(hcap * 4); add((hcap + 1) * 8); add(pcap * 4); add((size_t)q->max_pairs * sizeof(bwfm_pair));
     add(PC_WORDS * 8);
     add(sizeof(PersistentArgs));
-    const bool dpre = BWFM_GENE_DPREPASS == 1 && !plain;
     pl->dstride = ((mlen + 15) / 16) * 16;
     if (dpre) {
         add((size_t)nmax * 2 * pl->dstride);
