@@ -73,11 +73,12 @@ def kernel_source_hash(kernel: str = "k_align_persistent") -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str, workload: str = "c2"):
+def traffic_from_profiles(kernel: str, workload: str = "c2", **match):
     """HBM-side bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same
     counter reads for a device copy of known size), or None when the summary
-    was taken on other kernel sources."""
+    was taken on other kernel sources or with other settings (`match`: keys
+    of the summary's record that must hold these values)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_bytes.md")
     if not os.path.exists(path):
         return None
@@ -87,6 +88,8 @@ def traffic_from_profiles(kernel: str, workload: str = "c2"):
             if line.startswith("bench-traffic:"):
                 rec = dict(kv.split("=", 1) for kv in line.split()[1:])
     if not rec or rec.get("kernel") != kernel or rec.get("source") != kernel_source_hash(kernel):
+        return None
+    if any(rec.get(k) != str(v) for k, v in match.items()):
         return None
     cb = float(rec["copy_bytes"])
     fetch = float(rec["fetch_kib"]) * 1024 * cb / (float(rec["copy_fetch_kib"]) * 1024)
@@ -413,6 +416,16 @@ def main_se(args):
                         "bytes_per_read": bytes_per_read, "reads_per_launch": n, "avg_launch_ms": kms,
                         "note": "index resident in the Infinity Cache at this size; algorithmic bytes per step "
                                 "over the search's HIP-event time, against HBM's peak"}
+            if best == "batched" and cfg == "C5":
+                # counter-measured bytes of the same kernels at the same split
+                # budget (the budget moves work between the first pass and the
+                # rounds), summed over one step's launches
+                traffic = traffic_from_profiles("k_align_persistent", "c5", split=split)
+                roofline["traffic"] = traffic
+                if traffic:
+                    rate = traffic / (kms / 1e3) / 1e9
+                    roofline["traffic_rate"] = rate
+                    roofline["traffic_frac"] = rate / HBM_PEAK_GBS
     ms_step = out[best]["ms_per_step"]
     line = {
         "metric": f"aligned reads/s ({cfg} single-end) on 1 MI355X", "value": out[best]["aligned_reads_per_s"],
