@@ -77,19 +77,23 @@ def traffic_from_profiles(kernel: str, workload: str = "c2", **match):
     """HBM-side bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same
     counter reads for a device copy of known size), or None when the summary
-    was taken on other kernel sources or with other settings (`match`: keys
-    of the summary's record that must hold these values)."""
+    was taken on other kernel sources or with other settings.  A summary may
+    hold several records (one per setting); the first whose kernel, sources
+    and `match` keys all agree is used."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_bytes.md")
     if not os.path.exists(path):
         return None
     rec = None
     with open(path) as fh:
         for line in fh:
-            if line.startswith("bench-traffic:"):
-                rec = dict(kv.split("=", 1) for kv in line.split()[1:])
-    if not rec or rec.get("kernel") != kernel or rec.get("source") != kernel_source_hash(kernel):
-        return None
-    if any(rec.get(k) != str(v) for k, v in match.items()):
+            if not line.startswith("bench-traffic:"):
+                continue
+            r = dict(kv.split("=", 1) for kv in line.split()[1:])
+            if (r.get("kernel") == kernel and r.get("source") == kernel_source_hash(kernel)
+                    and all(r.get(k) == str(v) for k, v in match.items())):
+                rec = r
+                break
+    if rec is None:
         return None
     cb = float(rec["copy_bytes"])
     fetch = float(rec["fetch_kib"]) * 1024 * cb / (float(rec["copy_fetch_kib"]) * 1024)
@@ -303,7 +307,7 @@ def main_se(args):
     # minutes, so it is timed on a leading part of the batch there
     n_plain = n if cfg == "C1" else min(args.plain_reads, n)
     # the batched form's split budget: the one given, or on the stress batch
-    # the fastest of the library's default and two smaller ones, each
+    # the fastest of the library's default and three smaller ones, each
     # candidate's output byte-identical to the first's (a tuning knob like
     # the layout)
     split_tune = None
@@ -312,7 +316,7 @@ def main_se(args):
         split = 0
         if cfg == "C5":
             split_tune, ref = [], None
-            for cand in (0, 4096, 1024):
+            for cand in (0, 4096, 1024, 512):
                 p = bw.Params(**configs.PARAMS[cfg], split_budget=cand)
                 r = bw.align_batch(ix, b, o, p, max_len=max_len, hit_capacity=16 * n)
                 torch.cuda.synchronize()

@@ -1059,6 +1059,20 @@ __device__ __forceinline__ int check_read(const ReadsView &rd, const Params &P, 
     return 0;
 }
 
+// Copy n dwords, the loads of eight issued before their stores: through
+// generic pointers the compiler must assume a store may alias the next
+// load, so a plain loop waits one memory round trip per dword.
+__device__ __forceinline__ void copy_dwords(uint32_t *dst, const uint32_t *src, int n) {
+    for (int k0 = 0; k0 < n; k0 += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) v[j] = k0 + j < n ? src[k0 + j] : 0u;
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+            if (k0 + j < n) dst[k0 + j] = v[j];
+    }
+}
+
 // ------------------------------------------------------------------ split searches
 
 // Batched form: a read whose search outgrows a budget of expansions is
@@ -1140,9 +1154,8 @@ __device__ void put_tasks(const SplitBufs &X, uint32_t g, uint32_t off, uint32_t
 // Copy an m-byte pattern and D-array row from the lane's LDS row to the
 // slot: whole dwords, within both rows.
 __device__ __forceinline__ void save_row(const SplitBufs &X, uint32_t s, int strand, const uint8_t *pd, int m) {
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(pd);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(X.slot_rows + ((size_t)s * 2 + (size_t)strand) * X.dstride);
-    for (int k = 0; k < (m + 3) / 4; k++) dst[k] = src[k];
+    copy_dwords(reinterpret_cast<uint32_t *>(X.slot_rows + ((size_t)s * 2 + (size_t)strand) * X.dstride),
+                reinterpret_cast<const uint32_t *>(pd), (m + 3) / 4);
 }
 // Deliver the lane's hits to slot s -- those within the bound of the best
 // score known -- with its expansions; the lane's hit buffer is emptied.
@@ -1393,18 +1406,34 @@ __global__ __launch_bounds__(BLOCK) void k_dscan(DevIndex ix, ReadsView rd, Para
             fl |= (uint8_t)(1 << strand);
             continue;
         }
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(c.pd);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(drows + ((size_t)r * 2 + (size_t)strand) * dstride);
-        for (int k = 0; k < (m + 3) / 4; k++) dst[k] = src[k];
+        copy_dwords(reinterpret_cast<uint32_t *>(drows + ((size_t)r * 2 + (size_t)strand) * dstride),
+                    reinterpret_cast<const uint32_t *>(c.pd), (m + 3) / 4);
     }
     dflag[r] = fl;
 }
 
-// Copy a pre-pass row (m bytes) into the lane's LDS row.
+// Copy a pre-pass row (m bytes) into the lane's LDS row.  The rows start
+// 16-byte aligned and their stride is a multiple of 16, so whole 16-byte
+// blocks are read, four of them before any store: a row costs a few memory
+// round trips (one per dword when each load waits for the store before it,
+// which the compiler must assume may alias it).
 __device__ __forceinline__ void load_drow(uint8_t *pd, const uint8_t *row, int m) {
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(row);
+    const uint4 *src = reinterpret_cast<const uint4 *>(row);
     uint32_t *dst = reinterpret_cast<uint32_t *>(pd);
-    for (int k = 0; k < (m + 3) / 4; k++) dst[k] = src[k];
+    const int ndw = (m + 3) >> 2;
+    for (int q0 = 0; 4 * q0 < ndw; q0 += 4) {
+        uint4 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) v[j] = 4 * (q0 + j) < ndw ? src[q0 + j] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int k = 4 * (q0 + j);
+            if (k < ndw) dst[k] = v[j].x;
+            if (k + 1 < ndw) dst[k + 1] = v[j].y;
+            if (k + 2 < ndw) dst[k + 2] = v[j].z;
+            if (k + 3 < ndw) dst[k + 3] = v[j].w;
+        }
+    }
 }
 
 __global__ void k_set_args(PersistentArgs *dst, PersistentArgs a) {

@@ -42,6 +42,15 @@ def test_traffic_needs_matching_sources_and_settings(fake_root, monkeypatch):
     assert bench.traffic_from_profiles("k_align_persistent", "c5", split=1024) is None
 
 
+def test_the_record_of_the_setting_is_used(fake_root):
+    path = fake_root / "profiles" / "k_align_persistent_c5_bytes.md"
+    path.write_text(path.read_text() + RECORD.replace("split=1024", "split=512").replace("fetch_kib=100", "fetch_kib=200"))
+    one = bench.traffic_from_profiles("k_align_persistent", "c5", split=1024)
+    two = bench.traffic_from_profiles("k_align_persistent", "c5", split=512)
+    assert two - one == pytest.approx(100 * 1024 * 102400 / (50 * 1024))
+    assert bench.traffic_from_profiles("k_align_persistent", "c5", split=256) is None
+
+
 def test_committed_records_are_well_formed():
     files = glob.glob(os.path.join(ROOT, "profiles", "*_bytes.md"))
     recs = 0
