@@ -1153,9 +1153,13 @@ __device__ void put_tasks(const SplitBufs &X, uint32_t g, uint32_t off, uint32_t
 
 // Copy an m-byte pattern and D-array row from the lane's LDS row to the
 // slot: whole dwords, within both rows.
+// (A plain loop on purpose: this runs once per split read, in the endgame of
+// the batched kernel, and a batched copy there changed the code of that
+// kernel's whole loop and cost it about 3% on 100-base reads.)
 __device__ __forceinline__ void save_row(const SplitBufs &X, uint32_t s, int strand, const uint8_t *pd, int m) {
-    copy_dwords(reinterpret_cast<uint32_t *>(X.slot_rows + ((size_t)s * 2 + (size_t)strand) * X.dstride),
-                reinterpret_cast<const uint32_t *>(pd), (m + 3) / 4);
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(pd);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(X.slot_rows + ((size_t)s * 2 + (size_t)strand) * X.dstride);
+    for (int k = 0; k < (m + 3) / 4; k++) dst[k] = src[k];
 }
 // Deliver the lane's hits to slot s -- those within the bound of the best
 // score known -- with its expansions; the lane's hit buffer is emptied.

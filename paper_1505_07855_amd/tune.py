@@ -10,10 +10,11 @@ resident waves mean fewer lanes in the grid and more reads per lane).
 `tune_batched` times every candidate on the caller's own batch (the median
 of `repeats` timed calls after one untimed call), checks that every
 candidate returns the same bytes, and returns the fastest with the whole
-table.  Candidates within `tie` (1%) of the fastest median are treated as
-equally fast -- run-to-run spread on one batch is about that -- and among
-them the one with the longest rank lines wins: each rank-line access fills
-a 128-byte L2 line whatever the line size, so shorter lines leave part of
+table.  Candidates within `tie` (2%) of the fastest median are treated as
+equally fast -- the three layouts' medians on the C2 batch have come out
+in either order by up to 1.5% from one GPU to another -- and among them the
+one with the longest rank lines wins: each rank-line access fills a
+128-byte L2 line whatever the line size, so shorter lines leave part of
 every fill unused and move more bytes for the same work.
 """
 from __future__ import annotations
@@ -38,7 +39,7 @@ def index_label(ix: Index) -> str:
 
 
 def tune_batched(indexes, bases, offsets, params: Params, max_len: int, max_diff=None, waves=(0, 3, 2),
-                 repeats: int = 3, hit_capacity: int | None = None, log=None, tie: float = 0.01):
+                 repeats: int = 3, hit_capacity: int | None = None, log=None, tie: float = 0.02):
     """Time the batched form for every (index layout, waves per SIMD)
     candidate.  `indexes`: one uploaded index, or several of the same
     reference in different layouts (a list or a dict of any keys).  Returns
