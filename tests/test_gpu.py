@@ -436,7 +436,8 @@ def test_c5_full_size_sampled_parity(c2_full):
     250 bp (3% substitutions, 0.3% indel events, a tenth from repeat
     copies), at most 6 differences with a gap, no seed, all in one batched
     launch; 40,000 sampled reads against the oracle (hits, counts, status,
-    located positions), and whole-batch properties."""
+    located positions), at the default split budget and at 512 (the whole
+    batch byte-identical between the two), and whole-batch properties."""
     g, _, ix, ox = c2_full
     reads = configs.c5_reads(g)
     assert reads.n == 2_000_000 and (np.diff(reads.offsets) == 250).all()
@@ -460,6 +461,17 @@ def test_c5_full_size_sampled_parity(c2_full):
         got = [pos[po[h]:po[h + 1]].tolist() for h in range(a, b)]
         exp = [opos[opo[h]:opo[h + 1]].tolist() for h in range(oa, ob)]
         assert got == exp, r
+    # the split budget the C5 bench picks on this batch: the sample against
+    # the oracle again, and the whole batch byte-identical to the default's
+    p512, _ = _params_pair(**configs.PARAMS["C5"])
+    p512.split_budget = 512
+    print("[c5-full] aligning again at split budget 512", flush=True)
+    res512 = _gpu_align(ix, reads, p512)
+    _compare_align(res512, ores, rows=rows)
+    a0, a1 = res.to_numpy(), res512.to_numpy()
+    for x, y in zip(a0[:4], a1[:4]):
+        assert x.tobytes() == y.tobytes()
+    assert np.array_equal(a0[4] & 7, a1[4] & 7)
     st = res.status.cpu().numpy()
     ost = ores.status
     print(f"[c5-full] sample: {np.mean(ost & oracle.ST_HIT != 0):.3f} aligned, "
