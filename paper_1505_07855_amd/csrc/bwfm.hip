@@ -53,8 +53,11 @@ constexpr int INF_SCORE = 0x7fffffff;
 constexpr uint32_t PLAIN_STACK = 320;  // stack entries per lane, plain form first pass
 // Tuning constants a variant build may override with -D (results do not
 // depend on them; paper_1505_07855_amd/variants.py searches over them).
+// First-pass hit slots per lane: 128 keeps reads with up to that many
+// candidate hits, common on repeat-rich references, out of the second pass,
+// at no cost on reads with few hits.
 #ifndef BWFM_FAST_CAND
-#define BWFM_FAST_CAND 64
+#define BWFM_FAST_CAND 128
 #endif
 #ifndef BWFM_POPS_PER_STEP
 #define BWFM_POPS_PER_STEP 1

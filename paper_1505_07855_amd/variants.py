@@ -55,7 +55,7 @@ GENES = {
     "BWFM_GENE_SUBLOAD": (1, (0,)),
     "BWFM_GENE_KTLOOP": (0, (1,)),
     "BWFM_POPS_PER_STEP": (1, (2,)),
-    "BWFM_FAST_CAND": (64, (32, 128)),
+    "BWFM_FAST_CAND": (128, (64, 256)),
     "BWFM_SLOW_LANES": (16384, (8192,)),
 }
 
