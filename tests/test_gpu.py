@@ -192,8 +192,10 @@ def test_both_ends_in_one_batch(c2_small):
 @pytest.mark.parametrize("form,split", FORMS_SPLIT, ids=FORMS_SPLIT_IDS)
 def test_second_pass_and_overflow_parity(form, split):
     # a repeat-rich genome and ALL mode: many reads exceed the first pass's
-    # hit slots (or, in the plain form, its stack) and are searched again
-    g = gen.genome_repeats(91, 400_000, gc=0.41, repeat_frac=0.7, n_fam=5, min_len=300, max_len=800, div_lo=0.0,
+    # 128 hit slots (or, in the plain form, its stack) and are searched
+    # again (three repeat families over 800 kbp: about a hundred reads have
+    # more than 128 distinct hits within 3 differences)
+    g = gen.genome_repeats(91, 800_000, gc=0.41, repeat_frac=0.7, n_fam=3, min_len=300, max_len=800, div_lo=0.0,
                            div_hi=0.03)
     reads = gen.reads_se(92, g, 1500, 40, ps=0.03, indel_ratio=0.2, rep_frac=0.9)
     ox = oracle.Index(g.seq)
