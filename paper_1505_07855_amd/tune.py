@@ -77,7 +77,12 @@ def tune_batched(indexes, bases, offsets, params: Params, max_len: int, max_diff
             table.append(row)
             if log:
                 log(f"tune: {row['index']} waves_per_simd {w}: {row['ms']:.1f} ms (median of {repeats})")
+    return dict(pick(table, tie)), table
+
+
+def pick(table, tie: float = 0.02):
+    """The row the tuner returns: among the rows within `tie` of the fastest
+    median, the one with the longest rank lines, then the fastest."""
     fastest = min(r["ms"] for r in table)
     tied = [r for r in table if r["ms"] <= fastest * (1 + tie)]
-    best = min(tied, key=lambda r: (-r["line_bytes"], r["ms"]))
-    return dict(best), table
+    return min(tied, key=lambda r: (-r["line_bytes"], r["ms"]))

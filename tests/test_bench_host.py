@@ -64,3 +64,22 @@ def test_committed_records_are_well_formed():
                     assert float(rec[k]) > 0, (f, k)
                 recs += 1
     assert recs >= 3
+
+
+def test_tuner_prefers_longer_lines_within_the_tie():
+    from paper_1505_07855_amd import tune
+
+    def row(lb, w, ms):
+        return {"line_bytes": lb, "waves_per_simd": w, "ms": ms}
+
+    # 128-byte lines 1.25% behind the fastest 64-byte layout: a tie, the
+    # longer lines win (the case seen on one GPU)
+    t = [row(128, 0, 105.3), row(64, 0, 104.0), row(64, 3, 119.1)]
+    assert tune.pick(t) is t[0]
+    # beyond the tie the fastest wins, whatever its lines
+    assert tune.pick(t, tie=0.01) is t[1]
+    t2 = [row(128, 0, 107.0), row(64, 0, 104.0)]
+    assert tune.pick(t2) is t2[1]
+    # among tied rows of the same line size the faster one
+    t3 = [row(128, 3, 101.5), row(128, 0, 101.0), row(64, 0, 100.0)]
+    assert tune.pick(t3) is t3[1]
